@@ -1,0 +1,479 @@
+/* Oracle: a plain recursive FMM (test infrastructure only).
+ *
+ * Follows the phases of the paper's solver (Sec. 6.4, tab:complexity):
+ *   1. tree:     octree of cubic cells (Sec. 2.2.1); a cell holding more than
+ *                n_L particles is split into its non-empty octants.  Octants
+ *                come from 21-bit-per-axis quantised coordinates inside the
+ *                cube around the bounding box (the tree's definition, shared
+ *                with the GPU path by specification, not by code).
+ *   2. estimate: low-order FMM for the sink scale (Sec. 5.4.2): centres
+ *                z = s = z_com, acceptance theta < 1 with radii about z_com,
+ *                p = 1 for the acceleration a_b (criterion a) or the p = 0
+ *                monopole of the 1/r^2 Green's function for f_b (criterion f),
+ *                exact near field.  Walk one-sided (the paper's estimate pass
+ *                walks mutually; the estimate only needs ~15% accuracy).
+ *   3. up:       centres and radii, P2M at leaves, M2M upward (eq:P2M,
+ *                eq:M2M), multipole power P_n (eq:def:PA), minimum sink scale.
+ *   4. walk:     one-sided dual tree walk from (root, root) (Sec. 2.2.2,
+ *                Sec. 6.1): accepted interactions by M2L (eq:M2L) - or by
+ *                direct summation when N_A N_B is below a threshold - and
+ *                the rest split at the larger cell, leaf-leaf by P2P.
+ *                Acceptance: theta < 1 and Etilde M_A / r^2 < eps min_B{a_b}
+ *                (eq:mac:better:a) or min_B{f_b} (eq:mac:better:f).
+ *   5. down:     L2L (eq:L2L) top down, L2P (eq:L2P) at leaf particles.
+ *
+ * Expansion centre of every cell: z = s = the midpoint of the bounding box of
+ * its particles; rho = max distance of its particles from that centre
+ * (Sec. 4: rho_z, rho_s definitions).  The paper uses the centre of the
+ * smallest enclosing sphere (Sec. 5.1.1); the choice changes the cost of the
+ * walk, not its accuracy, because the acceptance test uses the actual radius.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define MAXLEVEL 21
+
+typedef struct {
+    int64_t begin, end;
+    int level, nchild;
+    int64_t child[8];
+    int64_t parent;
+    double mass, com[3], rho_com;
+    double c[3], rho;
+    double smin;
+    double complex *M, *F;   /* order p at c */
+    double complex Me[4], Fe[4]; /* order 1 at com (estimate of a) */
+    double fe;               /* 1/r^2 monopole sum (estimate of f) */
+    double *P;
+} cell_t;
+
+typedef struct {
+    const or_fmm_params *prm;
+    int64_t n;
+    int p, ncoef;
+    /* particles in Morton order */
+    double *x;      /* 3n */
+    double *m;
+    int64_t *orig;  /* Morton position -> input index */
+    uint64_t *key;
+    cell_t *cells; int64_t ncells, cap;
+    /* accumulators, Morton order */
+    double *pot, *acc;      /* near + far */
+    double *est_acc, *est_f;
+    double *scale;          /* per particle sink scale, Morton order */
+    or_fmm_stats *st;
+    or_fmm_lists *lists;
+    int64_t nm2l_rec, np2p_rec;
+    int oom;
+} fmm_t;
+
+/* ---------------------------------------------------------------- tree */
+
+typedef struct { uint64_t key; int64_t idx; } keyidx;
+
+static int cmp_keyidx(const void *a, const void *b) {
+    const keyidx *u = (const keyidx *)a, *v = (const keyidx *)b;
+    if (u->key != v->key) return u->key < v->key ? -1 : 1;
+    return (u->idx > v->idx) - (u->idx < v->idx);
+}
+
+/* bit i of the x, y, z cell index goes to key bit 3i, 3i+1, 3i+2 */
+static uint64_t morton(uint32_t qx, uint32_t qy, uint32_t qz) {
+    uint64_t k = 0;
+    for (int i = 0; i < MAXLEVEL; ++i) {
+        k |= (uint64_t)((qx >> i) & 1u) << (3 * i);
+        k |= (uint64_t)((qy >> i) & 1u) << (3 * i + 1);
+        k |= (uint64_t)((qz >> i) & 1u) << (3 * i + 2);
+    }
+    return k;
+}
+
+static int64_t new_cell(fmm_t *t) {
+    if (t->ncells == t->cap) {
+        int64_t cap = t->cap ? 2 * t->cap : 1024;
+        cell_t *c = (cell_t *)realloc(t->cells, sizeof(cell_t) * (size_t)cap);
+        if (!c) { t->oom = 1; return -1; }
+        t->cells = c; t->cap = cap;
+    }
+    memset(&t->cells[t->ncells], 0, sizeof(cell_t));
+    return t->ncells++;
+}
+
+static int64_t build(fmm_t *t, int64_t b, int64_t e, int level, int64_t parent) {
+    const int64_t id = new_cell(t);
+    if (id < 0) return -1;
+    cell_t *C = &t->cells[id];
+    C->begin = b; C->end = e; C->level = level; C->parent = parent;
+    if (e - b > t->prm->leaf_size && level < MAXLEVEL) {
+        const int shift = 3 * (MAXLEVEL - (level + 1));
+        int64_t s = b;
+        for (int oct = 0; oct < 8; ++oct) {
+            int64_t q = s;
+            while (q < e && (int)((t->key[q] >> shift) & 7u) == oct) ++q;
+            if (q > s) {
+                const int64_t ch = build(t, s, q, level + 1, id);
+                if (ch < 0) return -1;
+                C = &t->cells[id]; /* realloc may have moved it */
+                C->child[C->nchild++] = ch;
+            }
+            s = q;
+        }
+    }
+    return id;
+}
+
+static int is_leaf(const cell_t *C) { return C->nchild == 0; }
+
+static int64_t cell_id(const cell_t *C) { return ((int64_t)C->level << 40) | C->begin; }
+
+/* mass, centre of mass, bounding-box centre and the radii, straight from the
+ * cell's particles */
+static void cell_geometry(fmm_t *t, cell_t *C) {
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double M = 0, mx = 0, my = 0, mz = 0;
+    for (int64_t i = C->begin; i < C->end; ++i) {
+        const double *x = &t->x[3 * i];
+        for (int d = 0; d < 3; ++d) { lo[d] = fmin(lo[d], x[d]); hi[d] = fmax(hi[d], x[d]); }
+        M += t->m[i]; mx += t->m[i] * x[0]; my += t->m[i] * x[1]; mz += t->m[i] * x[2];
+    }
+    C->mass = M;
+    C->com[0] = mx / M; C->com[1] = my / M; C->com[2] = mz / M;
+    for (int d = 0; d < 3; ++d) C->c[d] = (lo[d] + hi[d]) * 0.5;
+    double r2max = 0, r2com = 0;
+    for (int64_t i = C->begin; i < C->end; ++i) {
+        const double *x = &t->x[3 * i];
+        const double dx = x[0] - C->c[0], dy = x[1] - C->c[1], dz = x[2] - C->c[2];
+        const double r2 = (dx * dx + dy * dy) + dz * dz;
+        if (r2 > r2max) r2max = r2;
+        const double ex = x[0] - C->com[0], ey = x[1] - C->com[1], ez = x[2] - C->com[2];
+        const double e2 = (ex * ex + ey * ey) + ez * ez;
+        if (e2 > r2com) r2com = e2;
+    }
+    C->rho = sqrt(r2max);
+    C->rho_com = sqrt(r2com);
+}
+
+/* ------------------------------------------------------------ direct sums */
+
+static void p2p(fmm_t *t, const cell_t *A, const cell_t *B, double *pot, double *acc,
+                int64_t *count) {
+    for (int64_t b = B->begin; b < B->end; ++b) {
+        const double *xb = &t->x[3 * b];
+        for (int64_t a = A->begin; a < A->end; ++a) {
+            if (a == b) continue;
+            const double dx = t->x[3 * a] - xb[0], dy = t->x[3 * a + 1] - xb[1],
+                         dz = t->x[3 * a + 2] - xb[2];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const double ir = 1.0 / sqrt(r2);
+            const double q = t->m[a] * ir, q3 = q * ir * ir;
+            if (pot) pot[b] += q;
+            acc[3 * b] += q3 * dx; acc[3 * b + 1] += q3 * dy; acc[3 * b + 2] += q3 * dz;
+            ++*count;
+        }
+    }
+}
+
+static void p2p_f(fmm_t *t, const cell_t *A, const cell_t *B, double *f, int64_t *count) {
+    for (int64_t b = B->begin; b < B->end; ++b)
+        for (int64_t a = A->begin; a < A->end; ++a) {
+            if (a == b) continue;
+            const double dx = t->x[3 * a] - t->x[3 * b], dy = t->x[3 * a + 1] - t->x[3 * b + 1],
+                         dz = t->x[3 * a + 2] - t->x[3 * b + 2];
+            f[b] += t->m[a] / (dx * dx + dy * dy + dz * dz);
+            ++*count;
+        }
+}
+
+/* ------------------------------------------- estimate of the sink scale */
+
+static int64_t split_choice(const cell_t *A, const cell_t *B, double rA, double rB) {
+    /* returns 0 to split A, 1 to split B: the larger cell, B on a tie, never a leaf */
+    if (is_leaf(A)) return 1;
+    if (is_leaf(B)) return 0;
+    return rA > rB ? 0 : 1;
+}
+
+static void est_walk(fmm_t *t, int64_t ia, int64_t ib) {
+    const cell_t *A = &t->cells[ia], *B = &t->cells[ib];
+    const int want_f = t->prm->mac == OR_MAC_F;
+    if (ia == ib) {
+        if (is_leaf(A)) {
+            if (want_f) p2p_f(t, A, A, t->est_f, &t->st->n_est_p2p_pairs);
+            else p2p(t, A, A, NULL, t->est_acc, &t->st->n_est_p2p_pairs);
+        } else {
+            for (int i = 0; i < A->nchild; ++i)
+                for (int j = 0; j < A->nchild; ++j) est_walk(t, A->child[i], A->child[j]);
+        }
+        return;
+    }
+    const double d[3] = {B->com[0] - A->com[0], B->com[1] - A->com[1], B->com[2] - A->com[2]};
+    const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    if (A->rho_com + B->rho_com < r) {
+        ++t->st->n_est_m2l;
+        if (want_f) t->cells[ib].fe += A->mass / (r * r);
+        else or_m2l(A->Me, d, 1, t->cells[ib].Fe);
+        return;
+    }
+    if (is_leaf(A) && is_leaf(B)) {
+        if (want_f) p2p_f(t, A, B, t->est_f, &t->st->n_est_p2p_pairs);
+        else p2p(t, A, B, NULL, t->est_acc, &t->st->n_est_p2p_pairs);
+        return;
+    }
+    if (split_choice(A, B, A->rho_com, B->rho_com) == 0) {
+        for (int i = 0; i < A->nchild; ++i) est_walk(t, t->cells[ia].child[i], ib);
+    } else {
+        for (int j = 0; j < B->nchild; ++j) est_walk(t, ia, t->cells[ib].child[j]);
+    }
+}
+
+static void est_up(fmm_t *t, int64_t ic) {
+    cell_t *C = &t->cells[ic];
+    if (is_leaf(C)) {
+        or_p2m(C->end - C->begin, &t->x[3 * C->begin], &t->m[C->begin], C->com, 1, C->Me);
+        return;
+    }
+    for (int i = 0; i < C->nchild; ++i) {
+        est_up(t, C->child[i]);
+        const cell_t *D = &t->cells[C->child[i]];
+        const double d[3] = {D->com[0] - C->com[0], D->com[1] - C->com[1], D->com[2] - C->com[2]};
+        or_m2m(D->Me, d, 1, C->Me);
+    }
+}
+
+static void est_down(fmm_t *t, int64_t ic) {
+    cell_t *C = &t->cells[ic];
+    const int want_f = t->prm->mac == OR_MAC_F;
+    if (is_leaf(C)) {
+        for (int64_t b = C->begin; b < C->end; ++b) {
+            if (want_f) { t->est_f[b] += C->fe; continue; }
+            const double d[3] = {C->com[0] - t->x[3 * b], C->com[1] - t->x[3 * b + 1],
+                                 C->com[2] - t->x[3 * b + 2]};
+            double psi, a[3];
+            or_l2p(C->Fe, d, 1, &psi, a);
+            for (int k = 0; k < 3; ++k) t->est_acc[3 * b + k] += a[k];
+        }
+        return;
+    }
+    for (int i = 0; i < C->nchild; ++i) {
+        cell_t *D = &t->cells[C->child[i]];
+        if (want_f) {
+            D->fe += C->fe;
+        } else {
+            const double d[3] = {C->com[0] - D->com[0], C->com[1] - D->com[1], C->com[2] - D->com[2]};
+            or_l2l(C->Fe, d, 1, D->Fe);
+        }
+        est_down(t, C->child[i]);
+    }
+}
+
+/* ----------------------------------------------------------- main pass */
+
+static void up(fmm_t *t, int64_t ic) {
+    cell_t *C = &t->cells[ic];
+    if (is_leaf(C)) {
+        or_p2m(C->end - C->begin, &t->x[3 * C->begin], &t->m[C->begin], C->c, t->p, C->M);
+    } else {
+        for (int i = 0; i < C->nchild; ++i) {
+            up(t, C->child[i]);
+            const cell_t *D = &t->cells[C->child[i]];
+            const double d[3] = {D->c[0] - C->c[0], D->c[1] - C->c[1], D->c[2] - C->c[2]};
+            or_m2m(D->M, d, t->p, C->M);
+        }
+    }
+    or_power(C->M, t->p, C->P);
+}
+
+static void record(int64_t *buf, int64_t cap, int64_t *cnt, const cell_t *A, const cell_t *B) {
+    if (buf && *cnt < cap) { buf[2 * *cnt] = cell_id(A); buf[2 * *cnt + 1] = cell_id(B); }
+    ++*cnt;
+}
+
+static int accept(fmm_t *t, const cell_t *A, const cell_t *B, const double d[3]) {
+    const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const or_fmm_params *q = t->prm;
+    if (q->mac == OR_MAC_THETA) return A->rho + B->rho < q->theta_crit * r;
+    if (!(A->rho + B->rho < r)) return 0;                        /* theta < 1 */
+    const double err = or_etilde_factor(A->rho, B->rho) * or_eab_times_mass(A->P, t->p, B->rho, r)
+                       / (r * r);                                /* Etilde M_A / r^2 */
+    return err < q->eps * B->smin;
+}
+
+static void walk(fmm_t *t, int64_t ia, int64_t ib) {
+    const cell_t *A = &t->cells[ia], *B = &t->cells[ib];
+    if (ia == ib) {
+        if (is_leaf(A)) {
+            p2p(t, A, A, t->pot, t->acc, &t->st->n_p2p_pairs);
+            ++t->st->n_p2p_cells;
+            record(t->lists ? t->lists->p2p : NULL, t->lists ? t->lists->p2p_cap : 0,
+                   &t->np2p_rec, A, A);
+        } else {
+            for (int i = 0; i < A->nchild; ++i)
+                for (int j = 0; j < A->nchild; ++j) walk(t, A->child[i], A->child[j]);
+        }
+        return;
+    }
+    const double d[3] = {B->c[0] - A->c[0], B->c[1] - A->c[1], B->c[2] - A->c[2]};
+    const int ok = accept(t, A, B, d);
+    if (ok && (double)(A->end - A->begin) * (double)(B->end - B->begin) >= t->prm->p2p_pairs) {
+        or_m2l(A->M, d, t->p, t->cells[ib].F);
+        ++t->st->n_m2l;
+        record(t->lists ? t->lists->m2l : NULL, t->lists ? t->lists->m2l_cap : 0,
+               &t->nm2l_rec, A, B);
+        return;
+    }
+    if (ok || (is_leaf(A) && is_leaf(B))) {
+        p2p(t, A, B, t->pot, t->acc, &t->st->n_p2p_pairs);
+        ++t->st->n_p2p_cells;
+        record(t->lists ? t->lists->p2p : NULL, t->lists ? t->lists->p2p_cap : 0,
+               &t->np2p_rec, A, B);
+        return;
+    }
+    if (split_choice(A, B, A->rho, B->rho) == 0) {
+        for (int i = 0; i < A->nchild; ++i) walk(t, t->cells[ia].child[i], ib);
+    } else {
+        for (int j = 0; j < B->nchild; ++j) walk(t, ia, t->cells[ib].child[j]);
+    }
+}
+
+static void down(fmm_t *t, int64_t ic) {
+    cell_t *C = &t->cells[ic];
+    if (is_leaf(C)) {
+        for (int64_t b = C->begin; b < C->end; ++b) {
+            const double d[3] = {C->c[0] - t->x[3 * b], C->c[1] - t->x[3 * b + 1],
+                                 C->c[2] - t->x[3 * b + 2]};
+            double psi, a[3];
+            or_l2p(C->F, d, t->p, &psi, a);
+            t->pot[b] += psi;
+            for (int k = 0; k < 3; ++k) t->acc[3 * b + k] += a[k];
+        }
+        return;
+    }
+    for (int i = 0; i < C->nchild; ++i) {
+        cell_t *D = &t->cells[C->child[i]];
+        const double d[3] = {C->c[0] - D->c[0], C->c[1] - D->c[1], C->c[2] - D->c[2]};
+        or_l2l(C->F, d, t->p, D->F);
+        down(t, C->child[i]);
+    }
+}
+
+static double subtree_min(fmm_t *t, int64_t ic) {
+    cell_t *C = &t->cells[ic];
+    double s = INFINITY;
+    for (int64_t b = C->begin; b < C->end; ++b) s = fmin(s, t->scale[b]);
+    C->smin = s;
+    for (int i = 0; i < C->nchild; ++i) subtree_min(t, C->child[i]);
+    return s;
+}
+
+/* ---------------------------------------------------------------- driver */
+
+static void release(fmm_t *t) {
+    for (int64_t i = 0; i < t->ncells; ++i) {
+        free(t->cells[i].M); free(t->cells[i].F); free(t->cells[i].P);
+    }
+    free(t->cells); free(t->x); free(t->m); free(t->orig); free(t->key);
+    free(t->pot); free(t->acc); free(t->est_acc); free(t->est_f); free(t->scale);
+}
+
+int or_fmm(const or_fmm_params *prm, int64_t n, const double *pos,
+           const double *mass, double *pot, double *acc,
+           or_fmm_stats *stats, or_fmm_lists *lists) {
+    or_fmm_stats dummy;
+    if (!stats) stats = &dummy;
+    memset(stats, 0, sizeof(*stats));
+    if (!prm || n < 0 || prm->p < 1 || prm->p > 30 || prm->leaf_size < 1) return -1;
+    if (n == 0) return 0;
+    if (!pos || !mass || !pot || !acc) return -1;
+    if (prm->scale_source == OR_SCALE_GIVEN && prm->mac != OR_MAC_THETA && !prm->scale) return -1;
+
+    fmm_t T; memset(&T, 0, sizeof(T));
+    fmm_t *t = &T;
+    t->prm = prm; t->n = n; t->p = prm->p; t->ncoef = (prm->p + 1) * (prm->p + 1);
+    t->st = stats; t->lists = lists;
+
+    /* 1. keys in the cube around the bounding box, sort, permute */
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = 0; i < n; ++i)
+        for (int d = 0; d < 3; ++d) { lo[d] = fmin(lo[d], pos[3 * i + d]); hi[d] = fmax(hi[d], pos[3 * i + d]); }
+    double L = 0;
+    for (int d = 0; d < 3; ++d) L = fmax(L, hi[d] - lo[d]);
+    const double scale = L > 0 ? 2097152.0 / L : 0.0;   /* 2^21 cells per axis */
+    keyidx *ki = (keyidx *)malloc(sizeof(keyidx) * (size_t)n);
+    t->x = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    t->m = (double *)malloc(sizeof(double) * (size_t)n);
+    t->orig = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    t->key = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+    t->pot = (double *)calloc((size_t)n, sizeof(double));
+    t->acc = (double *)calloc(3 * (size_t)n, sizeof(double));
+    t->est_acc = (double *)calloc(3 * (size_t)n, sizeof(double));
+    t->est_f = (double *)calloc((size_t)n, sizeof(double));
+    t->scale = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!ki || !t->x || !t->m || !t->orig || !t->key || !t->pot || !t->acc || !t->est_acc ||
+        !t->est_f || !t->scale) { free(ki); release(t); return -2; }
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t q[3];
+        for (int d = 0; d < 3; ++d) {
+            const double u = (pos[3 * i + d] - lo[d]) * scale;
+            q[d] = u >= 2097151.0 ? 2097151u : (uint32_t)u;
+        }
+        ki[i].key = morton(q[0], q[1], q[2]);
+        ki[i].idx = i;
+    }
+    qsort(ki, (size_t)n, sizeof(keyidx), cmp_keyidx);
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t j = ki[i].idx;
+        t->orig[i] = j; t->key[i] = ki[i].key; t->m[i] = mass[j];
+        for (int d = 0; d < 3; ++d) t->x[3 * i + d] = pos[3 * j + d];
+    }
+    free(ki);
+
+    /* octree */
+    if (build(t, 0, n, 0, -1) < 0 || t->oom) { release(t); return -2; }
+    for (int64_t i = 0; i < t->ncells; ++i) {
+        cell_t *C = &t->cells[i];
+        cell_geometry(t, C);
+        C->M = (double complex *)calloc((size_t)t->ncoef, sizeof(double complex));
+        C->F = (double complex *)calloc((size_t)t->ncoef, sizeof(double complex));
+        C->P = (double *)calloc((size_t)t->p + 1, sizeof(double));
+        if (!C->M || !C->F || !C->P) { release(t); return -2; }
+        if (is_leaf(C)) ++stats->n_leaves;
+        if (C->level > stats->depth) stats->depth = C->level;
+    }
+    stats->n_cells = t->ncells;
+
+    /* 2. sink scale */
+    if (prm->mac != OR_MAC_THETA) {
+        if (prm->scale_source == OR_SCALE_GIVEN) {
+            for (int64_t i = 0; i < n; ++i) t->scale[i] = prm->scale[t->orig[i]];
+        } else {
+            est_up(t, 0);
+            est_walk(t, 0, 0);
+            est_down(t, 0);
+            for (int64_t i = 0; i < n; ++i) {
+                const double *a = &t->est_acc[3 * i];
+                t->scale[i] = prm->mac == OR_MAC_F ? t->est_f[i]
+                                                   : sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+            }
+        }
+        if (lists && lists->scale_est)
+            for (int64_t i = 0; i < n; ++i) lists->scale_est[t->orig[i]] = t->scale[i];
+        subtree_min(t, 0);
+    }
+
+    /* 3-5. upward pass, walk, downward pass */
+    up(t, 0);
+    walk(t, 0, 0);
+    down(t, 0);
+    if (lists) { lists->m2l_count = t->nm2l_rec; lists->p2p_count = t->np2p_rec; }
+
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t j = t->orig[i];
+        pot[j] = -prm->G * t->pot[i];
+        for (int d = 0; d < 3; ++d) acc[3 * j + d] = prm->G * t->acc[3 * i + d];
+    }
+    release(t);
+    return 0;
+}

@@ -1,0 +1,118 @@
+/* CPU oracle for the fast multipole method of Dehnen, "A fast multipole method
+ * for stellar dynamics" (Comput. Astrophys. Cosmol. 2014).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the plain, slow, FP64 reference
+ * that the GPU path is checked against.  Only the test suite, the smoke check
+ * and the CPU-baseline leg of the benchmark may load it.  It shares no code
+ * with the HIP library: no headers, helpers, tables or kernels.
+ *
+ * Contents
+ *   direct.c    - the exact result: direct summation of eq. (1) (eq:P2P) and
+ *                 of the scale f (eq:f), Neumaier-compensated, threaded over
+ *                 sinks (result independent of the thread count).
+ *   harmonics.c - complex solid harmonics Theta_n^m, Upsilon_n^m (Sec. 2.1,
+ *                 App. A.3, A.5) and the FMM kernels P2M, M2M, M2L, L2L, L2P
+ *                 (eqs:fmm), multipole power P_n (eq:def:PA) and the error
+ *                 estimate E_{A->B} (eq:def:EAB, eq:err:tilde).
+ *   fmm.c       - a plain recursive FMM following the paper's phases: tree,
+ *                 low-order estimate of the sink scale (Sec. 5.4.2), upward
+ *                 pass, one-sided dual tree walk with the error-balancing
+ *                 acceptance criterion (eqs:mac:better), downward pass.
+ *
+ * Complex arrays are stored interleaved (re, im) with index n*n + n + m for
+ * 0 <= n <= p, -n <= m <= n, i.e. (p+1)^2 complex numbers.
+ */
+#ifndef FMM_ORACLE_H
+#define FMM_ORACLE_H
+
+#include <stdint.h>
+#include <complex.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OR_IDX(n, m) ((n) * (n) + (n) + (m))
+
+/* ---- direct summation (direct.c) -------------------------------------- */
+/* For every sink b in `sinks` (or all b when sinks == NULL):
+ *   pot[i] = -G sum_{a != b} mu_a / |x_b - x_a|           (physical potential)
+ *   acc[i] =  G sum_{a != b} mu_a (x_a - x_b)/|x_a - x_b|^3
+ *   f[i]   =  G sum_{a != b} mu_a / |x_a - x_b|^2          (eq:f)
+ * where i indexes the sink list.  Sources are taken in index order; each
+ * component is summed with Neumaier compensation.  Any of pot/acc/f may be
+ * NULL.  Returns 0, or -1 on bad arguments. */
+int or_direct(int64_t n, const double *pos, const double *mass, double G,
+              int64_t n_sinks, const int64_t *sinks, int threads,
+              double *pot, double *acc, double *f);
+
+/* ---- harmonics and kernels (harmonics.c), complex, all m ------------- */
+void or_theta(const double r[3], int p, double complex *T);
+void or_upsilon(const double r[3], int p, double complex *U);
+/* M_n^m(z) += sum_a mu_a Upsilon_n^m(x_a - z)                       eq:P2M */
+void or_p2m(int64_t n, const double *pos, const double *mass,
+            const double z[3], int p, double complex *M);
+/* Mout_n^m(z') += sum_{k,l} Upsilon_k^l(z - z') M_{n-k}^{m-l}(z)     eq:M2M */
+void or_m2m(const double complex *M, const double z_minus_zp[3], int p,
+            double complex *Mout);
+/* F_n^m(s_B) += sum_{k<=p-n} sum_l conj(M_k^l) Theta_{n+k}^{m+l}(s_B - z_A) eq:M2L */
+void or_m2l(const double complex *M, const double sB_minus_zA[3], int p,
+            double complex *F);
+/* Fout_n^m(s') += sum_{k<=p-n} sum_l conj(Upsilon_k^l(s - s')) F_{n+k}^{m+l}(s) eq:L2L */
+void or_l2l(const double complex *F, const double s_minus_sp[3], int p,
+            double complex *Fout);
+/* Psi_0^0 and a = -(Re Psi_1^1, Im Psi_1^1, Psi_1^0) at x_b     eq:L2P:Psi, eq:L2P */
+void or_l2p(const double complex *F, const double sB_minus_x[3], int p,
+            double *psi, double acc[3]);
+/* P_n = sqrt(sum_m (n-m)!(n+m)! |M_n^m|^2), n = 0..p              eq:def:PA */
+void or_power(const double complex *M, int p, double *P);
+/* E_{A->B} of eq:def:EAB times M_A (i.e. without the 1/M_A factor) */
+double or_eab_times_mass(const double *P, int p, double rho_sB, double r);
+/* factor 8 max(rho_A, rho_B)/(rho_A + rho_B) of eq:err:tilde (8 when both 0) */
+double or_etilde_factor(double rho_zA, double rho_sB);
+
+/* ---- the plain FMM (fmm.c) ------------------------------------------ */
+enum { OR_MAC_A = 0, OR_MAC_F = 1, OR_MAC_THETA = 2 };
+enum { OR_SCALE_ESTIMATE = 0, OR_SCALE_GIVEN = 1 };
+
+typedef struct {
+    int p;             /* expansion order, 1..30 */
+    double eps;        /* accuracy parameter epsilon of eqs:mac:better */
+    int leaf_size;     /* n_L: a cell with more particles is split (depth < 21) */
+    int mac;           /* OR_MAC_A (eq:mac:better:a), OR_MAC_F, OR_MAC_THETA */
+    double theta_crit; /* for OR_MAC_THETA only (eq:mac:theta) */
+    double p2p_pairs;  /* T: accepted pairs with N_A*N_B < T are summed directly */
+    int scale_source;  /* OR_SCALE_ESTIMATE or OR_SCALE_GIVEN */
+    const double *scale; /* OR_SCALE_GIVEN: per-particle a_b or f_b (input order, G=1 units) */
+    double G;
+} or_fmm_params;
+
+typedef struct {
+    int64_t n_cells, n_leaves, depth;
+    int64_t n_m2l;          /* accepted cell->cell interactions done by M2L */
+    int64_t n_p2p_cells;    /* cell->cell interactions done by direct summation */
+    int64_t n_p2p_pairs;    /* particle pairs summed directly (ordered, a != b) */
+    int64_t n_est_m2l, n_est_p2p_pairs; /* the same for the estimate pass */
+} or_fmm_stats;
+
+/* Optional outputs for list comparison.  A cell is identified by
+ * (level << 40) | begin, with begin its first particle in Morton order.
+ * m2l[2i] = source id, m2l[2i+1] = sink id; p2p likewise (sink may be any
+ * cell).  Entries are written while i < *_cap; *_count returns the total. */
+typedef struct {
+    int64_t *m2l; int64_t m2l_cap; int64_t m2l_count;
+    int64_t *p2p; int64_t p2p_cap; int64_t p2p_count;
+    double *scale_est;      /* per particle (input order): the sink scale used */
+} or_fmm_lists;
+
+/* pot[i] = physical potential, acc[i*3..] = acceleration of particle i (input
+ * order).  Returns 0 on success, -1 on bad arguments, -2 on allocation
+ * failure. */
+int or_fmm(const or_fmm_params *prm, int64_t n, const double *pos,
+           const double *mass, double *pot, double *acc,
+           or_fmm_stats *stats, or_fmm_lists *lists);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
