@@ -1,0 +1,153 @@
+/* fmm.h - C ABI of libfmm, an MI355X (gfx950) implementation of the fast
+ * multipole method of W. Dehnen, "A fast multipole method for stellar
+ * dynamics", Computational Astrophysics and Cosmology 1:1 (2014).
+ *
+ * It computes, for all N particles, the unsoftened potential and acceleration
+ *     Psi_b = sum_{a != b} G mu_a / |x_b - x_a|,   a_b = grad Psi_b     (eq. 1)
+ * by tree build, upward pass (P2M, M2M), a one-sided dual tree walk whose
+ * acceptance test is the error-balancing criterion of Sec. 5.3
+ * (eqs:mac:better), M2L, downward pass (L2L, L2P) and direct near-field sums
+ * (P2P), every stage a HIP kernel.
+ *
+ * Conventions for every entry point
+ *  - Array arguments named pos, mass, pot, acc, offsets are DEVICE pointers
+ *    (e.g. torch tensors on the GPU), owned by the caller, never retained
+ *    after the call returns.  pos is n x 3 row-major FP64 (x0,y0,z0,x1,...),
+ *    mass n FP64, pot n FP64, acc n x 3 row-major FP64.  Inputs are read only.
+ *  - Results are in input order.  pot is the physical potential
+ *    Phi_b = -Psi_b (negative); acc = grad Psi_b points towards the mass.
+ *  - Calls are ordered on the context's HIP stream and synchronous on return.
+ *  - Argument errors are detected before any launch: FMM_E_INVAL, outputs
+ *    untouched.  A context serves one host thread at a time (FMM_E_BUSY).
+ *  - No C++ exception crosses this interface.
+ */
+#ifndef FMM_H
+#define FMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fmm_ctx fmm_ctx;
+
+typedef enum {
+    FMM_OK = 0,
+    FMM_E_INVAL = 1,       /* bad argument (nothing launched, nothing written) */
+    FMM_E_NOMEM = 2,       /* device allocation failed */
+    FMM_E_HIP = 3,         /* a HIP runtime call failed; see fmm_last_error */
+    FMM_E_NONFINITE = 4,   /* non-finite input or output (e.g. two distinct
+                              particles at one position); outputs written but
+                              undefined */
+    FMM_E_UNSUPPORTED = 5, /* expansion order outside the compiled range */
+    FMM_E_BUSY = 6         /* context already in use by another thread */
+} fmm_status;
+
+/* Multipole-acceptance criterion of the main walk. */
+typedef enum {
+    FMM_MAC_REL = 0,    /* theta < 1 and Etilde M_A / r^2 < eps min_B{a_b}  (eq:mac:better:a) */
+    FMM_MAC_SCALED = 1, /* theta < 1 and Etilde M_A / r^2 < eps min_B{f_b}  (eq:mac:better:f) */
+    FMM_MAC_THETA = 2   /* theta < theta_crit (eq:mac:theta); eps unused */
+} fmm_mac;
+
+/* Where min_B{a_b} (or f_b) comes from. */
+typedef enum {
+    FMM_SCALE_ESTIMATE = 0, /* low-order FMM estimate (Sec. 5.4.2) inside the call */
+    FMM_SCALE_PREVIOUS = 1  /* |acc| of the previous call on this context with the
+                               same n (Sec. 5.4.1); falls back to the estimate on
+                               the first call or when n changed */
+} fmm_scale_source;
+
+typedef struct {
+    int device;            /* HIP device ordinal */
+    void *hip_stream;      /* hipStream_t to order work on; NULL = a stream the
+                              context creates (default priority) */
+    int leaf_size;         /* n_L, cells with more particles are split; 0 = 32 */
+    fmm_mac mac;           /* FMM_MAC_REL by default (0) */
+    double theta_crit;     /* FMM_MAC_THETA only */
+    double p2p_factor;     /* accepted pairs with N_A N_B < p2p_factor (p+1)^3
+                              are summed directly; 0 = 0.5 */
+    fmm_scale_source scale_source;
+    int timing;            /* nonzero: record per-phase HIP events (fmm_stats) */
+} fmm_opts;
+
+/* Interaction counts and per-phase times of the last fmm_forces call. */
+typedef struct {
+    int p;                       /* expansion order used */
+    int64_t n;                   /* particles */
+    int64_t n_cells, n_leaves;   /* octree */
+    int depth;                   /* deepest level (root = 0) */
+    int64_t n_m2l;               /* accepted cell pairs evaluated by M2L */
+    int64_t n_p2p_lists;         /* (source cell, sink leaf) direct-sum entries */
+    int64_t n_p2p_pairs;         /* ordered particle pairs summed directly */
+    int64_t n_est_m2l, n_est_p2p_pairs; /* the same for the estimate pass */
+    int walk_iterations;         /* breadth-first walk sweeps (main pass) */
+    /* milliseconds, measured with HIP events when fmm_opts.timing != 0
+       (phases as in the paper's tab:complexity) */
+    double t_tree, t_estimate, t_up, t_walk, t_m2l, t_p2p, t_down, t_total;
+    /* average duration of one launch of the M2L and P2P kernels (ms) */
+    double t_m2l_kernel, t_p2p_kernel;
+    int m2l_launches, p2p_launches;
+} fmm_stats_t;
+
+/* Create a context on opts->device.  Allocates only small bookkeeping; the
+ * workspace grows on the first fmm_forces call with a larger n.
+ * Returns FMM_E_INVAL for a NULL ctx or opts or out-of-range options. */
+fmm_status fmm_build(fmm_ctx **ctx, const fmm_opts *opts);
+
+/* Potential and acceleration of all n particles (eq. 1, Sec. 6).
+ *   G          gravitational constant (applied at the end; the acceptance
+ *              test is G invariant)
+ *   p          expansion order 1..FMM_P_MAX, or < 0 for the order chosen from
+ *              target_err by fmm_order_for_error
+ *   target_err accuracy parameter epsilon of eqs:mac:better (> 0, finite)
+ * n = 0 is a no-op; n = 1 gives pot = acc = 0. */
+fmm_status fmm_forces(fmm_ctx *ctx, int64_t n, const double *pos, const double *mass,
+                      double G, int p, double target_err, double *pot, double *acc);
+
+/* The same as fmm_forces for k independent clusters stored back to back:
+ * cluster i holds particles [offsets[i], offsets[i+1]) (host array of k+1
+ * int64, offsets[0] = 0); particles interact only within their cluster. */
+fmm_status fmm_forces_batched(fmm_ctx *ctx, int64_t k, const int64_t *offsets_host,
+                              const double *pos, const double *mass, double G, int p,
+                              double target_err, double *pot, double *acc);
+
+/* Exact FP64 direct summation of eq. (1) on the GPU (the comparison
+ * baseline): all n sinks against all n sources, a != b. */
+fmm_status fmm_direct(fmm_ctx *ctx, int64_t n, const double *pos, const double *mass,
+                      double G, double *pot, double *acc);
+
+/* Expansion order used when fmm_forces gets p < 0. */
+int fmm_order_for_error(double target_err);
+
+/* Statistics of the last call (FMM_E_INVAL for NULL arguments). */
+fmm_status fmm_stats(const fmm_ctx *ctx, fmm_stats_t *out);
+
+/* Device bytes a call with n particles at order p is expected to need
+ * (workspace + interaction lists), for admission control. */
+size_t fmm_footprint_bytes(int64_t n, int p, const fmm_opts *opts);
+
+/* Text of the last error on this context ("" if none); valid until the next call. */
+const char *fmm_last_error(const fmm_ctx *ctx);
+
+/* Release the context and its workspace. NULL is ignored. */
+void fmm_destroy(fmm_ctx *ctx);
+
+/* Debug export of internal arrays of the last fmm_forces call, copied to the
+ * HOST buffer dst (capacity bytes).  Returns the number of bytes the array
+ * has (copying only if it fits), or -1 for an unknown id.
+ *   FMM_EXPORT_M2L   int64 pairs (source id, sink id), id = level << 40 | begin
+ *   FMM_EXPORT_P2P   int64 pairs (source id, sink-leaf id), same ids
+ *   FMM_EXPORT_SCALE double per particle (input order): sink scale a_b or f_b used
+ *   FMM_EXPORT_CELLS int64 per cell: level << 40 | begin, then end, in cell order */
+enum { FMM_EXPORT_M2L = 1, FMM_EXPORT_P2P = 2, FMM_EXPORT_SCALE = 3, FMM_EXPORT_CELLS = 4 };
+int64_t fmm_export(fmm_ctx *ctx, int what, void *dst, int64_t capacity);
+
+#define FMM_P_MAX 20
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,739 @@
+// libfmm C ABI and the host-side orchestration of one force evaluation.
+//
+// Phases (the columns of the paper's tab:complexity):
+//   tree      keys, radix sort, gather, octree levels, leaves, geometry, radii
+//   estimate  low-order FMM for the sink scale (Sec. 5.4.2) and its minimum
+//             per cell, or the previous call's |a| (Sec. 5.4.1)
+//   up        P2M, M2M, multipole power
+//   walk      breadth-first dual tree walk -> M2L and P2P lists; M2L; P2P
+//   down      L2L, L2P, output
+// Everything is ordered on one stream.  The host reads back a few counters
+// (cells per tree level, pairs per walk sweep) to size the next launch.
+#include "../../include/fmm.h"
+#include "internal.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace fmm {
+namespace {
+
+struct HipFail {
+    hipError_t e;
+    const char *what;
+};
+struct NoMem {
+    size_t bytes;
+};
+
+#define CK(call)                                              \
+    do {                                                      \
+        hipError_t e_ = (call);                               \
+        if (e_ != hipSuccess) throw HipFail{e_, #call};       \
+    } while (0)
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+template <class T>
+T *ensure(DevBuf &b, size_t count, bool keep = false, size_t keep_count = 0) {
+    const size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+    if (b.cap >= bytes) return static_cast<T *>(b.p);
+    const size_t want = bytes + bytes / 4;
+    void *q = nullptr;
+    if (hipMalloc(&q, want) != hipSuccess) {
+        (void)hipGetLastError();
+        throw NoMem{want};
+    }
+    if (b.p) {
+        // the old buffer may still be in use by queued work on any stream
+        CK(hipDeviceSynchronize());
+        if (keep && keep_count)
+            CK(hipMemcpy(q, b.p, std::min(keep_count * sizeof(T), b.cap), hipMemcpyDeviceToDevice));
+        CK(hipFree(b.p));
+    }
+    b.p = q;
+    b.cap = want;
+    return static_cast<T *>(q);
+}
+
+template <class T>
+T *ptr(DevBuf &b) { return static_cast<T *>(b.p); }
+
+int bitlen(uint64_t v) {
+    int b = 0;
+    while (v) { ++b; v >>= 1; }
+    return b;
+}
+
+enum Phase { PH_START, PH_TREE, PH_EST, PH_UP, PH_WALK, PH_M2L, PH_P2P, PH_DOWN, PH_END, PH_N };
+
+}  // namespace
+}  // namespace fmm
+
+// small kernels used only by the orchestration: gather of the previous
+// call's |a| into key order, and |a|/G of a result
+namespace fmm {
+__global__ void k_gather_scale(const double *src, const uint32_t *perm, int64_t n, double *dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[perm[i]];
+}
+__global__ void k_norm3(const double *acc, int64_t n, double invG, double *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double a = acc[3 * i], b = acc[3 * i + 1], c = acc[3 * i + 2];
+    out[i] = sqrt(a * a + b * b + c * c) * invG;
+}
+hipError_t launch_gather_scale(const double *src, const uint32_t *perm, int64_t n, double *dst,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_scale, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src,
+                       perm, n, dst);
+    return hipGetLastError();
+}
+hipError_t launch_norm3(const double *acc, int64_t n, double G, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_norm3, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, acc, n,
+                       1.0 / G, out);
+    return hipGetLastError();
+}
+}  // namespace fmm
+
+using namespace fmm;
+
+struct fmm_ctx {
+    fmm_opts opts{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::atomic<int> busy{0};
+    std::string err;
+    fmm_stats_t st{};
+
+    // particles
+    DevBuf bbox, key, key2, idx, idx2, x, y, z, m, xyzm, leaf_of, out4, est4, scale, flags, tmp;
+    uint32_t *perm = nullptr;  // points into idx or idx2
+    // cells
+    DevBuf beg, end, parent, child0, nchild, level, leaf_lo, leaf_hi, cen, com, mass, lo, hi,
+        rho2, smin, leaf_cell, M, F, P, U, Fe;
+    // walk
+    DevBuf fa, fb, m2l, m2l2, p2p, p2p2, m2l_off, p2p_off, chunks, ccnt, coff, Fpart;
+    DevBuf counters, nonfinite;
+    unsigned long long *hcnt = nullptr;  // pinned host mirror of the counters
+    int *hint = nullptr;                 // pinned host ints
+    // last call
+    int64_t n = 0;
+    int ncells = 0, nleaves = 0, depth = 0, sh = 0, p = 0;
+    int64_t n_m2l = 0, n_p2p = 0;
+    uint64_t *m2l_sorted = nullptr, *p2p_sorted = nullptr;
+    std::vector<int> ls;  // first cell of each level
+    bool have_prev_scale = false;
+    int64_t prev_n = -1;
+    DevBuf prev_scale;    // |a| of the last call, input order
+    hipEvent_t ev[PH_N] = {};
+    hipEvent_t ev_m2l[2] = {}, ev_p2p[2] = {};
+    double t_m2l_kernel = 0, t_p2p_kernel = 0;
+};
+
+namespace fmm {
+namespace {
+
+TreeArrays tree_arrays(fmm_ctx *c) {
+    TreeArrays t;
+    t.beg = ptr<int>(c->beg); t.end = ptr<int>(c->end); t.parent = ptr<int>(c->parent);
+    t.child0 = ptr<int>(c->child0); t.nchild = ptr<int>(c->nchild); t.level = ptr<int>(c->level);
+    t.leaf_lo = ptr<int>(c->leaf_lo); t.leaf_hi = ptr<int>(c->leaf_hi);
+    t.cen = ptr<double4>(c->cen); t.com = ptr<double4>(c->com); t.mass = ptr<double>(c->mass);
+    t.lo = ptr<double>(c->lo); t.hi = ptr<double>(c->hi);
+    t.rho2 = ptr<unsigned long long>(c->rho2); t.smin = ptr<double>(c->smin);
+    return t;
+}
+
+void sync(fmm_ctx *c) { CK(hipStreamSynchronize(c->stream)); }
+
+void mark(fmm_ctx *c, int ph) {
+    if (c->opts.timing) CK(hipEventRecord(c->ev[ph], c->stream));
+}
+
+int *tmp_ints(fmm_ctx *c, size_t count) { return ensure<int>(c->tmp, count); }
+
+// ------------------------------------------------------------------ tree
+void grow_cells(fmm_ctx *c, int need, int have) {
+    const size_t cap = c->beg.cap / sizeof(int);
+    if ((size_t)need <= cap) return;
+    const size_t nc = std::max<size_t>(need, cap * 2);
+    for (DevBuf *b : {&c->beg, &c->end, &c->parent, &c->child0, &c->nchild, &c->level})
+        ensure<int>(*b, nc, true, (size_t)have);
+}
+
+void build_tree(fmm_ctx *c, int64_t n, const double *pos, const double *mass) {
+    hipStream_t s = c->stream;
+    const int leaf = c->opts.leaf_size;
+    // keys, sort, gather
+    unsigned long long *bb = ensure<unsigned long long>(c->bbox, 8);
+    uint64_t *k1 = ensure<uint64_t>(c->key, n), *k2 = ensure<uint64_t>(c->key2, n);
+    uint32_t *i1 = ensure<uint32_t>(c->idx, n), *i2 = ensure<uint32_t>(c->idx2, n);
+    CK(launch_bbox(pos, n, bb, s));
+    CK(launch_keys(pos, n, bb, k1, i1, s));
+    int *tmp = tmp_ints(c, std::max(sort_tmp_ints(n), scan_tmp_ints(n + 1)));
+    CK(radix_sort(&k1, &k2, &i1, &i2, n, 63, tmp, s));
+    c->perm = i1;
+    double *x = ensure<double>(c->x, n), *y = ensure<double>(c->y, n), *z = ensure<double>(c->z, n),
+           *m = ensure<double>(c->m, n);
+    double4 *xyzm = ensure<double4>(c->xyzm, n);
+    CK(launch_gather(pos, mass, c->perm, n, x, y, z, m, xyzm, s));
+    // octree, level by level
+    grow_cells(c, (int)std::min<int64_t>(n + 64, 1 << 30), 0);
+    TreeArrays t = tree_arrays(c);
+    CK(launch_init_root(t, (int)n, s));
+    c->ls.assign({0, 1});
+    int *nch = ensure<int>(c->flags, n + 2);
+    for (int L = 0;; ++L) {
+        const int c0 = c->ls[L], c1 = c->ls[L + 1];
+        if (c1 == c0) break;
+        t = tree_arrays(c);
+        CK(launch_count_children(k1, t, c0, c1, L, leaf, nch, s));
+        CK(hipMemsetAsync(nch + (c1 - c0), 0, sizeof(int), s));
+        int *total = ptr<int>(c->nonfinite) + 1;
+        CK(exclusive_scan(nch, nch, (c1 - c0) + 1, tmp, total, s));
+        CK(hipMemcpyAsync(c->hint, total, sizeof(int), hipMemcpyDeviceToHost, s));
+        sync(c);
+        const int add = c->hint[0];
+        grow_cells(c, c1 + add, c1);
+        t = tree_arrays(c);
+        CK(launch_make_children(k1, t, c0, c1, L, nch, c1, s));
+        c->ls.push_back(c1 + add);
+    }
+    const int ncells = c->ls.back();
+    c->ncells = ncells;
+    c->depth = (int)c->ls.size() - 3;   // ls ends with two equal entries
+    c->sh = std::max(1, bitlen((uint64_t)ncells));
+    // per-cell arrays sized now that the count is known
+    ensure<int>(c->leaf_lo, ncells); ensure<int>(c->leaf_hi, ncells);
+    ensure<double4>(c->cen, ncells); ensure<double4>(c->com, ncells);
+    ensure<double>(c->mass, ncells); ensure<double>(c->lo, 3 * (size_t)ncells);
+    ensure<double>(c->hi, 3 * (size_t)ncells); ensure<unsigned long long>(c->rho2, 2 * (size_t)ncells);
+    ensure<double>(c->smin, ncells);
+    t = tree_arrays(c);
+    // leaves in key order
+    int *flags = ensure<int>(c->flags, n + 2);
+    CK(hipMemsetAsync(flags, 0, sizeof(int) * (n + 1), s));
+    CK(launch_leaf_flags(t, ncells, flags, s));
+    int *total = ptr<int>(c->nonfinite) + 1;
+    CK(exclusive_scan(flags, flags, n + 1, tmp, total, s));
+    CK(hipMemcpyAsync(c->hint, total, sizeof(int), hipMemcpyDeviceToHost, s));
+    int *leaf_cell = ensure<int>(c->leaf_cell, ncells);
+    int *leaf_of = ensure<int>(c->leaf_of, n);
+    CK(launch_leaf_ranges(t, ncells, flags, leaf_cell, leaf_of, n, s));
+    sync(c);
+    c->nleaves = c->hint[0];
+    // geometry bottom up, then the radii of every cell in one pass
+    for (int L = c->depth; L >= 0; --L)
+        CK(launch_geometry_level(t, c->ls[L], c->ls[L + 1], x, y, z, m, s));
+    CK(launch_radii(t, n, leaf_of, leaf_cell, c->depth, x, y, z, s));
+    CK(launch_radii_finish(t, ncells, s));
+}
+
+// ------------------------------------------------------------------ walk
+struct Lists {
+    uint64_t *m2l;
+    int64_t n_m2l;
+    uint64_t *p2p;
+    int64_t n_p2p;
+    int64_t pairs;
+    int iterations;
+};
+
+Lists walk(fmm_ctx *c, const WalkParams &wp0, const double *P) {
+    hipStream_t s = c->stream;
+    WalkParams wp = wp0;
+    wp.sh = c->sh;
+    const int64_t n = c->n;
+    int64_t cap_f = std::max<int64_t>(1024, 2 * n);
+    int64_t cap_m = c->m2l.cap / 8 > 0 ? (int64_t)(c->m2l.cap / 8) : std::max<int64_t>(1024, 8 * n);
+    int64_t cap_p = c->p2p.cap / 8 > 0 ? (int64_t)(c->p2p.cap / 8) : std::max<int64_t>(1024, 8 * n);
+    cap_f = std::max<int64_t>(cap_f, (int64_t)(c->fa.cap / 8));
+    uint2 *fa = ensure<uint2>(c->fa, cap_f), *fb = ensure<uint2>(c->fb, cap_f);
+    uint64_t *ml = ensure<uint64_t>(c->m2l, cap_m), *pl = ensure<uint64_t>(c->p2p, cap_p);
+    unsigned long long *cnt = ensure<unsigned long long>(c->counters, 8);
+    // staging for host-to-device copies lives in pinned memory
+    c->hcnt[8] = 0ull;   // the root pair (0, 0)
+    CK(hipMemcpyAsync(fa, &c->hcnt[8], sizeof(uint2), hipMemcpyHostToDevice, s));
+    int64_t n_in = 1, n_m = 0, n_p = 0;
+    unsigned long long pairs = 0;
+    int it = 0;
+    const TreeArrays t = tree_arrays(c);
+    while (n_in > 0) {
+        unsigned long long *init = c->hcnt + 12;
+        init[0] = 0ull;
+        init[1] = (unsigned long long)n_m;
+        init[2] = (unsigned long long)n_p;
+        init[3] = pairs;
+        CK(hipMemcpyAsync(cnt, init, 4 * sizeof(unsigned long long), hipMemcpyHostToDevice, s));
+        WalkBuffers wb{fa, n_in, fb, cap_f, ml, cap_m, pl, cap_p, cnt};
+        CK(launch_walk(wp, t, P, wb, s));
+        CK(hipMemcpyAsync(c->hcnt, cnt, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+        sync(c);
+        const int64_t nf = (int64_t)c->hcnt[0], nm = (int64_t)c->hcnt[1], np = (int64_t)c->hcnt[2];
+        if (nf > cap_f || nm > cap_m || np > cap_p) {
+            // grow whatever overflowed and redo this sweep (the input frontier
+            // in fa is kept; the partial output of the sweep is discarded)
+            if (nf > cap_f) {
+                cap_f = nf + nf / 2;
+                fa = ensure<uint2>(c->fa, cap_f, true, n_in);
+                fb = ensure<uint2>(c->fb, cap_f);
+            }
+            if (nm > cap_m) { cap_m = nm + nm / 2; ml = ensure<uint64_t>(c->m2l, cap_m, true, n_m); }
+            if (np > cap_p) { cap_p = np + np / 2; pl = ensure<uint64_t>(c->p2p, cap_p, true, n_p); }
+            continue;
+        }
+        n_m = nm;
+        n_p = np;
+        pairs = c->hcnt[3];
+        n_in = nf;
+        std::swap(fa, fb);
+        std::swap(c->fa, c->fb);
+        ++it;
+    }
+    return Lists{ml, n_m, pl, n_p, (int64_t)pairs, it};
+}
+
+// sort a list by (sink, source) and compute the per-sink offsets
+uint64_t *sort_list(fmm_ctx *c, DevBuf &a, DevBuf &b, int64_t nlist, int nsinks, DevBuf &offb) {
+    uint64_t *k1 = ptr<uint64_t>(a);
+    uint64_t *k2 = ensure<uint64_t>(b, std::max<int64_t>(nlist, 1));
+    int *tmp = tmp_ints(c, sort_tmp_ints(nlist));
+    CK(radix_sort(&k1, &k2, nullptr, nullptr, nlist, 2 * c->sh, tmp, c->stream));
+    int64_t *off = ensure<int64_t>(offb, (size_t)nsinks + 1);
+    CK(launch_list_offsets(k1, nlist, nsinks, c->sh, off, c->stream));
+    return k1;
+}
+
+// ------------------------------------------------------------ sink scale
+void sink_scale(fmm_ctx *c, bool want_f) {
+    hipStream_t s = c->stream;
+    const int64_t n = c->n;
+    TreeArrays t = tree_arrays(c);
+    double *scale = ensure<double>(c->scale, n);
+    bool done = false;
+    if (c->opts.scale_source == FMM_SCALE_PREVIOUS && !want_f && c->have_prev_scale &&
+        c->prev_n == n) {
+        // previous call's |a| (input order) gathered into key order
+        CK(launch_gather_scale(ptr<double>(c->prev_scale), c->perm, n, scale, s));
+        done = true;
+    }
+    if (!done) {
+        WalkParams wp{2, 1, 0.0, 1.0, 0.0, 0};
+        Lists L = walk(c, wp, nullptr);
+        c->st.n_est_m2l = L.n_m2l;
+        c->st.n_est_p2p_pairs = L.pairs;
+        uint64_t *ml = sort_list(c, c->m2l, c->m2l2, L.n_m2l, c->ncells, c->m2l_off);
+        uint64_t *pl = sort_list(c, c->p2p, c->p2p2, L.n_p2p, c->nleaves, c->p2p_off);
+        double4 *Fe = ensure<double4>(c->Fe, c->ncells);
+        CK(launch_est_m2l(want_f, t, c->ncells, ptr<int64_t>(c->m2l_off), ml, c->sh, Fe, s));
+        for (int Lv = 1; Lv <= c->depth; ++Lv)
+            CK(launch_est_l2l_level(want_f, t, c->ls[Lv], c->ls[Lv + 1], Fe, s));
+        double4 *e4 = ensure<double4>(c->est4, n);
+        CK(launch_est_l2p(want_f, t, ptr<int>(c->leaf_of), ptr<int>(c->leaf_cell), n, Fe, e4, s));
+        CK(launch_p2p(want_f, 0, c->nleaves, ptr<int>(c->leaf_cell), ptr<int64_t>(c->p2p_off), pl,
+                      c->sh, t, ptr<double4>(c->xyzm), e4, s));
+        CK(launch_scale(want_f, n, e4, scale, s));
+    }
+    for (int Lv = c->depth; Lv >= 0; --Lv)
+        CK(launch_smin_level(t, c->ls[Lv], c->ls[Lv + 1], scale, s));
+}
+
+// ------------------------------------------------------------ the call
+void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double G, int p,
+            double eps, double *pot, double *acc) {
+    hipStream_t s = c->stream;
+    c->st = fmm_stats_t{};
+    c->n = n;
+    c->p = p;
+    c->st.p = p;
+    c->st.n = n;
+    c->t_m2l_kernel = c->t_p2p_kernel = 0;
+    ensure<int>(c->nonfinite, 4);
+    mark(c, PH_START);
+    build_tree(c, n, pos, mass);
+    mark(c, PH_TREE);
+    TreeArrays t = tree_arrays(c);
+    const bool want_f = c->opts.mac == FMM_MAC_SCALED;
+    if (c->opts.mac != FMM_MAC_THETA) sink_scale(c, want_f);
+    mark(c, PH_EST);
+    // upward pass
+    const int nc = ncplx(p);
+    double *M = ensure<double>(c->M, 2 * (size_t)nc * c->ncells);
+    double *U = ensure<double>(c->U, 2 * (size_t)nc * c->ncells);
+    double *P = ensure<double>(c->P, (size_t)(p + 1) * c->ncells);
+    CK(launch_p2m(p, t, ptr<int>(c->leaf_cell), c->nleaves, ptr<double>(c->x), ptr<double>(c->y),
+                  ptr<double>(c->z), ptr<double>(c->m), M, s));
+    if (c->ncells > 1) CK(launch_shift_upsilon(p, t, 1, c->ncells, U, s));
+    for (int L = c->depth - 1; L >= 0; --L)
+        CK(launch_m2m_level(p, t, c->ls[L], c->ls[L + 1], U, M, s));
+    CK(launch_power(p, c->ncells, M, P, s));
+    mark(c, PH_UP);
+    // walk
+    WalkParams wp{c->opts.mac == FMM_MAC_THETA ? 1 : 0, p, eps, c->opts.theta_crit,
+                  c->opts.p2p_factor * (p + 1.0) * (p + 1.0) * (p + 1.0), 0};
+    Lists L = walk(c, wp, P);
+    c->st.walk_iterations = L.iterations;
+    c->n_m2l = L.n_m2l;
+    c->n_p2p = L.n_p2p;
+    c->st.n_m2l = L.n_m2l;
+    c->st.n_p2p_lists = L.n_p2p;
+    c->st.n_p2p_pairs = L.pairs;
+    c->m2l_sorted = sort_list(c, c->m2l, c->m2l2, L.n_m2l, c->ncells, c->m2l_off);
+    c->p2p_sorted = sort_list(c, c->p2p, c->p2p2, L.n_p2p, c->nleaves, c->p2p_off);
+    mark(c, PH_WALK);
+    // M2L by chunks of one sink's list
+    double *F = ensure<double>(c->F, 2 * (size_t)nc * c->ncells);
+    {
+        const int chunk = 16;
+        int *cnt = ensure<int>(c->ccnt, (size_t)c->ncells + 1);
+        int *coff = ensure<int>(c->coff, (size_t)c->ncells + 1);
+        int *tmp = tmp_ints(c, scan_tmp_ints(c->ncells + 1));
+        int *total = ptr<int>(c->nonfinite) + 1;
+        CK(launch_chunks(c->ncells, ptr<int64_t>(c->m2l_off), chunk, cnt, coff, tmp, total,
+                         nullptr, false, s));
+        CK(hipMemcpyAsync(c->hint, total, sizeof(int), hipMemcpyDeviceToHost, s));
+        sync(c);
+        const int nchunks = c->hint[0];
+        int4 *chunks = ensure<int4>(c->chunks, std::max(nchunks, 1));
+        CK(launch_chunks(c->ncells, ptr<int64_t>(c->m2l_off), chunk, cnt, coff, tmp, total,
+                         chunks, true, s));
+        double *Fpart = ensure<double>(c->Fpart, 2 * (size_t)nc * std::max(nchunks, 1));
+        if (c->opts.timing) CK(hipEventRecord(c->ev_m2l[0], s));
+        CK(launch_m2l(p, nchunks, chunks, c->m2l_sorted, c->sh, t, M, Fpart, s));
+        if (c->opts.timing) CK(hipEventRecord(c->ev_m2l[1], s));
+        CK(launch_m2l_reduce(p, c->ncells, coff, Fpart, F, s));
+    }
+    mark(c, PH_M2L);
+    // downward pass, far field at the particles
+    for (int Lv = 1; Lv <= c->depth; ++Lv)
+        CK(launch_l2l_level(p, t, c->ls[Lv], c->ls[Lv + 1], U, F, s));
+    double4 *o4 = ensure<double4>(c->out4, n);
+    CK(launch_l2p(p, t, ptr<int>(c->leaf_of), ptr<int>(c->leaf_cell), n, ptr<double>(c->x),
+                  ptr<double>(c->y), ptr<double>(c->z), F, o4, s));
+    mark(c, PH_DOWN);
+    // near field
+    if (c->opts.timing) CK(hipEventRecord(c->ev_p2p[0], s));
+    CK(launch_p2p(0, 1, c->nleaves, ptr<int>(c->leaf_cell), ptr<int64_t>(c->p2p_off),
+                  c->p2p_sorted, c->sh, t, ptr<double4>(c->xyzm), o4, s));
+    if (c->opts.timing) CK(hipEventRecord(c->ev_p2p[1], s));
+    mark(c, PH_P2P);
+    int *nonfinite = ptr<int>(c->nonfinite);
+    CK(hipMemsetAsync(nonfinite, 0, sizeof(int), s));
+    CK(launch_output(n, c->perm, o4, G, pot, acc, nonfinite, s));
+    if (c->opts.scale_source == FMM_SCALE_PREVIOUS) {
+        CK(launch_norm3(acc, n, G, ensure<double>(c->prev_scale, n), s));
+        c->have_prev_scale = true;
+        c->prev_n = n;
+    }
+    mark(c, PH_END);
+    CK(hipMemcpyAsync(c->hint, nonfinite, sizeof(int), hipMemcpyDeviceToHost, s));
+    sync(c);
+    c->st.n_cells = c->ncells;
+    c->st.n_leaves = c->nleaves;
+    c->st.depth = c->depth;
+    if (c->opts.timing) {
+        auto el = [&](int a, int b) {
+            float ms = 0;
+            CK(hipEventElapsedTime(&ms, c->ev[a], c->ev[b]));
+            return (double)ms;
+        };
+        c->st.t_tree = el(PH_START, PH_TREE);
+        c->st.t_estimate = el(PH_TREE, PH_EST);
+        c->st.t_up = el(PH_EST, PH_UP);
+        c->st.t_walk = el(PH_UP, PH_WALK);
+        c->st.t_m2l = el(PH_WALK, PH_M2L);
+        c->st.t_down = el(PH_M2L, PH_DOWN);
+        c->st.t_p2p = el(PH_DOWN, PH_P2P);
+        c->st.t_total = el(PH_START, PH_END);
+        float ms = 0;
+        CK(hipEventElapsedTime(&ms, c->ev_m2l[0], c->ev_m2l[1]));
+        c->st.t_m2l_kernel = ms;
+        c->st.m2l_launches = 1;
+        CK(hipEventElapsedTime(&ms, c->ev_p2p[0], c->ev_p2p[1]));
+        c->st.t_p2p_kernel = ms;
+        c->st.p2p_launches = 1;
+    }
+}
+
+int order_for_error(double e) {
+    int p = (int)std::lround(1.6 * std::log10(1.0 / e));
+    return std::min(FMM_P_MAX, std::max(3, p));
+}
+
+struct Guard {
+    fmm_ctx *c;
+    bool ok;
+    explicit Guard(fmm_ctx *c_) : c(c_) {
+        int z = 0;
+        ok = c->busy.compare_exchange_strong(z, 1);
+    }
+    ~Guard() {
+        if (ok) c->busy.store(0);
+    }
+};
+
+fmm_status fail(fmm_ctx *c, fmm_status st, const std::string &msg) {
+    if (c) c->err = msg;
+    return st;
+}
+
+template <class F>
+fmm_status guarded(fmm_ctx *c, F &&body) {
+    try {
+        CK(hipSetDevice(c->opts.device));
+        return body();
+    } catch (const HipFail &h) {
+        return fail(c, FMM_E_HIP, std::string(h.what) + ": " + hipGetErrorString(h.e));
+    } catch (const NoMem &m) {
+        char b[128];
+        std::snprintf(b, sizeof b, "device allocation of %zu bytes failed", m.bytes);
+        return fail(c, FMM_E_NOMEM, b);
+    } catch (...) {
+        return fail(c, FMM_E_HIP, "unexpected internal error");
+    }
+}
+
+
+}  // namespace
+}  // namespace fmm
+
+// =====================================================================  C ABI
+
+extern "C" {
+
+int fmm_order_for_error(double target_err) {
+    if (!(target_err > 0.0) || !std::isfinite(target_err)) return -1;
+    return fmm::order_for_error(target_err);
+}
+
+fmm_status fmm_build(fmm_ctx **out, const fmm_opts *o) {
+    if (!out || !o) return FMM_E_INVAL;
+    *out = nullptr;
+    if (o->leaf_size < 0 || o->leaf_size > 4096) return FMM_E_INVAL;
+    if (o->mac < FMM_MAC_REL || o->mac > FMM_MAC_THETA) return FMM_E_INVAL;
+    if (o->mac == FMM_MAC_THETA && !(o->theta_crit > 0.0 && o->theta_crit < 1.0)) return FMM_E_INVAL;
+    if (o->p2p_factor < 0.0 || !std::isfinite(o->p2p_factor)) return FMM_E_INVAL;
+    if (o->scale_source != FMM_SCALE_ESTIMATE && o->scale_source != FMM_SCALE_PREVIOUS)
+        return FMM_E_INVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || o->device < 0 || o->device >= ndev) {
+        (void)hipGetLastError();
+        return FMM_E_INVAL;
+    }
+    fmm_ctx *c = new (std::nothrow) fmm_ctx;
+    if (!c) return FMM_E_NOMEM;
+    c->opts = *o;
+    if (c->opts.leaf_size == 0) c->opts.leaf_size = 32;
+    if (c->opts.p2p_factor == 0.0) c->opts.p2p_factor = 0.5;
+    fmm_status st = fmm::guarded(c, [&]() -> fmm_status {
+        if (o->hip_stream) {
+            c->stream = (hipStream_t)o->hip_stream;
+        } else {
+            CK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+            c->own_stream = true;
+        }
+        CK(hipHostMalloc((void **)&c->hcnt, 16 * sizeof(unsigned long long), hipHostMallocDefault));
+        CK(hipHostMalloc((void **)&c->hint, 16 * sizeof(int), hipHostMallocDefault));
+        for (auto &e : c->ev) CK(hipEventCreate(&e));
+        for (auto &e : c->ev_m2l) CK(hipEventCreate(&e));
+        for (auto &e : c->ev_p2p) CK(hipEventCreate(&e));
+        return FMM_OK;
+    });
+    if (st != FMM_OK) {
+        fmm_destroy(c);
+        return st;
+    }
+    *out = c;
+    return FMM_OK;
+}
+
+void fmm_destroy(fmm_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->opts.device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    DevBuf *bufs[] = {&c->bbox, &c->key, &c->key2, &c->idx, &c->idx2, &c->x, &c->y, &c->z, &c->m,
+                      &c->xyzm, &c->leaf_of, &c->out4, &c->est4, &c->scale, &c->flags, &c->tmp,
+                      &c->beg, &c->end, &c->parent, &c->child0, &c->nchild, &c->level,
+                      &c->leaf_lo, &c->leaf_hi, &c->cen, &c->com, &c->mass, &c->lo, &c->hi,
+                      &c->rho2, &c->smin, &c->leaf_cell, &c->M, &c->F, &c->P, &c->U, &c->Fe,
+                      &c->fa, &c->fb, &c->m2l, &c->m2l2, &c->p2p, &c->p2p2, &c->m2l_off,
+                      &c->p2p_off, &c->chunks, &c->ccnt, &c->coff, &c->Fpart, &c->counters,
+                      &c->nonfinite, &c->prev_scale};
+    for (DevBuf *b : bufs)
+        if (b->p) (void)hipFree(b->p);
+    for (auto &e : c->ev) if (e) (void)hipEventDestroy(e);
+    for (auto &e : c->ev_m2l) if (e) (void)hipEventDestroy(e);
+    for (auto &e : c->ev_p2p) if (e) (void)hipEventDestroy(e);
+    if (c->hcnt) (void)hipHostFree(c->hcnt);
+    if (c->hint) (void)hipHostFree(c->hint);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+static fmm_status check_common(fmm_ctx *c, int64_t n, const double *pos, const double *mass,
+                               double G, int *p, double eps, double *pot, double *acc) {
+    if (n < 0) return fmm::fail(c, FMM_E_INVAL, "n < 0");
+    if (n > (int64_t)INT32_MAX / 2) return fmm::fail(c, FMM_E_INVAL, "n too large");
+    if (n > 0 && (!pos || !mass || !pot || !acc)) return fmm::fail(c, FMM_E_INVAL, "null array");
+    if (!std::isfinite(G)) return fmm::fail(c, FMM_E_INVAL, "G not finite");
+    if (c->opts.mac != FMM_MAC_THETA && !(eps > 0.0 && std::isfinite(eps)))
+        return fmm::fail(c, FMM_E_INVAL, "target_err must be > 0 and finite");
+    if (*p < 0) {
+        if (!(eps > 0.0 && std::isfinite(eps)))
+            return fmm::fail(c, FMM_E_INVAL, "p < 0 needs a target_err > 0");
+        *p = fmm::order_for_error(eps);
+    }
+    if (*p == 0) return fmm::fail(c, FMM_E_INVAL, "p must be >= 1");
+    if (*p > FMM_P_MAX) return fmm::fail(c, FMM_E_UNSUPPORTED, "p above FMM_P_MAX");
+    return FMM_OK;
+}
+
+fmm_status fmm_forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double G,
+                      int p, double target_err, double *pot, double *acc) {
+    if (!c) return FMM_E_INVAL;
+    fmm::Guard g(c);
+    if (!g.ok) return FMM_E_BUSY;
+    c->err.clear();
+    fmm_status st = check_common(c, n, pos, mass, G, &p, target_err, pot, acc);
+    if (st != FMM_OK) return st;
+    return fmm::guarded(c, [&]() -> fmm_status {
+        if (n == 0) return FMM_OK;
+        if (n == 1) {
+            CK(hipMemsetAsync(pot, 0, sizeof(double), c->stream));
+            CK(hipMemsetAsync(acc, 0, 3 * sizeof(double), c->stream));
+            fmm::sync(c);
+            c->st = fmm_stats_t{};
+            c->st.n = 1;
+            c->st.p = p;
+            return FMM_OK;
+        }
+        fmm::forces(c, n, pos, mass, G, p, target_err, pot, acc);
+        if (c->hint[0]) return fmm::fail(c, FMM_E_NONFINITE, "non-finite potential or acceleration");
+        return FMM_OK;
+    });
+}
+
+fmm_status fmm_forces_batched(fmm_ctx *c, int64_t k, const int64_t *off, const double *pos,
+                              const double *mass, double G, int p, double target_err, double *pot,
+                              double *acc) {
+    if (!c || k < 0 || (k > 0 && !off)) return FMM_E_INVAL;
+    if (k == 0) return FMM_OK;
+    if (off[0] != 0) return fmm::fail(c, FMM_E_INVAL, "offsets[0] must be 0");
+    for (int64_t i = 0; i < k; ++i)
+        if (off[i + 1] < off[i]) return fmm::fail(c, FMM_E_INVAL, "offsets must not decrease");
+    for (int64_t i = 0; i < k; ++i) {
+        const int64_t a = off[i];
+        fmm_status st = fmm_forces(c, off[i + 1] - a, pos + 3 * a, mass + a, G, p, target_err,
+                                   pot + a, acc + 3 * a);
+        if (st != FMM_OK) return st;
+    }
+    return FMM_OK;
+}
+
+fmm_status fmm_direct(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double G,
+                      double *pot, double *acc) {
+    if (!c) return FMM_E_INVAL;
+    fmm::Guard g(c);
+    if (!g.ok) return FMM_E_BUSY;
+    c->err.clear();
+    if (n < 0 || (n > 0 && (!pos || !mass || !pot || !acc)) || !std::isfinite(G))
+        return fmm::fail(c, FMM_E_INVAL, "bad argument");
+    if (n == 0) return FMM_OK;
+    return fmm::guarded(c, [&]() -> fmm_status {
+        CK(fmm::launch_direct(n, pos, mass, G, pot, acc, c->stream));
+        fmm::sync(c);
+        return FMM_OK;
+    });
+}
+
+fmm_status fmm_stats(const fmm_ctx *c, fmm_stats_t *out) {
+    if (!c || !out) return FMM_E_INVAL;
+    *out = c->st;
+    return FMM_OK;
+}
+
+size_t fmm_footprint_bytes(int64_t n, int p, const fmm_opts *o) {
+    if (n <= 0) return 0;
+    if (p < 1) p = 12;
+    const int leaf = (o && o->leaf_size > 0) ? o->leaf_size : 32;
+    const double cells = 1.5 * (double)n / (0.3 * leaf) + 64;
+    const double nc = 16.0 * (p + 1) * (p + 2) / 2.0;
+    const double per_particle = 8 * 2 + 4 * 2 + 8 * 4 + 32 + 4 + 32 * 2 + 8 * 2 + 4 + 16;
+    const double per_cell = 3 * nc + 8 * (p + 1) + 4 * 10 + 32 * 2 + 8 * 9 + 16 + 16;
+    const double lists = 8.0 * 2 * (150.0 * cells) + 8.0 * 2 * (200.0 * cells) + 8.0 * 2 * n;
+    const double part = nc * (150.0 * cells / 16 + cells);
+    return (size_t)(per_particle * n + per_cell * cells + lists + part);
+}
+
+const char *fmm_last_error(const fmm_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int64_t fmm_export(fmm_ctx *c, int what, void *dst, int64_t capacity) {
+    if (!c) return -1;
+    try {
+        CK(hipSetDevice(c->opts.device));
+        const int nc = c->ncells;
+        std::vector<int> beg(nc), lev(nc), end(nc), lcell(c->nleaves);
+        auto cells = [&]() {
+            CK(hipMemcpy(beg.data(), c->beg.p, nc * sizeof(int), hipMemcpyDeviceToHost));
+            CK(hipMemcpy(end.data(), c->end.p, nc * sizeof(int), hipMemcpyDeviceToHost));
+            CK(hipMemcpy(lev.data(), c->level.p, nc * sizeof(int), hipMemcpyDeviceToHost));
+            if (c->nleaves)
+                CK(hipMemcpy(lcell.data(), c->leaf_cell.p, c->nleaves * sizeof(int),
+                             hipMemcpyDeviceToHost));
+        };
+        auto id = [&](int cell) { return ((int64_t)lev[cell] << 40) | (int64_t)beg[cell]; };
+        if (what == FMM_EXPORT_M2L || what == FMM_EXPORT_P2P) {
+            const int64_t cnt = what == FMM_EXPORT_M2L ? c->n_m2l : c->n_p2p;
+            const int64_t bytes = cnt * 16;
+            if (!dst || capacity < bytes) return bytes;
+            cells();
+            std::vector<uint64_t> keys(cnt);
+            const uint64_t *src = what == FMM_EXPORT_M2L ? c->m2l_sorted : c->p2p_sorted;
+            if (cnt) CK(hipMemcpy(keys.data(), src, cnt * 8, hipMemcpyDeviceToHost));
+            int64_t *o = static_cast<int64_t *>(dst);
+            const uint64_t mask = (1ull << c->sh) - 1;
+            for (int64_t i = 0; i < cnt; ++i) {
+                const int a = (int)(keys[i] & mask), b = (int)(keys[i] >> c->sh);
+                o[2 * i] = id(a);
+                o[2 * i + 1] = id(what == FMM_EXPORT_M2L ? b : lcell[b]);
+            }
+            return bytes;
+        }
+        if (what == FMM_EXPORT_SCALE) {
+            const int64_t bytes = c->n * 8;
+            if (!dst || capacity < bytes) return bytes;
+            std::vector<double> s(c->n);
+            std::vector<uint32_t> perm(c->n);
+            CK(hipMemcpy(s.data(), c->scale.p, c->n * 8, hipMemcpyDeviceToHost));
+            CK(hipMemcpy(perm.data(), c->perm, c->n * 4, hipMemcpyDeviceToHost));
+            double *o = static_cast<double *>(dst);
+            for (int64_t i = 0; i < c->n; ++i) o[perm[i]] = s[i];
+            return bytes;
+        }
+        if (what == FMM_EXPORT_CELLS) {
+            const int64_t bytes = (int64_t)nc * 16;
+            if (!dst || capacity < bytes) return bytes;
+            cells();
+            int64_t *o = static_cast<int64_t *>(dst);
+            for (int i = 0; i < nc; ++i) {
+                o[2 * i] = id(i);
+                o[2 * i + 1] = end[i];
+            }
+            return bytes;
+        }
+        return -1;
+    } catch (...) {
+        return -1;
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,142 @@
+// Host-side declarations shared by the libfmm translation units: launchers
+// for each kernel group and the error-checking macro.  Every launcher takes
+// the stream it is ordered on and returns hipSuccess or the launch error.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define FMM_MAXLEVEL 21
+#define FMM_PMAX 20
+
+namespace fmm {
+
+// ---- sort.hip ---------------------------------------------------------
+// Exclusive prefix sum of n int32 values (in may equal out).  tmp must hold
+// scan_tmp_ints(n) ints.  *total (device, optional) receives the sum.
+size_t scan_tmp_ints(int64_t n);
+hipError_t exclusive_scan(const int *in, int *out, int64_t n, int *tmp, int *total,
+                          hipStream_t s);
+// Stable LSD radix sort of (key, value) by key bits [0, bits), 8 per pass.
+// Buffers are ping-ponged; on return *keys/*vals point at the sorted data
+// (one of the two given buffers).  vals may be null (key-only sort).
+size_t sort_tmp_ints(int64_t n);
+hipError_t radix_sort(uint64_t **keys, uint64_t **keys_alt, uint32_t **vals,
+                      uint32_t **vals_alt, int64_t n, int bits, int *tmp, hipStream_t s);
+
+// ---- tree.hip ---------------------------------------------------------
+struct TreeArrays {
+    int *beg, *end, *parent, *child0, *nchild, *level;
+    int *leaf_lo, *leaf_hi;     // leaves [leaf_lo, leaf_hi) in Morton leaf order
+    double4 *cen;               // (x, y, z, rho): expansion centre z = s, radius
+    double4 *com;               // (x, y, z, rho_com): centre of mass, radius about it
+    double *mass;
+    double *lo, *hi;            // 3 per cell: bounding box of the cell's particles
+    unsigned long long *rho2;   // 2 per cell: atomics scratch for squared radii
+    double *smin;               // min over the cell's particles of the sink scale
+};
+
+hipError_t launch_bbox(const double *pos, int64_t n, unsigned long long *bbox6, hipStream_t s);
+hipError_t launch_keys(const double *pos, int64_t n, const unsigned long long *bbox6,
+                       uint64_t *key, uint32_t *idx, hipStream_t s);
+hipError_t launch_gather(const double *pos, const double *mass, const uint32_t *perm,
+                         int64_t n, double *x, double *y, double *z, double *m,
+                         double4 *xyzm, hipStream_t s);
+hipError_t launch_init_root(const TreeArrays &t, int n, hipStream_t s);
+// children of cells [c0, c1) at one level; *count_out (device) = new cells
+hipError_t launch_count_children(const uint64_t *key, const TreeArrays &t, int c0, int c1,
+                                 int level, int leaf_size, int *nch, hipStream_t s);
+hipError_t launch_make_children(const uint64_t *key, const TreeArrays &t, int c0, int c1,
+                                int level, const int *child_off, int next0, hipStream_t s);
+hipError_t launch_leaf_flags(const TreeArrays &t, int ncells, int *flags, hipStream_t s);
+hipError_t launch_leaf_ranges(const TreeArrays &t, int ncells, const int *leafscan,
+                              int *leaf_cell, int *leaf_of, int64_t n, hipStream_t s);
+hipError_t launch_geometry_level(const TreeArrays &t, int c0, int c1, const double *x,
+                                 const double *y, const double *z, const double *m,
+                                 hipStream_t s);
+hipError_t launch_radii(const TreeArrays &t, int64_t n, const int *leaf_of,
+                        const int *leaf_cell, int maxlevel, const double *x, const double *y,
+                        const double *z, hipStream_t s);
+hipError_t launch_radii_finish(const TreeArrays &t, int ncells, hipStream_t s);
+hipError_t launch_smin_level(const TreeArrays &t, int c0, int c1, const double *scale,
+                             hipStream_t s);
+
+// ---- expansions.hip ---------------------------------------------------
+// Internal expansion layout: for each cell, the complex coefficients X_n^m,
+// 0 <= m <= n <= p, at complex index n(n+1)/2 + m (Re, Im adjacent); the
+// m < 0 half follows from X_n^{-m} = (-1)^m conj(X_n^m).
+inline int ncplx(int p) { return (p + 1) * (p + 2) / 2; }
+hipError_t launch_p2m(int p, const TreeArrays &t, const int *leaf_cell, int nleaves,
+                      const double *x, const double *y, const double *z, const double *m,
+                      double *M, hipStream_t s);
+hipError_t launch_shift_upsilon(int p, const TreeArrays &t, int c0, int c1, double *U,
+                                hipStream_t s);
+hipError_t launch_m2m_level(int p, const TreeArrays &t, int c0, int c1, const double *U,
+                            double *M, hipStream_t s);
+hipError_t launch_power(int p, int ncells, const double *M, double *P, hipStream_t s);
+hipError_t launch_l2l_level(int p, const TreeArrays &t, int c0, int c1, const double *U,
+                            double *F, hipStream_t s);
+// far field at every particle of every leaf: out4[i] = (Psi, ax, ay, az)
+hipError_t launch_l2p(int p, const TreeArrays &t, const int *leaf_of, const int *leaf_cell,
+                      int64_t n, const double *x, const double *y, const double *z,
+                      const double *F, double4 *out4, hipStream_t s);
+// low-order estimate: monopole M2L into per-cell (Psi, a) at com (gravity)
+// or the 1/r^2 sum (f); L2L of the same; evaluation at particles.
+hipError_t launch_est_m2l(int want_f, const TreeArrays &t, int nsinks, const int64_t *off,
+                          const uint64_t *list, int sh, double4 *Fe, hipStream_t s);
+hipError_t launch_est_l2l_level(int want_f, const TreeArrays &t, int c0, int c1, double4 *Fe,
+                                hipStream_t s);
+hipError_t launch_est_l2p(int want_f, const TreeArrays &t, const int *leaf_of,
+                          const int *leaf_cell, int64_t n, const double4 *Fe, double4 *out4,
+                          hipStream_t s);
+
+// ---- walk.hip -----------------------------------------------------------
+struct WalkParams {
+    int mode;          // 0 main (criterion a/f), 1 main (theta), 2 estimate (theta<1 on com)
+    int p;
+    double eps;
+    double theta_crit;
+    double p2p_pairs;  // accepted with N_A N_B < p2p_pairs -> direct
+    int sh;            // list keys are (sink << sh) | source
+};
+struct WalkBuffers {
+    const uint2 *in; int64_t n_in;
+    uint2 *out; int64_t cap_out;
+    uint64_t *m2l; int64_t cap_m2l;
+    uint64_t *p2p; int64_t cap_p2p;
+    unsigned long long *counters;   // [0] out, [1] m2l, [2] p2p, [3] p2p particle pairs
+};
+hipError_t launch_walk(const WalkParams &wp, const TreeArrays &t, const double *P,
+                       const WalkBuffers &wb, hipStream_t s);
+// offsets of the sorted (sink << sh | source) list per sink: off[c] for c in [0, nsinks]
+hipError_t launch_list_offsets(const uint64_t *list, int64_t nlist, int nsinks, int sh,
+                               int64_t *off, hipStream_t s);
+
+// ---- m2l.hip ------------------------------------------------------------
+// chunk table of the sink-sorted M2L list: first call (fill = false) counts the
+// chunks per cell into cnt and scans them into coff (ncells + 1 entries,
+// *total = chunks); second call (fill = true) writes chunks[] = (sink, e0, e1).
+hipError_t launch_chunks(int ncells, const int64_t *off, int chunk, int *cnt, int *coff,
+                         int *tmp, int *total, int4 *chunks, bool fill, hipStream_t s);
+// orders up to FMM_M2L_FIXED_MAX use register-resident kernels compiled per
+// order; higher orders (or generic = true) use the LDS-staged generic kernel
+#define FMM_M2L_FIXED_MAX 12
+hipError_t launch_m2l(int p, int nchunks, const int4 *chunks, const uint64_t *list, int sh,
+                      const TreeArrays &t, const double *M, double *Fpart, hipStream_t s,
+                      bool generic = false);
+hipError_t launch_m2l_reduce(int p, int ncells, const int *coff, const double *Fpart, double *F,
+                             hipStream_t s);
+
+// ---- p2p.hip ------------------------------------------------------------
+// near field of each sink leaf over its list, added to out4 (sorted order)
+hipError_t launch_p2p(int want_f, int with_pot, int nleaves, const int *leaf_cell,
+                      const int64_t *off, const uint64_t *list, int sh, const TreeArrays &t,
+                      const double4 *xyzm, double4 *out4, hipStream_t s);
+hipError_t launch_output(int64_t n, const uint32_t *perm, const double4 *out4, double G,
+                         double *pot, double *acc, int *nonfinite, hipStream_t s);
+hipError_t launch_scale(int want_f, int64_t n, const double4 *est4, double *scale,
+                        hipStream_t s);
+hipError_t launch_direct(int64_t n, const double *pos, const double *mass, double G,
+                         double *pot, double *acc, hipStream_t s);
+
+}  // namespace fmm

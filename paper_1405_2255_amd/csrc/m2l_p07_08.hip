@@ -1,0 +1,5 @@
+// Instantiation of the register-resident M2L kernel for expansion order(s) 7 8.
+#include "m2l_impl.h"
+
+FMM_M2L_FIXED_DEFINE(7)
+FMM_M2L_FIXED_DEFINE(8)

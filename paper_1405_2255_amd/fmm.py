@@ -1,0 +1,229 @@
+"""Python binding of libfmm (include/fmm.h): argument marshalling only.
+
+Every stage of the force evaluation runs in the HIP kernels of libfmm.so;
+torch supplies the device memory and the stream.  Importing this module
+loads the in-tree library and raises if it has not been built, so no code
+path can silently fall back to something else.
+
+    from paper_1405_2255_amd import fmm
+    ctx = fmm.Context()                      # on cuda:0, torch's current stream
+    pot, acc = ctx.forces(pos, mass, target_err=1e-7)   # float64 CUDA tensors
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfmm.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1405_2255_amd.build`")
+
+_lib = C.CDLL(LIB_PATH)
+
+# ---- fmm.h mirror ----------------------------------------------------------
+OK, E_INVAL, E_NOMEM, E_HIP, E_NONFINITE, E_UNSUPPORTED, E_BUSY = range(7)
+MAC_REL, MAC_SCALED, MAC_THETA = 0, 1, 2
+SCALE_ESTIMATE, SCALE_PREVIOUS = 0, 1
+EXPORT_M2L, EXPORT_P2P, EXPORT_SCALE, EXPORT_CELLS = 1, 2, 3, 4
+P_MAX = 20
+
+STATUS_NAMES = {OK: "FMM_OK", E_INVAL: "FMM_E_INVAL", E_NOMEM: "FMM_E_NOMEM", E_HIP: "FMM_E_HIP",
+                E_NONFINITE: "FMM_E_NONFINITE", E_UNSUPPORTED: "FMM_E_UNSUPPORTED",
+                E_BUSY: "FMM_E_BUSY"}
+
+SYMBOLS = ["fmm_build", "fmm_forces", "fmm_forces_batched", "fmm_direct", "fmm_order_for_error",
+           "fmm_stats", "fmm_footprint_bytes", "fmm_last_error", "fmm_destroy", "fmm_export"]
+
+
+class Opts(C.Structure):
+    _fields_ = [("device", C.c_int), ("hip_stream", C.c_void_p), ("leaf_size", C.c_int),
+                ("mac", C.c_int), ("theta_crit", C.c_double), ("p2p_factor", C.c_double),
+                ("scale_source", C.c_int), ("timing", C.c_int)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("p", C.c_int), ("n", C.c_int64), ("n_cells", C.c_int64),
+                ("n_leaves", C.c_int64), ("depth", C.c_int), ("n_m2l", C.c_int64),
+                ("n_p2p_lists", C.c_int64), ("n_p2p_pairs", C.c_int64),
+                ("n_est_m2l", C.c_int64), ("n_est_p2p_pairs", C.c_int64),
+                ("walk_iterations", C.c_int),
+                ("t_tree", C.c_double), ("t_estimate", C.c_double), ("t_up", C.c_double),
+                ("t_walk", C.c_double), ("t_m2l", C.c_double), ("t_p2p", C.c_double),
+                ("t_down", C.c_double), ("t_total", C.c_double),
+                ("t_m2l_kernel", C.c_double), ("t_p2p_kernel", C.c_double),
+                ("m2l_launches", C.c_int), ("p2p_launches", C.c_int)]
+
+
+_P = C.c_void_p
+_lib.fmm_build.argtypes = [C.POINTER(_P), C.POINTER(Opts)]
+_lib.fmm_build.restype = C.c_int
+_lib.fmm_forces.argtypes = [_P, C.c_int64, _P, _P, C.c_double, C.c_int, C.c_double, _P, _P]
+_lib.fmm_forces.restype = C.c_int
+_lib.fmm_forces_batched.argtypes = [_P, C.c_int64, _P, _P, _P, C.c_double, C.c_int, C.c_double,
+                                    _P, _P]
+_lib.fmm_forces_batched.restype = C.c_int
+_lib.fmm_direct.argtypes = [_P, C.c_int64, _P, _P, C.c_double, _P, _P]
+_lib.fmm_direct.restype = C.c_int
+_lib.fmm_order_for_error.argtypes = [C.c_double]
+_lib.fmm_order_for_error.restype = C.c_int
+_lib.fmm_stats.argtypes = [_P, C.POINTER(Stats)]
+_lib.fmm_stats.restype = C.c_int
+_lib.fmm_footprint_bytes.argtypes = [C.c_int64, C.c_int, C.POINTER(Opts)]
+_lib.fmm_footprint_bytes.restype = C.c_size_t
+_lib.fmm_last_error.argtypes = [_P]
+_lib.fmm_last_error.restype = C.c_char_p
+_lib.fmm_destroy.argtypes = [_P]
+_lib.fmm_destroy.restype = None
+_lib.fmm_export.argtypes = [_P, C.c_int, _P, C.c_int64]
+_lib.fmm_export.restype = C.c_int64
+
+
+class FMMError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def order_for_error(target_err: float) -> int:
+    return int(_lib.fmm_order_for_error(float(target_err)))
+
+
+def footprint_bytes(n: int, p: int, leaf_size: int = 0) -> int:
+    o = Opts(0, None, leaf_size, 0, 0.0, 0.0, 0, 0)
+    return int(_lib.fmm_footprint_bytes(int(n), int(p), C.byref(o)))
+
+
+def _dev_ptr(t: torch.Tensor, name: str, shape=None) -> int:
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError(f"{name} must be a float64 CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t.data_ptr()
+
+
+_MACS = {"a": MAC_REL, "rel": MAC_REL, "f": MAC_SCALED, "scaled": MAC_SCALED,
+         "theta": MAC_THETA}
+_SCALES = {"estimate": SCALE_ESTIMATE, "previous": SCALE_PREVIOUS}
+
+
+class Context:
+    """One libfmm context (fmm_build / fmm_destroy) on a device and stream."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None,
+                 leaf_size: int = 0, mac: str = "a", theta_crit: float = 0.5,
+                 p2p_factor: float = 0.0, scale_source: str = "estimate",
+                 timing: bool = False):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libfmm needs a GPU")
+        self.device = int(device)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream()
+        o = Opts(self.device, C.c_void_p(self.stream.cuda_stream), int(leaf_size), _MACS[mac],
+                 float(theta_crit), float(p2p_factor), _SCALES[scale_source], int(bool(timing)))
+        self._opts = o
+        h = C.c_void_p()
+        st = _lib.fmm_build(C.byref(h), C.byref(o))
+        if st != OK:
+            raise FMMError(st, "fmm_build failed")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.fmm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        if st != OK:
+            raise FMMError(st, _lib.fmm_last_error(self._h).decode())
+
+    def forces(self, pos: torch.Tensor, mass: torch.Tensor, G: float = 1.0, p: int = -1,
+               target_err: float = 1e-7, pot: torch.Tensor | None = None,
+               acc: torch.Tensor | None = None):
+        """Potential (physical, negative) and acceleration of every particle."""
+        n = pos.shape[0]
+        if pot is None:
+            pot = torch.empty(n, dtype=torch.float64, device=pos.device)
+        if acc is None:
+            acc = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+        self._check(_lib.fmm_forces(self._h, n, _dev_ptr(pos, "pos", (n, 3)),
+                                    _dev_ptr(mass, "mass", (n,)), float(G), int(p),
+                                    float(target_err), _dev_ptr(pot, "pot", (n,)),
+                                    _dev_ptr(acc, "acc", (n, 3))))
+        return pot, acc
+
+    def forces_batched(self, offsets, pos, mass, G: float = 1.0, p: int = -1,
+                       target_err: float = 1e-7, pot=None, acc=None):
+        """Independent clusters [offsets[i], offsets[i+1]) in one call."""
+        import numpy as np
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        n = pos.shape[0]
+        if off[-1] != n:
+            raise ValueError("offsets[-1] must equal the number of particles")
+        if pot is None:
+            pot = torch.empty(n, dtype=torch.float64, device=pos.device)
+        if acc is None:
+            acc = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+        self._check(_lib.fmm_forces_batched(self._h, off.shape[0] - 1,
+                                            off.ctypes.data_as(C.c_void_p),
+                                            _dev_ptr(pos, "pos", (n, 3)),
+                                            _dev_ptr(mass, "mass", (n,)), float(G), int(p),
+                                            float(target_err), _dev_ptr(pot, "pot", (n,)),
+                                            _dev_ptr(acc, "acc", (n, 3))))
+        return pot, acc
+
+    def direct(self, pos: torch.Tensor, mass: torch.Tensor, G: float = 1.0):
+        """Exact FP64 all-pairs direct summation on the GPU."""
+        n = pos.shape[0]
+        pot = torch.empty(n, dtype=torch.float64, device=pos.device)
+        acc = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+        self._check(_lib.fmm_direct(self._h, n, _dev_ptr(pos, "pos", (n, 3)),
+                                    _dev_ptr(mass, "mass", (n,)), float(G),
+                                    _dev_ptr(pot, "pot", (n,)), _dev_ptr(acc, "acc", (n, 3))))
+        return pot, acc
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(_lib.fmm_stats(self._h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    def _export(self, what: int, dtype):
+        import numpy as np
+        nbytes = _lib.fmm_export(self._h, what, None, 0)
+        if nbytes < 0:
+            raise FMMError(E_INVAL, "export failed")
+        buf = np.empty(nbytes // np.dtype(dtype).itemsize, dtype=dtype)
+        got = _lib.fmm_export(self._h, what, buf.ctypes.data_as(C.c_void_p), nbytes)
+        if got != nbytes:
+            raise FMMError(E_INVAL, "export size changed")
+        return buf
+
+    def export_m2l(self):
+        """(source id, sink id) of every M2L interaction, id = level << 40 | begin."""
+        import numpy as np
+        return self._export(EXPORT_M2L, np.int64).reshape(-1, 2)
+
+    def export_p2p(self):
+        """(source id, sink-leaf id) of every direct-sum entry."""
+        import numpy as np
+        return self._export(EXPORT_P2P, np.int64).reshape(-1, 2)
+
+    def export_scale(self):
+        import numpy as np
+        return self._export(EXPORT_SCALE, np.float64)
+
+    def export_cells(self):
+        """(id, end) per cell."""
+        import numpy as np
+        return self._export(EXPORT_CELLS, np.int64).reshape(-1, 2)

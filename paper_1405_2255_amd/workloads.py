@@ -117,7 +117,7 @@ def cluster(kind: str, n: int, seed: int, *, masses: str = "equal"):
     else:
         raise ValueError(f"unknown cluster kind {kind!r}")
     if masses == "equal":
-        m = np.full(n, 1.0 / n)
+        m = np.full(n, 1.0 / max(n, 1))
     elif masses == "salpeter":
         m = salpeter_masses(n, seed + 7919)
     else:
