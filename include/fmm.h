@@ -139,7 +139,10 @@ void fmm_destroy(fmm_ctx *ctx);
  * HOST buffer dst (capacity bytes).  Returns the number of bytes the array
  * has (copying only if it fits), or -1 for an unknown id.
  *   FMM_EXPORT_M2L   int64 pairs (source id, sink id), id = level << 40 | begin
- *   FMM_EXPORT_P2P   int64 pairs (source id, sink-leaf id), same ids
+ *                    with begin the cell's first particle in Morton order
+ *   FMM_EXPORT_P2P   int64 triples (sink id, first, end): the sink cell and the
+ *                    Morton-order particle range of the source cell summed
+ *                    directly onto it
  *   FMM_EXPORT_SCALE double per particle (input order): sink scale a_b or f_b used
  *   FMM_EXPORT_CELLS int64 per cell: level << 40 | begin, then end, in cell order */
 enum { FMM_EXPORT_M2L = 1, FMM_EXPORT_P2P = 2, FMM_EXPORT_SCALE = 3, FMM_EXPORT_CELLS = 4 };

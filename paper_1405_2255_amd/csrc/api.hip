@@ -121,15 +121,18 @@ struct fmm_ctx {
     DevBuf beg, end, parent, child0, nchild, level, leaf_lo, leaf_hi, cen, com, mass, lo, hi,
         rho2, smin, leaf_cell, M, F, P, U, Fe;
     // walk
-    DevBuf fa, fb, m2l, m2l2, p2p, p2p2, m2l_off, p2p_off, chunks, ccnt, coff, Fpart;
+    DevBuf fa, fb, m2l, m2l2, p2p, p2p2, p2pe, p2pe2, m2l_off, p2p_off, chunks, ccnt, coff, Fpart;
+    DevBuf rflag, ranges, rkey;
+    DevBuf pt_n, pt_m, pt_s, pt_off, pt_moff, ptasks, ppart;
     DevBuf counters, nonfinite;
     unsigned long long *hcnt = nullptr;  // pinned host mirror of the counters
     int *hint = nullptr;                 // pinned host ints
     // last call
     int64_t n = 0;
-    int ncells = 0, nleaves = 0, depth = 0, sh = 0, p = 0;
-    int64_t n_m2l = 0, n_p2p = 0;
+    int ncells = 0, nleaves = 0, depth = 0, sh = 0, pb = 0, p = 0;
+    int64_t n_m2l = 0, n_p2p = 0, n_ranges = 0;
     uint64_t *m2l_sorted = nullptr, *p2p_sorted = nullptr;
+    uint32_t *p2pe_sorted = nullptr;
     std::vector<int> ls;  // first cell of each level
     bool have_prev_scale = false;
     int64_t prev_n = -1;
@@ -212,6 +215,7 @@ void build_tree(fmm_ctx *c, int64_t n, const double *pos, const double *mass) {
     c->ncells = ncells;
     c->depth = (int)c->ls.size() - 3;   // ls ends with two equal entries
     c->sh = std::max(1, bitlen((uint64_t)ncells));
+    c->pb = std::max(1, bitlen((uint64_t)n));
     // per-cell arrays sized now that the count is known
     ensure<int>(c->leaf_lo, ncells); ensure<int>(c->leaf_hi, ncells);
     ensure<double4>(c->cen, ncells); ensure<double4>(c->com, ncells);
@@ -243,6 +247,7 @@ struct Lists {
     uint64_t *m2l;
     int64_t n_m2l;
     uint64_t *p2p;
+    uint32_t *p2p_end;
     int64_t n_p2p;
     int64_t pairs;
     int iterations;
@@ -252,6 +257,7 @@ Lists walk(fmm_ctx *c, const WalkParams &wp0, const double *P) {
     hipStream_t s = c->stream;
     WalkParams wp = wp0;
     wp.sh = c->sh;
+    wp.pb = c->pb;
     const int64_t n = c->n;
     int64_t cap_f = std::max<int64_t>(1024, 2 * n);
     int64_t cap_m = c->m2l.cap / 8 > 0 ? (int64_t)(c->m2l.cap / 8) : std::max<int64_t>(1024, 8 * n);
@@ -259,6 +265,7 @@ Lists walk(fmm_ctx *c, const WalkParams &wp0, const double *P) {
     cap_f = std::max<int64_t>(cap_f, (int64_t)(c->fa.cap / 8));
     uint2 *fa = ensure<uint2>(c->fa, cap_f), *fb = ensure<uint2>(c->fb, cap_f);
     uint64_t *ml = ensure<uint64_t>(c->m2l, cap_m), *pl = ensure<uint64_t>(c->p2p, cap_p);
+    uint32_t *pe = ensure<uint32_t>(c->p2pe, cap_p);
     unsigned long long *cnt = ensure<unsigned long long>(c->counters, 8);
     // staging for host-to-device copies lives in pinned memory
     c->hcnt[8] = 0ull;   // the root pair (0, 0)
@@ -274,7 +281,7 @@ Lists walk(fmm_ctx *c, const WalkParams &wp0, const double *P) {
         init[2] = (unsigned long long)n_p;
         init[3] = pairs;
         CK(hipMemcpyAsync(cnt, init, 4 * sizeof(unsigned long long), hipMemcpyHostToDevice, s));
-        WalkBuffers wb{fa, n_in, fb, cap_f, ml, cap_m, pl, cap_p, cnt};
+        WalkBuffers wb{fa, n_in, fb, cap_f, ml, cap_m, pl, pe, cap_p, cnt};
         CK(launch_walk(wp, t, P, wb, s));
         CK(hipMemcpyAsync(c->hcnt, cnt, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
         sync(c);
@@ -288,7 +295,11 @@ Lists walk(fmm_ctx *c, const WalkParams &wp0, const double *P) {
                 fb = ensure<uint2>(c->fb, cap_f);
             }
             if (nm > cap_m) { cap_m = nm + nm / 2; ml = ensure<uint64_t>(c->m2l, cap_m, true, n_m); }
-            if (np > cap_p) { cap_p = np + np / 2; pl = ensure<uint64_t>(c->p2p, cap_p, true, n_p); }
+            if (np > cap_p) {
+                cap_p = np + np / 2;
+                pl = ensure<uint64_t>(c->p2p, cap_p, true, n_p);
+                pe = ensure<uint32_t>(c->p2pe, cap_p, true, n_p);
+            }
             continue;
         }
         n_m = nm;
@@ -299,7 +310,7 @@ Lists walk(fmm_ctx *c, const WalkParams &wp0, const double *P) {
         std::swap(c->fa, c->fb);
         ++it;
     }
-    return Lists{ml, n_m, pl, n_p, (int64_t)pairs, it};
+    return Lists{ml, n_m, pl, pe, n_p, (int64_t)pairs, it};
 }
 
 // sort a list by (sink, source) and compute the per-sink offsets
@@ -311,6 +322,64 @@ uint64_t *sort_list(fmm_ctx *c, DevBuf &a, DevBuf &b, int64_t nlist, int nsinks,
     int64_t *off = ensure<int64_t>(offb, (size_t)nsinks + 1);
     CK(launch_list_offsets(k1, nlist, nsinks, c->sh, off, c->stream));
     return k1;
+}
+
+// sort the direct-sum entries by (sink cell, first source particle), merge
+// adjacent source ranges of each sink and index the ranges by sink cell
+void prepare_p2p(fmm_ctx *c, int64_t nlist) {
+    hipStream_t s = c->stream;
+    uint64_t *k1 = ptr<uint64_t>(c->p2p);
+    uint64_t *k2 = ensure<uint64_t>(c->p2p2, std::max<int64_t>(nlist, 1));
+    uint32_t *v1 = ptr<uint32_t>(c->p2pe);
+    uint32_t *v2 = ensure<uint32_t>(c->p2pe2, std::max<int64_t>(nlist, 1));
+    int *tmp = tmp_ints(c, std::max(sort_tmp_ints(nlist), scan_tmp_ints(nlist + 1)));
+    CK(radix_sort(&k1, &k2, &v1, &v2, nlist, c->sh + c->pb, tmp, s));
+    c->p2p_sorted = k1;
+    c->p2pe_sorted = v1;
+    int *flag = ensure<int>(c->rflag, (size_t)nlist + 2);
+    int2 *rg = ensure<int2>(c->ranges, std::max<int64_t>(nlist, 1));
+    uint64_t *rk = ensure<uint64_t>(c->rkey, std::max<int64_t>(nlist, 1));
+    int *total = ptr<int>(c->nonfinite) + 1;
+    int64_t runs = 0;
+    if (nlist > 0) {
+        CK(launch_range_merge(k1, v1, nlist, c->pb, flag, tmp, total, rg, rk, false, s));
+        CK(hipMemcpyAsync(c->hint, total, sizeof(int), hipMemcpyDeviceToHost, s));
+        CK(launch_range_merge(k1, v1, nlist, c->pb, flag, tmp, total, rg, rk, true, s));
+        sync(c);
+        runs = c->hint[0];
+    }
+    c->n_ranges = runs;
+    int64_t *off = ensure<int64_t>(c->p2p_off, (size_t)c->ncells + 1);
+    CK(launch_list_offsets(rk, runs, c->ncells, c->pb, off, s));
+}
+
+// direct sums of every leaf (prepared ranges), added into out4
+void run_p2p(fmm_ctx *c, int want_f, int with_pot, double4 *out4, bool timed) {
+    hipStream_t s = c->stream;
+    const int nl = c->nleaves;
+    TreeArrays t = tree_arrays(c);
+    int *ntask = ensure<int>(c->pt_n, (size_t)nl + 1), *mtask = ensure<int>(c->pt_m, (size_t)nl + 1);
+    int *nts = ensure<int>(c->pt_s, (size_t)nl + 1), *toff = ensure<int>(c->pt_off, (size_t)nl + 1);
+    int *moff = ensure<int>(c->pt_moff, (size_t)nl + 1);
+    int *tmp = tmp_ints(c, scan_tmp_ints(nl + 1));
+    int *totals = ptr<int>(c->nonfinite) + 1;
+    const int64_t *off = ptr<int64_t>(c->p2p_off);
+    const int2 *rg = ptr<int2>(c->ranges);
+    CK(launch_p2p_plan(nl, ptr<int>(c->leaf_cell), off, rg, t, ntask, mtask, nts, toff, moff, tmp,
+                       totals, s));
+    CK(hipMemcpyAsync(c->hint, totals, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    sync(c);
+    const int ntasks = c->hint[0], prows = c->hint[1];
+    int2 *tasks = ensure<int2>(c->ptasks, std::max(ntasks, 1));
+    double4 *part = ensure<double4>(c->ppart, (size_t)std::max(prows, 1) * 64);
+    CK(launch_p2p_tasks(nl, toff, tasks, s));
+    if (timed && c->opts.timing) CK(hipEventRecord(c->ev_p2p[0], s));
+    CK(launch_p2p(want_f, with_pot, ntasks, tasks, ptr<int>(c->leaf_cell), nts, moff, off, rg, t,
+                  ptr<double4>(c->xyzm), out4, part, s));
+    if (timed && c->opts.timing) CK(hipEventRecord(c->ev_p2p[1], s));
+    if (prows > 0)
+        CK(launch_p2p_reduce(c->n, ptr<int>(c->leaf_of), ptr<int>(c->leaf_cell), nts, moff, t,
+                             part, out4, s));
 }
 
 // ------------------------------------------------------------ sink scale
@@ -332,15 +401,14 @@ void sink_scale(fmm_ctx *c, bool want_f) {
         c->st.n_est_m2l = L.n_m2l;
         c->st.n_est_p2p_pairs = L.pairs;
         uint64_t *ml = sort_list(c, c->m2l, c->m2l2, L.n_m2l, c->ncells, c->m2l_off);
-        uint64_t *pl = sort_list(c, c->p2p, c->p2p2, L.n_p2p, c->nleaves, c->p2p_off);
+        prepare_p2p(c, L.n_p2p);
         double4 *Fe = ensure<double4>(c->Fe, c->ncells);
         CK(launch_est_m2l(want_f, t, c->ncells, ptr<int64_t>(c->m2l_off), ml, c->sh, Fe, s));
         for (int Lv = 1; Lv <= c->depth; ++Lv)
             CK(launch_est_l2l_level(want_f, t, c->ls[Lv], c->ls[Lv + 1], Fe, s));
         double4 *e4 = ensure<double4>(c->est4, n);
         CK(launch_est_l2p(want_f, t, ptr<int>(c->leaf_of), ptr<int>(c->leaf_cell), n, Fe, e4, s));
-        CK(launch_p2p(want_f, 0, c->nleaves, ptr<int>(c->leaf_cell), ptr<int64_t>(c->p2p_off), pl,
-                      c->sh, t, ptr<double4>(c->xyzm), e4, s));
+        run_p2p(c, want_f, 0, e4, false);
         CK(launch_scale(want_f, n, e4, scale, s));
     }
     for (int Lv = c->depth; Lv >= 0; --Lv)
@@ -388,7 +456,7 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
     c->st.n_p2p_lists = L.n_p2p;
     c->st.n_p2p_pairs = L.pairs;
     c->m2l_sorted = sort_list(c, c->m2l, c->m2l2, L.n_m2l, c->ncells, c->m2l_off);
-    c->p2p_sorted = sort_list(c, c->p2p, c->p2p2, L.n_p2p, c->nleaves, c->p2p_off);
+    prepare_p2p(c, L.n_p2p);
     mark(c, PH_WALK);
     // M2L by chunks of one sink's list
     double *F = ensure<double>(c->F, 2 * (size_t)nc * c->ncells);
@@ -421,10 +489,7 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
                   ptr<double>(c->y), ptr<double>(c->z), F, o4, s));
     mark(c, PH_DOWN);
     // near field
-    if (c->opts.timing) CK(hipEventRecord(c->ev_p2p[0], s));
-    CK(launch_p2p(0, 1, c->nleaves, ptr<int>(c->leaf_cell), ptr<int64_t>(c->p2p_off),
-                  c->p2p_sorted, c->sh, t, ptr<double4>(c->xyzm), o4, s));
-    if (c->opts.timing) CK(hipEventRecord(c->ev_p2p[1], s));
+    run_p2p(c, 0, 1, o4, true);
     mark(c, PH_P2P);
     int *nonfinite = ptr<int>(c->nonfinite);
     CK(hipMemsetAsync(nonfinite, 0, sizeof(int), s));
@@ -565,7 +630,9 @@ void fmm_destroy(fmm_ctx *c) {
                       &c->beg, &c->end, &c->parent, &c->child0, &c->nchild, &c->level,
                       &c->leaf_lo, &c->leaf_hi, &c->cen, &c->com, &c->mass, &c->lo, &c->hi,
                       &c->rho2, &c->smin, &c->leaf_cell, &c->M, &c->F, &c->P, &c->U, &c->Fe,
-                      &c->fa, &c->fb, &c->m2l, &c->m2l2, &c->p2p, &c->p2p2, &c->m2l_off,
+                      &c->fa, &c->fb, &c->m2l, &c->m2l2, &c->p2p, &c->p2p2, &c->p2pe,
+                      &c->p2pe2, &c->rflag, &c->ranges, &c->rkey, &c->pt_n, &c->pt_m,
+                      &c->pt_s, &c->pt_off, &c->pt_moff, &c->ptasks, &c->ppart, &c->m2l_off,
                       &c->p2p_off, &c->chunks, &c->ccnt, &c->coff, &c->Fpart, &c->counters,
                       &c->nonfinite, &c->prev_scale};
     for (DevBuf *b : bufs)
@@ -691,20 +758,38 @@ int64_t fmm_export(fmm_ctx *c, int what, void *dst, int64_t capacity) {
                              hipMemcpyDeviceToHost));
         };
         auto id = [&](int cell) { return ((int64_t)lev[cell] << 40) | (int64_t)beg[cell]; };
-        if (what == FMM_EXPORT_M2L || what == FMM_EXPORT_P2P) {
-            const int64_t cnt = what == FMM_EXPORT_M2L ? c->n_m2l : c->n_p2p;
+        if (what == FMM_EXPORT_M2L) {
+            const int64_t cnt = c->n_m2l;
             const int64_t bytes = cnt * 16;
             if (!dst || capacity < bytes) return bytes;
             cells();
             std::vector<uint64_t> keys(cnt);
-            const uint64_t *src = what == FMM_EXPORT_M2L ? c->m2l_sorted : c->p2p_sorted;
-            if (cnt) CK(hipMemcpy(keys.data(), src, cnt * 8, hipMemcpyDeviceToHost));
+            if (cnt) CK(hipMemcpy(keys.data(), c->m2l_sorted, cnt * 8, hipMemcpyDeviceToHost));
             int64_t *o = static_cast<int64_t *>(dst);
             const uint64_t mask = (1ull << c->sh) - 1;
             for (int64_t i = 0; i < cnt; ++i) {
-                const int a = (int)(keys[i] & mask), b = (int)(keys[i] >> c->sh);
-                o[2 * i] = id(a);
-                o[2 * i + 1] = id(what == FMM_EXPORT_M2L ? b : lcell[b]);
+                o[2 * i] = id((int)(keys[i] & mask));
+                o[2 * i + 1] = id((int)(keys[i] >> c->sh));
+            }
+            return bytes;
+        }
+        if (what == FMM_EXPORT_P2P) {
+            const int64_t cnt = c->n_p2p;
+            const int64_t bytes = cnt * 24;
+            if (!dst || capacity < bytes) return bytes;
+            cells();
+            std::vector<uint64_t> keys(cnt);
+            std::vector<uint32_t> ends(cnt);
+            if (cnt) {
+                CK(hipMemcpy(keys.data(), c->p2p_sorted, cnt * 8, hipMemcpyDeviceToHost));
+                CK(hipMemcpy(ends.data(), c->p2pe_sorted, cnt * 4, hipMemcpyDeviceToHost));
+            }
+            int64_t *o = static_cast<int64_t *>(dst);
+            const uint64_t mask = (1ull << c->pb) - 1;
+            for (int64_t i = 0; i < cnt; ++i) {
+                o[3 * i] = id((int)(keys[i] >> c->pb));
+                o[3 * i + 1] = (int64_t)(keys[i] & mask);
+                o[3 * i + 2] = (int64_t)ends[i];
             }
             return bytes;
         }

@@ -97,13 +97,14 @@ struct WalkParams {
     double eps;
     double theta_crit;
     double p2p_pairs;  // accepted with N_A N_B < p2p_pairs -> direct
-    int sh;            // list keys are (sink << sh) | source
+    int sh;            // M2L keys are (sink << sh) | source cell
+    int pb;            // direct-sum keys are (sink << pb) | first source particle
 };
 struct WalkBuffers {
     const uint2 *in; int64_t n_in;
     uint2 *out; int64_t cap_out;
     uint64_t *m2l; int64_t cap_m2l;
-    uint64_t *p2p; int64_t cap_p2p;
+    uint64_t *p2p; uint32_t *p2p_end; int64_t cap_p2p;   // key, end of the source range
     unsigned long long *counters;   // [0] out, [1] m2l, [2] p2p, [3] p2p particle pairs
 };
 hipError_t launch_walk(const WalkParams &wp, const TreeArrays &t, const double *P,
@@ -111,6 +112,12 @@ hipError_t launch_walk(const WalkParams &wp, const TreeArrays &t, const double *
 // offsets of the sorted (sink << sh | source) list per sink: off[c] for c in [0, nsinks]
 hipError_t launch_list_offsets(const uint64_t *list, int64_t nlist, int nsinks, int sh,
                                int64_t *off, hipStream_t s);
+// merge key-sorted direct-sum entries into maximal particle ranges per sink:
+// first call (write = false) flags and scans (flag: n + 1 ints, *total = runs);
+// second call writes range[run] = (begin, end) and rkey[run] = its key.
+hipError_t launch_range_merge(const uint64_t *key, const uint32_t *end, int64_t n, int pb,
+                              int *flag, int *tmp, int *total, int2 *range, uint64_t *rkey,
+                              bool write, hipStream_t s);
 
 // ---- m2l.hip ------------------------------------------------------------
 // chunk table of the sink-sorted M2L list: first call (fill = false) counts the
@@ -129,9 +136,22 @@ hipError_t launch_m2l_reduce(int p, int ncells, const int *coff, const double *F
 
 // ---- p2p.hip ------------------------------------------------------------
 // near field of each sink leaf over its list, added to out4 (sorted order)
-hipError_t launch_p2p(int want_f, int with_pot, int nleaves, const int *leaf_cell,
-                      const int64_t *off, const uint64_t *list, int sh, const TreeArrays &t,
-                      const double4 *xyzm, double4 *out4, hipStream_t s);
+// off: ncells + 1 offsets into range (per sink cell).  Planning: per leaf
+// the task counts (ntask, mtask, nsrc_tasks: nleaves + 1 ints each) and their
+// scans task_off, moff; totals[0] = tasks, totals[1] = partial rows.
+#define P2P_TASK 8192
+hipError_t launch_p2p_plan(int nleaves, const int *leaf_cell, const int64_t *off,
+                           const int2 *range, const TreeArrays &t, int *ntask, int *mtask,
+                           int *nsrc_tasks, int *task_off, int *moff, int *tmp, int *totals,
+                           hipStream_t s);
+hipError_t launch_p2p_tasks(int nleaves, const int *task_off, int2 *tasks, hipStream_t s);
+hipError_t launch_p2p(int want_f, int with_pot, int ntasks, const int2 *tasks,
+                      const int *leaf_cell, const int *nsrc_tasks, const int *moff,
+                      const int64_t *off, const int2 *range, const TreeArrays &t,
+                      const double4 *xyzm, double4 *out4, double4 *partial, hipStream_t s);
+hipError_t launch_p2p_reduce(int64_t n, const int *leaf_of, const int *leaf_cell,
+                             const int *nsrc_tasks, const int *moff, const TreeArrays &t,
+                             const double4 *partial, double4 *out4, hipStream_t s);
 hipError_t launch_output(int64_t n, const uint32_t *perm, const double4 *out4, double G,
                          double *pot, double *acc, int *nonfinite, hipStream_t s);
 hipError_t launch_scale(int want_f, int64_t n, const double4 *est4, double *scale,

@@ -2,12 +2,18 @@
 // pairs), the all-pairs GPU direct summation used as a comparison baseline,
 // and the final un-permute / scale / finiteness check.
 //
-// P2P: one wavefront per sink leaf.  For a leaf of nb <= 64 particles the
-// 64 lanes are (sink, phase) with nbp = next power of two >= nb sinks and
-// 64/nbp phases; the phases stride through each source cell's particles and
-// are summed with shuffles at the end, so small leaves still fill the
-// wavefront.  Source particles are read as (x, y, z, m) double4 from the
-// Morton-sorted copy, contiguous per source cell.
+// P2P: the sources of a sink leaf are the merged particle ranges listed for
+// the leaf and for each of its ancestors (a direct sum accepted for a cell
+// applies to all particles below it).  A leaf's work is cut into tasks of at
+// most 64 sinks x P2P_TASK sources - a sparse leaf far out in an untruncated
+// halo can be summed against every particle, and as one wavefront's serial
+// loop it would set the kernel time.  One wavefront per task: the 64 lanes
+// are (sink, phase) with nbp = next power of two >= the task's sinks and
+// 64/nbp phases; the phases stride through each range and are summed with
+// shuffles at the end, so small leaves still fill the wavefront.  A leaf
+// with one task adds into the output directly; otherwise each task writes a
+// row of partial sums that a second kernel adds in task order (deterministic).
+// Source particles are read as (x, y, z, m) double4 from the key-sorted copy.
 #include "internal.h"
 #include "dev.h"
 
@@ -15,30 +21,82 @@ namespace fmm {
 
 namespace {
 
+// Work of one sink leaf: its direct-sum ranges and those of its ancestors,
+// read as one concatenated list of source particles.
+__device__ __forceinline__ int64_t leaf_sources(int c, const int *parent, const int64_t *off,
+                                                const int2 *range) {
+    int64_t s = 0;
+    for (int anc = c; anc >= 0; anc = parent[anc])
+        for (int64_t r = off[anc]; r < off[anc + 1]; ++r) s += range[r].y - range[r].x;
+    return s;
+}
+
+// per leaf: tasks = sink chunks of 64 x source chunks of P2P_TASK sources;
+// mtask = tasks that need a partial-sum row (leaves with more than one task)
+__global__ void k_p2p_count(int nleaves, const int *leaf_cell, const int64_t *off,
+                            const int2 *range, TreeArrays t, int *ntask, int *mtask,
+                            int *nsrc_tasks) {
+    const int leaf = blockIdx.x * blockDim.x + threadIdx.x;
+    if (leaf > nleaves) return;
+    if (leaf == nleaves) {
+        ntask[leaf] = 0;
+        mtask[leaf] = 0;
+        return;
+    }
+    const int c = leaf_cell[leaf];
+    const int64_t S = leaf_sources(c, t.parent, off, range);
+    const int nsc = (t.end[c] - t.beg[c] + FMM_WAVE - 1) / FMM_WAVE;
+    const int nts = (int)max((int64_t)1, (S + P2P_TASK - 1) / P2P_TASK);
+    nsrc_tasks[leaf] = nts;
+    ntask[leaf] = nsc * nts;
+    mtask[leaf] = nsc * nts > 1 ? nsc * nts : 0;
+}
+
+__global__ void k_p2p_tasks(int nleaves, const int *task_off, int2 *tasks) {
+    const int leaf = blockIdx.x * blockDim.x + threadIdx.x;
+    if (leaf >= nleaves) return;
+    for (int k = task_off[leaf]; k < task_off[leaf + 1]; ++k) tasks[k] = make_int2(leaf, k - task_off[leaf]);
+}
+
 template <int WANT_F, int WITH_POT>
 __global__ void __launch_bounds__(256)
-k_p2p(int nleaves, const int *leaf_cell, const int64_t *off, const uint64_t *list, uint64_t mask,
-      TreeArrays t, const double4 *xyzm, double4 *out4) {
-    const int leaf = blockIdx.x * 4 + threadIdx.x / FMM_WAVE;
-    if (leaf >= nleaves) return;
+k_p2p(int ntasks, const int2 *tasks, const int *leaf_cell, const int *nsrc_tasks,
+      const int *moff, const int64_t *off, const int2 *range, TreeArrays t, const double4 *xyzm,
+      double4 *out4, double4 *partial) {
+    const int task = blockIdx.x * 4 + threadIdx.x / FMM_WAVE;
+    if (task >= ntasks) return;
     const int lane = lane_id();
+    const int2 tk = tasks[task];
+    const int leaf = tk.x;
     const int c = leaf_cell[leaf];
+    const int nts = nsrc_tasks[leaf];
+    const int sc = tk.y / nts, ts = tk.y % nts;
     const int beg = t.beg[c], end = t.end[c];
-    const int64_t e0 = off[leaf], e1 = off[leaf + 1];
-    for (int sb = beg; sb < end; sb += FMM_WAVE) {
-        const int nb = min(end - sb, FMM_WAVE);
-        int nbp = 1;
-        while (nbp < nb) nbp <<= 1;
-        const int S = FMM_WAVE / nbp;
-        const int slot = lane & (nbp - 1), phase = lane / nbp;
-        const int bi = sb + slot;
-        const bool active = slot < nb;
-        const double4 xb = xyzm[active ? bi : sb];
-        double pot = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
-        for (int64_t e = e0; e < e1; ++e) {
-            const int A = (int)(list[e] & mask);
-            const int a0 = t.beg[A], a1 = t.end[A];
-            for (int j = a0 + phase; j < a1; j += S) {
+    const int sb = beg + sc * FMM_WAVE;
+    const int nb = min(end - sb, FMM_WAVE);
+    int nbp = 1;
+    while (nbp < nb) nbp <<= 1;
+    const int S = FMM_WAVE / nbp;
+    const int slot = lane & (nbp - 1), phase = lane / nbp;
+    const int bi = sb + slot;
+    const bool active = slot < nb;
+    const double4 xb = xyzm[active ? bi : sb];
+    double pot = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
+    // sources [ts * P2P_TASK, (ts + 1) * P2P_TASK) of the leaf's list
+    int64_t skip = (int64_t)ts * P2P_TASK, left = P2P_TASK;
+    for (int anc = c; anc >= 0 && left > 0; anc = t.parent[anc]) {
+        for (int64_t r = off[anc]; r < off[anc + 1] && left > 0; ++r) {
+            int2 rg = range[r];
+            const int len = rg.y - rg.x;
+            if (skip >= len) {
+                skip -= len;
+                continue;
+            }
+            rg.x += (int)skip;
+            skip = 0;
+            if (rg.y - rg.x > left) rg.y = rg.x + (int)left;
+            left -= rg.y - rg.x;
+            for (int j = rg.x + phase; j < rg.y; j += S) {
                 const double4 s = xyzm[j];
                 const double dx = s.x - xb.x, dy = s.y - xb.y, dz = s.z - xb.z;
                 const bool self = j == bi;
@@ -57,25 +115,43 @@ k_p2p(int nleaves, const int *leaf_cell, const int64_t *off, const uint64_t *lis
                 }
             }
         }
-        // sum the phases of each sink
-        for (int o = nbp; o < FMM_WAVE; o <<= 1) {
-            pot += __shfl_xor(pot, o, FMM_WAVE);
-            if (!WANT_F) {
-                ax += __shfl_xor(ax, o, FMM_WAVE);
-                ay += __shfl_xor(ay, o, FMM_WAVE);
-                az += __shfl_xor(az, o, FMM_WAVE);
-            }
-        }
-        if (active && phase == 0) {
-            double4 v = out4[bi];
-            v.x += pot;
-            v.y += ax;
-            v.z += ay;
-            v.w += az;
-            out4[bi] = v;
-        }
-        (void)S;
     }
+    // sum the phases of each sink
+    for (int o = nbp; o < FMM_WAVE; o <<= 1) {
+        pot += __shfl_xor(pot, o, FMM_WAVE);
+        if (!WANT_F) {
+            ax += __shfl_xor(ax, o, FMM_WAVE);
+            ay += __shfl_xor(ay, o, FMM_WAVE);
+            az += __shfl_xor(az, o, FMM_WAVE);
+        }
+    }
+    if (!(active && phase == 0)) return;
+    if (moff[leaf + 1] == moff[leaf]) {          // the leaf's only task
+        double4 v = out4[bi];
+        v.x += pot; v.y += ax; v.z += ay; v.w += az;
+        out4[bi] = v;
+    } else {
+        partial[((int64_t)moff[leaf] + tk.y) * FMM_WAVE + slot] = make_double4(pot, ax, ay, az);
+    }
+}
+
+// add the partial sums of multi-task leaves, in task order
+__global__ void k_p2p_reduce(int64_t n, const int *leaf_of, const int *leaf_cell,
+                             const int *nsrc_tasks, const int *moff, TreeArrays t,
+                             const double4 *partial, double4 *out4) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int leaf = leaf_of[i];
+    if (moff[leaf + 1] == moff[leaf]) return;
+    const int c = leaf_cell[leaf];
+    const int k = (int)(i - t.beg[c]);
+    const int sc = k / FMM_WAVE, slot = k % FMM_WAVE, nts = nsrc_tasks[leaf];
+    double4 v = out4[i];
+    for (int ts = 0; ts < nts; ++ts) {
+        const double4 q = partial[((int64_t)moff[leaf] + sc * nts + ts) * FMM_WAVE + slot];
+        v.x += q.x; v.y += q.y; v.z += q.z; v.w += q.w;
+    }
+    out4[i] = v;
 }
 
 // all-pairs direct sum: one sink per thread, sources in order, read as
@@ -132,21 +208,48 @@ inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
 
-hipError_t launch_p2p(int want_f, int with_pot, int nleaves, const int *leaf_cell,
-                      const int64_t *off, const uint64_t *list, int sh, const TreeArrays &t,
-                      const double4 *xyzm, double4 *out4, hipStream_t s) {
-    if (nleaves <= 0) return hipSuccess;
-    const uint64_t mask = (1ull << sh) - 1;
-    const dim3 g(blocks(nleaves, 4)), b(256);
+hipError_t launch_p2p_plan(int nleaves, const int *leaf_cell, const int64_t *off,
+                           const int2 *range, const TreeArrays &t, int *ntask, int *mtask,
+                           int *nsrc_tasks, int *task_off, int *moff, int *tmp, int *totals,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_p2p_count, dim3(blocks(nleaves + 1, 256)), dim3(256), 0, s, nleaves,
+                       leaf_cell, off, range, t, ntask, mtask, nsrc_tasks);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = exclusive_scan(ntask, task_off, nleaves + 1, tmp, totals, s);
+    if (e != hipSuccess) return e;
+    return exclusive_scan(mtask, moff, nleaves + 1, tmp, totals + 1, s);
+}
+
+hipError_t launch_p2p_tasks(int nleaves, const int *task_off, int2 *tasks, hipStream_t s) {
+    hipLaunchKernelGGL(k_p2p_tasks, dim3(blocks(nleaves, 256)), dim3(256), 0, s, nleaves,
+                       task_off, tasks);
+    return hipGetLastError();
+}
+
+hipError_t launch_p2p(int want_f, int with_pot, int ntasks, const int2 *tasks,
+                      const int *leaf_cell, const int *nsrc_tasks, const int *moff,
+                      const int64_t *off, const int2 *range, const TreeArrays &t,
+                      const double4 *xyzm, double4 *out4, double4 *partial, hipStream_t s) {
+    if (ntasks <= 0) return hipSuccess;
+    const dim3 g(blocks(ntasks, 4)), b(256);
     if (want_f)
-        hipLaunchKernelGGL((k_p2p<1, 0>), g, b, 0, s, nleaves, leaf_cell, off, list, mask, t, xyzm,
-                           out4);
+        hipLaunchKernelGGL((k_p2p<1, 0>), g, b, 0, s, ntasks, tasks, leaf_cell, nsrc_tasks, moff,
+                           off, range, t, xyzm, out4, partial);
     else if (with_pot)
-        hipLaunchKernelGGL((k_p2p<0, 1>), g, b, 0, s, nleaves, leaf_cell, off, list, mask, t, xyzm,
-                           out4);
+        hipLaunchKernelGGL((k_p2p<0, 1>), g, b, 0, s, ntasks, tasks, leaf_cell, nsrc_tasks, moff,
+                           off, range, t, xyzm, out4, partial);
     else
-        hipLaunchKernelGGL((k_p2p<0, 0>), g, b, 0, s, nleaves, leaf_cell, off, list, mask, t, xyzm,
-                           out4);
+        hipLaunchKernelGGL((k_p2p<0, 0>), g, b, 0, s, ntasks, tasks, leaf_cell, nsrc_tasks, moff,
+                           off, range, t, xyzm, out4, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_p2p_reduce(int64_t n, const int *leaf_of, const int *leaf_cell,
+                             const int *nsrc_tasks, const int *moff, const TreeArrays &t,
+                             const double4 *partial, double4 *out4, hipStream_t s) {
+    hipLaunchKernelGGL(k_p2p_reduce, dim3(blocks(n, 256)), dim3(256), 0, s, n, leaf_of, leaf_cell,
+                       nsrc_tasks, moff, t, partial, out4);
     return hipGetLastError();
 }
 

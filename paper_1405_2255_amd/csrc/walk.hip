@@ -15,7 +15,10 @@
 // order, so the lists equal those of a depth-first recursion.
 //
 // Outputs are appended with one atomic per wavefront per list; the lists are
-// sorted afterwards, which also makes their order deterministic.
+// sorted afterwards, which also makes their order deterministic.  An M2L entry
+// is (sink cell, source cell); a direct-sum entry is (sink cell, source
+// particle range), the sink being any cell: its particles are reached from
+// each leaf below it through the leaf's ancestor chain.
 #include "internal.h"
 #include "dev.h"
 
@@ -84,7 +87,7 @@ k_walk(WalkParams wp, TreeArrays t, const double *P, WalkBuffers wb) {
             const double na = (double)(t.end[A] - t.beg[A]), nb = (double)(t.end[B] - t.beg[B]);
             if (acc) {
                 if (wp.mode != 2 && na * nb < wp.p2p_pairs) {
-                    kind = 4; np = t.leaf_hi[B] - t.leaf_lo[B]; npairs = na * nb;
+                    kind = 4; np = 1; npairs = na * nb;
                 } else {
                     kind = 5; nm = 1;
                 }
@@ -137,13 +140,12 @@ k_walk(WalkParams wp, TreeArrays t, const double *P, WalkBuffers wb) {
             for (int i = 0; i < nf; ++i) wb.out[of + i] = make_uint2(A, k0 + i);
         break;
     }
-    case 4: {   // direct sum of A onto every leaf under B
-        const int l0 = t.leaf_lo[B];
-        if (op + np <= wb.cap_p2p)
-            for (int i = 0; i < np; ++i)
-                wb.p2p[op + i] = ((uint64_t)(l0 + i) << sh) | (uint64_t)A;
+    case 4:     // direct sum of A's particles onto B's (B may be any cell)
+        if (op + 1 <= wb.cap_p2p) {
+            wb.p2p[op] = ((uint64_t)B << wp.pb) | (uint64_t)t.beg[A];
+            wb.p2p_end[op] = (uint32_t)t.end[A];
+        }
         break;
-    }
     case 5:
         if (om + 1 <= wb.cap_m2l) wb.m2l[om] = ((uint64_t)B << sh) | (uint64_t)A;
         break;
@@ -154,6 +156,7 @@ k_walk(WalkParams wp, TreeArrays t, const double *P, WalkBuffers wb) {
 
 __global__ void k_list_offsets(const uint64_t *list, int64_t nlist, int nsinks, int sh,
                                int64_t *off) {
+    // list sorted by key; the sink is key >> sh
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s > nsinks) return;
     // first entry whose sink is >= s
@@ -166,9 +169,61 @@ __global__ void k_list_offsets(const uint64_t *list, int64_t nlist, int nsinks, 
     off[s] = lo;
 }
 
+// Direct-sum entries sorted by (sink, source begin): an entry starts a new
+// range unless it continues the previous one (same sink, adjacent particles).
+__global__ void k_range_flags(const uint64_t *key, const uint32_t *end, int64_t n, int pb,
+                              int *flag) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e > n) return;
+    if (e == n) {
+        flag[e] = 0;
+        return;
+    }
+    const uint64_t mask = (1ull << pb) - 1;
+    bool start = e == 0;
+    if (!start) {
+        const uint64_t k = key[e], q = key[e - 1];
+        start = (k >> pb) != (q >> pb) || (uint32_t)(k & mask) != end[e - 1];
+    }
+    flag[e] = start ? 1 : 0;
+}
+
+// run r = [first entry's begin, last entry's end) with its sink
+__global__ void k_range_write(const uint64_t *key, const uint32_t *end, int64_t n, int pb,
+                              const int *scan, int2 *range, uint64_t *rkey) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const uint64_t mask = (1ull << pb) - 1;
+    const int starts_here = scan[e + 1] - scan[e];
+    const int run = scan[e + 1] - 1;
+    if (starts_here) {
+        range[run].x = (int)(key[e] & mask);
+        rkey[run] = key[e];
+    }
+    if (e == n - 1 || scan[e + 2] - scan[e + 1]) range[run].y = (int)end[e];
+}
+
 inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
+
+hipError_t launch_range_merge(const uint64_t *key, const uint32_t *end, int64_t n, int pb,
+                              int *flag, int *tmp, int *total, int2 *range, uint64_t *rkey,
+                              bool write, hipStream_t s) {
+    if (!write) {
+        hipLaunchKernelGGL(k_range_flags, dim3(blocks(n + 1, 256)), dim3(256), 0, s, key, end, n,
+                           pb, flag);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        // flag -> exclusive scan of n + 1 entries; flag[n] = 0 so scan[n] = runs
+        e = exclusive_scan(flag, flag, n + 1, tmp, total, s);
+        if (e != hipSuccess) return e;
+        return hipSuccess;
+    }
+    hipLaunchKernelGGL(k_range_write, dim3(blocks(n, 256)), dim3(256), 0, s, key, end, n, pb, flag,
+                       range, rkey);
+    return hipGetLastError();
+}
 
 hipError_t launch_walk(const WalkParams &wp, const TreeArrays &t, const double *P,
                        const WalkBuffers &wb, hipStream_t s) {

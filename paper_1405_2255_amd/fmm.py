@@ -215,9 +215,10 @@ class Context:
         return self._export(EXPORT_M2L, np.int64).reshape(-1, 2)
 
     def export_p2p(self):
-        """(source id, sink-leaf id) of every direct-sum entry."""
+        """(sink id, first, end) of every direct-sum entry: source particle
+        range [first, end) in Morton order."""
         import numpy as np
-        return self._export(EXPORT_P2P, np.int64).reshape(-1, 2)
+        return self._export(EXPORT_P2P, np.int64).reshape(-1, 3)
 
     def export_scale(self):
         import numpy as np

@@ -91,6 +91,10 @@ def test_fmm_matches_oracle_fmm(gpu_lib, kind, n, masses, p, eps, leaf):
     assert st["depth"] == ref["stats"]["depth"]
     np.testing.assert_array_equal(_ids_sorted(ctx.export_m2l()), _ids_sorted(ref["m2l"]))
     gp2p = ctx.export_p2p()
+    end_of = dict(map(tuple, ctx.export_cells()))
+    mask = (1 << 40) - 1
+    want = np.array([(b, a & mask, end_of[a]) for a, b in ref["p2p"]], dtype=np.int64)
+    np.testing.assert_array_equal(gp2p[np.lexsort(gp2p.T[::-1])], want[np.lexsort(want.T[::-1])])
     assert st["n_p2p_pairs"] == ref["stats"]["n_p2p_pairs"]
     assert st["n_m2l"] == ref["stats"]["n_m2l"]
     # the sink scale of the estimate pass
