@@ -90,6 +90,10 @@ typedef struct {
     /* average duration of one launch of the M2L and P2P kernels (ms) */
     double t_m2l_kernel, t_p2p_kernel;
     int m2l_launches, p2p_launches;
+    /* cell pairs visited by the walk sweeps and the sweeps' time (ms),
+       main pass and estimate pass */
+    int64_t walk_pairs, est_walk_pairs;
+    double t_sweeps, t_est_sweeps;
 } fmm_stats_t;
 
 /* Create a context on opts->device.  Allocates only small bookkeeping; the

@@ -124,7 +124,7 @@ struct fmm_ctx {
     DevBuf fa, fb, m2l, m2l2, p2p, p2p2, p2pe, p2pe2, m2l_off, p2p_off, chunks, ccnt, coff, Fpart;
     DevBuf rflag, ranges, rkey;
     DevBuf pt_n, pt_m, pt_s, pt_off, pt_moff, ptasks, ppart;
-    DevBuf counters, nonfinite;
+    DevBuf counters, nonfinite, walktmp;
     unsigned long long *hcnt = nullptr;  // pinned host mirror of the counters
     int *hint = nullptr;                 // pinned host ints
     // last call
@@ -138,7 +138,9 @@ struct fmm_ctx {
     int64_t prev_n = -1;
     DevBuf prev_scale;    // |a| of the last call, input order
     hipEvent_t ev[PH_N] = {};
-    hipEvent_t ev_m2l[2] = {}, ev_p2p[2] = {};
+    hipEvent_t ev_m2l[2] = {}, ev_p2p[2] = {}, ev_walk[2] = {};
+    int64_t last_walk_pairs = 0;
+    double last_sweep_ms = 0;
     double t_m2l_kernel = 0, t_p2p_kernel = 0;
 };
 
@@ -258,59 +260,58 @@ Lists walk(fmm_ctx *c, const WalkParams &wp0, const double *P) {
     WalkParams wp = wp0;
     wp.sh = c->sh;
     wp.pb = c->pb;
+    wp.binom[0] = 1.0;
+    for (int k = 1; k <= std::min(wp.p, FMM_PMAX); ++k)
+        wp.binom[k] = wp.binom[k - 1] * (double)(wp.p - k + 1) / (double)k;
     const int64_t n = c->n;
-    int64_t cap_f = std::max<int64_t>(1024, 2 * n);
-    int64_t cap_m = c->m2l.cap / 8 > 0 ? (int64_t)(c->m2l.cap / 8) : std::max<int64_t>(1024, 8 * n);
-    int64_t cap_p = c->p2p.cap / 8 > 0 ? (int64_t)(c->p2p.cap / 8) : std::max<int64_t>(1024, 8 * n);
-    cap_f = std::max<int64_t>(cap_f, (int64_t)(c->fa.cap / 8));
-    uint2 *fa = ensure<uint2>(c->fa, cap_f), *fb = ensure<uint2>(c->fb, cap_f);
-    uint64_t *ml = ensure<uint64_t>(c->m2l, cap_m), *pl = ensure<uint64_t>(c->p2p, cap_p);
-    uint32_t *pe = ensure<uint32_t>(c->p2pe, cap_p);
-    unsigned long long *cnt = ensure<unsigned long long>(c->counters, 8);
-    // staging for host-to-device copies lives in pinned memory
-    c->hcnt[8] = 0ull;   // the root pair (0, 0)
-    CK(hipMemcpyAsync(fa, &c->hcnt[8], sizeof(uint2), hipMemcpyHostToDevice, s));
-    int64_t n_in = 1, n_m = 0, n_p = 0;
-    unsigned long long pairs = 0;
-    int it = 0;
+    // every sweep descends one level in A or in B
+    const int sweeps = 2 * c->depth + 4;
+    int64_t cap_f = std::max<int64_t>({1024, 2 * n, (int64_t)(c->fa.cap / 8)});
+    int64_t cap_m = std::max<int64_t>(1024, c->m2l.cap ? (int64_t)(c->m2l.cap / 8) : 8 * n);
+    int64_t cap_p = std::max<int64_t>(1024, c->p2p.cap ? (int64_t)(c->p2p.cap / 8) : 4 * n);
+    unsigned long long *cnt = ensure<unsigned long long>(c->counters, 8 + sweeps);
+    unsigned long long *btmp = ensure<unsigned long long>(c->walktmp, walk_tmp_u64());
     const TreeArrays t = tree_arrays(c);
-    while (n_in > 0) {
-        unsigned long long *init = c->hcnt + 12;
-        init[0] = 0ull;
-        init[1] = (unsigned long long)n_m;
-        init[2] = (unsigned long long)n_p;
-        init[3] = pairs;
-        CK(hipMemcpyAsync(cnt, init, 4 * sizeof(unsigned long long), hipMemcpyHostToDevice, s));
-        WalkBuffers wb{fa, n_in, fb, cap_f, ml, cap_m, pl, pe, cap_p, cnt};
-        CK(launch_walk(wp, t, P, wb, s));
-        CK(hipMemcpyAsync(c->hcnt, cnt, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    for (;;) {
+        uint2 *fa = ensure<uint2>(c->fa, cap_f), *fb = ensure<uint2>(c->fb, cap_f);
+        uint64_t *ml = ensure<uint64_t>(c->m2l, cap_m), *pl = ensure<uint64_t>(c->p2p, cap_p);
+        uint32_t *pe = ensure<uint32_t>(c->p2pe, cap_p);
+        CK(hipMemsetAsync(cnt, 0, (8 + sweeps) * sizeof(unsigned long long), s));
+        CK(hipMemsetAsync(fa, 0, sizeof(uint2), s));     // the root pair (0, 0)
+        if (c->opts.timing) CK(hipEventRecord(c->ev_walk[0], s));
+        for (int i = 0; i < sweeps; ++i) {
+            WalkBuffers wb{(i & 1) ? fb : fa, (i & 1) ? fa : fb, cap_f, ml, cap_m, pl, pe, cap_p,
+                           cnt};
+            CK(launch_walk(wp, t, P, wb, i, btmp, s));
+        }
+        if (c->opts.timing) CK(hipEventRecord(c->ev_walk[1], s));
+        CK(hipMemcpyAsync(c->hcnt, cnt, (4 + sweeps) * sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, s));
         sync(c);
-        const int64_t nf = (int64_t)c->hcnt[0], nm = (int64_t)c->hcnt[1], np = (int64_t)c->hcnt[2];
-        if (nf > cap_f || nm > cap_m || np > cap_p) {
-            // grow whatever overflowed and redo this sweep (the input frontier
-            // in fa is kept; the partial output of the sweep is discarded)
-            if (nf > cap_f) {
-                cap_f = nf + nf / 2;
-                fa = ensure<uint2>(c->fa, cap_f, true, n_in);
-                fb = ensure<uint2>(c->fb, cap_f);
-            }
-            if (nm > cap_m) { cap_m = nm + nm / 2; ml = ensure<uint64_t>(c->m2l, cap_m, true, n_m); }
-            if (np > cap_p) {
-                cap_p = np + np / 2;
-                pl = ensure<uint64_t>(c->p2p, cap_p, true, n_p);
-                pe = ensure<uint32_t>(c->p2pe, cap_p, true, n_p);
-            }
+        const unsigned long long *h = c->hcnt;
+        int64_t maxf = 0, visited = 1;
+        int used = 0;
+        for (int i = 0; i < sweeps; ++i) {
+            maxf = std::max<int64_t>(maxf, (int64_t)h[4 + i]);
+            visited += (int64_t)h[4 + i];
+            if (h[4 + i]) used = i + 1;
+        }
+        c->last_walk_pairs = visited;
+        if (c->opts.timing) {
+            float ms = 0;
+            CK(hipEventElapsedTime(&ms, c->ev_walk[0], c->ev_walk[1]));
+            c->last_sweep_ms = ms;
+        }
+        const bool of = maxf > cap_f || (int64_t)h[0] > cap_m || (int64_t)h[1] > cap_p || h[3];
+        if (of) {   // grow what overflowed and redo the walk
+            if (maxf > cap_f || h[3]) cap_f = std::max(2 * cap_f, maxf + maxf / 2);
+            if ((int64_t)h[0] > cap_m) cap_m = (int64_t)h[0] + (int64_t)h[0] / 2;
+            if ((int64_t)h[1] > cap_p) cap_p = (int64_t)h[1] + (int64_t)h[1] / 2;
             continue;
         }
-        n_m = nm;
-        n_p = np;
-        pairs = c->hcnt[3];
-        n_in = nf;
-        std::swap(fa, fb);
-        std::swap(c->fa, c->fb);
-        ++it;
+        if (h[4 + sweeps - 1] != 0) throw HipFail{hipErrorUnknown, "walk did not terminate"};
+        return Lists{ml, (int64_t)h[0], pl, pe, (int64_t)h[1], (int64_t)h[2], used + 1};
     }
-    return Lists{ml, n_m, pl, pe, n_p, (int64_t)pairs, it};
 }
 
 // sort a list by (sink, source) and compute the per-sink offsets
@@ -396,8 +397,10 @@ void sink_scale(fmm_ctx *c, bool want_f) {
         done = true;
     }
     if (!done) {
-        WalkParams wp{2, 1, 0.0, 1.0, 0.0, 0};
+        WalkParams wp{2, 1, 0.0, 1.0, 0.0, 0, 0, {}};
         Lists L = walk(c, wp, nullptr);
+        c->st.est_walk_pairs = c->last_walk_pairs;
+        c->st.t_est_sweeps = c->last_sweep_ms;
         c->st.n_est_m2l = L.n_m2l;
         c->st.n_est_p2p_pairs = L.pairs;
         uint64_t *ml = sort_list(c, c->m2l, c->m2l2, L.n_m2l, c->ncells, c->m2l_off);
@@ -447,8 +450,10 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
     mark(c, PH_UP);
     // walk
     WalkParams wp{c->opts.mac == FMM_MAC_THETA ? 1 : 0, p, eps, c->opts.theta_crit,
-                  c->opts.p2p_factor * (p + 1.0) * (p + 1.0) * (p + 1.0), 0};
+                  c->opts.p2p_factor * (p + 1.0) * (p + 1.0) * (p + 1.0), 0, 0, {}};
     Lists L = walk(c, wp, P);
+    c->st.walk_pairs = c->last_walk_pairs;
+    c->st.t_sweeps = c->last_sweep_ms;
     c->st.walk_iterations = L.iterations;
     c->n_m2l = L.n_m2l;
     c->n_p2p = L.n_p2p;
@@ -606,11 +611,12 @@ fmm_status fmm_build(fmm_ctx **out, const fmm_opts *o) {
             CK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
             c->own_stream = true;
         }
-        CK(hipHostMalloc((void **)&c->hcnt, 16 * sizeof(unsigned long long), hipHostMallocDefault));
+        CK(hipHostMalloc((void **)&c->hcnt, 64 * sizeof(unsigned long long), hipHostMallocDefault));
         CK(hipHostMalloc((void **)&c->hint, 16 * sizeof(int), hipHostMallocDefault));
         for (auto &e : c->ev) CK(hipEventCreate(&e));
         for (auto &e : c->ev_m2l) CK(hipEventCreate(&e));
         for (auto &e : c->ev_p2p) CK(hipEventCreate(&e));
+        for (auto &e : c->ev_walk) CK(hipEventCreate(&e));
         return FMM_OK;
     });
     if (st != FMM_OK) {
@@ -634,12 +640,13 @@ void fmm_destroy(fmm_ctx *c) {
                       &c->p2pe2, &c->rflag, &c->ranges, &c->rkey, &c->pt_n, &c->pt_m,
                       &c->pt_s, &c->pt_off, &c->pt_moff, &c->ptasks, &c->ppart, &c->m2l_off,
                       &c->p2p_off, &c->chunks, &c->ccnt, &c->coff, &c->Fpart, &c->counters,
-                      &c->nonfinite, &c->prev_scale};
+                      &c->nonfinite, &c->prev_scale, &c->walktmp};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (auto &e : c->ev) if (e) (void)hipEventDestroy(e);
     for (auto &e : c->ev_m2l) if (e) (void)hipEventDestroy(e);
     for (auto &e : c->ev_p2p) if (e) (void)hipEventDestroy(e);
+    for (auto &e : c->ev_walk) if (e) (void)hipEventDestroy(e);
     if (c->hcnt) (void)hipHostFree(c->hcnt);
     if (c->hint) (void)hipHostFree(c->hint);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);

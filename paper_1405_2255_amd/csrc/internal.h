@@ -99,16 +99,21 @@ struct WalkParams {
     double p2p_pairs;  // accepted with N_A N_B < p2p_pairs -> direct
     int sh;            // M2L keys are (sink << sh) | source cell
     int pb;            // direct-sum keys are (sink << pb) | first source particle
+    double binom[FMM_PMAX + 1];   // C(p, k)
 };
 struct WalkBuffers {
-    const uint2 *in; int64_t n_in;
-    uint2 *out; int64_t cap_out;
+    const uint2 *in;
+    uint2 *out; int64_t cap_out;     // both frontier buffers hold cap_out pairs
     uint64_t *m2l; int64_t cap_m2l;
     uint64_t *p2p; uint32_t *p2p_end; int64_t cap_p2p;   // key, end of the source range
-    unsigned long long *counters;   // [0] out, [1] m2l, [2] p2p, [3] p2p particle pairs
+    unsigned long long *counters;   // [0] m2l, [1] direct entries, [2] direct particle
+                                    // pairs, [3] overflow, [4 + i] frontier after sweep i
 };
+// sweep i reads the frontier size from counters[4 + i - 1] (1 for sweep 0);
+// btmp holds walk_tmp_u64() entries of per-block scratch
+size_t walk_tmp_u64();
 hipError_t launch_walk(const WalkParams &wp, const TreeArrays &t, const double *P,
-                       const WalkBuffers &wb, hipStream_t s);
+                       const WalkBuffers &wb, int sweep, unsigned long long *btmp, hipStream_t s);
 // offsets of the sorted (sink << sh | source) list per sink: off[c] for c in [0, nsinks]
 hipError_t launch_list_offsets(const uint64_t *list, int64_t nlist, int nsinks, int sh,
                                int64_t *off, hipStream_t s);

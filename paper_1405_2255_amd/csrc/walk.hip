@@ -14,8 +14,10 @@
 // The set of decisions depends only on the pair, never on the visiting
 // order, so the lists equal those of a depth-first recursion.
 //
-// Outputs are appended with one atomic per wavefront per list; the lists are
-// sorted afterwards, which also makes their order deterministic.  An M2L entry
+// The lists are sorted by sink afterwards.  One
+// shortcut (marked below) emits, for a sink leaf that no cell below A can
+// ever pass the radius test against, the direct sum with all of A at once:
+// the same particle pairs as the recursion, without descending A.  An M2L entry
 // is (sink cell, source cell); a direct-sum entry is (sink cell, source
 // particle range), the sink being any cell: its particles are reached from
 // each leaf below it through the leaf's ancestor chain.
@@ -34,123 +36,270 @@ __device__ __forceinline__ double dist_rn(double4 a, double4 b) {
                                 __dmul_rn(dz, dz)));
 }
 
-__global__ void __launch_bounds__(256)
-k_walk(WalkParams wp, TreeArrays t, const double *P, WalkBuffers wb) {
-    const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = lane_id();
-    const bool valid = gi < wb.n_in;
-    int nf = 0, nm = 0, np = 0;      // outputs: frontier pairs, M2L entries, P2P entries
-    int kind = 0;                    // 1 self-split, 2 split A, 3 split B, 4 P2P range, 5 M2L
-    int A = 0, B = 0;
-    double npairs = 0.0;
-    if (valid) {
-        const uint2 pr = wb.in[gi];
-        A = (int)pr.x;
-        B = (int)pr.y;
-        const int nchA = t.nchild[A], nchB = t.nchild[B];
-        if (A == B) {
-            if (nchA == 0) {
-                kind = 4; np = 1;
-                const double na = (double)(t.end[A] - t.beg[A]);
-                npairs = na * (na - 1.0);
-            } else {
-                kind = 1; nf = nchA * nchA;
-            }
-        } else {
-            const bool est = wp.mode == 2;
-            const double4 ca = est ? t.com[A] : t.cen[A];
-            const double4 cb = est ? t.com[B] : t.cen[B];
-            const double r = dist_rn(ca, cb);
-            const double rA = ca.w, rB = cb.w;
-            bool acc;
-            if (wp.mode == 1) {
-                acc = rA + rB < wp.theta_crit * r;
-            } else {
-                acc = rA + rB < r;
-                if (acc && wp.mode == 0) {
-                    // Etilde M_A = 8 max/(sum) * sum_k C(p,k) P_k rho_B^{p-k} / r^p,
-                    // by Horner in q = rho_B / r
-                    const int p = wp.p;
-                    const double *Pa = P + (size_t)A * (p + 1);
-                    const double u = 1.0 / r, q = rB * u;
-                    double S = Pa[0], up = 1.0, bin = 1.0;
-                    for (int k = 1; k <= p; ++k) {
-                        up *= u;
-                        bin = bin * (double)(p - k + 1) / (double)k;
-                        S = fma(S, q, bin * Pa[k] * up);
-                    }
-                    const double sum = rA + rB;
-                    const double fac = sum > 0.0 ? 8.0 * fmax(rA, rB) / sum : 8.0;
-                    acc = fac * S * u * u < wp.eps * t.smin[B];
-                }
-            }
-            const double na = (double)(t.end[A] - t.beg[A]), nb = (double)(t.end[B] - t.beg[B]);
-            if (acc) {
-                if (wp.mode != 2 && na * nb < wp.p2p_pairs) {
-                    kind = 4; np = 1; npairs = na * nb;
-                } else {
-                    kind = 5; nm = 1;
-                }
-            } else if (nchA == 0 && nchB == 0) {
-                kind = 4; np = 1; npairs = na * nb;
-            } else {
-                const bool splitA = nchA > 0 && (nchB == 0 || rA > rB);
-                kind = splitA ? 2 : 3;
-                nf = splitA ? nchA : nchB;
-            }
+// The decision for one cell pair (as the recursive walk would take it).
+struct Decision {
+    int kind;      // 0 none, 1 self-split, 2 split A, 3 split B, 4 direct, 5 M2L
+    int nf;        // frontier pairs emitted
+    double pairs;  // particle pairs summed directly
+};
+
+__device__ __forceinline__ Decision decide(const WalkParams &wp, const TreeArrays &t,
+                                           const double *P, int A, int B) {
+    const int nchA = t.nchild[A], nchB = t.nchild[B];
+    if (A == B) {
+        if (nchA == 0) {
+            const double na = (double)(t.end[A] - t.beg[A]);
+            return {4, 0, na * (na - 1.0)};
         }
+        return {1, nchA * nchA, 0.0};
     }
-    // wavefront-aggregated reservation in the three output lists
-    const int sf = wave_incl_scan(nf), sm = wave_incl_scan(nm), sp = wave_incl_scan(np);
-    __shared__ unsigned long long base_s[4][3];
-    const int w = threadIdx.x / FMM_WAVE;
+    const bool est = wp.mode == 2;
+    const double4 ca = est ? t.com[A] : t.cen[A];
+    const double4 cb = est ? t.com[B] : t.cen[B];
+    const double r = dist_rn(ca, cb);
+    const double rA = ca.w, rB = cb.w;
+    const double tc = wp.mode == 1 ? wp.theta_crit : 1.0;
+    bool acc = rA + rB < tc * r;
+    if (acc && wp.mode == 0) {
+        // Etilde M_A = 8 max/(sum) * sum_k C(p,k) P_k rho_B^{p-k} / r^p, by Horner
+        // in q = rho_B / r
+        const int p = wp.p;
+        const double *Pa = P + (size_t)A * (p + 1);
+        const double u = 1.0 / r, q = rB * u;
+        double S = Pa[0], up = 1.0;
+        for (int k = 1; k <= p; ++k) {
+            up *= u;
+            S = fma(S, q, wp.binom[k] * Pa[k] * up);
+        }
+        const double sum = rA + rB;
+        const double fac = sum > 0.0 ? 8.0 * fmax(rA, rB) / sum : 8.0;
+        acc = fac * S * u * u < wp.eps * t.smin[B];
+    }
+    const double na = (double)(t.end[A] - t.beg[A]);
+    const double nb = (double)(t.end[B] - t.beg[B]);
+    if (acc) {
+        if (wp.mode != 2 && na * nb < wp.p2p_pairs) return {4, 0, na * nb};
+        return {5, 0, 0.0};
+    }
+    if (nchA == 0 && nchB == 0) return {4, 0, na * nb};
+    if (nchB == 0 && rB >= tc * (r + rA) * (1.0 + 1e-12)) {
+        // B cannot be split, and no cell below A can pass the radius test
+        // against it: every centre below A lies in A's sphere, so its distance
+        // to B is at most r + rho_A.  The recursion would end in direct sums
+        // with all of A's leaves.
+        return {4, 0, na * nb};
+    }
+    const bool splitA = nchA > 0 && (nchB == 0 || rA > rB);
+    return {splitA ? 2 : 3, splitA ? nchA : nchB, 0.0};
+}
+
+// Sweeps run without host round trips: sweep i reads its frontier size from
+// counters[4 + i - 1].  Each sweep is three launches over a fixed grid of
+// WALK_BLOCKS blocks, block b owning a contiguous chunk of the frontier:
+// count (per-block totals), scan (block offsets, list sizes), write (the
+// outputs at their offsets, in frontier order).  No atomics; the output order
+// is deterministic.
+constexpr int WALK_BLOCKS = 1024;
+constexpr int WALK_THREADS = 256;
+
+__device__ __forceinline__ int64_t sweep_input(const unsigned long long *cnt, int sweep) {
+    return sweep == 0 ? 1 : (int64_t)cnt[4 + sweep - 1];
+}
+
+// block-wide inclusive scan of three ints (256 threads = 4 waves)
+__device__ __forceinline__ void block_scan3(int &a, int &b, int &c, int *tot) {
+    __shared__ int ws[WALK_THREADS / FMM_WAVE][3];
+    const int lane = lane_id(), w = threadIdx.x / FMM_WAVE;
+    a = wave_incl_scan(a);
+    b = wave_incl_scan(b);
+    c = wave_incl_scan(c);
     if (lane == FMM_WAVE - 1) {
-        base_s[w][0] = sf ? atomicAdd(&wb.counters[0], (unsigned long long)sf) : 0ull;
-        base_s[w][1] = sm ? atomicAdd(&wb.counters[1], (unsigned long long)sm) : 0ull;
-        base_s[w][2] = sp ? atomicAdd(&wb.counters[2], (unsigned long long)sp) : 0ull;
+        ws[w][0] = a;
+        ws[w][1] = b;
+        ws[w][2] = c;
     }
-    // pair count of the direct sums, for the statistics
-    double tot = npairs;
-#pragma unroll
-    for (int off = FMM_WAVE / 2; off > 0; off >>= 1) tot += __shfl_xor(tot, off, FMM_WAVE);
-    if (lane == 0 && tot > 0.0) atomicAdd(&wb.counters[3], (unsigned long long)tot);
     __syncthreads();
-    if (!valid) return;
-    const int64_t of = (int64_t)base_s[w][0] + sf - nf;
-    const int64_t om = (int64_t)base_s[w][1] + sm - nm;
-    const int64_t op = (int64_t)base_s[w][2] + sp - np;
-    const int sh = wp.sh;
-    switch (kind) {
-    case 1: {   // all ordered daughter pairs of A
-        const int k0 = t.child0[A], nch = t.nchild[A];
-        if (of + nf <= wb.cap_out)
-            for (int i = 0; i < nch; ++i)
-                for (int j = 0; j < nch; ++j) wb.out[of + i * nch + j] = make_uint2(k0 + i, k0 + j);
-        break;
-    }
-    case 2: {
-        const int k0 = t.child0[A];
-        if (of + nf <= wb.cap_out)
-            for (int i = 0; i < nf; ++i) wb.out[of + i] = make_uint2(k0 + i, B);
-        break;
-    }
-    case 3: {
-        const int k0 = t.child0[B];
-        if (of + nf <= wb.cap_out)
-            for (int i = 0; i < nf; ++i) wb.out[of + i] = make_uint2(A, k0 + i);
-        break;
-    }
-    case 4:     // direct sum of A's particles onto B's (B may be any cell)
-        if (op + 1 <= wb.cap_p2p) {
-            wb.p2p[op] = ((uint64_t)B << wp.pb) | (uint64_t)t.beg[A];
-            wb.p2p_end[op] = (uint32_t)t.end[A];
+    int oa = 0, ob = 0, oc = 0, ta = 0, tb = 0, tcn = 0;
+#pragma unroll
+    for (int i = 0; i < WALK_THREADS / FMM_WAVE; ++i) {
+        if (i < w) {
+            oa += ws[i][0];
+            ob += ws[i][1];
+            oc += ws[i][2];
         }
-        break;
-    case 5:
-        if (om + 1 <= wb.cap_m2l) wb.m2l[om] = ((uint64_t)B << sh) | (uint64_t)A;
-        break;
-    default:
-        break;
+        ta += ws[i][0];
+        tb += ws[i][1];
+        tcn += ws[i][2];
+    }
+    __syncthreads();
+    a += oa;
+    b += ob;
+    c += oc;
+    tot[0] = ta;
+    tot[1] = tb;
+    tot[2] = tcn;
+}
+
+__global__ void __launch_bounds__(WALK_THREADS)
+k_walk_count(WalkParams wp, TreeArrays t, const double *P, WalkBuffers wb, int sweep,
+             unsigned long long *btot) {
+    const unsigned long long *cnt = wb.counters;
+    const int64_t n_in = sweep_input(cnt, sweep);
+    unsigned long long f = 0, m = 0, q = 0;
+    double pairs = 0.0;
+    if (n_in <= wb.cap_out) {
+        const int64_t chunk = (n_in + WALK_BLOCKS - 1) / WALK_BLOCKS;
+        const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(n_in, lo + chunk);
+        for (int64_t i = lo + threadIdx.x; i < hi; i += WALK_THREADS) {
+            const uint2 pr = wb.in[i];
+            const Decision d = decide(wp, t, P, (int)pr.x, (int)pr.y);
+            f += d.nf;
+            m += d.kind == 5;
+            q += d.kind == 4;
+            pairs += d.pairs;
+        }
+    }
+    // block reduction
+    double fv = (double)f, mv = (double)m, qv = (double)q;
+#pragma unroll
+    for (int off = FMM_WAVE / 2; off > 0; off >>= 1) {
+        fv += __shfl_xor(fv, off, FMM_WAVE);
+        mv += __shfl_xor(mv, off, FMM_WAVE);
+        qv += __shfl_xor(qv, off, FMM_WAVE);
+        pairs += __shfl_xor(pairs, off, FMM_WAVE);
+    }
+    __shared__ double red[WALK_THREADS / FMM_WAVE][4];
+    const int w = threadIdx.x / FMM_WAVE;
+    if (lane_id() == 0) {
+        red[w][0] = fv;
+        red[w][1] = mv;
+        red[w][2] = qv;
+        red[w][3] = pairs;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+        for (int i = 0; i < WALK_THREADS / FMM_WAVE; ++i) {
+            s0 += red[i][0];
+            s1 += red[i][1];
+            s2 += red[i][2];
+            s3 += red[i][3];
+        }
+        unsigned long long *o = btot + 4 * (size_t)blockIdx.x;
+        o[0] = (unsigned long long)s0;
+        o[1] = (unsigned long long)s1;
+        o[2] = (unsigned long long)s2;
+        o[3] = (unsigned long long)s3;
+    }
+}
+
+// one block of WALK_BLOCKS threads: exclusive offsets of every block in the
+// three outputs, and the new totals
+__global__ void __launch_bounds__(WALK_BLOCKS)
+k_walk_scan(WalkBuffers wb, int sweep, unsigned long long *btot) {
+    unsigned long long *cnt = wb.counters;
+    const int b = threadIdx.x, lane = lane_id(), w = b / FMM_WAVE;
+    constexpr int NW = WALK_BLOCKS / FMM_WAVE;
+    __shared__ unsigned long long ws[NW][4];
+    unsigned long long v[4], inc[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[k] = btot[4 * b + k];
+        inc[k] = v[k];
+#pragma unroll
+        for (int off = 1; off < FMM_WAVE; off <<= 1) {
+            const unsigned long long o = __shfl_up(inc[k], off, FMM_WAVE);
+            if (lane >= off) inc[k] += o;
+        }
+        if (lane == FMM_WAVE - 1) ws[w][k] = inc[k];
+    }
+    __syncthreads();
+    unsigned long long pre[4] = {0, 0, 0, 0}, tot[4] = {0, 0, 0, 0};
+    for (int i = 0; i < NW; ++i)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (i < w) pre[k] += ws[i][k];
+            tot[k] += ws[i][k];
+        }
+    const unsigned long long m0 = cnt[0], p0 = cnt[1];
+    // offsets: frontier from 0, lists after what earlier sweeps appended
+    btot[4 * b + 0] = pre[0] + inc[0] - v[0];
+    btot[4 * b + 1] = m0 + pre[1] + inc[1] - v[1];
+    btot[4 * b + 2] = p0 + pre[2] + inc[2] - v[2];
+    __syncthreads();
+    if (b == 0) {
+        const int64_t n_in = sweep_input(cnt, sweep);
+        if (n_in > wb.cap_out) cnt[3] = 1ull;
+        cnt[4 + sweep] = tot[0];
+        cnt[0] = m0 + tot[1];
+        cnt[1] = p0 + tot[2];
+        cnt[2] += tot[3];
+    }
+}
+
+__global__ void __launch_bounds__(WALK_THREADS)
+k_walk_write(WalkParams wp, TreeArrays t, const double *P, WalkBuffers wb, int sweep,
+             const unsigned long long *boff) {
+    const unsigned long long *cnt = wb.counters;
+    // the scan kernel already replaced this sweep's output count: read the
+    // input size from the previous slot (unchanged)
+    const int64_t n_in = sweep_input(cnt, sweep);
+    if (n_in > wb.cap_out) return;
+    const int64_t chunk = (n_in + WALK_BLOCKS - 1) / WALK_BLOCKS;
+    const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(n_in, lo + chunk);
+    int64_t of = (int64_t)boff[4 * blockIdx.x + 0];
+    int64_t om = (int64_t)boff[4 * blockIdx.x + 1];
+    int64_t op = (int64_t)boff[4 * blockIdx.x + 2];
+    for (int64_t base = lo; base < hi; base += WALK_THREADS) {
+        const int64_t i = base + threadIdx.x;
+        Decision d = {0, 0, 0.0};
+        int A = 0, B = 0;
+        if (i < hi) {
+            const uint2 pr = wb.in[i];
+            A = (int)pr.x;
+            B = (int)pr.y;
+            d = decide(wp, t, P, A, B);
+        }
+        int sf = d.nf, sm = d.kind == 5, sp = d.kind == 4;
+        int tot[3];
+        block_scan3(sf, sm, sp, tot);
+        const int64_t pf = of + sf - d.nf, pm = om + sm - (d.kind == 5), pp = op + sp - (d.kind == 4);
+        switch (d.kind) {
+        case 1: {   // all ordered daughter pairs of A
+            const int k0 = t.child0[A], nch = t.nchild[A];
+            if (pf + d.nf <= wb.cap_out)
+                for (int a = 0; a < nch; ++a)
+                    for (int b = 0; b < nch; ++b)
+                        wb.out[pf + a * nch + b] = make_uint2(k0 + a, k0 + b);
+            break;
+        }
+        case 2: {
+            const int k0 = t.child0[A];
+            if (pf + d.nf <= wb.cap_out)
+                for (int a = 0; a < d.nf; ++a) wb.out[pf + a] = make_uint2(k0 + a, B);
+            break;
+        }
+        case 3: {
+            const int k0 = t.child0[B];
+            if (pf + d.nf <= wb.cap_out)
+                for (int b = 0; b < d.nf; ++b) wb.out[pf + b] = make_uint2(A, k0 + b);
+            break;
+        }
+        case 4:     // direct sum of A's particles onto B's (B may be any cell)
+            if (pp + 1 <= wb.cap_p2p) {
+                wb.p2p[pp] = ((uint64_t)B << wp.pb) | (uint64_t)t.beg[A];
+                wb.p2p_end[pp] = (uint32_t)t.end[A];
+            }
+            break;
+        case 5:
+            if (pm + 1 <= wb.cap_m2l) wb.m2l[pm] = ((uint64_t)B << wp.sh) | (uint64_t)A;
+            break;
+        default:
+            break;
+        }
+        of += tot[0];
+        om += tot[1];
+        op += tot[2];
     }
 }
 
@@ -225,10 +374,19 @@ hipError_t launch_range_merge(const uint64_t *key, const uint32_t *end, int64_t 
     return hipGetLastError();
 }
 
+size_t walk_tmp_u64() { return 4 * (size_t)WALK_BLOCKS; }
+
 hipError_t launch_walk(const WalkParams &wp, const TreeArrays &t, const double *P,
-                       const WalkBuffers &wb, hipStream_t s) {
-    if (wb.n_in <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_walk, dim3(blocks(wb.n_in, 256)), dim3(256), 0, s, wp, t, P, wb);
+                       const WalkBuffers &wb, int sweep, unsigned long long *btmp, hipStream_t s) {
+    hipLaunchKernelGGL(k_walk_count, dim3(WALK_BLOCKS), dim3(WALK_THREADS), 0, s, wp, t, P, wb,
+                       sweep, btmp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_walk_scan, dim3(1), dim3(WALK_BLOCKS), 0, s, wb, sweep, btmp);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_walk_write, dim3(WALK_BLOCKS), dim3(WALK_THREADS), 0, s, wp, t, P, wb,
+                       sweep, (const unsigned long long *)btmp);
     return hipGetLastError();
 }
 

@@ -55,7 +55,9 @@ class Stats(C.Structure):
                 ("t_walk", C.c_double), ("t_m2l", C.c_double), ("t_p2p", C.c_double),
                 ("t_down", C.c_double), ("t_total", C.c_double),
                 ("t_m2l_kernel", C.c_double), ("t_p2p_kernel", C.c_double),
-                ("m2l_launches", C.c_int), ("p2p_launches", C.c_int)]
+                ("m2l_launches", C.c_int), ("p2p_launches", C.c_int),
+                ("walk_pairs", C.c_int64), ("est_walk_pairs", C.c_int64),
+                ("t_sweeps", C.c_double), ("t_est_sweeps", C.c_double)]
 
 
 _P = C.c_void_p

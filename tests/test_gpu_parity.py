@@ -47,6 +47,19 @@ def _gpu_fmm(ctx, pos, m, p, eps, G=1.0):
     return pot.cpu().numpy(), acc.cpu().numpy()
 
 
+def _merged(entries):
+    """(sink id, first, end) entries -> per-sink maximal particle ranges."""
+    e = np.asarray(entries, dtype=np.int64).reshape(-1, 3)
+    e = e[np.lexsort((e[:, 1], e[:, 0]))]
+    out = []
+    for sink, a, b in e:
+        if out and out[-1][0] == sink and out[-1][2] == a:
+            out[-1][2] = b
+        else:
+            out.append([sink, a, b])
+    return np.array(out, dtype=np.int64).reshape(-1, 3)
+
+
 def _ids_sorted(a):
     a = np.asarray(a)
     if a.size == 0:
@@ -94,7 +107,10 @@ def test_fmm_matches_oracle_fmm(gpu_lib, kind, n, masses, p, eps, leaf):
     end_of = dict(map(tuple, ctx.export_cells()))
     mask = (1 << 40) - 1
     want = np.array([(b, a & mask, end_of[a]) for a, b in ref["p2p"]], dtype=np.int64)
-    np.testing.assert_array_equal(gp2p[np.lexsort(gp2p.T[::-1])], want[np.lexsort(want.T[::-1])])
+    # the same particle pairs summed directly onto each sink cell (the GPU walk
+    # emits a whole source cell at once where the recursion would reach only
+    # its leaves; merged ranges compare equal)
+    np.testing.assert_array_equal(_merged(gp2p), _merged(want))
     assert st["n_p2p_pairs"] == ref["stats"]["n_p2p_pairs"]
     assert st["n_m2l"] == ref["stats"]["n_m2l"]
     # the sink scale of the estimate pass
