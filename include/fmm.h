@@ -68,7 +68,7 @@ typedef struct {
     fmm_mac mac;           /* FMM_MAC_REL by default (0) */
     double theta_crit;     /* FMM_MAC_THETA only */
     double p2p_factor;     /* accepted pairs with N_A N_B < p2p_factor (p+1)^3
-                              are summed directly; 0 = 0.5 */
+                              are summed directly; 0 = 2 */
     fmm_scale_source scale_source;
     int timing;            /* nonzero: record per-phase HIP events (fmm_stats) */
 } fmm_opts;

@@ -603,7 +603,7 @@ fmm_status fmm_build(fmm_ctx **out, const fmm_opts *o) {
     if (!c) return FMM_E_NOMEM;
     c->opts = *o;
     if (c->opts.leaf_size == 0) c->opts.leaf_size = 32;
-    if (c->opts.p2p_factor == 0.0) c->opts.p2p_factor = 0.5;
+    if (c->opts.p2p_factor == 0.0) c->opts.p2p_factor = 2.0;
     fmm_status st = fmm::guarded(c, [&]() -> fmm_status {
         if (o->hip_stream) {
             c->stream = (hipStream_t)o->hip_stream;

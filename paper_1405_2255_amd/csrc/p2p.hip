@@ -7,11 +7,10 @@
 // applies to all particles below it).  A leaf's work is cut into tasks of at
 // most 64 sinks x P2P_TASK sources - a sparse leaf far out in an untruncated
 // halo can be summed against every particle, and as one wavefront's serial
-// loop it would set the kernel time.  One wavefront per task: the 64 lanes
-// are (sink, phase) with nbp = next power of two >= the task's sinks and
-// 64/nbp phases; the phases stride through each range and are summed with
-// shuffles at the end, so small leaves still fill the wavefront.  A leaf
-// with one task adds into the output directly; otherwise each task writes a
+// loop it would set the kernel time.  One wavefront per task: for nb sinks the
+// first nb * floor(64/nb) lanes are (sink, phase); the phases stride through
+// each range (two sources per iteration) and are summed through LDS at the
+// end, so small leaves still fill the wavefront.  A leaf with one task adds into the output directly; otherwise each task writes a
 // row of partial sums that a second kernel adds in task order (deterministic).
 // Source particles are read as (x, y, z, m) double4 from the key-sorted copy.
 #include "internal.h"
@@ -59,13 +58,33 @@ __global__ void k_p2p_tasks(int nleaves, const int *task_off, int2 *tasks) {
 }
 
 template <int WANT_F, int WITH_POT>
+__device__ __forceinline__ void pair(const double4 s, const double4 xb, bool skip, double &pot,
+                                     double &ax, double &ay, double &az) {
+    const double dx = s.x - xb.x, dy = s.y - xb.y, dz = s.z - xb.z;
+    const double r2 = skip ? 1.0 : fma(dx, dx, fma(dy, dy, dz * dz));
+    const double mu = skip ? 0.0 : s.w;
+    if (WANT_F) {
+        pot += mu / r2;
+    } else {
+        const double ri = rsqrt_nr(r2);
+        const double q = mu * ri;
+        const double q3 = q * ri * ri;
+        if (WITH_POT) pot += q;
+        ax = fma(q3, dx, ax);
+        ay = fma(q3, dy, ay);
+        az = fma(q3, dz, az);
+    }
+}
+
+template <int WANT_F, int WITH_POT>
 __global__ void __launch_bounds__(256)
 k_p2p(int ntasks, const int2 *tasks, const int *leaf_cell, const int *nsrc_tasks,
       const int *moff, const int64_t *off, const int2 *range, TreeArrays t, const double4 *xyzm,
       double4 *out4, double4 *partial) {
+    __shared__ double4 red[4][FMM_WAVE];
     const int task = blockIdx.x * 4 + threadIdx.x / FMM_WAVE;
     if (task >= ntasks) return;
-    const int lane = lane_id();
+    const int lane = lane_id(), w = threadIdx.x / FMM_WAVE;
     const int2 tk = tasks[task];
     const int leaf = tk.x;
     const int c = leaf_cell[leaf];
@@ -74,13 +93,12 @@ k_p2p(int ntasks, const int2 *tasks, const int *leaf_cell, const int *nsrc_tasks
     const int beg = t.beg[c], end = t.end[c];
     const int sb = beg + sc * FMM_WAVE;
     const int nb = min(end - sb, FMM_WAVE);
-    int nbp = 1;
-    while (nbp < nb) nbp <<= 1;
-    const int S = FMM_WAVE / nbp;
-    const int slot = lane & (nbp - 1), phase = lane / nbp;
+    // lanes [0, nb*S) are (sink slot, phase) = (lane % nb, lane / nb)
+    const int S = FMM_WAVE / nb;
+    const int slot = lane % nb, phase = lane / nb;
+    const bool active = phase < S;
     const int bi = sb + slot;
-    const bool active = slot < nb;
-    const double4 xb = xyzm[active ? bi : sb];
+    const double4 xb = xyzm[bi];
     double pot = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
     // sources [ts * P2P_TASK, (ts + 1) * P2P_TASK) of the leaf's list
     int64_t skip = (int64_t)ts * P2P_TASK, left = P2P_TASK;
@@ -96,36 +114,27 @@ k_p2p(int ntasks, const int2 *tasks, const int *leaf_cell, const int *nsrc_tasks
             skip = 0;
             if (rg.y - rg.x > left) rg.y = rg.x + (int)left;
             left -= rg.y - rg.x;
-            for (int j = rg.x + phase; j < rg.y; j += S) {
-                const double4 s = xyzm[j];
-                const double dx = s.x - xb.x, dy = s.y - xb.y, dz = s.z - xb.z;
-                const bool self = j == bi;
-                const double r2 = self ? 1.0 : fma(dx, dx, fma(dy, dy, dz * dz));
-                const double mu = self ? 0.0 : s.w;
-                if (WANT_F) {
-                    pot += mu / r2;
-                } else {
-                    const double ri = rsqrt_nr(r2);
-                    const double q = mu * ri;
-                    const double q3 = q * ri * ri;
-                    if (WITH_POT) pot += q;
-                    ax = fma(q3, dx, ax);
-                    ay = fma(q3, dy, ay);
-                    az = fma(q3, dz, az);
-                }
+            if (!active) continue;
+            // two sources per iteration, loads issued before the arithmetic
+            int j = rg.x + phase;
+            for (; j + S < rg.y; j += 2 * S) {
+                const double4 s0 = xyzm[j], s1 = xyzm[j + S];
+                pair<WANT_F, WITH_POT>(s0, xb, j == bi, pot, ax, ay, az);
+                pair<WANT_F, WITH_POT>(s1, xb, j + S == bi, pot, ax, ay, az);
             }
+            if (j < rg.y) pair<WANT_F, WITH_POT>(xyzm[j], xb, j == bi, pot, ax, ay, az);
         }
     }
-    // sum the phases of each sink
-    for (int o = nbp; o < FMM_WAVE; o <<= 1) {
-        pot += __shfl_xor(pot, o, FMM_WAVE);
-        if (!WANT_F) {
-            ax += __shfl_xor(ax, o, FMM_WAVE);
-            ay += __shfl_xor(ay, o, FMM_WAVE);
-            az += __shfl_xor(az, o, FMM_WAVE);
-        }
+    // sum the phases of each sink through LDS
+    red[w][lane] = active ? make_double4(pot, ax, ay, az) : make_double4(0.0, 0.0, 0.0, 0.0);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane >= nb) return;
+    for (int ph = 1; ph < S; ++ph) {
+        const double4 q = red[w][lane + ph * nb];
+        pot += q.x; ax += q.y; ay += q.z; az += q.w;
     }
-    if (!(active && phase == 0)) return;
     if (moff[leaf + 1] == moff[leaf]) {          // the leaf's only task
         double4 v = out4[bi];
         v.x += pot; v.y += ax; v.z += ay; v.w += az;

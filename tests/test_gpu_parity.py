@@ -137,7 +137,7 @@ def test_fmm_accuracy_against_direct_sum(ctx):
 
 def test_high_order_generic_kernel_matches_oracle(gpu_lib):
     """Orders above the register kernels go through the LDS-staged kernel."""
-    ctx = gpu_lib.Context(leaf_size=16)
+    ctx = gpu_lib.Context(leaf_size=16, p2p_factor=0.5)
     for p in (13, 16):
         pos, m = W.cluster("plummer", 5000, 9)
         pot, acc = _gpu_fmm(ctx, pos, m, p, 1e-9)
@@ -148,13 +148,13 @@ def test_high_order_generic_kernel_matches_oracle(gpu_lib):
 
 def test_criterion_f_and_theta_modes(gpu_lib):
     pos, m = W.cluster("plummer", 8000, 2)
-    c_f = gpu_lib.Context(mac="f")
+    c_f = gpu_lib.Context(mac="f", p2p_factor=0.5)
     _, acc = _gpu_fmm(c_f, pos, m, 10, 10 ** -6.25)
     ref = oracle.fmm(pos, m, p=10, eps=10 ** -6.25, leaf_size=32, mac=oracle.MAC_F,
                      p2p_pairs=0.5 * 11 ** 3)
     assert c_f.stats()["n_m2l"] == ref["stats"]["n_m2l"]
     assert _rel(acc, ref["acc"]).max() < 1e-10
-    c_t = gpu_lib.Context(mac="theta", theta_crit=0.4)
+    c_t = gpu_lib.Context(mac="theta", theta_crit=0.4, p2p_factor=0.5)
     _, acc = _gpu_fmm(c_t, pos, m, 8, 0.0)
     ref = oracle.fmm(pos, m, p=8, eps=0.0, leaf_size=32, mac=oracle.MAC_THETA, theta_crit=0.4,
                      p2p_pairs=0.5 * 9 ** 3)
