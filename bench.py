@@ -53,10 +53,10 @@ def main() -> int:
     ap.add_argument("--leaf", type=int, default=0)
     ap.add_argument("--p2p-factor", type=float, default=0.0)
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--check-sinks", type=int, default=4096)
-    ap.add_argument("--cpu-sinks", type=int, default=4096)
+    ap.add_argument("--check-sinks", type=int, default=16384,
+                    help="sinks checked against the CPU oracle (also the CPU-baseline sample)")
     ap.add_argument("--no-direct", action="store_true")
-    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true", help="omit the CPU baseline field")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -68,7 +68,7 @@ def main() -> int:
     from paper_1405_2255_amd import fmm, workloads
 
     target_rms = 1e-7
-    eps = args.eps if args.eps is not None else 0.5 * target_rms
+    eps = args.eps if args.eps is not None else 5e-8
     n = args.n
     pos_np, m_np = workloads.cluster("plummer", n, args.seed)
     dev = torch.device("cuda:0")
@@ -93,12 +93,14 @@ def main() -> int:
     st = kstats[-1]
     print(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step", file=sys.stderr, flush=True)
 
-    # accuracy of the last result
+    # accuracy of the last result: the CPU oracle on a sample of sinks (timed:
+    # this is also the CPU baseline), all sinks against the GPU direct sum
     acc_np = acc.cpu().numpy()
     rng = np.random.default_rng(12345)
     sinks = np.sort(rng.choice(n, min(n, args.check_sinks), replace=False))
+    cores = len(os.sched_getaffinity(0))
     t1 = time.perf_counter()
-    _, a_true, _ = oracle.direct(pos_np, m_np, sinks=sinks)
+    _, a_true, _ = oracle.direct(pos_np, m_np, sinks=sinks, threads=cores)
     t_cpu = time.perf_counter() - t1
     rel = np.linalg.norm(acc_np[sinks] - a_true, axis=1) / np.linalg.norm(a_true, axis=1)
     err_oracle = oracle.error_summary(rel)
@@ -141,16 +143,11 @@ def main() -> int:
 
     cpu = None
     if not args.no_cpu:
-        cores = len(os.sched_getaffinity(0))
-        cs = np.sort(rng.choice(n, min(n, args.cpu_sinks), replace=False))
-        t3 = time.perf_counter()
-        oracle.direct(pos_np, m_np, sinks=cs, threads=cores)
-        tc = time.perf_counter() - t3
-        cpu = {"value": len(cs) / tc, "unit": "particle-forces/s", "cores": cores,
+        cpu = {"value": len(sinks) / t_cpu, "unit": "particle-forces/s", "cores": cores,
                "kind": "oracle",
-               "sample": f"{len(cs)} sinks of the N={n} Plummer workload against all {n} "
-                         f"sources (FP64 compensated direct sum)",
-               "seconds": tc}
+               "sample": f"{len(sinks)} seeded random sinks of the N={n} Plummer workload "
+                         f"against all {n} sources (FP64 Neumaier-compensated direct sum)",
+               "seconds": t_cpu}
 
     phases = {k: st[k] for k in ("t_tree", "t_estimate", "t_up", "t_walk", "t_m2l", "t_down",
                                  "t_p2p", "t_total")}
@@ -174,7 +171,7 @@ def main() -> int:
                    "parallelism": "single GPU"},
         "errors": {"vs_oracle_sampled": err_oracle, "vs_gpu_direct_all": err_direct,
                    "target_rms": target_rms,
-                   "meets_target": bool(err_oracle["rms"] <= target_rms)},
+                   "meets_target": bool((err_direct or err_oracle)["rms"] <= target_rms)},
         "direct": direct,
         "roofline": roofline,
         "cpu_baseline": cpu,
