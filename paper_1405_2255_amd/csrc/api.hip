@@ -124,7 +124,10 @@ struct fmm_ctx {
     DevBuf fa, fb, m2l, m2l2, p2p, p2p2, p2pe, p2pe2, m2l_off, p2p_off, chunks, ccnt, coff, Fpart;
     DevBuf rflag, ranges, rkey;
     DevBuf pt_n, pt_m, pt_s, pt_off, pt_moff, ptasks, ppart;
-    DevBuf counters, nonfinite, walktmp;
+    DevBuf counters, nonfinite, walktmp, coffsets, roots, ckey, ckey2, order, order2;
+    void *pin = nullptr;      // pinned staging for host-to-device copies
+    size_t pin_cap = 0;
+    int nroots = 0;
     unsigned long long *hcnt = nullptr;  // pinned host mirror of the counters
     int *hint = nullptr;                 // pinned host ints
     // last call
@@ -175,27 +178,63 @@ void grow_cells(fmm_ctx *c, int need, int have) {
         ensure<int>(*b, nc, true, (size_t)have);
 }
 
-void build_tree(fmm_ctx *c, int64_t n, const double *pos, const double *mass) {
+void *pinned(fmm_ctx *c, size_t bytes) {
+    if (c->pin_cap < bytes) {
+        if (c->pin) CK(hipHostFree(c->pin));
+        c->pin = nullptr;
+        c->pin_cap = 0;
+        CK(hipHostMalloc(&c->pin, bytes, hipHostMallocDefault));
+        c->pin_cap = bytes;
+    }
+    return c->pin;
+}
+
+// K clusters, cluster k = particles [off[k], off[k+1]) (host offsets)
+void build_tree(fmm_ctx *c, int64_t n, const double *pos, const double *mass, int K,
+                const int64_t *off) {
     hipStream_t s = c->stream;
     const int leaf = c->opts.leaf_size;
-    // keys, sort, gather
-    unsigned long long *bb = ensure<unsigned long long>(c->bbox, 8);
+    // cluster offsets and the roots (non-empty clusters) to the device
+    std::vector<int2> roots;
+    for (int k = 0; k < K; ++k)
+        if (off[k + 1] > off[k]) roots.push_back(make_int2((int)off[k], (int)off[k + 1]));
+    const int R = (int)roots.size();
+    char *pin = static_cast<char *>(pinned(c, sizeof(int64_t) * (K + 1) + sizeof(int2) * R));
+    std::memcpy(pin, off, sizeof(int64_t) * (K + 1));
+    std::memcpy(pin + sizeof(int64_t) * (K + 1), roots.data(), sizeof(int2) * R);
+    int64_t *doff = ensure<int64_t>(c->coffsets, (size_t)K + 1);
+    int2 *droots = ensure<int2>(c->roots, (size_t)R);
+    CK(hipMemcpyAsync(doff, pin, sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice, s));
+    CK(hipMemcpyAsync(droots, pin + sizeof(int64_t) * (K + 1), sizeof(int2) * R,
+                      hipMemcpyHostToDevice, s));
+    c->nroots = R;
+    // keys in each cluster's cube, sort by key and then (stably) by cluster
+    unsigned long long *bb = ensure<unsigned long long>(c->bbox, 6 * (size_t)K);
     uint64_t *k1 = ensure<uint64_t>(c->key, n), *k2 = ensure<uint64_t>(c->key2, n);
     uint32_t *i1 = ensure<uint32_t>(c->idx, n), *i2 = ensure<uint32_t>(c->idx2, n);
-    CK(launch_bbox(pos, n, bb, s));
-    CK(launch_keys(pos, n, bb, k1, i1, s));
+    CK(launch_bbox(pos, n, K, doff, bb, s));
+    CK(launch_keys(pos, n, K, doff, bb, k1, i1, s));
     int *tmp = tmp_ints(c, std::max(sort_tmp_ints(n), scan_tmp_ints(n + 1)));
     CK(radix_sort(&k1, &k2, &i1, &i2, n, 63, tmp, s));
+    if (K > 1) {
+        uint64_t *c1 = ensure<uint64_t>(c->ckey, n), *c2 = ensure<uint64_t>(c->ckey2, n);
+        uint32_t *o1 = ensure<uint32_t>(c->order, n), *o2 = ensure<uint32_t>(c->order2, n);
+        CK(launch_cluster_keys(i1, n, K, doff, c1, o1, s));
+        CK(radix_sort(&c1, &c2, &o1, &o2, n, std::max(1, bitlen((uint64_t)(K - 1))), tmp, s));
+        CK(launch_apply_order(o1, k1, i1, n, k2, i2, s));
+        std::swap(k1, k2);
+        std::swap(i1, i2);
+    }
     c->perm = i1;
     double *x = ensure<double>(c->x, n), *y = ensure<double>(c->y, n), *z = ensure<double>(c->z, n),
            *m = ensure<double>(c->m, n);
     double4 *xyzm = ensure<double4>(c->xyzm, n);
     CK(launch_gather(pos, mass, c->perm, n, x, y, z, m, xyzm, s));
-    // octree, level by level
-    grow_cells(c, (int)std::min<int64_t>(n + 64, 1 << 30), 0);
+    // octree, level by level, from one root per cluster
+    grow_cells(c, (int)std::min<int64_t>(n + R + 64, 1 << 30), 0);
     TreeArrays t = tree_arrays(c);
-    CK(launch_init_root(t, (int)n, s));
-    c->ls.assign({0, 1});
+    CK(launch_init_roots(t, R, droots, s));
+    c->ls.assign({0, R});
     int *nch = ensure<int>(c->flags, n + 2);
     for (int L = 0;; ++L) {
         const int c0 = c->ls[L], c1 = c->ls[L + 1];
@@ -258,6 +297,7 @@ struct Lists {
 Lists walk(fmm_ctx *c, const WalkParams &wp0, const double *P) {
     hipStream_t s = c->stream;
     WalkParams wp = wp0;
+    wp.nroots = c->nroots;
     wp.sh = c->sh;
     wp.pb = c->pb;
     wp.binom[0] = 1.0;
@@ -266,7 +306,7 @@ Lists walk(fmm_ctx *c, const WalkParams &wp0, const double *P) {
     const int64_t n = c->n;
     // every sweep descends one level in A or in B
     const int sweeps = 2 * c->depth + 4;
-    int64_t cap_f = std::max<int64_t>({1024, 2 * n, (int64_t)(c->fa.cap / 8)});
+    int64_t cap_f = std::max<int64_t>({1024, 2 * n, (int64_t)c->nroots, (int64_t)(c->fa.cap / 8)});
     int64_t cap_m = std::max<int64_t>(1024, c->m2l.cap ? (int64_t)(c->m2l.cap / 8) : 8 * n);
     int64_t cap_p = std::max<int64_t>(1024, c->p2p.cap ? (int64_t)(c->p2p.cap / 8) : 4 * n);
     unsigned long long *cnt = ensure<unsigned long long>(c->counters, 8 + sweeps);
@@ -277,7 +317,7 @@ Lists walk(fmm_ctx *c, const WalkParams &wp0, const double *P) {
         uint64_t *ml = ensure<uint64_t>(c->m2l, cap_m), *pl = ensure<uint64_t>(c->p2p, cap_p);
         uint32_t *pe = ensure<uint32_t>(c->p2pe, cap_p);
         CK(hipMemsetAsync(cnt, 0, (8 + sweeps) * sizeof(unsigned long long), s));
-        CK(hipMemsetAsync(fa, 0, sizeof(uint2), s));     // the root pair (0, 0)
+        CK(launch_root_pairs(fa, c->nroots, s));           // (r, r) for every root
         if (c->opts.timing) CK(hipEventRecord(c->ev_walk[0], s));
         for (int i = 0; i < sweeps; ++i) {
             WalkBuffers wb{(i & 1) ? fb : fa, (i & 1) ? fa : fb, cap_f, ml, cap_m, pl, pe, cap_p,
@@ -397,7 +437,7 @@ void sink_scale(fmm_ctx *c, bool want_f) {
         done = true;
     }
     if (!done) {
-        WalkParams wp{2, 1, 0.0, 1.0, 0.0, 0, 0, {}};
+        WalkParams wp{2, 1, 0.0, 1.0, 0.0, 0, 0, 0, {}};
         Lists L = walk(c, wp, nullptr);
         c->st.est_walk_pairs = c->last_walk_pairs;
         c->st.t_est_sweeps = c->last_sweep_ms;
@@ -420,7 +460,7 @@ void sink_scale(fmm_ctx *c, bool want_f) {
 
 // ------------------------------------------------------------ the call
 void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double G, int p,
-            double eps, double *pot, double *acc) {
+            double eps, double *pot, double *acc, int K, const int64_t *off) {
     hipStream_t s = c->stream;
     c->st = fmm_stats_t{};
     c->n = n;
@@ -430,7 +470,7 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
     c->t_m2l_kernel = c->t_p2p_kernel = 0;
     ensure<int>(c->nonfinite, 4);
     mark(c, PH_START);
-    build_tree(c, n, pos, mass);
+    build_tree(c, n, pos, mass, K, off);
     mark(c, PH_TREE);
     TreeArrays t = tree_arrays(c);
     const bool want_f = c->opts.mac == FMM_MAC_SCALED;
@@ -450,7 +490,7 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
     mark(c, PH_UP);
     // walk
     WalkParams wp{c->opts.mac == FMM_MAC_THETA ? 1 : 0, p, eps, c->opts.theta_crit,
-                  c->opts.p2p_factor * (p + 1.0) * (p + 1.0) * (p + 1.0), 0, 0, {}};
+                  c->opts.p2p_factor * (p + 1.0) * (p + 1.0) * (p + 1.0), 0, 0, 0, {}};
     Lists L = walk(c, wp, P);
     c->st.walk_pairs = c->last_walk_pairs;
     c->st.t_sweeps = c->last_sweep_ms;
@@ -640,7 +680,8 @@ void fmm_destroy(fmm_ctx *c) {
                       &c->p2pe2, &c->rflag, &c->ranges, &c->rkey, &c->pt_n, &c->pt_m,
                       &c->pt_s, &c->pt_off, &c->pt_moff, &c->ptasks, &c->ppart, &c->m2l_off,
                       &c->p2p_off, &c->chunks, &c->ccnt, &c->coff, &c->Fpart, &c->counters,
-                      &c->nonfinite, &c->prev_scale, &c->walktmp};
+                      &c->nonfinite, &c->prev_scale, &c->walktmp, &c->coffsets, &c->roots,
+                      &c->ckey, &c->ckey2, &c->order, &c->order2};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (auto &e : c->ev) if (e) (void)hipEventDestroy(e);
@@ -649,6 +690,7 @@ void fmm_destroy(fmm_ctx *c) {
     for (auto &e : c->ev_walk) if (e) (void)hipEventDestroy(e);
     if (c->hcnt) (void)hipHostFree(c->hcnt);
     if (c->hint) (void)hipHostFree(c->hint);
+    if (c->pin) (void)hipHostFree(c->pin);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -690,7 +732,8 @@ fmm_status fmm_forces(fmm_ctx *c, int64_t n, const double *pos, const double *ma
             c->st.p = p;
             return FMM_OK;
         }
-        fmm::forces(c, n, pos, mass, G, p, target_err, pot, acc);
+        const int64_t off[2] = {0, n};
+        fmm::forces(c, n, pos, mass, G, p, target_err, pot, acc, 1, off);
         if (c->hint[0]) return fmm::fail(c, FMM_E_NONFINITE, "non-finite potential or acceleration");
         return FMM_OK;
     });
@@ -699,18 +742,25 @@ fmm_status fmm_forces(fmm_ctx *c, int64_t n, const double *pos, const double *ma
 fmm_status fmm_forces_batched(fmm_ctx *c, int64_t k, const int64_t *off, const double *pos,
                               const double *mass, double G, int p, double target_err, double *pot,
                               double *acc) {
-    if (!c || k < 0 || (k > 0 && !off)) return FMM_E_INVAL;
+    if (!c) return FMM_E_INVAL;
+    fmm::Guard g(c);
+    if (!g.ok) return FMM_E_BUSY;
+    c->err.clear();
+    if (k < 0 || (k > 0 && !off)) return fmm::fail(c, FMM_E_INVAL, "bad cluster offsets");
     if (k == 0) return FMM_OK;
+    if (k > (1 << 24)) return fmm::fail(c, FMM_E_INVAL, "too many clusters");
     if (off[0] != 0) return fmm::fail(c, FMM_E_INVAL, "offsets[0] must be 0");
     for (int64_t i = 0; i < k; ++i)
         if (off[i + 1] < off[i]) return fmm::fail(c, FMM_E_INVAL, "offsets must not decrease");
-    for (int64_t i = 0; i < k; ++i) {
-        const int64_t a = off[i];
-        fmm_status st = fmm_forces(c, off[i + 1] - a, pos + 3 * a, mass + a, G, p, target_err,
-                                   pot + a, acc + 3 * a);
-        if (st != FMM_OK) return st;
-    }
-    return FMM_OK;
+    const int64_t n = off[k];
+    fmm_status st = check_common(c, n, pos, mass, G, &p, target_err, pot, acc);
+    if (st != FMM_OK) return st;
+    return fmm::guarded(c, [&]() -> fmm_status {
+        if (n == 0) return FMM_OK;
+        fmm::forces(c, n, pos, mass, G, p, target_err, pot, acc, (int)k, off);
+        if (c->hint[0]) return fmm::fail(c, FMM_E_NONFINITE, "non-finite potential or acceleration");
+        return FMM_OK;
+    });
 }
 
 fmm_status fmm_direct(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double G,

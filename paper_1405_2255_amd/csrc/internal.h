@@ -36,13 +36,20 @@ struct TreeArrays {
     double *smin;               // min over the cell's particles of the sink scale
 };
 
-hipError_t launch_bbox(const double *pos, int64_t n, unsigned long long *bbox6, hipStream_t s);
-hipError_t launch_keys(const double *pos, int64_t n, const unsigned long long *bbox6,
-                       uint64_t *key, uint32_t *idx, hipStream_t s);
+// K clusters: particles [off[k], off[k+1]) (device int64 offsets); bb holds 6K keys
+hipError_t launch_bbox(const double *pos, int64_t n, int K, const int64_t *off,
+                       unsigned long long *bb, hipStream_t s);
+hipError_t launch_keys(const double *pos, int64_t n, int K, const int64_t *off,
+                       const unsigned long long *bb, uint64_t *key, uint32_t *idx,
+                       hipStream_t s);
+hipError_t launch_cluster_keys(const uint32_t *idx, int64_t n, int K, const int64_t *off,
+                               uint64_t *ckey, uint32_t *order, hipStream_t s);
+hipError_t launch_apply_order(const uint32_t *order, const uint64_t *key, const uint32_t *idx,
+                              int64_t n, uint64_t *key_out, uint32_t *idx_out, hipStream_t s);
 hipError_t launch_gather(const double *pos, const double *mass, const uint32_t *perm,
                          int64_t n, double *x, double *y, double *z, double *m,
                          double4 *xyzm, hipStream_t s);
-hipError_t launch_init_root(const TreeArrays &t, int n, hipStream_t s);
+hipError_t launch_init_roots(const TreeArrays &t, int nroots, const int2 *roots, hipStream_t s);
 // children of cells [c0, c1) at one level; *count_out (device) = new cells
 hipError_t launch_count_children(const uint64_t *key, const TreeArrays &t, int c0, int c1,
                                  int level, int leaf_size, int *nch, hipStream_t s);
@@ -97,6 +104,7 @@ struct WalkParams {
     double eps;
     double theta_crit;
     double p2p_pairs;  // accepted with N_A N_B < p2p_pairs -> direct
+    int nroots;        // the walk starts from (r, r) for every root r < nroots
     int sh;            // M2L keys are (sink << sh) | source cell
     int pb;            // direct-sum keys are (sink << pb) | first source particle
     double binom[FMM_PMAX + 1];   // C(p, k)
@@ -112,6 +120,7 @@ struct WalkBuffers {
 // sweep i reads the frontier size from counters[4 + i - 1] (1 for sweep 0);
 // btmp holds walk_tmp_u64() entries of per-block scratch
 size_t walk_tmp_u64();
+hipError_t launch_root_pairs(uint2 *f, int nroots, hipStream_t s);
 hipError_t launch_walk(const WalkParams &wp, const TreeArrays &t, const double *P,
                        const WalkBuffers &wb, int sweep, unsigned long long *btmp, hipStream_t s);
 // offsets of the sorted (sink << sh | source) list per sink: off[c] for c in [0, nsinks]

@@ -2,6 +2,11 @@
 // levels, leaves, cell geometry (bounding box, mass, centre of mass,
 // expansion centre and radii) and the per-cell minimum sink scale.
 //
+// A batch of K independent clusters (particles of cluster k back to back) is
+// one forest: each cluster gets its own cube and keys, the sort groups
+// clusters and orders keys inside each, and every non-empty cluster has a
+// root at level 0.  All later kernels serve all clusters in the same launch.
+//
 // The octree (Sec. 2.2.1): cubic cells, a cell holding more than n_L
 // particles is split into its non-empty octants, up to depth 21.  Octants
 // come from 21-bit quantised coordinates in the cube around the bounding box
@@ -20,32 +25,66 @@ namespace fmm {
 
 namespace {
 
-__global__ void k_bbox(const double *pos, int64_t n, unsigned long long *bb) {
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
+// cluster of particle i: offsets off[0..K] (off[0] = 0), clusters back to back
+__device__ __forceinline__ int cluster_of(const int64_t *off, int K, int64_t i) {
+    int lo = 0, hi = K - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// bounding box of every cluster: bb[6k..6k+5] = min x, y, z, max x, y, z as
+// order-preserving keys
+__global__ void k_bbox(const double *pos, int64_t n, int K, const int64_t *off,
+                       unsigned long long *bb) {
+    const int lane = lane_id();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(FMM_WAVE - 1));
+         base < n; base += stride) {
+        const int64_t i = base + lane;
+        const bool valid = i < n;
+        const int cl = valid ? cluster_of(off, K, i) : -1;
+        double lo[3], hi[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            const double v = pos[3 * i + d];
-            lo[d] = fmin(lo[d], v);
-            hi[d] = fmax(hi[d], v);
+            const double v = valid ? pos[3 * i + d] : 0.0;
+            lo[d] = valid ? v : INFINITY;
+            hi[d] = valid ? v : -INFINITY;
+        }
+        const int c0 = __shfl(cl, 0, FMM_WAVE);
+        const bool uniform = __ballot(valid && cl != c0) == 0ull;
+        if (uniform) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+#pragma unroll
+                for (int o = FMM_WAVE / 2; o > 0; o >>= 1) {
+                    lo[d] = fmin(lo[d], __shfl_xor(lo[d], o, FMM_WAVE));
+                    hi[d] = fmax(hi[d], __shfl_xor(hi[d], o, FMM_WAVE));
+                }
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    atomicMin(&bb[6 * c0 + d], ordered_key(lo[d]));
+                    atomicMax(&bb[6 * c0 + 3 + d], ordered_key(hi[d]));
+                }
+            }
+        } else if (valid) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                atomicMin(&bb[6 * cl + d], ordered_key(lo[d]));
+                atomicMax(&bb[6 * cl + 3 + d], ordered_key(hi[d]));
+            }
         }
     }
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-#pragma unroll
-        for (int off = FMM_WAVE / 2; off > 0; off >>= 1) {
-            lo[d] = fmin(lo[d], __shfl_xor(lo[d], off, FMM_WAVE));
-            hi[d] = fmax(hi[d], __shfl_xor(hi[d], off, FMM_WAVE));
-        }
-    }
-    if (lane_id() == 0) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            atomicMin(&bb[d], ordered_key(lo[d]));
-            atomicMax(&bb[3 + d], ordered_key(hi[d]));
-        }
-    }
+}
+
+__global__ void k_bbox_init(int K, unsigned long long *bb) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 6 * K) bb[i] = (i % 6) < 3 ? ~0ull : 0ull;
 }
 
 __device__ __forceinline__ uint64_t spread3(uint32_t v) {
@@ -58,15 +97,16 @@ __device__ __forceinline__ uint64_t spread3(uint32_t v) {
     return x;
 }
 
-__global__ void k_keys(const double *pos, int64_t n, const unsigned long long *bb, uint64_t *key,
-                       uint32_t *idx) {
+__global__ void k_keys(const double *pos, int64_t n, int K, const int64_t *off,
+                       const unsigned long long *bb, uint64_t *key, uint32_t *idx) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const unsigned long long *b = bb + 6 * cluster_of(off, K, i);
     double lo[3], L = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        lo[d] = ordered_val(bb[d]);
-        L = fmax(L, ordered_val(bb[3 + d]) - lo[d]);
+        lo[d] = ordered_val(b[d]);
+        L = fmax(L, ordered_val(b[3 + d]) - lo[d]);
     }
     const double scale = L > 0.0 ? 2097152.0 / L : 0.0;   // 2^21 cells per axis
     uint32_t q[3];
@@ -77,6 +117,24 @@ __global__ void k_keys(const double *pos, int64_t n, const unsigned long long *b
     }
     key[i] = spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2);
     idx[i] = (uint32_t)i;
+}
+
+// second sort of a batch: by cluster, carrying the position in key order
+__global__ void k_cluster_keys(const uint32_t *idx, int64_t n, int K, const int64_t *off,
+                               uint64_t *ckey, uint32_t *pos_in_key_order) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    ckey[i] = (uint64_t)cluster_of(off, K, idx[i]);
+    pos_in_key_order[i] = (uint32_t)i;
+}
+
+__global__ void k_apply_order(const uint32_t *order, const uint64_t *key, const uint32_t *idx,
+                              int64_t n, uint64_t *key_out, uint32_t *idx_out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t j = order[i];
+    key_out[i] = key[j];
+    idx_out[i] = idx[j];
 }
 
 __global__ void k_gather(const double *pos, const double *mass, const uint32_t *perm, int64_t n,
@@ -149,13 +207,16 @@ __global__ void k_make_children(const uint64_t *key, TreeArrays t, int c0, int c
     }
 }
 
-__global__ void k_init_root(TreeArrays t, int n) {
-    t.beg[0] = 0;
-    t.end[0] = n;
-    t.parent[0] = -1;
-    t.level[0] = 0;
-    t.nchild[0] = 0;
-    t.child0[0] = -1;
+// one root per non-empty cluster: particles [rb[r], re[r])
+__global__ void k_init_roots(TreeArrays t, int nroots, const int2 *roots) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nroots) return;
+    t.beg[r] = roots[r].x;
+    t.end[r] = roots[r].y;
+    t.parent[r] = -1;
+    t.level[r] = 0;
+    t.nchild[r] = 0;
+    t.child0[r] = -1;
 }
 
 __global__ void k_leaf_flags(TreeArrays t, int ncells, int *flags) {
@@ -339,20 +400,35 @@ inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
 
-hipError_t launch_bbox(const double *pos, int64_t n, unsigned long long *bbox6, hipStream_t s) {
-    hipError_t e = hipMemsetAsync(bbox6, 0xff, 3 * sizeof(unsigned long long), s);
-    if (e != hipSuccess) return e;
-    e = hipMemsetAsync(bbox6 + 3, 0, 3 * sizeof(unsigned long long), s);
+hipError_t launch_bbox(const double *pos, int64_t n, int K, const int64_t *off,
+                       unsigned long long *bb, hipStream_t s) {
+    hipLaunchKernelGGL(k_bbox_init, dim3(blocks(6 * (int64_t)K, 256)), dim3(256), 0, s, K, bb);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     unsigned g = blocks(n, 256);
     if (g > 2048) g = 2048;
-    hipLaunchKernelGGL(k_bbox, dim3(g), dim3(256), 0, s, pos, n, bbox6);
+    hipLaunchKernelGGL(k_bbox, dim3(g), dim3(256), 0, s, pos, n, K, off, bb);
     return hipGetLastError();
 }
 
-hipError_t launch_keys(const double *pos, int64_t n, const unsigned long long *bbox6,
-                       uint64_t *key, uint32_t *idx, hipStream_t s) {
-    hipLaunchKernelGGL(k_keys, dim3(blocks(n, 256)), dim3(256), 0, s, pos, n, bbox6, key, idx);
+hipError_t launch_keys(const double *pos, int64_t n, int K, const int64_t *off,
+                       const unsigned long long *bb, uint64_t *key, uint32_t *idx,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_keys, dim3(blocks(n, 256)), dim3(256), 0, s, pos, n, K, off, bb, key, idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_cluster_keys(const uint32_t *idx, int64_t n, int K, const int64_t *off,
+                               uint64_t *ckey, uint32_t *order, hipStream_t s) {
+    hipLaunchKernelGGL(k_cluster_keys, dim3(blocks(n, 256)), dim3(256), 0, s, idx, n, K, off, ckey,
+                       order);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_order(const uint32_t *order, const uint64_t *key, const uint32_t *idx,
+                              int64_t n, uint64_t *key_out, uint32_t *idx_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_apply_order, dim3(blocks(n, 256)), dim3(256), 0, s, order, key, idx, n,
+                       key_out, idx_out);
     return hipGetLastError();
 }
 
@@ -364,8 +440,8 @@ hipError_t launch_gather(const double *pos, const double *mass, const uint32_t *
     return hipGetLastError();
 }
 
-hipError_t launch_init_root(const TreeArrays &t, int n, hipStream_t s) {
-    hipLaunchKernelGGL(k_init_root, dim3(1), dim3(1), 0, s, t, n);
+hipError_t launch_init_roots(const TreeArrays &t, int nroots, const int2 *roots, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_roots, dim3(blocks(nroots, 256)), dim3(256), 0, s, t, nroots, roots);
     return hipGetLastError();
 }
 

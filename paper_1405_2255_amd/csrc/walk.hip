@@ -102,8 +102,9 @@ __device__ __forceinline__ Decision decide(const WalkParams &wp, const TreeArray
 constexpr int WALK_BLOCKS = 1024;
 constexpr int WALK_THREADS = 256;
 
-__device__ __forceinline__ int64_t sweep_input(const unsigned long long *cnt, int sweep) {
-    return sweep == 0 ? 1 : (int64_t)cnt[4 + sweep - 1];
+__device__ __forceinline__ int64_t sweep_input(const WalkParams &wp,
+                                               const unsigned long long *cnt, int sweep) {
+    return sweep == 0 ? wp.nroots : (int64_t)cnt[4 + sweep - 1];
 }
 
 // block-wide inclusive scan of three ints (256 threads = 4 waves)
@@ -144,7 +145,7 @@ __global__ void __launch_bounds__(WALK_THREADS)
 k_walk_count(WalkParams wp, TreeArrays t, const double *P, WalkBuffers wb, int sweep,
              unsigned long long *btot) {
     const unsigned long long *cnt = wb.counters;
-    const int64_t n_in = sweep_input(cnt, sweep);
+    const int64_t n_in = sweep_input(wp, cnt, sweep);
     unsigned long long f = 0, m = 0, q = 0;
     double pairs = 0.0;
     if (n_in <= wb.cap_out) {
@@ -196,7 +197,7 @@ k_walk_count(WalkParams wp, TreeArrays t, const double *P, WalkBuffers wb, int s
 // one block of WALK_BLOCKS threads: exclusive offsets of every block in the
 // three outputs, and the new totals
 __global__ void __launch_bounds__(WALK_BLOCKS)
-k_walk_scan(WalkBuffers wb, int sweep, unsigned long long *btot) {
+k_walk_scan(WalkParams wp, WalkBuffers wb, int sweep, unsigned long long *btot) {
     unsigned long long *cnt = wb.counters;
     const int b = threadIdx.x, lane = lane_id(), w = b / FMM_WAVE;
     constexpr int NW = WALK_BLOCKS / FMM_WAVE;
@@ -228,7 +229,7 @@ k_walk_scan(WalkBuffers wb, int sweep, unsigned long long *btot) {
     btot[4 * b + 2] = p0 + pre[2] + inc[2] - v[2];
     __syncthreads();
     if (b == 0) {
-        const int64_t n_in = sweep_input(cnt, sweep);
+        const int64_t n_in = sweep_input(wp, cnt, sweep);
         if (n_in > wb.cap_out) cnt[3] = 1ull;
         cnt[4 + sweep] = tot[0];
         cnt[0] = m0 + tot[1];
@@ -243,7 +244,7 @@ k_walk_write(WalkParams wp, TreeArrays t, const double *P, WalkBuffers wb, int s
     const unsigned long long *cnt = wb.counters;
     // the scan kernel already replaced this sweep's output count: read the
     // input size from the previous slot (unchanged)
-    const int64_t n_in = sweep_input(cnt, sweep);
+    const int64_t n_in = sweep_input(wp, cnt, sweep);
     if (n_in > wb.cap_out) return;
     const int64_t chunk = (n_in + WALK_BLOCKS - 1) / WALK_BLOCKS;
     const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(n_in, lo + chunk);
@@ -376,13 +377,23 @@ hipError_t launch_range_merge(const uint64_t *key, const uint32_t *end, int64_t 
 
 size_t walk_tmp_u64() { return 4 * (size_t)WALK_BLOCKS; }
 
+__global__ void k_root_pairs(uint2 *f, int nroots) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < nroots) f[r] = make_uint2(r, r);
+}
+
+hipError_t launch_root_pairs(uint2 *f, int nroots, hipStream_t s) {
+    hipLaunchKernelGGL(k_root_pairs, dim3((nroots + 255) / 256), dim3(256), 0, s, f, nroots);
+    return hipGetLastError();
+}
+
 hipError_t launch_walk(const WalkParams &wp, const TreeArrays &t, const double *P,
                        const WalkBuffers &wb, int sweep, unsigned long long *btmp, hipStream_t s) {
     hipLaunchKernelGGL(k_walk_count, dim3(WALK_BLOCKS), dim3(WALK_THREADS), 0, s, wp, t, P, wb,
                        sweep, btmp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_walk_scan, dim3(1), dim3(WALK_BLOCKS), 0, s, wb, sweep, btmp);
+    hipLaunchKernelGGL(k_walk_scan, dim3(1), dim3(WALK_BLOCKS), 0, s, wp, wb, sweep, btmp);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_walk_write, dim3(WALK_BLOCKS), dim3(WALK_THREADS), 0, s, wp, t, P, wb,
