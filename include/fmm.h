@@ -55,9 +55,9 @@ typedef enum {
 /* Where min_B{a_b} (or f_b) comes from. */
 typedef enum {
     FMM_SCALE_ESTIMATE = 0, /* low-order FMM estimate (Sec. 5.4.2) inside the call */
-    FMM_SCALE_PREVIOUS = 1  /* |acc| of the previous call on this context with the
-                               same n (Sec. 5.4.1); falls back to the estimate on
-                               the first call or when n changed */
+    FMM_SCALE_PREVIOUS = 1  /* in fmm_forces_refit calls that recycle the tree (the
+                               same particles one step later): |acc| of the previous
+                               call (Sec. 5.4.1); the estimate otherwise */
 } fmm_scale_source;
 
 typedef struct {
@@ -94,6 +94,7 @@ typedef struct {
        main pass and estimate pass */
     int64_t walk_pairs, est_walk_pairs;
     double t_sweeps, t_est_sweeps;
+    int refitted;                /* 1 if the last call recycled the tree */
 } fmm_stats_t;
 
 /* Create a context on opts->device.  Allocates only small bookkeeping; the
@@ -117,6 +118,16 @@ fmm_status fmm_forces(fmm_ctx *ctx, int64_t n, const double *pos, const double *
 fmm_status fmm_forces_batched(fmm_ctx *ctx, int64_t k, const int64_t *offsets_host,
                               const double *pos, const double *mass, double G, int p,
                               double target_err, double *pot, double *acc);
+
+/* fmm_forces with tree recycling (Sec. 7.1): if the previous call on this
+ * context built a tree for the same n (single cluster), its particle order and
+ * cell membership are kept and only positions, cell geometry, radii,
+ * expansions and interaction lists are recomputed; otherwise a full build.
+ * Meant for time steps that move particles little.  The acceptance test uses
+ * the true radii, so the result has the same accuracy; a recycled tree only
+ * costs more as particles drift.  fmm_stats().refitted tells which happened. */
+fmm_status fmm_forces_refit(fmm_ctx *ctx, int64_t n, const double *pos, const double *mass,
+                            double G, int p, double target_err, double *pot, double *acc);
 
 /* Exact FP64 direct summation of eq. (1) on the GPU (the comparison
  * baseline): all n sinks against all n sources, a != b. */

@@ -128,6 +128,9 @@ struct fmm_ctx {
     void *pin = nullptr;      // pinned staging for host-to-device copies
     size_t pin_cap = 0;
     int nroots = 0;
+    bool tree_valid = false, refitted = false;
+    int64_t tree_n = -1;
+    std::vector<int64_t> tree_off;
     unsigned long long *hcnt = nullptr;  // pinned host mirror of the counters
     int *hint = nullptr;                 // pinned host ints
     // last call
@@ -190,10 +193,25 @@ void *pinned(fmm_ctx *c, size_t bytes) {
 }
 
 // K clusters, cluster k = particles [off[k], off[k+1]) (host offsets)
+// With refit (and the same n and clusters as the tree on the context) the
+// particle order and cell membership of the last build are kept - tree
+// recycling between nearby time steps - and only positions, geometry and
+// radii are refreshed.  The acceptance test uses the true radii, so a
+// recycled tree stays valid; it only gets less efficient as particles drift.
 void build_tree(fmm_ctx *c, int64_t n, const double *pos, const double *mass, int K,
-                const int64_t *off) {
+                const int64_t *off, bool refit) {
     hipStream_t s = c->stream;
     const int leaf = c->opts.leaf_size;
+    const bool reuse = refit && c->tree_valid && c->tree_n == n &&
+                       c->tree_off == std::vector<int64_t>(off, off + K + 1);
+    double *x = ensure<double>(c->x, n), *y = ensure<double>(c->y, n), *z = ensure<double>(c->z, n),
+           *m = ensure<double>(c->m, n);
+    double4 *xyzm = ensure<double4>(c->xyzm, n);
+    c->refitted = reuse;
+    if (reuse) {
+        CK(launch_gather(pos, mass, c->perm, n, x, y, z, m, xyzm, s));
+    } else {
+    c->tree_valid = false;
     // cluster offsets and the roots (non-empty clusters) to the device
     std::vector<int2> roots;
     for (int k = 0; k < K; ++k)
@@ -226,9 +244,6 @@ void build_tree(fmm_ctx *c, int64_t n, const double *pos, const double *mass, in
         std::swap(i1, i2);
     }
     c->perm = i1;
-    double *x = ensure<double>(c->x, n), *y = ensure<double>(c->y, n), *z = ensure<double>(c->z, n),
-           *m = ensure<double>(c->m, n);
-    double4 *xyzm = ensure<double4>(c->xyzm, n);
     CK(launch_gather(pos, mass, c->perm, n, x, y, z, m, xyzm, s));
     // octree, level by level, from one root per cluster
     grow_cells(c, (int)std::min<int64_t>(n + R + 64, 1 << 30), 0);
@@ -276,6 +291,13 @@ void build_tree(fmm_ctx *c, int64_t n, const double *pos, const double *mass, in
     CK(launch_leaf_ranges(t, ncells, flags, leaf_cell, leaf_of, n, s));
     sync(c);
     c->nleaves = c->hint[0];
+    c->tree_valid = true;
+    c->tree_n = n;
+    c->tree_off.assign(off, off + K + 1);
+    }
+    const int ncells = c->ncells;
+    TreeArrays t = tree_arrays(c);
+    const int *leaf_of = ptr<int>(c->leaf_of), *leaf_cell = ptr<int>(c->leaf_cell);
     // geometry bottom up, then the radii of every cell in one pass
     for (int L = c->depth; L >= 0; --L)
         CK(launch_geometry_level(t, c->ls[L], c->ls[L + 1], x, y, z, m, s));
@@ -431,7 +453,7 @@ void sink_scale(fmm_ctx *c, bool want_f) {
     double *scale = ensure<double>(c->scale, n);
     bool done = false;
     if (c->opts.scale_source == FMM_SCALE_PREVIOUS && !want_f && c->have_prev_scale &&
-        c->prev_n == n) {
+        c->prev_n == n && c->refitted) {
         // previous call's |a| (input order) gathered into key order
         CK(launch_gather_scale(ptr<double>(c->prev_scale), c->perm, n, scale, s));
         done = true;
@@ -460,7 +482,7 @@ void sink_scale(fmm_ctx *c, bool want_f) {
 
 // ------------------------------------------------------------ the call
 void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double G, int p,
-            double eps, double *pot, double *acc, int K, const int64_t *off) {
+            double eps, double *pot, double *acc, int K, const int64_t *off, bool refit) {
     hipStream_t s = c->stream;
     c->st = fmm_stats_t{};
     c->n = n;
@@ -470,7 +492,7 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
     c->t_m2l_kernel = c->t_p2p_kernel = 0;
     ensure<int>(c->nonfinite, 4);
     mark(c, PH_START);
-    build_tree(c, n, pos, mass, K, off);
+    build_tree(c, n, pos, mass, K, off, refit);
     mark(c, PH_TREE);
     TreeArrays t = tree_arrays(c);
     const bool want_f = c->opts.mac == FMM_MAC_SCALED;
@@ -548,6 +570,7 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
     CK(hipMemcpyAsync(c->hint, nonfinite, sizeof(int), hipMemcpyDeviceToHost, s));
     sync(c);
     c->st.n_cells = c->ncells;
+    c->st.refitted = c->refitted ? 1 : 0;
     c->st.n_leaves = c->nleaves;
     c->st.depth = c->depth;
     if (c->opts.timing) {
@@ -733,7 +756,7 @@ fmm_status fmm_forces(fmm_ctx *c, int64_t n, const double *pos, const double *ma
             return FMM_OK;
         }
         const int64_t off[2] = {0, n};
-        fmm::forces(c, n, pos, mass, G, p, target_err, pot, acc, 1, off);
+        fmm::forces(c, n, pos, mass, G, p, target_err, pot, acc, 1, off, false);
         if (c->hint[0]) return fmm::fail(c, FMM_E_NONFINITE, "non-finite potential or acceleration");
         return FMM_OK;
     });
@@ -757,7 +780,30 @@ fmm_status fmm_forces_batched(fmm_ctx *c, int64_t k, const int64_t *off, const d
     if (st != FMM_OK) return st;
     return fmm::guarded(c, [&]() -> fmm_status {
         if (n == 0) return FMM_OK;
-        fmm::forces(c, n, pos, mass, G, p, target_err, pot, acc, (int)k, off);
+        fmm::forces(c, n, pos, mass, G, p, target_err, pot, acc, (int)k, off, false);
+        if (c->hint[0]) return fmm::fail(c, FMM_E_NONFINITE, "non-finite potential or acceleration");
+        return FMM_OK;
+    });
+}
+
+fmm_status fmm_forces_refit(fmm_ctx *c, int64_t n, const double *pos, const double *mass,
+                            double G, int p, double target_err, double *pot, double *acc) {
+    if (!c) return FMM_E_INVAL;
+    fmm::Guard g(c);
+    if (!g.ok) return FMM_E_BUSY;
+    c->err.clear();
+    fmm_status st = check_common(c, n, pos, mass, G, &p, target_err, pot, acc);
+    if (st != FMM_OK) return st;
+    return fmm::guarded(c, [&]() -> fmm_status {
+        if (n == 0) return FMM_OK;
+        if (n == 1) {
+            CK(hipMemsetAsync(pot, 0, sizeof(double), c->stream));
+            CK(hipMemsetAsync(acc, 0, 3 * sizeof(double), c->stream));
+            fmm::sync(c);
+            return FMM_OK;
+        }
+        const int64_t off[2] = {0, n};
+        fmm::forces(c, n, pos, mass, G, p, target_err, pot, acc, 1, off, true);
         if (c->hint[0]) return fmm::fail(c, FMM_E_NONFINITE, "non-finite potential or acceleration");
         return FMM_OK;
     });

@@ -35,8 +35,9 @@ STATUS_NAMES = {OK: "FMM_OK", E_INVAL: "FMM_E_INVAL", E_NOMEM: "FMM_E_NOMEM", E_
                 E_NONFINITE: "FMM_E_NONFINITE", E_UNSUPPORTED: "FMM_E_UNSUPPORTED",
                 E_BUSY: "FMM_E_BUSY"}
 
-SYMBOLS = ["fmm_build", "fmm_forces", "fmm_forces_batched", "fmm_direct", "fmm_order_for_error",
-           "fmm_stats", "fmm_footprint_bytes", "fmm_last_error", "fmm_destroy", "fmm_export"]
+SYMBOLS = ["fmm_build", "fmm_forces", "fmm_forces_batched", "fmm_forces_refit", "fmm_direct",
+           "fmm_order_for_error", "fmm_stats", "fmm_footprint_bytes", "fmm_last_error",
+           "fmm_destroy", "fmm_export"]
 
 
 class Opts(C.Structure):
@@ -57,7 +58,8 @@ class Stats(C.Structure):
                 ("t_m2l_kernel", C.c_double), ("t_p2p_kernel", C.c_double),
                 ("m2l_launches", C.c_int), ("p2p_launches", C.c_int),
                 ("walk_pairs", C.c_int64), ("est_walk_pairs", C.c_int64),
-                ("t_sweeps", C.c_double), ("t_est_sweeps", C.c_double)]
+                ("t_sweeps", C.c_double), ("t_est_sweeps", C.c_double),
+                ("refitted", C.c_int)]
 
 
 _P = C.c_void_p
@@ -68,6 +70,9 @@ _lib.fmm_forces.restype = C.c_int
 _lib.fmm_forces_batched.argtypes = [_P, C.c_int64, _P, _P, _P, C.c_double, C.c_int, C.c_double,
                                     _P, _P]
 _lib.fmm_forces_batched.restype = C.c_int
+_lib.fmm_forces_refit.argtypes = [_P, C.c_int64, _P, _P, C.c_double, C.c_int, C.c_double, _P,
+                                  _P]
+_lib.fmm_forces_refit.restype = C.c_int
 _lib.fmm_direct.argtypes = [_P, C.c_int64, _P, _P, C.c_double, _P, _P]
 _lib.fmm_direct.restype = C.c_int
 _lib.fmm_order_for_error.argtypes = [C.c_double]
@@ -152,14 +157,16 @@ class Context:
 
     def forces(self, pos: torch.Tensor, mass: torch.Tensor, G: float = 1.0, p: int = -1,
                target_err: float = 1e-7, pot: torch.Tensor | None = None,
-               acc: torch.Tensor | None = None):
-        """Potential (physical, negative) and acceleration of every particle."""
+               acc: torch.Tensor | None = None, refit: bool = False):
+        """Potential (physical, negative) and acceleration of every particle.
+        refit=True recycles the context's tree when n is unchanged."""
         n = pos.shape[0]
         if pot is None:
             pot = torch.empty(n, dtype=torch.float64, device=pos.device)
         if acc is None:
             acc = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
-        self._check(_lib.fmm_forces(self._h, n, _dev_ptr(pos, "pos", (n, 3)),
+        fn = _lib.fmm_forces_refit if refit else _lib.fmm_forces
+        self._check(fn(self._h, n, _dev_ptr(pos, "pos", (n, 3)),
                                     _dev_ptr(mass, "mass", (n,)), float(G), int(p),
                                     float(target_err), _dev_ptr(pot, "pot", (n,)),
                                     _dev_ptr(acc, "acc", (n, 3))))
