@@ -15,6 +15,12 @@ Prints ONE JSON line (rank 0): metric, value, ... plus
   roofline      for the dominant kernel (algorithmic FLOP per launch / the
                 launch's HIP-event duration on the library's stream)
   cpu_baseline  the CPU oracle (direct sum) on a bounded sample of sinks
+  batched       512 independent Plummer clusters, N log-uniform in [1e3, 1e5],
+                in one call, against the same clusters one call each
+  served        a Poisson stream of requests (N log-uniform in [1e4, 4e6],
+                mixed profiles and error targets, 10 drift steps each with the
+                tree recycled) through the serving loop: p50/p99 latency and
+                throughput at an offered load of 0.8
 """
 from __future__ import annotations
 
@@ -41,6 +47,161 @@ def m2l_flops(p: int) -> float:
 P2P_FLOPS = 20.0   # per ordered particle pair: 3 sub, 5 for r^2, rsqrt, 3 mul, 3 fma, 1 add (+ rsqrt)
 
 
+def _rel_err(a, a_true):
+    import torch
+    d = torch.linalg.norm(a - a_true, dim=1) / torch.linalg.norm(a_true, dim=1)
+    return d.cpu().numpy()
+
+
+def _pct(e, q):
+    e = np.sort(e)
+    return float(e[min(max(int(np.ceil(q / 100.0 * e.size)) - 1, 0), e.size - 1)])
+
+
+def batched_leg(args, fmm, workloads):
+    """K independent Plummer clusters (total mass 1, scale radius 1 each,
+    equal masses) with N log-uniform in [1e3, 1e5], evaluated in one call;
+    errors against the GPU direct sum on every 16th cluster; the same
+    clusters one call each for comparison."""
+    import torch
+    k = args.batched_clusters
+    sizes = workloads.log_uniform_sizes(k, args.seed + 77, 1e3, 1e5)
+    pos = np.vstack([workloads.cluster("plummer", int(m), args.seed + 100 + i)[0]
+                     for i, m in enumerate(sizes)])
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    ntot = int(off[-1])
+    mass = np.concatenate([np.full(int(m), 1.0 / m) for m in sizes])
+    dev = torch.device("cuda:0")
+    P = torch.from_numpy(pos).to(dev)
+    M = torch.from_numpy(mass).to(dev)
+    pot = torch.empty(ntot, dtype=torch.float64, device=dev)
+    acc = torch.empty((ntot, 3), dtype=torch.float64, device=dev)
+    eps = args.eps if args.eps is not None else 5e-8
+    ctx = fmm.Context(device=0, leaf_size=args.leaf, p2p_factor=args.p2p_factor, timing=True)
+    ctx.forces_batched(off, P, M, 1.0, args.p, eps, pot, acc)
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.forces_batched(off, P, M, 1.0, args.p, eps, pot, acc)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    st = ctx.stats()
+    print(f"batched: {k} clusters, {ntot} particles, {1e3 * t_batch:.1f} ms", file=sys.stderr,
+          flush=True)
+    errs = []
+    for i in range(0, k, 16):
+        a, b = int(off[i]), int(off[i + 1])
+        _, ad = ctx.direct(P[a:b].contiguous(), M[a:b].contiguous(), 1.0)
+        errs.append(_rel_err(acc[a:b], ad))
+    e = np.concatenate(errs)
+    # one call per cluster (after one warm pass that sizes the workspace)
+    single = fmm.Context(device=0, leaf_size=args.leaf, p2p_factor=args.p2p_factor)
+    for i in range(k):
+        a, b = int(off[i]), int(off[i + 1])
+        single.forces(P[a:b], M[a:b], 1.0, args.p, eps, pot[a:b], acc[a:b])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(k):
+        a, b = int(off[i]), int(off[i + 1])
+        single.forces(P[a:b], M[a:b], 1.0, args.p, eps, pot[a:b], acc[a:b])
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    ctx.close()
+    single.close()
+    return {"workload": f"{k} Plummer clusters, N log-uniform in [1e3, 1e5] (seed "
+                        f"{args.seed + 77}), {ntot} particles, FP64, eps={eps:g}, p={st['p']}",
+            "value": ntot / t_batch, "unit": "particle-forces/s", "ms_per_call": 1e3 * t_batch,
+            "one_call_per_cluster": {"value": ntot / t_single, "ms": 1e3 * t_single},
+            "errors_vs_gpu_direct": {"clusters_checked": len(errs), "sinks": int(e.size),
+                                     "rms": float(np.sqrt(np.mean(e ** 2))),
+                                     "p99.9": _pct(e, 99.9), "max": float(e.max())},
+            "phases_ms": {k_: st[k_] for k_ in ("t_tree", "t_estimate", "t_up", "t_walk",
+                                                "t_m2l", "t_down", "t_p2p", "t_total")}}
+
+
+SERVE_KINDS = ("plummer", "dehnen0", "dehnen1", "dehnen1.5", "uniform")
+
+
+def serve_leg(args, fmm, workloads, capacity_pfs):
+    """Poisson arrivals at an offered load of args.serve_load times the
+    single-request throughput measured above; every request takes 10 force
+    evaluations with drift steps x += v dt (dt = 1e-3) in between, the tree
+    recycled and the previous step's |a| as the sink scale."""
+    import torch
+    from paper_1405_2255_amd import serve
+    rng = np.random.default_rng(args.seed + 2000)
+    r = args.serve_requests
+    steps = 10
+    sizes = workloads.log_uniform_sizes(r, args.seed + 2001, 1e4, args.serve_nmax)
+    kinds = [SERVE_KINDS[i] for i in rng.integers(0, len(SERVE_KINDS), r)]
+    errs = rng.choice([1e-5, 1e-6, 1e-7], r)
+    dev = torch.device("cuda:0")
+    inputs = []
+    for i in range(r):
+        pos, m = workloads.cluster(kinds[i], int(sizes[i]), args.seed + 3000 + i)
+        vel = workloads.drift_velocities(kinds[i], pos, args.seed + 4000 + i)
+        inputs.append(tuple(torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+                            for x in (pos, m, vel)))
+
+    def make(i, steps=steps):
+        pos, m, vel = inputs[i]
+        # epsilon = half the requested rms error (the calibration of the
+        # N = 1e6 Plummer run), p from the library's table
+        return serve.Request(pos=pos, mass=m, target_err=0.5 * float(errs[i]), steps=steps,
+                             vel=vel, dt=1e-3)
+
+    srv = serve.Server(device=0, slots=args.serve_slots)
+    # warm every slot's workspace with the largest request
+    big = int(np.argmax(sizes))
+    warm = [srv.submit(make(big, 1)) for _ in range(args.serve_slots)]
+    for w in warm:
+        w.result(600)
+    mean_service = float(np.mean(sizes)) * steps / capacity_pfs
+    gaps = rng.exponential(mean_service / args.serve_load, r)
+    reqs = []
+    t0 = time.perf_counter()
+    t_next = t0
+    for i in range(r):
+        t_next += gaps[i]
+        dt = t_next - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        reqs.append(srv.submit(make(i)))
+    for q in reqs:
+        q.result(600)
+    t_all = max(q.t_end for q in reqs) - t0
+    srv.close()
+    lat = serve.latency_summary(reqs)
+    print(f"served {r} requests in {t_all:.2f} s: {lat}", file=sys.stderr, flush=True)
+    # accuracy of the last step of every request with N <= 3e5 against the GPU
+    # direct sum on the same drifted positions
+    checks = []
+    ctx = fmm.Context(device=0)
+    for i, q in enumerate(reqs):
+        if sizes[i] > 300_000:
+            continue
+        pos, m, vel = inputs[i]
+        x = pos.clone()
+        for _ in range(steps - 1):
+            x.add_(vel, alpha=1e-3)
+        _, ad = ctx.direct(x, m, 1.0)
+        e = _rel_err(q.acc, ad)
+        checks.append({"n": int(sizes[i]), "kind": kinds[i], "target_rms": float(errs[i]),
+                       "rms": float(np.sqrt(np.mean(e ** 2))), "p99.9": _pct(e, 99.9)})
+    ctx.close()
+    work = float(np.sum(sizes)) * steps
+    return {"workload": f"{r} requests, Poisson arrivals at offered load {args.serve_load} "
+                        f"of the single-request throughput, N log-uniform in [1e4, "
+                        f"{args.serve_nmax:g}], profiles {'/'.join(SERVE_KINDS)}, rms targets "
+                        f"1e-5/1e-6/1e-7, {steps} evaluations per request with drift "
+                        f"(dt=1e-3) and tree recycling, {args.serve_slots} slots",
+            "latency": lat, "value": work / t_all, "unit": "particle-forces/s",
+            "seconds": t_all, "mean_service_s_estimate": mean_service,
+            "accuracy_last_step": checks,
+            "all_within_target": bool(all(c["rms"] <= c["target_rms"] for c in checks))}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -57,6 +218,13 @@ def main() -> int:
                     help="sinks checked against the CPU oracle (also the CPU-baseline sample)")
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--no-cpu", action="store_true", help="omit the CPU baseline field")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--batched-clusters", type=int, default=512)
+    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-nmax", type=float, default=4e6)
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-load", type=float, default=0.8)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -149,11 +317,15 @@ def main() -> int:
                          f"against all {n} sources (FP64 Neumaier-compensated direct sum)",
                "seconds": t_cpu}
 
+    value = n / (ms_per_step * 1e-3)
+    batched = None if args.no_batched else batched_leg(args, fmm, workloads)
+    served = None if args.no_serve else serve_leg(args, fmm, workloads, value)
+
     phases = {k: st[k] for k in ("t_tree", "t_estimate", "t_up", "t_walk", "t_m2l", "t_down",
                                  "t_p2p", "t_total")}
     out = {
         "metric": "particle-forces/s at rms rel. force err 1e-7 vs plain FMM & direct sum; p99 lat",
-        "value": n / (ms_per_step * 1e-3),
+        "value": value,
         "unit": "particle-forces/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -175,6 +347,8 @@ def main() -> int:
         "direct": direct,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched": batched,
+        "served": served,
         "phases_ms": phases,
         "counts": {k: st[k] for k in ("n_cells", "n_leaves", "depth", "n_m2l", "n_p2p_lists",
                                       "n_p2p_pairs", "n_est_m2l", "n_est_p2p_pairs",

@@ -5,7 +5,13 @@
  *                n_L particles is split into its non-empty octants.  Octants
  *                come from 21-bit-per-axis quantised coordinates inside the
  *                cube around the bounding box (the tree's definition, shared
- *                with the GPU path by specification, not by code).
+ *                with the GPU path by specification, not by code).  A cell
+ *                at level 21 that still holds more than n_L particles (a
+ *                dense cusp inside a very wide halo) is refined further with
+ *                the next 21 bits of the same quantisation: its particles
+ *                are re-sorted by those bits (ties by input index) and the
+ *                split continues down to level 42, where leaves may be
+ *                overfull.  The paper's tree has no depth limit.
  *   2. estimate: low-order FMM for the sink scale (Sec. 5.4.2): centres
  *                z = s = z_com, acceptance theta < 1 with radii about z_com,
  *                p = 1 for the acceleration a_b (criterion a) or the p = 0
@@ -34,7 +40,8 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define MAXLEVEL 21
+#define KEYLEVELS 21              /* levels resolved by one 63-bit key */
+#define MAXLEVEL (2 * KEYLEVELS)  /* levels 22..42 use the second key word */
 
 typedef struct {
     int64_t begin, end;
@@ -58,7 +65,9 @@ typedef struct {
     double *x;      /* 3n */
     double *m;
     int64_t *orig;  /* Morton position -> input index */
-    uint64_t *key;
+    uint64_t *key;  /* levels 1..21 */
+    uint64_t *key2; /* levels 22..42 (only inside overfull level-21 cells) */
+    double lo[3], kscale;     /* key cube: lower corner, 2^21 / side */
     cell_t *cells; int64_t ncells, cap;
     /* accumulators, Morton order */
     double *pot, *acc;      /* near + far */
@@ -83,7 +92,7 @@ static int cmp_keyidx(const void *a, const void *b) {
 /* bit i of the x, y, z cell index goes to key bit 3i, 3i+1, 3i+2 */
 static uint64_t morton(uint32_t qx, uint32_t qy, uint32_t qz) {
     uint64_t k = 0;
-    for (int i = 0; i < MAXLEVEL; ++i) {
+    for (int i = 0; i < KEYLEVELS; ++i) {
         k |= (uint64_t)((qx >> i) & 1u) << (3 * i);
         k |= (uint64_t)((qy >> i) & 1u) << (3 * i + 1);
         k |= (uint64_t)((qz >> i) & 1u) << (3 * i + 2);
@@ -102,17 +111,58 @@ static int64_t new_cell(fmm_t *t) {
     return t->ncells++;
 }
 
+/* The second key word of particle i (Morton order): bits 22..42 of the
+ * quantised coordinates, u * 2^21 with u the same product as for the first
+ * word (so both words describe one 42-bit cell index per axis). */
+static uint64_t deep_key(const fmm_t *t, int64_t i) {
+    uint32_t q[3];
+    for (int d = 0; d < 3; ++d) {
+        const double u = (t->x[3 * i + d] - t->lo[d]) * t->kscale;
+        const double u42 = u * 2097152.0;
+        const uint64_t v = u42 >= 4398046511103.0 ? 4398046511103ull : (uint64_t)u42;
+        q[d] = (uint32_t)(v & 2097151u);
+    }
+    return morton(q[0], q[1], q[2]);
+}
+
+/* sort particles [b, e) by (second key word, input index); the range is one
+ * level-21 cell, whose particles are in input-index order */
+static int refine(fmm_t *t, int64_t b, int64_t e) {
+    const int64_t k = e - b;
+    keyidx *ki = (keyidx *)malloc(sizeof(keyidx) * (size_t)k);
+    double *x = (double *)malloc(sizeof(double) * 3 * (size_t)k);
+    double *m = (double *)malloc(sizeof(double) * (size_t)k);
+    int64_t *o = (int64_t *)malloc(sizeof(int64_t) * (size_t)k);
+    if (!ki || !x || !m || !o) { free(ki); free(x); free(m); free(o); return -1; }
+    for (int64_t i = 0; i < k; ++i) { ki[i].key = deep_key(t, b + i); ki[i].idx = i; }
+    qsort(ki, (size_t)k, sizeof(keyidx), cmp_keyidx);
+    memcpy(x, t->x + 3 * b, sizeof(double) * 3 * (size_t)k);
+    memcpy(m, t->m + b, sizeof(double) * (size_t)k);
+    memcpy(o, t->orig + b, sizeof(int64_t) * (size_t)k);
+    for (int64_t i = 0; i < k; ++i) {
+        const int64_t j = ki[i].idx;
+        t->orig[b + i] = o[j];
+        t->m[b + i] = m[j];
+        for (int d = 0; d < 3; ++d) t->x[3 * (b + i) + d] = x[3 * j + d];
+        t->key2[b + i] = ki[i].key;
+    }
+    free(ki); free(x); free(m); free(o);
+    return 0;
+}
+
 static int64_t build(fmm_t *t, int64_t b, int64_t e, int level, int64_t parent) {
     const int64_t id = new_cell(t);
     if (id < 0) return -1;
     cell_t *C = &t->cells[id];
     C->begin = b; C->end = e; C->level = level; C->parent = parent;
     if (e - b > t->prm->leaf_size && level < MAXLEVEL) {
-        const int shift = 3 * (MAXLEVEL - (level + 1));
+        if (level == KEYLEVELS && refine(t, b, e) < 0) { t->oom = 1; return -1; }
+        const uint64_t *key = level < KEYLEVELS ? t->key : t->key2;
+        const int shift = 3 * ((level < KEYLEVELS ? KEYLEVELS : MAXLEVEL) - (level + 1));
         int64_t s = b;
         for (int oct = 0; oct < 8; ++oct) {
             int64_t q = s;
-            while (q < e && (int)((t->key[q] >> shift) & 7u) == oct) ++q;
+            while (q < e && (int)((key[q] >> shift) & 7u) == oct) ++q;
             if (q > s) {
                 const int64_t ch = build(t, s, q, level + 1, id);
                 if (ch < 0) return -1;
@@ -374,7 +424,7 @@ static void release(fmm_t *t) {
     for (int64_t i = 0; i < t->ncells; ++i) {
         free(t->cells[i].M); free(t->cells[i].F); free(t->cells[i].P);
     }
-    free(t->cells); free(t->x); free(t->m); free(t->orig); free(t->key);
+    free(t->cells); free(t->x); free(t->m); free(t->orig); free(t->key); free(t->key2);
     free(t->pot); free(t->acc); free(t->est_acc); free(t->est_f); free(t->scale);
 }
 
@@ -401,17 +451,20 @@ int or_fmm(const or_fmm_params *prm, int64_t n, const double *pos,
     double L = 0;
     for (int d = 0; d < 3; ++d) L = fmax(L, hi[d] - lo[d]);
     const double scale = L > 0 ? 2097152.0 / L : 0.0;   /* 2^21 cells per axis */
+    for (int d = 0; d < 3; ++d) t->lo[d] = lo[d];
+    t->kscale = scale;
     keyidx *ki = (keyidx *)malloc(sizeof(keyidx) * (size_t)n);
     t->x = (double *)malloc(sizeof(double) * 3 * (size_t)n);
     t->m = (double *)malloc(sizeof(double) * (size_t)n);
     t->orig = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
     t->key = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+    t->key2 = (uint64_t *)calloc((size_t)n, sizeof(uint64_t));
     t->pot = (double *)calloc((size_t)n, sizeof(double));
     t->acc = (double *)calloc(3 * (size_t)n, sizeof(double));
     t->est_acc = (double *)calloc(3 * (size_t)n, sizeof(double));
     t->est_f = (double *)calloc((size_t)n, sizeof(double));
     t->scale = (double *)malloc(sizeof(double) * (size_t)n);
-    if (!ki || !t->x || !t->m || !t->orig || !t->key || !t->pot || !t->acc || !t->est_acc ||
+    if (!ki || !t->x || !t->m || !t->orig || !t->key || !t->key2 || !t->pot || !t->acc || !t->est_acc ||
         !t->est_f || !t->scale) { free(ki); release(t); return -2; }
     for (int64_t i = 0; i < n; ++i) {
         uint32_t q[3];

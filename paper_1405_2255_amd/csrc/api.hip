@@ -106,6 +106,10 @@ hipError_t launch_norm3(const double *acc, int64_t n, double G, double *out, hip
 
 using namespace fmm;
 
+// entries of the pinned host mirror of the walk counters: 4 totals plus one
+// frontier size per sweep (at most 2 * FMM_MAXLEVEL + 4 sweeps)
+constexpr int HCNT = 128;
+
 struct fmm_ctx {
     fmm_opts opts{};
     hipStream_t stream = nullptr;
@@ -125,13 +129,16 @@ struct fmm_ctx {
     DevBuf rflag, ranges, rkey;
     DevBuf pt_n, pt_m, pt_s, pt_off, pt_moff, ptasks, ppart;
     DevBuf counters, nonfinite, walktmp, coffsets, roots, ckey, ckey2, order, order2;
+    DevBuf dkey, dsort, dsort2, runstart;   // deep refinement below level 21
+    uint64_t *kdeep = nullptr;            // second key word of the sorted particles
+    bool deep = false;
     void *pin = nullptr;      // pinned staging for host-to-device copies
     size_t pin_cap = 0;
     int nroots = 0;
     bool tree_valid = false, refitted = false;
     int64_t tree_n = -1;
     std::vector<int64_t> tree_off;
-    unsigned long long *hcnt = nullptr;  // pinned host mirror of the counters
+    unsigned long long *hcnt = nullptr;  // pinned host mirror of the counters (HCNT entries)
     int *hint = nullptr;                 // pinned host ints
     // last call
     int64_t n = 0;
@@ -243,6 +250,32 @@ void build_tree(fmm_ctx *c, int64_t n, const double *pos, const double *mass, in
         std::swap(k1, k2);
         std::swap(i1, i2);
     }
+    // level-21 cells with more than `leaf` particles get a second key word;
+    // each such run is re-sorted by (second word, position)
+    uint64_t *kd = ensure<uint64_t>(c->dkey, n);
+    {
+        uint64_t *rs = ensure<uint64_t>(c->runstart, n);
+        uint64_t *sa = ensure<uint64_t>(c->dsort, n), *sb = ensure<uint64_t>(c->dsort2, n);
+        uint32_t *o1 = ensure<uint32_t>(c->order, n), *o2 = ensure<uint32_t>(c->order2, n);
+        int *any = ptr<int>(c->nonfinite) + 4;
+        CK(hipMemsetAsync(any, 0, sizeof(int), s));
+        CK(launch_deep_keys(pos, i1, k1, n, K, doff, bb, leaf, kd, rs, o1, any, s));
+        CK(hipMemcpyAsync(c->hint, any, sizeof(int), hipMemcpyDeviceToHost, s));
+        sync(c);
+        c->deep = c->hint[0] != 0;
+        if (c->deep) {
+            CK(hipMemcpyAsync(sa, kd, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
+            CK(radix_sort(&sa, &sb, &o1, &o2, n, 63, tmp, s));          // by (second word, position)
+            CK(launch_gather_u64(o1, rs, n, sb, s));                     // run of each
+            CK(radix_sort(&sb, &sa, &o1, &o2, n, std::max(1, bitlen((uint64_t)n)), tmp, s));
+            // sa is free now: it receives the second words in the final order
+            CK(launch_apply_order2(o1, k1, kd, i1, n, k2, sa, i2, s));
+            std::swap(k1, k2);
+            std::swap(i1, i2);
+            kd = sa;
+        }
+    }
+    c->kdeep = kd;
     c->perm = i1;
     CK(launch_gather(pos, mass, c->perm, n, x, y, z, m, xyzm, s));
     // octree, level by level, from one root per cluster
@@ -255,7 +288,7 @@ void build_tree(fmm_ctx *c, int64_t n, const double *pos, const double *mass, in
         const int c0 = c->ls[L], c1 = c->ls[L + 1];
         if (c1 == c0) break;
         t = tree_arrays(c);
-        CK(launch_count_children(k1, t, c0, c1, L, leaf, nch, s));
+        CK(launch_count_children(k1, kd, t, c0, c1, L, leaf, nch, s));
         CK(hipMemsetAsync(nch + (c1 - c0), 0, sizeof(int), s));
         int *total = ptr<int>(c->nonfinite) + 1;
         CK(exclusive_scan(nch, nch, (c1 - c0) + 1, tmp, total, s));
@@ -264,7 +297,7 @@ void build_tree(fmm_ctx *c, int64_t n, const double *pos, const double *mass, in
         const int add = c->hint[0];
         grow_cells(c, c1 + add, c1);
         t = tree_arrays(c);
-        CK(launch_make_children(k1, t, c0, c1, L, nch, c1, s));
+        CK(launch_make_children(k1, kd, t, c0, c1, L, nch, c1, s));
         c->ls.push_back(c1 + add);
     }
     const int ncells = c->ls.back();
@@ -317,6 +350,7 @@ struct Lists {
 };
 
 Lists walk(fmm_ctx *c, const WalkParams &wp0, const double *P) {
+    static_assert(4 + 2 * FMM_MAXLEVEL + 4 <= HCNT, "counter mirror too small for the deepest tree");
     hipStream_t s = c->stream;
     WalkParams wp = wp0;
     wp.nroots = c->nroots;
@@ -490,7 +524,7 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
     c->st.p = p;
     c->st.n = n;
     c->t_m2l_kernel = c->t_p2p_kernel = 0;
-    ensure<int>(c->nonfinite, 4);
+    ensure<int>(c->nonfinite, 8);
     mark(c, PH_START);
     build_tree(c, n, pos, mass, K, off, refit);
     mark(c, PH_TREE);
@@ -674,7 +708,7 @@ fmm_status fmm_build(fmm_ctx **out, const fmm_opts *o) {
             CK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
             c->own_stream = true;
         }
-        CK(hipHostMalloc((void **)&c->hcnt, 64 * sizeof(unsigned long long), hipHostMallocDefault));
+        CK(hipHostMalloc((void **)&c->hcnt, HCNT * sizeof(unsigned long long), hipHostMallocDefault));
         CK(hipHostMalloc((void **)&c->hint, 16 * sizeof(int), hipHostMallocDefault));
         for (auto &e : c->ev) CK(hipEventCreate(&e));
         for (auto &e : c->ev_m2l) CK(hipEventCreate(&e));
@@ -837,7 +871,7 @@ size_t fmm_footprint_bytes(int64_t n, int p, const fmm_opts *o) {
     const int leaf = (o && o->leaf_size > 0) ? o->leaf_size : 32;
     const double cells = 1.5 * (double)n / (0.3 * leaf) + 64;
     const double nc = 16.0 * (p + 1) * (p + 2) / 2.0;
-    const double per_particle = 8 * 2 + 4 * 2 + 8 * 4 + 32 + 4 + 32 * 2 + 8 * 2 + 4 + 16;
+    const double per_particle = 8 * 2 + 4 * 2 + 8 * 4 + 32 + 4 + 32 * 2 + 8 * 2 + 4 + 16 + 8 * 4;
     const double per_cell = 3 * nc + 8 * (p + 1) + 4 * 10 + 32 * 2 + 8 * 9 + 16 + 16;
     const double lists = 8.0 * 2 * (150.0 * cells) + 8.0 * 2 * (200.0 * cells) + 8.0 * 2 * n;
     const double part = nc * (150.0 * cells / 16 + cells);

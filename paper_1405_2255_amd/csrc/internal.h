@@ -6,7 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#define FMM_MAXLEVEL 21
+#define FMM_KEYLEVELS 21                  // levels resolved by one 63-bit key
+#define FMM_MAXLEVEL (2 * FMM_KEYLEVELS)  // levels 22..42 use the second key word
 #define FMM_PMAX 20
 
 namespace fmm {
@@ -46,15 +47,33 @@ hipError_t launch_cluster_keys(const uint32_t *idx, int64_t n, int K, const int6
                                uint64_t *ckey, uint32_t *order, hipStream_t s);
 hipError_t launch_apply_order(const uint32_t *order, const uint64_t *key, const uint32_t *idx,
                               int64_t n, uint64_t *key_out, uint32_t *idx_out, hipStream_t s);
+// Second key word (levels 22..42) of sorted position i, for particles whose
+// level-21 cell (a run of equal first keys inside one cluster) holds more
+// than leaf_size particles, else 0; runstart[i] = first position of that run;
+// *any (device int, zeroed by the caller) set to 1 if some run is overfull.
+hipError_t launch_deep_keys(const double *pos, const uint32_t *perm, const uint64_t *key,
+                            int64_t n, int K, const int64_t *off, const unsigned long long *bb,
+                            int leaf_size, uint64_t *key2, uint64_t *runstart, uint32_t *iota,
+                            int *any, hipStream_t s);
+// out[i] = in[order[i]]
+hipError_t launch_gather_u64(const uint32_t *order, const uint64_t *in, int64_t n, uint64_t *out,
+                             hipStream_t s);
+// key_out[i] = key[order[i]], key2_out[i] = key2[order[i]], idx_out[i] = idx[order[i]]
+hipError_t launch_apply_order2(const uint32_t *order, const uint64_t *key, const uint64_t *key2,
+                               const uint32_t *idx, int64_t n, uint64_t *key_out,
+                               uint64_t *key2_out, uint32_t *idx_out, hipStream_t s);
 hipError_t launch_gather(const double *pos, const double *mass, const uint32_t *perm,
                          int64_t n, double *x, double *y, double *z, double *m,
                          double4 *xyzm, hipStream_t s);
 hipError_t launch_init_roots(const TreeArrays &t, int nroots, const int2 *roots, hipStream_t s);
 // children of cells [c0, c1) at one level; *count_out (device) = new cells
-hipError_t launch_count_children(const uint64_t *key, const TreeArrays &t, int c0, int c1,
-                                 int level, int leaf_size, int *nch, hipStream_t s);
-hipError_t launch_make_children(const uint64_t *key, const TreeArrays &t, int c0, int c1,
-                                int level, const int *child_off, int next0, hipStream_t s);
+// key: levels 1..21, key2: levels 22..42 (read only below level 21)
+hipError_t launch_count_children(const uint64_t *key, const uint64_t *key2, const TreeArrays &t,
+                                 int c0, int c1, int level, int leaf_size, int *nch,
+                                 hipStream_t s);
+hipError_t launch_make_children(const uint64_t *key, const uint64_t *key2, const TreeArrays &t,
+                                int c0, int c1, int level, const int *child_off, int next0,
+                                hipStream_t s);
 hipError_t launch_leaf_flags(const TreeArrays &t, int ncells, int *flags, hipStream_t s);
 hipError_t launch_leaf_ranges(const TreeArrays &t, int ncells, const int *leafscan,
                               int *leaf_cell, int *leaf_of, int64_t n, hipStream_t s);

@@ -147,9 +147,88 @@ __global__ void k_gather(const double *pos, const double *mass, const uint32_t *
     xyzm[i] = make_double4(a, b, c, w);
 }
 
+// Deep refinement.  A level-21 cell that holds more than leaf_size particles
+// (a dense cusp inside a very wide halo) is split further by the next 21 bits
+// of the same quantisation, u * 2^21 with u the product of the first word
+// (exact: a power-of-two scale), so both words describe one 42-bit cell index
+// per axis.  Only the particles of such cells get a second word; the sort then
+// orders each overfull run by (second word, position), and positions inside a
+// run follow the input order.
+__global__ void k_deep_keys(const double *pos, const uint32_t *perm, const uint64_t *key,
+                            int64_t n, int K, const int64_t *off, const unsigned long long *bb,
+                            int leaf_size, uint64_t *key2, uint64_t *runstart, uint32_t *iota,
+                            int *any) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    // sorted positions keep the cluster ranges [off[c], off[c+1])
+    const int c = cluster_of(off, K, i);
+    const int64_t c0 = K > 1 ? off[c] : 0, c1 = K > 1 ? off[c + 1] : n;
+    const uint64_t k = key[i];
+    int64_t lo = c0, hi = i;            // first position with key == k
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (key[mid] < k) lo = mid + 1;
+        else hi = mid;
+    }
+    const int64_t a = lo;
+    lo = i + 1;
+    hi = c1;                            // first position with key > k
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (key[mid] <= k) lo = mid + 1;
+        else hi = mid;
+    }
+    const int64_t b = lo;
+    runstart[i] = (uint64_t)a;
+    iota[i] = (uint32_t)i;
+    uint64_t k2 = 0;
+    if (b - a > leaf_size) {
+        const unsigned long long *box = bb + 6 * c;
+        double l[3], L = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            l[d] = ordered_val(box[d]);
+            L = fmax(L, ordered_val(box[3 + d]) - l[d]);
+        }
+        const double scale = L > 0.0 ? 2097152.0 / L : 0.0;
+        const uint32_t j = perm[i];
+        uint32_t q[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double u = __dmul_rn(pos[3 * (int64_t)j + d] - l[d], scale);
+            const double u42 = u * 2097152.0;
+            const uint64_t v = u42 >= 4398046511103.0 ? 4398046511103ull : (uint64_t)u42;
+            q[d] = (uint32_t)(v & 2097151u);
+        }
+        k2 = spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2);
+        if (i == a) atomicOr(any, 1);
+    }
+    key2[i] = k2;
+}
+
+__global__ void k_gather_u64(const uint32_t *order, const uint64_t *in, int64_t n,
+                             uint64_t *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in[order[i]];
+}
+
+__global__ void k_apply_order2(const uint32_t *order, const uint64_t *key, const uint64_t *key2,
+                               const uint32_t *idx, int64_t n, uint64_t *key_out,
+                               uint64_t *key2_out, uint32_t *idx_out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t j = order[i];
+    key_out[i] = key[j];
+    key2_out[i] = key2[j];
+    idx_out[i] = idx[j];
+}
+
 // boundaries of the 8 octants at `level + 1` inside the cell's key range
-__device__ void octant_bounds(const uint64_t *key, int beg, int end, int level, int b[9]) {
-    const int shift = 3 * (FMM_MAXLEVEL - (level + 1));
+__device__ void octant_bounds(const uint64_t *key1, const uint64_t *key2, int beg, int end,
+                              int level, int b[9]) {
+    const bool deep = level >= FMM_KEYLEVELS;
+    const uint64_t *key = deep ? key2 : key1;
+    const int shift = 3 * ((deep ? FMM_MAXLEVEL : FMM_KEYLEVELS) - (level + 1));
     b[0] = beg;
     b[8] = end;
 #pragma unroll
@@ -164,15 +243,15 @@ __device__ void octant_bounds(const uint64_t *key, int beg, int end, int level, 
     }
 }
 
-__global__ void k_count_children(const uint64_t *key, TreeArrays t, int c0, int c1, int level,
-                                 int leaf_size, int *nch) {
+__global__ void k_count_children(const uint64_t *key, const uint64_t *key2, TreeArrays t, int c0,
+                                 int c1, int level, int leaf_size, int *nch) {
     const int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= c1) return;
     const int beg = t.beg[c], end = t.end[c];
     int k = 0;
     if (end - beg > leaf_size && level < FMM_MAXLEVEL) {
         int b[9];
-        octant_bounds(key, beg, end, level, b);
+        octant_bounds(key, key2, beg, end, level, b);
 #pragma unroll
         for (int o = 0; o < 8; ++o) k += b[o + 1] > b[o];
     }
@@ -180,8 +259,8 @@ __global__ void k_count_children(const uint64_t *key, TreeArrays t, int c0, int 
     t.nchild[c] = k;
 }
 
-__global__ void k_make_children(const uint64_t *key, TreeArrays t, int c0, int c1, int level,
-                                const int *child_off, int next0) {
+__global__ void k_make_children(const uint64_t *key, const uint64_t *key2, TreeArrays t, int c0,
+                                int c1, int level, const int *child_off, int next0) {
     const int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= c1) return;
     if (t.nchild[c] == 0) {
@@ -191,7 +270,7 @@ __global__ void k_make_children(const uint64_t *key, TreeArrays t, int c0, int c
     const int first = next0 + child_off[c - c0];
     t.child0[c] = first;
     int b[9];
-    octant_bounds(key, t.beg[c], t.end[c], level, b);
+    octant_bounds(key, key2, t.beg[c], t.end[c], level, b);
     int k = first;
 #pragma unroll
     for (int o = 0; o < 8; ++o) {
@@ -445,19 +524,47 @@ hipError_t launch_init_roots(const TreeArrays &t, int nroots, const int2 *roots,
     return hipGetLastError();
 }
 
-hipError_t launch_count_children(const uint64_t *key, const TreeArrays &t, int c0, int c1,
-                                 int level, int leaf_size, int *nch, hipStream_t s) {
+hipError_t launch_count_children(const uint64_t *key, const uint64_t *key2, const TreeArrays &t,
+                                 int c0, int c1, int level, int leaf_size, int *nch,
+                                 hipStream_t s) {
     if (c1 <= c0) return hipSuccess;
-    hipLaunchKernelGGL(k_count_children, dim3(blocks(c1 - c0, 256)), dim3(256), 0, s, key, t, c0,
-                       c1, level, leaf_size, nch);
+    hipLaunchKernelGGL(k_count_children, dim3(blocks(c1 - c0, 256)), dim3(256), 0, s, key, key2,
+                       t, c0, c1, level, leaf_size, nch);
     return hipGetLastError();
 }
 
-hipError_t launch_make_children(const uint64_t *key, const TreeArrays &t, int c0, int c1,
-                                int level, const int *child_off, int next0, hipStream_t s) {
+hipError_t launch_make_children(const uint64_t *key, const uint64_t *key2, const TreeArrays &t,
+                                int c0, int c1, int level, const int *child_off, int next0,
+                                hipStream_t s) {
     if (c1 <= c0) return hipSuccess;
-    hipLaunchKernelGGL(k_make_children, dim3(blocks(c1 - c0, 256)), dim3(256), 0, s, key, t, c0,
-                       c1, level, child_off, next0);
+    hipLaunchKernelGGL(k_make_children, dim3(blocks(c1 - c0, 256)), dim3(256), 0, s, key, key2,
+                       t, c0, c1, level, child_off, next0);
+    return hipGetLastError();
+}
+
+hipError_t launch_deep_keys(const double *pos, const uint32_t *perm, const uint64_t *key,
+                            int64_t n, int K, const int64_t *off, const unsigned long long *bb,
+                            int leaf_size, uint64_t *key2, uint64_t *runstart, uint32_t *iota,
+                            int *any, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_deep_keys, dim3(blocks(n, 256)), dim3(256), 0, s, pos, perm, key, n, K,
+                       off, bb, leaf_size, key2, runstart, iota, any);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_u64(const uint32_t *order, const uint64_t *in, int64_t n, uint64_t *out,
+                             hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_u64, dim3(blocks(n, 256)), dim3(256), 0, s, order, in, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_order2(const uint32_t *order, const uint64_t *key, const uint64_t *key2,
+                               const uint32_t *idx, int64_t n, uint64_t *key_out,
+                               uint64_t *key2_out, uint32_t *idx_out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_apply_order2, dim3(blocks(n, 256)), dim3(256), 0, s, order, key, key2,
+                       idx, n, key_out, key2_out, idx_out);
     return hipGetLastError();
 }
 

@@ -21,6 +21,7 @@ __all__ = [
     "salpeter_masses",
     "cluster",
     "log_uniform_sizes",
+    "drift_velocities",
 ]
 
 
@@ -129,3 +130,25 @@ def log_uniform_sizes(k: int, seed: int, lo: float, hi: float) -> np.ndarray:
     """k integers round(10^U(log10 lo, log10 hi))."""
     rng = _rng(seed)
     return np.rint(10.0 ** rng.uniform(np.log10(lo), np.log10(hi), k)).astype(np.int64)
+
+
+def _enclosed_mass(kind: str, r: np.ndarray) -> np.ndarray:
+    if kind == "plummer":
+        return r ** 3 / (r * r + 1.0) ** 1.5
+    if kind.startswith("dehnen"):
+        g = float(kind[len("dehnen"):])
+        return (r / (r + 1.0)) ** (3.0 - g)
+    if kind == "uniform":
+        return np.minimum(r, 1.0) ** 3
+    raise ValueError(f"unknown cluster kind {kind!r}")
+
+
+def drift_velocities(kind: str, pos: np.ndarray, seed: int) -> np.ndarray:
+    """Velocities for drift steps: an isotropic Gaussian whose 1-D dispersion
+    is the local circular speed over sqrt(3), sigma^2 = M(<r) / (3 r) (G = 1,
+    total mass 1).  They only move particles between force evaluations; the
+    force metric does not depend on them."""
+    rng = _rng(seed)
+    r = np.sqrt(np.einsum("ij,ij->i", pos, pos))
+    sig = np.sqrt(_enclosed_mass(kind, r) / (3.0 * np.maximum(r, 1e-300)))
+    return sig[:, None] * rng.standard_normal((pos.shape[0], 3))

@@ -85,3 +85,41 @@ def test_batched_bad_offsets(gpu_lib):
     with pytest.raises(gpu_lib.FMMError) as e:
         ctx.forces_batched([0, 6, 4, 10], P, M)
     assert e.value.status == gpu_lib.E_INVAL
+
+
+def test_batched_deep_and_shallow_clusters_equal_single_calls(gpu_lib):
+    """Clusters that need the second key word (a far outlier squeezes them
+    into a few level-21 cells) next to clusters that do not: each cluster's
+    result is bitwise the single call's, and the deep ones match the oracle."""
+    import torch
+    parts, masses = [], []
+    for i, (n, far) in enumerate([(3000, True), (2500, False), (4000, True), (700, False)]):
+        p, m = W.cluster("plummer", n, 40 + i)
+        if far:
+            p = np.vstack([p, [[-1e7, 5.0, 1.0]]])
+            m = np.append(m, m[0])
+        parts.append(p)
+        masses.append(m)
+    sizes = [len(m) for m in masses]
+    pos, m = np.vstack(parts), np.concatenate(masses)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    P = torch.from_numpy(pos).cuda()
+    M = torch.from_numpy(m).cuda()
+    ctx = gpu_lib.Context(p2p_factor=0.5)
+    pot, acc = ctx.forces_batched(off, P, M, G=1.0, p=8, target_err=1e-7)
+    torch.cuda.synchronize()
+    assert ctx.stats()["depth"] > 21
+    pot, acc = pot.cpu().numpy(), acc.cpu().numpy()
+    single = gpu_lib.Context(p2p_factor=0.5)
+    for k in range(len(sizes)):
+        a, b = off[k], off[k + 1]
+        print(f"cluster {k} n={b - a}", flush=True)
+        ps, as_ = single.forces(P[a:b].contiguous(), M[a:b].contiguous(), G=1.0, p=8,
+                                target_err=1e-7)
+        torch.cuda.synchronize()
+        assert np.array_equal(ps.cpu().numpy(), pot[a:b])
+        assert np.array_equal(as_.cpu().numpy(), acc[a:b])
+        ref = oracle.fmm(pos[a:b], m[a:b], p=8, eps=1e-7, leaf_size=32, p2p_pairs=0.5 * 9 ** 3)
+        assert ref["stats"]["depth"] == single.stats()["depth"]
+        d = np.linalg.norm(acc[a:b] - ref["acc"], axis=1) / np.linalg.norm(ref["acc"], axis=1)
+        assert d.max() < 1e-10

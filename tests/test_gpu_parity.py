@@ -79,9 +79,23 @@ def test_direct_sum_matches_oracle(ctx, n):
     assert _rel(acc.cpu().numpy(), a0).max() < 1e-12
 
 
+def _input(kind, n, masses, seed=5):
+    """W.cluster, or with '+far': n - 1 particles of the profile and one more
+    1e7 away, which squeezes the cluster into a few level-21 cells (the tree
+    then refines them with the second key word)."""
+    if kind.endswith("+far"):
+        pos, m = W.cluster(kind[:-4], n - 1, seed, masses=masses)
+        pos = np.vstack([pos, [[1e7, -3.0, 2.0]]])
+        m = np.append(m, m.mean())
+        return np.ascontiguousarray(pos), np.ascontiguousarray(m)
+    return W.cluster(kind, n, seed, masses=masses)
+
+
 CASES = [
     # (kind, n, masses, p, eps, leaf) - the small paper workload first
     ("plummer", 4096, "equal", 8, 1e-7, 32),
+    ("plummer+far", 6001, "equal", 8, 1e-7, 32),
+    ("dehnen1.5+far", 9001, "salpeter", 6, 1e-6, 16),
     ("plummer", 20011, "equal", 10, 1e-7, 32),
     ("dehnen1.5", 12345, "salpeter", 6, 1e-5, 16),
     ("uniform", 7777, "equal", 12, 1e-8, 24),
@@ -93,7 +107,7 @@ CASES = [
 def test_fmm_matches_oracle_fmm(gpu_lib, kind, n, masses, p, eps, leaf):
     print(f"case {kind} n={n} p={p} eps={eps} leaf={leaf}", flush=True)
     ctx = gpu_lib.Context(leaf_size=leaf, p2p_factor=0.5)
-    pos, m = W.cluster(kind, n, 5, masses=masses)
+    pos, m = _input(kind, n, masses)
     pot, acc = _gpu_fmm(ctx, pos, m, p, eps)
     st = ctx.stats()
     ref = oracle.fmm(pos, m, p=p, eps=eps, leaf_size=leaf, p2p_pairs=0.5 * (p + 1) ** 3,
@@ -182,13 +196,13 @@ def test_tiny_and_degenerate_inputs(ctx, gpu_lib):
         p0, a0, _ = oracle.direct(pos, m)
         np.testing.assert_allclose(pot, p0, rtol=1e-13, atol=0)
         np.testing.assert_allclose(acc, a0, rtol=1e-12, atol=1e-300)
-    # particles closer than the 21-bit quantum: an overfull leaf at depth 21
+    # particles closer than the 42-bit quantum: an overfull leaf at depth 42
     rng = np.random.default_rng(4)
-    pos = np.vstack([1e-9 * rng.normal(size=(40, 3)) + 0.5, 100.0 * rng.normal(size=(60, 3))])
+    pos = np.vstack([1e-14 * rng.normal(size=(40, 3)) + 0.5, 100.0 * rng.normal(size=(60, 3))])
     m = np.full(100, 0.01)
     c4 = gpu_lib.Context(leaf_size=4)
     _, acc = _gpu_fmm(c4, pos, m, 8, 1e-10)
-    assert c4.stats()["depth"] == 21
+    assert c4.stats()["depth"] == 42
     _, a0, _ = oracle.direct(pos, m)
     assert _rel(acc, a0)[:40].max() < 1e-9
 

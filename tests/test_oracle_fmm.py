@@ -49,17 +49,46 @@ def test_tiny_inputs():
 
 
 def test_overfull_leaf_at_max_depth():
-    """Particles closer than the 21-bit quantum cannot be separated: a depth-21
+    """Particles closer than the 42-bit quantum cannot be separated: a depth-42
     leaf holds more than n_L of them and the result is still exact there."""
     rng = np.random.default_rng(4)
-    clump = 1e-9 * rng.normal(size=(40, 3)) + np.array([0.5, 0.5, 0.5])
+    clump = 1e-14 * rng.normal(size=(40, 3)) + np.array([0.5, 0.5, 0.5])
     far = rng.normal(size=(60, 3)) * 100.0
     pos = np.vstack([clump, far])
     m = np.full(100, 0.01)
     pot0, acc0, _ = oracle.direct(pos, m)
     r = oracle.fmm(pos, m, p=8, eps=1e-10, leaf_size=4)
-    assert r["stats"]["depth"] == 21
+    assert r["stats"]["depth"] == 42
     assert _rel(r["acc"], acc0)[:40].max() < 1e-9
+
+
+def test_deep_refinement_below_level_21():
+    """A cusp inside a very wide halo: one particle 1e7 away puts the whole
+    Plummer sphere into a few level-21 cells, which are refined further with
+    the second key word.  The tree goes below level 21, the walk still covers
+    every ordered particle pair exactly once, and the result is within the
+    error bound of the direct sum."""
+    n = 3001
+    pos, m = W.cluster("plummer", n - 1, 5)
+    pos = np.vstack([pos, [[1e7, 0.0, 0.0]]])
+    m = np.append(m, 1.0 / (n - 1))
+    eps = 1e-7
+    r = oracle.fmm(pos, m, p=8, eps=eps, leaf_size=32, p2p_pairs=729)
+    st = r["stats"]
+    assert st["depth"] > 21
+    _, a0, _ = oracle.direct(pos, m)
+    e = _rel(r["acc"], a0)
+    assert np.sqrt(np.mean(e ** 2)) < 2 * eps
+    # eps -> 0 on the deep tree: nothing accepted, every ordered pair summed
+    # directly exactly once
+    r0 = oracle.fmm(pos, m, p=4, eps=1e-300, leaf_size=32, p2p_pairs=2)
+    assert r0["stats"]["depth"] == st["depth"] and r0["stats"]["n_m2l"] == 0
+    assert r0["stats"]["n_p2p_pairs"] == n * (n - 1)
+    assert _rel(r0["acc"], a0).max() < 1e-12
+    # the same particles with n_L >= N: a single leaf, the exact sum
+    r1 = oracle.fmm(pos, m, p=8, eps=eps, leaf_size=4000)
+    assert r1["stats"]["depth"] == 0
+    assert _rel(r1["acc"], a0).max() < 1e-13
 
 
 @pytest.mark.parametrize("kind,eps", [("plummer", 1e-6), ("dehnen1.5", 1e-6), ("plummer", 1e-8)])
