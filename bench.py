@@ -95,6 +95,7 @@ def batched_leg(args, fmm, workloads):
         _, ad = ctx.direct(P[a:b].contiguous(), M[a:b].contiguous(), 1.0)
         errs.append(_rel_err(acc[a:b], ad))
     e = np.concatenate(errs)
+    print(f"batched: errors checked on {len(errs)} clusters", file=sys.stderr, flush=True)
     # one call per cluster (after one warm pass that sizes the workspace)
     single = fmm.Context(device=0, leaf_size=args.leaf, p2p_factor=args.p2p_factor)
     for i in range(k):
@@ -107,6 +108,7 @@ def batched_leg(args, fmm, workloads):
         single.forces(P[a:b], M[a:b], 1.0, args.p, eps, pot[a:b], acc[a:b])
     torch.cuda.synchronize()
     t_single = time.perf_counter() - t0
+    print(f"batched: one call per cluster {1e3 * t_single:.1f} ms", file=sys.stderr, flush=True)
     ctx.close()
     single.close()
     return {"workload": f"{k} Plummer clusters, N log-uniform in [1e3, 1e5] (seed "
@@ -143,6 +145,8 @@ def serve_leg(args, fmm, workloads, capacity_pfs):
         vel = workloads.drift_velocities(kinds[i], pos, args.seed + 4000 + i)
         inputs.append(tuple(torch.from_numpy(np.ascontiguousarray(x)).to(dev)
                             for x in (pos, m, vel)))
+    print(f"serve: {r} request inputs ready, {int(np.sum(sizes))} particles", file=sys.stderr,
+          flush=True)
 
     def make(i, steps=steps):
         pos, m, vel = inputs[i]
@@ -157,6 +161,7 @@ def serve_leg(args, fmm, workloads, capacity_pfs):
     warm = [srv.submit(make(big, 1)) for _ in range(args.serve_slots)]
     for w in warm:
         w.result(600)
+    print("serve: slots warmed", file=sys.stderr, flush=True)
     mean_service = float(np.mean(sizes)) * steps / capacity_pfs
     gaps = rng.exponential(mean_service / args.serve_load, r)
     reqs = []
@@ -168,8 +173,10 @@ def serve_leg(args, fmm, workloads, capacity_pfs):
         if dt > 0:
             time.sleep(dt)
         reqs.append(srv.submit(make(i)))
-    for q in reqs:
+    for i, q in enumerate(reqs):
         q.result(600)
+        print(f"serve: request {i} n={sizes[i]} {kinds[i]} done, latency "
+              f"{1e3 * q.latency:.1f} ms", file=sys.stderr, flush=True)
     t_all = max(q.t_end for q in reqs) - t0
     srv.close()
     lat = serve.latency_summary(reqs)
