@@ -52,6 +52,17 @@ typedef enum {
     FMM_MAC_THETA = 2   /* theta < theta_crit (eq:mac:theta); eps unused */
 } fmm_mac;
 
+/* Arithmetic of the evaluation kernels.  The tree, the low-order estimate
+ * and the walk are FP64 in both modes, so both modes accept the same
+ * interactions. */
+typedef enum {
+    FMM_PREC_FP64 = 0,  /* every step in FP64 */
+    FMM_PREC_MIXED = 1  /* direct sums: separations formed in FP64 and rounded
+                           once, then FP32 pair arithmetic and FP32 running sums
+                           flushed into FP64 every 32 sources per lane; results
+                           accumulated and returned in FP64 */
+} fmm_precision;
+
 /* Where min_B{a_b} (or f_b) comes from. */
 typedef enum {
     FMM_SCALE_ESTIMATE = 0, /* low-order FMM estimate (Sec. 5.4.2) inside the call */
@@ -71,6 +82,7 @@ typedef struct {
                               are summed directly; 0 = 2 */
     fmm_scale_source scale_source;
     int timing;            /* nonzero: record per-phase HIP events (fmm_stats) */
+    fmm_precision precision; /* FMM_PREC_FP64 by default (0) */
 } fmm_opts;
 
 /* Interaction counts and per-phase times of the last fmm_forces call. */

@@ -451,7 +451,7 @@ void prepare_p2p(fmm_ctx *c, int64_t nlist) {
 }
 
 // direct sums of every leaf (prepared ranges), added into out4
-void run_p2p(fmm_ctx *c, int want_f, int with_pot, double4 *out4, bool timed) {
+void run_p2p(fmm_ctx *c, int want_f, int with_pot, int mixed, double4 *out4, bool timed) {
     hipStream_t s = c->stream;
     const int nl = c->nleaves;
     TreeArrays t = tree_arrays(c);
@@ -471,7 +471,7 @@ void run_p2p(fmm_ctx *c, int want_f, int with_pot, double4 *out4, bool timed) {
     double4 *part = ensure<double4>(c->ppart, (size_t)std::max(prows, 1) * 64);
     CK(launch_p2p_tasks(nl, toff, tasks, s));
     if (timed && c->opts.timing) CK(hipEventRecord(c->ev_p2p[0], s));
-    CK(launch_p2p(want_f, with_pot, ntasks, tasks, ptr<int>(c->leaf_cell), nts, moff, off, rg, t,
+    CK(launch_p2p(want_f, with_pot, mixed, ntasks, tasks, ptr<int>(c->leaf_cell), nts, moff, off, rg, t,
                   ptr<double4>(c->xyzm), out4, part, s));
     if (timed && c->opts.timing) CK(hipEventRecord(c->ev_p2p[1], s));
     if (prows > 0)
@@ -507,7 +507,7 @@ void sink_scale(fmm_ctx *c, bool want_f) {
             CK(launch_est_l2l_level(want_f, t, c->ls[Lv], c->ls[Lv + 1], Fe, s));
         double4 *e4 = ensure<double4>(c->est4, n);
         CK(launch_est_l2p(want_f, t, ptr<int>(c->leaf_of), ptr<int>(c->leaf_cell), n, Fe, e4, s));
-        run_p2p(c, want_f, 0, e4, false);
+        run_p2p(c, want_f, 0, 0, e4, false);
         CK(launch_scale(want_f, n, e4, scale, s));
     }
     for (int Lv = c->depth; Lv >= 0; --Lv)
@@ -590,7 +590,7 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
                   ptr<double>(c->y), ptr<double>(c->z), F, o4, s));
     mark(c, PH_DOWN);
     // near field
-    run_p2p(c, 0, 1, o4, true);
+    run_p2p(c, 0, 1, c->opts.precision == FMM_PREC_MIXED, o4, true);
     mark(c, PH_P2P);
     int *nonfinite = ptr<int>(c->nonfinite);
     CK(hipMemsetAsync(nonfinite, 0, sizeof(int), s));
@@ -689,6 +689,7 @@ fmm_status fmm_build(fmm_ctx **out, const fmm_opts *o) {
     if (o->mac < FMM_MAC_REL || o->mac > FMM_MAC_THETA) return FMM_E_INVAL;
     if (o->mac == FMM_MAC_THETA && !(o->theta_crit > 0.0 && o->theta_crit < 1.0)) return FMM_E_INVAL;
     if (o->p2p_factor < 0.0 || !std::isfinite(o->p2p_factor)) return FMM_E_INVAL;
+    if (o->precision != FMM_PREC_FP64 && o->precision != FMM_PREC_MIXED) return FMM_E_INVAL;
     if (o->scale_source != FMM_SCALE_ESTIMATE && o->scale_source != FMM_SCALE_PREVIOUS)
         return FMM_E_INVAL;
     int ndev = 0;

@@ -178,7 +178,8 @@ hipError_t launch_p2p_plan(int nleaves, const int *leaf_cell, const int64_t *off
                            int *nsrc_tasks, int *task_off, int *moff, int *tmp, int *totals,
                            hipStream_t s);
 hipError_t launch_p2p_tasks(int nleaves, const int *task_off, int2 *tasks, hipStream_t s);
-hipError_t launch_p2p(int want_f, int with_pot, int ntasks, const int2 *tasks,
+// mixed != 0: FP32 pair arithmetic (separations in FP64, sums flushed to FP64)
+hipError_t launch_p2p(int want_f, int with_pot, int mixed, int ntasks, const int2 *tasks,
                       const int *leaf_cell, const int *nsrc_tasks, const int *moff,
                       const int64_t *off, const int2 *range, const TreeArrays &t,
                       const double4 *xyzm, double4 *out4, double4 *partial, hipStream_t s);

@@ -7,11 +7,12 @@
 // applies to all particles below it).  A leaf's work is cut into tasks of at
 // most 64 sinks x P2P_TASK sources - a sparse leaf far out in an untruncated
 // halo can be summed against every particle, and as one wavefront's serial
-// loop it would set the kernel time.  One wavefront per task: for nb sinks the
-// first nb * floor(64/nb) lanes are (sink, phase); the phases stride through
-// each range (two sources per iteration) and are summed through LDS at the
-// end, so small leaves still fill the wavefront.  A leaf with one task adds into the output directly; otherwise each task writes a
-// row of partial sums that a second kernel adds in task order (deterministic).
+// loop it would set the kernel time.  One wavefront per task: every lane holds
+// two sinks, lanes are (sink group, phase) pairs, the phases stride through
+// each range and are summed through LDS at the end, so small leaves still fill
+// the wavefront and every source load serves two pairs.  A leaf with one task
+// adds into the output directly; otherwise each task writes a row of partial
+// sums that a second kernel adds in task order (deterministic).
 // Source particles are read as (x, y, z, m) double4 from the key-sorted copy.
 #include "internal.h"
 #include "dev.h"
@@ -19,6 +20,10 @@
 namespace fmm {
 
 namespace {
+
+// sinks per lane of the P2P kernel (two halves the source loads per pair;
+// more costs occupancy)
+constexpr int P2P_R = 2;
 
 // Work of one sink leaf: its direct-sum ranges and those of its ancestors,
 // read as one concatenated list of source particles.
@@ -76,12 +81,91 @@ __device__ __forceinline__ void pair(const double4 s, const double4 xb, bool ski
     }
 }
 
+// One lane's share of a source range for its R sinks: sources p[0],
+// p[stride], ... below pe, the next source loaded before the current one is
+// summed.  CHECK: the range may contain the sinks themselves (skipped by
+// address); other ranges need no test.
+// Mixed precision: the separation is formed in FP64 and rounded once; the
+// squared distance, reciprocal square root, products and the running sums
+// are FP32 (every pair's contribution carries a relative error of a few
+// FP32 units).
 template <int WANT_F, int WITH_POT>
+__device__ __forceinline__ void pair32(const double4 s, const double4 xb, bool skip, float &pot,
+                                       float &ax, float &ay, float &az) {
+    const float dx = (float)(s.x - xb.x), dy = (float)(s.y - xb.y), dz = (float)(s.z - xb.z);
+    const float r2 = skip ? 1.0f : fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    const float mu = skip ? 0.0f : (float)s.w;
+    if (WANT_F) {
+        pot += mu * __builtin_amdgcn_rcpf(r2);
+    } else {
+        const float ri = __builtin_amdgcn_rsqf(r2);
+        const float q = mu * ri;
+        const float q3 = q * ri * ri;
+        if (WITH_POT) pot += q;
+        ax = fmaf(q3, dx, ax);
+        ay = fmaf(q3, dy, ay);
+        az = fmaf(q3, dz, az);
+    }
+}
+
+// FP32 partial sums run over at most this many sources per lane before they
+// are added into the FP64 sums
+constexpr int P2P_CHUNK32 = 32;
+
+template <int R, int WANT_F, int WITH_POT, bool CHECK>
+__device__ __forceinline__ void sum_range32(const double4 *p, const double4 *pe, int stride,
+                                            const double4 (&xb)[R],
+                                            const double4 *const (&self)[R], double4 (&f)[R]) {
+    while (p < pe) {
+        float4 g[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) g[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int it = 0; it < P2P_CHUNK32 && p < pe; ++it, p += stride) {
+            const double4 a = p[0];
+#pragma unroll
+            for (int k = 0; k < R; ++k)
+                pair32<WANT_F, WITH_POT>(a, xb[k], CHECK && p == self[k], g[k].x, g[k].y, g[k].z,
+                                         g[k].w);
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            f[k].x += (double)g[k].x;
+            f[k].y += (double)g[k].y;
+            f[k].z += (double)g[k].z;
+            f[k].w += (double)g[k].w;
+        }
+    }
+}
+
+template <int R, int WANT_F, int WITH_POT, bool CHECK>
+__device__ __forceinline__ void sum_range(const double4 *p, const double4 *pe, int stride,
+                                          const double4 (&xb)[R], const double4 *const (&self)[R],
+                                          double4 (&f)[R]) {
+    if (p >= pe) return;
+    double4 a = p[0];
+    for (;;) {
+        const double4 *q = p + stride;
+        const bool more = q < pe;
+        const double4 b = (more ? q : p)[0];
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            pair<WANT_F, WITH_POT>(a, xb[k], CHECK && p == self[k], f[k].x, f[k].y, f[k].z,
+                                   f[k].w);
+        if (!more) break;
+        p = q;
+        a = b;
+    }
+}
+
+// R sinks per lane: ng = ceil(nb / R) lane groups, group g holds sink slots
+// g, g + ng, g + 2 ng, ... (a slot past the leaf repeats slot g and is
+// discarded); lanes [0, ng * S) are (group, phase) with S = floor(64 / ng).
+template <int R, int WANT_F, int WITH_POT, int MIXED>
 __global__ void __launch_bounds__(256)
 k_p2p(int ntasks, const int2 *tasks, const int *leaf_cell, const int *nsrc_tasks,
       const int *moff, const int64_t *off, const int2 *range, TreeArrays t, const double4 *xyzm,
       double4 *out4, double4 *partial) {
-    __shared__ double4 red[4][FMM_WAVE];
+    __shared__ double4 red[4][R * FMM_WAVE];
     const int task = blockIdx.x * 4 + threadIdx.x / FMM_WAVE;
     if (task >= ntasks) return;
     const int lane = lane_id(), w = threadIdx.x / FMM_WAVE;
@@ -93,13 +177,19 @@ k_p2p(int ntasks, const int2 *tasks, const int *leaf_cell, const int *nsrc_tasks
     const int beg = t.beg[c], end = t.end[c];
     const int sb = beg + sc * FMM_WAVE;
     const int nb = min(end - sb, FMM_WAVE);
-    // lanes [0, nb*S) are (sink slot, phase) = (lane % nb, lane / nb)
-    const int S = FMM_WAVE / nb;
-    const int slot = lane % nb, phase = lane / nb;
+    const int ng = (nb + R - 1) / R;
+    const int S = FMM_WAVE / ng;
+    const int g = lane % ng, phase = lane / ng;
     const bool active = phase < S;
-    const int bi = sb + slot;
-    const double4 xb = xyzm[bi];
-    double pot = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
+    double4 xb[R], f[R];
+    const double4 *self[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int slot = g + k * ng < nb ? g + k * ng : g;
+        self[k] = xyzm + sb + slot;
+        xb[k] = *self[k];
+        f[k] = make_double4(0.0, 0.0, 0.0, 0.0);
+    }
     // sources [ts * P2P_TASK, (ts + 1) * P2P_TASK) of the leaf's list
     int64_t skip = (int64_t)ts * P2P_TASK, left = P2P_TASK;
     for (int anc = c; anc >= 0 && left > 0; anc = t.parent[anc]) {
@@ -115,32 +205,39 @@ k_p2p(int ntasks, const int2 *tasks, const int *leaf_cell, const int *nsrc_tasks
             if (rg.y - rg.x > left) rg.y = rg.x + (int)left;
             left -= rg.y - rg.x;
             if (!active) continue;
-            // two sources per iteration, loads issued before the arithmetic
-            int j = rg.x + phase;
-            for (; j + S < rg.y; j += 2 * S) {
-                const double4 s0 = xyzm[j], s1 = xyzm[j + S];
-                pair<WANT_F, WITH_POT>(s0, xb, j == bi, pot, ax, ay, az);
-                pair<WANT_F, WITH_POT>(s1, xb, j + S == bi, pot, ax, ay, az);
+            const double4 *p = xyzm + rg.x + phase, *pe = xyzm + rg.y;
+            const bool own = rg.x < sb + nb && rg.y > sb;   // overlaps the task's sinks
+            if (MIXED) {
+                if (own) sum_range32<R, WANT_F, WITH_POT, true>(p, pe, S, xb, self, f);
+                else sum_range32<R, WANT_F, WITH_POT, false>(p, pe, S, xb, self, f);
+            } else {
+                if (own) sum_range<R, WANT_F, WITH_POT, true>(p, pe, S, xb, self, f);
+                else sum_range<R, WANT_F, WITH_POT, false>(p, pe, S, xb, self, f);
             }
-            if (j < rg.y) pair<WANT_F, WITH_POT>(xyzm[j], xb, j == bi, pot, ax, ay, az);
         }
     }
-    // sum the phases of each sink through LDS
-    red[w][lane] = active ? make_double4(pot, ax, ay, az) : make_double4(0.0, 0.0, 0.0, 0.0);
+    // sum the phases of each sink through LDS: red[w][slot + phase * R * ng];
+    // active lanes cover every index below R * ng * S <= R * 64 exactly once
+    if (active) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) red[w][g + k * ng + phase * R * ng] = f[k];
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (lane >= nb) return;
+    double4 v = red[w][lane];
     for (int ph = 1; ph < S; ++ph) {
-        const double4 q = red[w][lane + ph * nb];
-        pot += q.x; ax += q.y; ay += q.z; az += q.w;
+        const double4 q = red[w][lane + ph * R * ng];
+        v.x += q.x; v.y += q.y; v.z += q.z; v.w += q.w;
     }
+    const int bi = sb + lane;
     if (moff[leaf + 1] == moff[leaf]) {          // the leaf's only task
-        double4 v = out4[bi];
-        v.x += pot; v.y += ax; v.z += ay; v.w += az;
-        out4[bi] = v;
+        double4 o = out4[bi];
+        o.x += v.x; o.y += v.y; o.z += v.z; o.w += v.w;
+        out4[bi] = o;
     } else {
-        partial[((int64_t)moff[leaf] + tk.y) * FMM_WAVE + slot] = make_double4(pot, ax, ay, az);
+        partial[((int64_t)moff[leaf] + tk.y) * FMM_WAVE + lane] = v;
     }
 }
 
@@ -236,21 +333,25 @@ hipError_t launch_p2p_tasks(int nleaves, const int *task_off, int2 *tasks, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_p2p(int want_f, int with_pot, int ntasks, const int2 *tasks,
+hipError_t launch_p2p(int want_f, int with_pot, int mixed, int ntasks, const int2 *tasks,
                       const int *leaf_cell, const int *nsrc_tasks, const int *moff,
                       const int64_t *off, const int2 *range, const TreeArrays &t,
                       const double4 *xyzm, double4 *out4, double4 *partial, hipStream_t s) {
     if (ntasks <= 0) return hipSuccess;
     const dim3 g(blocks(ntasks, 4)), b(256);
-    if (want_f)
-        hipLaunchKernelGGL((k_p2p<1, 0>), g, b, 0, s, ntasks, tasks, leaf_cell, nsrc_tasks, moff,
-                           off, range, t, xyzm, out4, partial);
-    else if (with_pot)
-        hipLaunchKernelGGL((k_p2p<0, 1>), g, b, 0, s, ntasks, tasks, leaf_cell, nsrc_tasks, moff,
-                           off, range, t, xyzm, out4, partial);
-    else
-        hipLaunchKernelGGL((k_p2p<0, 0>), g, b, 0, s, ntasks, tasks, leaf_cell, nsrc_tasks, moff,
-                           off, range, t, xyzm, out4, partial);
+#define FMM_P2P_LAUNCH(F, P, X)                                                                  \
+    hipLaunchKernelGGL((k_p2p<P2P_R, F, P, X>), g, b, 0, s, ntasks, tasks, leaf_cell, nsrc_tasks, \
+                       moff, off, range, t, xyzm, out4, partial)
+    if (mixed) {
+        if (want_f) FMM_P2P_LAUNCH(1, 0, 1);
+        else if (with_pot) FMM_P2P_LAUNCH(0, 1, 1);
+        else FMM_P2P_LAUNCH(0, 0, 1);
+    } else {
+        if (want_f) FMM_P2P_LAUNCH(1, 0, 0);
+        else if (with_pot) FMM_P2P_LAUNCH(0, 1, 0);
+        else FMM_P2P_LAUNCH(0, 0, 0);
+    }
+#undef FMM_P2P_LAUNCH
     return hipGetLastError();
 }
 

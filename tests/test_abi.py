@@ -68,3 +68,26 @@ def test_host_only_entry_points(lib):
     lib.fmm_forces.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_double,
                                C.c_int, C.c_double, C.c_void_p, C.c_void_p]
     assert lib.fmm_forces(None, 10, None, None, 1.0, 8, 1e-7, None, None) == 1
+
+
+def test_option_and_stats_layouts_match_header():
+    """The binding's ctypes structures list the header's members in order."""
+    import re
+    from paper_1405_2255_amd import fmm
+    hdr = open(HDR).read()
+
+    def members(name):
+        body = re.search(r"typedef struct \{([^{}]*)\}\s*" + name + ";", hdr).group(1)
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        out = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            names = decl.split(None, 1)[1] if " " in decl else decl
+            for v in names.split(","):
+                out.append(v.strip().lstrip("*").strip())
+        return out
+
+    assert [f[0] for f in fmm.Opts._fields_] == members("fmm_opts")
+    assert [f[0] for f in fmm.Stats._fields_] == members("fmm_stats_t")

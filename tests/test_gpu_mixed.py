@@ -1,0 +1,69 @@
+"""Mixed precision (FMM_PREC_MIXED): the same tree, estimate and walk as the
+FP64 mode, so the same accepted interactions as the FP64 oracle; the direct
+sums run in FP32 arithmetic.  Bounds derived from the arithmetic: each pair's
+contribution carries a relative error below ~20 FP32 units (one rounding of
+the separation, r^2, the reciprocal square root, and the products), and the
+FP32 running sums over at most 32 terms add at most 32 units of the sum of
+magnitudes; so |a_mixed - a_fp64| <= 64 u32 sum_a mu_a / r_ab^2 <= 64 u32 f_b
+with f_b the scaled force of the exact direct sum."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1405_2255_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+def _run(gpu_lib, pos, m, p, eps, precision, p2p_factor=0.5):
+    import torch
+    ctx = gpu_lib.Context(p2p_factor=p2p_factor, precision=precision)
+    P, M = torch.from_numpy(pos).cuda(), torch.from_numpy(m).cuda()
+    pot, acc = ctx.forces(P, M, G=1.0, p=p, target_err=eps)
+    torch.cuda.synchronize()
+    return pot.cpu().numpy(), acc.cpu().numpy(), ctx.stats()
+
+
+@pytest.mark.parametrize("kind,n,masses,p,eps", [
+    ("plummer", 20011, "equal", 10, 1e-7),
+    ("dehnen1.5", 12345, "salpeter", 8, 1e-6),
+    ("uniform", 7777, "equal", 6, 1e-5),
+])
+def test_mixed_within_fp32_bound_of_oracle(gpu_lib, kind, n, masses, p, eps):
+    print(f"case {kind} n={n} p={p}", flush=True)
+    pos, m = W.cluster(kind, n, 5, masses=masses)
+    pot, acc, st = _run(gpu_lib, pos, m, p, eps, "mixed")
+    ref = oracle.fmm(pos, m, p=p, eps=eps, leaf_size=32, p2p_pairs=0.5 * (p + 1) ** 3)
+    # the walk is FP64 in both modes: the same interactions
+    assert st["n_m2l"] == ref["stats"]["n_m2l"]
+    assert st["n_p2p_pairs"] == ref["stats"]["n_p2p_pairs"]
+    p0, a0, f0 = oracle.direct(pos, m)
+    da = np.linalg.norm(acc - ref["acc"], axis=1)
+    bound = 64 * U32 * f0 + 1e-10 * np.linalg.norm(ref["acc"], axis=1)
+    assert np.all(da <= bound), float(np.max(da / bound))
+    # potential: the same argument with sum mu / r = |pot|
+    assert np.all(np.abs(pot - ref["pot"]) <= 64 * U32 * np.abs(p0) + 1e-10 * np.abs(ref["pot"]))
+    # typical size of the FP32 rounding: well below the error target
+    rel = da / np.linalg.norm(ref["acc"], axis=1)
+    print("mixed vs fp64 oracle: rms", np.sqrt(np.mean(rel ** 2)), "max", rel.max(), flush=True)
+    assert np.sqrt(np.mean(rel ** 2)) < 0.5 * eps
+
+
+def test_mixed_accuracy_against_direct_sum(gpu_lib):
+    n, eps = 50000, 5e-8
+    pos, m = W.cluster("plummer", n, 8)
+    _, acc, st = _run(gpu_lib, pos, m, -1, eps, "mixed", p2p_factor=0.0)
+    _, acc64, _ = _run(gpu_lib, pos, m, -1, eps, "fp64", p2p_factor=0.0)
+    sinks = np.random.default_rng(1).choice(n, 3000, replace=False)
+    _, a0, _ = oracle.direct(pos, m, sinks=sinks)
+    e = oracle.error_summary(np.linalg.norm(acc[sinks] - a0, axis=1) / np.linalg.norm(a0, axis=1))
+    e64 = oracle.error_summary(np.linalg.norm(acc64[sinks] - a0, axis=1) / np.linalg.norm(a0, axis=1))
+    print("mixed", e, "fp64", e64, flush=True)
+    assert e["rms"] < 1e-7 and e["p99.9"] < 1e-6
+
+
+def test_bad_precision_rejected(gpu_lib):
+    with pytest.raises(KeyError):
+        gpu_lib.Context(precision="fp16")
