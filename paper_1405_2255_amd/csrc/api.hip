@@ -130,6 +130,8 @@ struct fmm_ctx {
     DevBuf pt_n, pt_m, pt_s, pt_off, pt_moff, ptasks, ppart;
     DevBuf counters, nonfinite, walktmp, coffsets, roots, ckey, ckey2, order, order2;
     DevBuf dkey, dsort, dsort2, runstart;   // deep refinement below level 21
+    DevBuf plans;                          // output plans of M2M and L2L for order plan_p
+    int plan_p = -1;
     uint64_t *kdeep = nullptr;            // second key word of the sorted particles
     bool deep = false;
     void *pin = nullptr;      // pinned staging for host-to-device copies
@@ -540,8 +542,16 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
     CK(launch_p2m(p, t, ptr<int>(c->leaf_cell), c->nleaves, ptr<double>(c->x), ptr<double>(c->y),
                   ptr<double>(c->z), ptr<double>(c->m), M, s));
     if (c->ncells > 1) CK(launch_shift_upsilon(p, t, 1, c->ncells, U, s));
+    short *plans = ensure<short>(c->plans, 2 * FMM_PLAN_SIZE);
+    if (c->plan_p != p) {
+        std::vector<short> h(2 * FMM_PLAN_SIZE);
+        translation_plans(p, h.data(), h.data() + FMM_PLAN_SIZE);
+        CK(hipMemcpyAsync(plans, h.data(), h.size() * sizeof(short), hipMemcpyHostToDevice, s));
+        sync(c);
+        c->plan_p = p;
+    }
     for (int L = c->depth - 1; L >= 0; --L)
-        CK(launch_m2m_level(p, t, c->ls[L], c->ls[L + 1], U, M, s));
+        CK(launch_m2m_level(p, t, c->ls[L], c->ls[L + 1], U, M, plans, s));
     CK(launch_power(p, c->ncells, M, P, s));
     mark(c, PH_UP);
     // walk
@@ -584,7 +594,8 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
     mark(c, PH_M2L);
     // downward pass, far field at the particles
     for (int Lv = 1; Lv <= c->depth; ++Lv)
-        CK(launch_l2l_level(p, t, c->ls[Lv], c->ls[Lv + 1], U, F, s));
+        CK(launch_l2l_level(p, t, c->ls[Lv], c->ls[Lv + 1], U, F,
+                            ptr<short>(c->plans) + FMM_PLAN_SIZE, s));
     double4 *o4 = ensure<double4>(c->out4, n);
     CK(launch_l2p(p, t, ptr<int>(c->leaf_of), ptr<int>(c->leaf_cell), n, ptr<double>(c->x),
                   ptr<double>(c->y), ptr<double>(c->z), F, o4, s));

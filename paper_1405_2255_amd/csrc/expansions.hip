@@ -4,6 +4,9 @@
 //
 // Storage: per cell the complex X_n^m for 0 <= m <= n <= p at complex index
 // tri(n, m) = n(n+1)/2 + m, (Re, Im) adjacent, Im = 0 for m = 0.
+#include <algorithm>
+#include <vector>
+
 #include "internal.h"
 #include "harmonics.h"
 
@@ -11,44 +14,90 @@ namespace fmm {
 
 namespace {
 
-// ---- P2M: one wavefront per leaf, lanes over particles ----------------------
-// M_n^m(z) = sum_a mu_a Upsilon_n^m(x_a - z): each lane generates the rows of
-// its particle, the wavefront sums every coefficient, lane 0 stores it.
+// 1 / (n^2 - m^2) for 0 <= m < n <= FMM_PMAX (the Upsilon column recurrence)
+struct InvTable {
+    double v[FMM_PMAX + 1][FMM_PMAX + 1];
+};
+constexpr InvTable make_inv_table() {
+    InvTable tb{};
+    for (int n = 0; n <= FMM_PMAX; ++n)
+        for (int m = 0; m <= FMM_PMAX; ++m)
+            tb.v[n][m] = n > m ? 1.0 / (double)(n * n - m * m) : 0.0;
+    return tb;
+}
+__constant__ InvTable kInvN2M2 = make_inv_table();
+
+// ---- P2M: one wavefront per leaf, a lane per (particle, column m) ------------
+// M_n^m(z) = sum_a mu_a Upsilon_n^m(x_a - z).  Lanes are (particle slot,
+// column): C lanes per particle, lane `col` generates column m = col of its
+// particle's Upsilon - the diagonal Upsilon_m^m = prod_{j<=m} (x+iy)/(2j),
+// then Upsilon_{m+1}^m = z Upsilon_m^m and
+// (n^2 - m^2) Upsilon_n^m = (2n-1) z Upsilon_{n-1}^m - r^2 Upsilon_{n-2}^m -
+// and keeps the running sums of that column; the particle slots are added
+// with two cross-lane steps at the end.
 template <int P>
 __global__ void __launch_bounds__(256)
 k_p2m(TreeArrays t, const int *leaf_cell, int nleaves, const double *x, const double *y,
       const double *z, const double *m, double *M) {
+    constexpr int C = P < 16 ? 16 : 32;       // lanes per particle (columns 0..P)
+    constexpr int SL = FMM_WAVE / C;          // particles per step
     const int leaf = blockIdx.x * 4 + threadIdx.x / FMM_WAVE;
     if (leaf >= nleaves) return;
-    const int lane = lane_id();
+    const int lane = lane_id(), col = lane % C, slot = lane / C;
     const int c = leaf_cell[leaf];
     const int beg = t.beg[c], end = t.end[c];
     const double4 cen = t.cen[c];
-    cplx *Mc = reinterpret_cast<cplx *>(M) + (size_t)c * tri(P + 1, 0);
-    for (int ch = beg; ch < end; ch += FMM_WAVE) {
-        const int i = ch + lane;
-        const bool valid = i < end;
-        const double mu = valid ? m[i] : 0.0;
-        RowGen<P> g;
-        g.upsilon_start(valid ? x[i] - cen.x : 0.0, valid ? y[i] - cen.y : 0.0,
-                        valid ? z[i] - cen.z : 0.0);
-        const bool first = ch == beg;
-        auto emit = [&]<int N>() {
-            if constexpr (N > 0) g.template upsilon_row<N>();
-            const cplx *row = g.template row<N>();
+    cplx acc[P + 1];
 #pragma unroll
-            for (int mm = 0; mm <= N; ++mm) {
-                const double re = wave_sum(mu * row[mm].re);
-                const double im = mm == 0 ? 0.0 : wave_sum(mu * row[mm].im);
-                if (lane == 0) {
-                    cplx &dst = Mc[tri(N, mm)];
-                    if (first) dst = {re, im};
-                    else dst = {dst.re + re, dst.im + im};
-                }
+    for (int n = 0; n <= P; ++n) acc[n] = {0.0, 0.0};
+    for (int i0 = beg; i0 < end; i0 += SL) {
+        const int i = i0 + slot;
+        const bool valid = i < end && col <= P;
+        const double mu = valid ? m[i] : 0.0;
+        const double dx = valid ? x[i] - cen.x : 0.0, dy = valid ? y[i] - cen.y : 0.0,
+                     dz = valid ? z[i] - cen.z : 0.0;
+        const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+        cplx d = {1.0, 0.0};
+#pragma unroll
+        for (int j = 1; j <= P; ++j) {
+            if (j <= col) {
+                const double h = 1.0 / (2.0 * j);
+                d = {h * (dx * d.re - dy * d.im), h * (dx * d.im + dy * d.re)};
             }
-        };
-        Unroll<0, P>::run(emit);
+        }
+        cplx u1 = {0.0, 0.0}, u2 = {0.0, 0.0};
+#pragma unroll
+        for (int n = 0; n <= P; ++n) {
+            cplx u;
+            if (n < col) {
+                u = {0.0, 0.0};
+            } else if (n == col) {
+                u = d;
+            } else if (n == col + 1) {
+                u = {dz * u1.re, dz * u1.im};
+            } else {
+                const double inv = kInvN2M2.v[n][col < FMM_PMAX ? col : FMM_PMAX];
+                const double s = (2.0 * n - 1.0) * dz;
+                u = {(s * u1.re - r2 * u2.re) * inv, (s * u1.im - r2 * u2.im) * inv};
+            }
+            acc[n].re = fma(mu, u.re, acc[n].re);
+            acc[n].im = fma(mu, u.im, acc[n].im);
+            u2 = u1;
+            u1 = u;
+        }
     }
+#pragma unroll
+    for (int off = C; off < FMM_WAVE; off <<= 1)
+#pragma unroll
+        for (int n = 0; n <= P; ++n) {
+            acc[n].re += __shfl_xor(acc[n].re, off, FMM_WAVE);
+            acc[n].im += __shfl_xor(acc[n].im, off, FMM_WAVE);
+        }
+    if (slot != 0 || col > P) return;
+    cplx *Mc = reinterpret_cast<cplx *>(M) + (size_t)c * tri(P + 1, 0);
+#pragma unroll
+    for (int n = 0; n <= P; ++n)
+        if (n >= col) Mc[tri(n, col)] = {acc[n].re, col == 0 ? 0.0 : acc[n].im};
 }
 
 // ---- Upsilon of each cell's offset from its parent's centre -----------------
@@ -75,38 +124,126 @@ __device__ __forceinline__ cplx ld(const cplx *X, int n, int q) {
     return sym(X[tri(n, q < 0 ? -q : q)], q);
 }
 
-// ---- M2M: one thread per (parent, coefficient) ------------------------------
-// M_n^m(z') = sum_{k=0}^{n} sum_{l=-k}^{k} Upsilon_k^l(z - z') M_{n-k}^{m-l}(z)
-__global__ void k_m2m_level(int p, TreeArrays t, int c0, int c1, const double *U, double *M) {
-    const int nc = tri(p + 1, 0);
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int c = c0 + (int)(gid / nc);
-    const int o = (int)(gid % nc);
+constexpr int NCMAX = tri(FMM_PMAX + 1, 0);   // complex coefficients at the largest order
+constexpr int NFULL = (FMM_PMAX + 1) * (FMM_PMAX + 1);   // all orders -n..n
+constexpr int OUT_PER_LANE = (NCMAX + FMM_WAVE - 1) / FMM_WAVE;
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// degree and order of coefficient index o (o = tri(n, m))
+__device__ __forceinline__ void nm_of(int o, int &n, int &m) {
+    n = 0;
+    while (tri(n + 1, 0) <= o) ++n;
+    m = o - tri(n, 0);
+}
+
+// Staging of an expansion into LDS as all orders -n <= q <= n at index
+// n^2 + n + q (eq:sym for q < 0).  Lane `lane` handles entries
+// e = lane + 64 r, r < STAGE_R; all its loads are issued before any is used.
+constexpr int STAGE_R = (NFULL + FMM_WAVE - 1) / FMM_WAVE;
+
+struct StageMap {
+    int src[STAGE_R];   // stored index tri(n, |q|), or -1 past the end
+    int q[STAGE_R];
+};
+
+__device__ __forceinline__ StageMap stage_map(int p, int lane) {
+    StageMap sm;
+    const int nf = (p + 1) * (p + 1);
+#pragma unroll
+    for (int r = 0; r < STAGE_R; ++r) {
+        const int e = lane + r * FMM_WAVE;
+        int n = (int)sqrtf((float)e);
+        while (n * n > e) --n;
+        while ((n + 1) * (n + 1) <= e) ++n;
+        const int q = e - n * n - n;
+        sm.src[r] = e < nf ? tri(n, q < 0 ? -q : q) : -1;
+        sm.q[r] = q;
+    }
+    return sm;
+}
+
+__device__ __forceinline__ void stage_load(const cplx *X, const StageMap &sm,
+                                           cplx (&v)[STAGE_R]) {
+#pragma unroll
+    for (int r = 0; r < STAGE_R; ++r)
+        if (sm.src[r] >= 0) v[r] = X[sm.src[r]];
+}
+
+__device__ __forceinline__ void stage_store(cplx *dst, const StageMap &sm, int lane,
+                                            const cplx (&v)[STAGE_R]) {
+#pragma unroll
+    for (int r = 0; r < STAGE_R; ++r)
+        if (sm.src[r] >= 0) dst[lane + r * FMM_WAVE] = sym(v[r], sm.q[r]);
+}
+
+// ---- M2M: one wavefront per parent, lanes over output coefficients ------------
+// M_n^m(z') = sum_{k=0}^{n} sum_{l=-k}^{k} Upsilon_k^l(z - z') M_{n-k}^{m-l}(z);
+// each child's M and shift Upsilon are staged (all orders) in the wavefront's
+// LDS.  plan[q * 64 + lane] is the lane's q-th output (or -1): outputs sorted
+// by their number of terms and dealt out in snake order, for balanced lanes.
+__global__ void __launch_bounds__(256)
+k_m2m_level(int p, TreeArrays t, int c0, int c1, const double *U, double *M, const short *plan) {
+    __shared__ cplx sU[4][NFULL], sM[4][NFULL];
+    const int w = threadIdx.x / FMM_WAVE, lane = lane_id();
+    const int c = c0 + blockIdx.x * 4 + w;
     if (c >= c1) return;
     const int nch = t.nchild[c];
     if (nch == 0) return;
-    int n = 0;
-    while (tri(n + 1, 0) <= o) ++n;
-    const int m = o - tri(n, 0);
+    const int nc = tri(p + 1, 0);
     const cplx *Ub = reinterpret_cast<const cplx *>(U);
     const cplx *Mb = reinterpret_cast<const cplx *>(M);
-    cplx acc = {0.0, 0.0};
-    const int k0 = t.child0[c];
-    for (int ch = k0; ch < k0 + nch; ++ch) {
-        const cplx *Uc = Ub + (size_t)ch * nc;
-        const cplx *Mc = Mb + (size_t)ch * nc;
-        for (int k = 0; k <= n; ++k) {
-            const int nn = n - k;
-            const int lmin = max(-k, m - nn), lmax = min(k, m + nn);
-            for (int l = lmin; l <= lmax; ++l) {
-                const cplx u = ld(Uc, k, l), v = ld(Mc, nn, m - l);
-                acc.re = fma(u.re, v.re, fma(-u.im, v.im, acc.re));
-                acc.im = fma(u.re, v.im, fma(u.im, v.re, acc.im));
-            }
-        }
+    int o[OUT_PER_LANE], on[OUT_PER_LANE], om[OUT_PER_LANE];
+#pragma unroll
+    for (int q = 0; q < OUT_PER_LANE; ++q) o[q] = plan[q * FMM_WAVE + lane];
+    cplx acc[OUT_PER_LANE];
+#pragma unroll
+    for (int q = 0; q < OUT_PER_LANE; ++q) {
+        on[q] = -1;
+        om[q] = 0;
+        if (o[q] >= 0) nm_of(o[q], on[q], om[q]);
+        acc[q] = {0.0, 0.0};
     }
-    if (m == 0) acc.im = 0.0;
-    reinterpret_cast<cplx *>(M)[(size_t)c * nc + o] = acc;
+    const StageMap sm = stage_map(p, lane);
+    const int k0 = t.child0[c];
+    cplx ru[STAGE_R], rm[STAGE_R];
+    stage_load(Ub + (size_t)k0 * nc, sm, ru);
+    stage_load(Mb + (size_t)k0 * nc, sm, rm);
+    for (int ch = k0; ch < k0 + nch; ++ch) {
+        stage_store(sU[w], sm, lane, ru);
+        stage_store(sM[w], sm, lane, rm);
+        wave_lds_sync();
+        if (ch + 1 < k0 + nch) {            // next child's data in flight meanwhile
+            stage_load(Ub + (size_t)(ch + 1) * nc, sm, ru);
+            stage_load(Mb + (size_t)(ch + 1) * nc, sm, rm);
+        }
+#pragma unroll
+        for (int q = 0; q < OUT_PER_LANE; ++q) {
+            const int n = on[q], m = om[q];
+            cplx a = acc[q];
+            for (int k = 0; k <= n; ++k) {
+                const int nn = n - k;
+                const int lmin = max(-k, m - nn), lmax = min(k, m + nn);
+                const int bu = k * k + k, bv = nn * nn + nn + m;
+#pragma unroll 4
+                for (int l = lmin; l <= lmax; ++l) {
+                    const cplx u = sU[w][bu + l], v = sM[w][bv - l];
+                    a.re = fma(u.re, v.re, fma(-u.im, v.im, a.re));
+                    a.im = fma(u.re, v.im, fma(u.im, v.re, a.im));
+                }
+            }
+            acc[q] = a;
+        }
+        wave_lds_sync();
+    }
+    cplx *Mc = reinterpret_cast<cplx *>(M) + (size_t)c * nc;
+#pragma unroll
+    for (int q = 0; q < OUT_PER_LANE; ++q)
+        if (on[q] >= 0) Mc[o[q]] = {acc[q].re, om[q] == 0 ? 0.0 : acc[q].im};
 }
 
 // ---- multipole power P_n^2 = sum_m (n-m)!(n+m)! |M_n^m|^2 ----------------------
@@ -129,36 +266,56 @@ __global__ void k_power(int p, int ncells, const double *M, double *P) {
     }
 }
 
-// ---- L2L: one thread per (child, coefficient) -------------------------------
+// ---- L2L: one wavefront per child, lanes over output coefficients ------------
 // F_n^m(s') += sum_{k=0}^{p-n} sum_l conj(Upsilon_k^l(s - s')) F_{n+k}^{m+l}(s),
-// with Upsilon_k^l(s - s') = (-1)^k Upsilon_k^l(s' - s) from the stored shift.
-__global__ void k_l2l_level(int p, TreeArrays t, int c0, int c1, const double *U, double *F) {
-    const int nc = tri(p + 1, 0);
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int c = c0 + (int)(gid / nc);
-    const int o = (int)(gid % nc);
+// with Upsilon_k^l(s - s') = (-1)^k Upsilon_k^l(s' - s) from the stored shift;
+// the parent's F and the child's shift are staged (all orders) in LDS; plan
+// as for M2M.
+__global__ void __launch_bounds__(256)
+k_l2l_level(int p, TreeArrays t, int c0, int c1, const double *U, double *F, const short *plan) {
+    __shared__ cplx sU[4][NFULL], sF[4][NFULL];
+    const int w = threadIdx.x / FMM_WAVE, lane = lane_id();
+    const int c = c0 + blockIdx.x * 4 + w;
     if (c >= c1) return;
     const int pc = t.parent[c];
     if (pc < 0) return;
-    int n = 0;
-    while (tri(n + 1, 0) <= o) ++n;
-    const int m = o - tri(n, 0);
-    const cplx *Uc = reinterpret_cast<const cplx *>(U) + (size_t)c * nc;
-    const cplx *Fp = reinterpret_cast<const cplx *>(F) + (size_t)pc * nc;
-    cplx acc = {0.0, 0.0};
-    for (int k = 0; k <= p - n; ++k) {
-        const double sg = (k & 1) ? -1.0 : 1.0;
-        for (int l = -k; l <= k; ++l) {
-            const cplx u = ld(Uc, k, l), f = ld(Fp, n + k, m + l);
-            // conj(sg u) * f
-            const double ur = sg * u.re, ui = -sg * u.im;
-            acc.re = fma(ur, f.re, fma(-ui, f.im, acc.re));
-            acc.im = fma(ur, f.im, fma(ui, f.re, acc.im));
-        }
+    const int nc = tri(p + 1, 0);
+    int o[OUT_PER_LANE];
+#pragma unroll
+    for (int q = 0; q < OUT_PER_LANE; ++q) o[q] = plan[q * FMM_WAVE + lane];
+    const StageMap sm = stage_map(p, lane);
+    {
+        cplx ru[STAGE_R], rf[STAGE_R];
+        stage_load(reinterpret_cast<const cplx *>(U) + (size_t)c * nc, sm, ru);
+        stage_load(reinterpret_cast<const cplx *>(F) + (size_t)pc * nc, sm, rf);
+        stage_store(sU[w], sm, lane, ru);
+        stage_store(sF[w], sm, lane, rf);
     }
-    cplx &dst = reinterpret_cast<cplx *>(F)[(size_t)c * nc + o];
-    dst.re += acc.re;
-    if (m != 0) dst.im += acc.im;
+    wave_lds_sync();
+    cplx *Fc = reinterpret_cast<cplx *>(F) + (size_t)c * nc;
+#pragma unroll
+    for (int q = 0; q < OUT_PER_LANE; ++q) {
+        if (o[q] < 0) continue;
+        int n, m;
+        nm_of(o[q], n, m);
+        cplx acc = {0.0, 0.0};
+        for (int k = 0; k <= p - n; ++k) {
+            const double sg = (k & 1) ? -1.0 : 1.0;
+            const int nk = n + k;
+            const int bu = k * k + k, bf = nk * nk + nk + m;
+#pragma unroll 4
+            for (int l = -k; l <= k; ++l) {
+                const cplx u = sU[w][bu + l], f = sF[w][bf + l];
+                // conj(sg u) * f
+                const double ur = sg * u.re, ui = -sg * u.im;
+                acc.re = fma(ur, f.re, fma(-ui, f.im, acc.re));
+                acc.im = fma(ur, f.im, fma(ui, f.re, acc.im));
+            }
+        }
+        cplx &dst = Fc[o[q]];
+        dst.re += acc.re;
+        if (m != 0) dst.im += acc.im;
+    }
 }
 
 // ---- L2P: one thread per particle ------------------------------------------
@@ -278,6 +435,41 @@ inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
 
+// Outputs sorted by their number of terms (most first, ties by index) and
+// dealt to the 64 lanes in snake order, row by row.
+void translation_plans(int p, short *m2m, short *l2l) {
+    static_assert(OUT_PER_LANE == FMM_PLAN_ROWS && FMM_PLAN_SIZE == FMM_PLAN_ROWS * FMM_WAVE, "plan rows");
+    const int nc = tri(p + 1, 0);
+    auto deal = [&](auto work, short *plan) {
+        std::vector<int> order(nc);
+        for (int o = 0; o < nc; ++o) order[o] = o;
+        std::vector<long> w(nc);
+        for (int n = 0; n <= p; ++n)
+            for (int m = 0; m <= n; ++m) w[tri(n, m)] = work(n, m);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return w[a] > w[b]; });
+        for (int i = 0; i < FMM_PLAN_ROWS * FMM_WAVE; ++i) plan[i] = -1;
+        for (int i = 0; i < nc; ++i) {
+            const int r = i / FMM_WAVE, pos = i % FMM_WAVE;
+            const int lane = (r & 1) ? FMM_WAVE - 1 - pos : pos;
+            plan[r * FMM_WAVE + lane] = (short)order[i];
+        }
+    };
+    deal([&](int n, int m) {
+        long c = 0;
+        for (int k = 0; k <= n; ++k) {
+            const int nn = n - k;
+            const int lo = std::max(-k, m - nn), hi = std::min(k, m + nn);
+            if (hi >= lo) c += hi - lo + 1;
+        }
+        return c;
+    }, m2m);
+    deal([&](int n, int) {
+        long c = 0;
+        for (int k = 0; k <= p - n; ++k) c += 2 * k + 1;
+        return c;
+    }, l2l);
+}
+
 hipError_t launch_p2m(int p, const TreeArrays &t, const int *leaf_cell, int nleaves,
                       const double *x, const double *y, const double *z, const double *m,
                       double *M, hipStream_t s) {
@@ -300,10 +492,10 @@ hipError_t launch_shift_upsilon(int p, const TreeArrays &t, int c0, int c1, doub
 }
 
 hipError_t launch_m2m_level(int p, const TreeArrays &t, int c0, int c1, const double *U,
-                            double *M, hipStream_t s) {
+                            double *M, const short *plan, hipStream_t s) {
     if (c1 <= c0) return hipSuccess;
-    const int64_t work = (int64_t)(c1 - c0) * tri(p + 1, 0);
-    hipLaunchKernelGGL(k_m2m_level, dim3(blocks(work, 128)), dim3(128), 0, s, p, t, c0, c1, U, M);
+    hipLaunchKernelGGL(k_m2m_level, dim3(blocks(c1 - c0, 4)), dim3(256), 0, s, p, t, c0, c1, U, M,
+                       plan);
     return hipGetLastError();
 }
 
@@ -313,10 +505,10 @@ hipError_t launch_power(int p, int ncells, const double *M, double *P, hipStream
 }
 
 hipError_t launch_l2l_level(int p, const TreeArrays &t, int c0, int c1, const double *U,
-                            double *F, hipStream_t s) {
+                            double *F, const short *plan, hipStream_t s) {
     if (c1 <= c0) return hipSuccess;
-    const int64_t work = (int64_t)(c1 - c0) * tri(p + 1, 0);
-    hipLaunchKernelGGL(k_l2l_level, dim3(blocks(work, 128)), dim3(128), 0, s, p, t, c0, c1, U, F);
+    hipLaunchKernelGGL(k_l2l_level, dim3(blocks(c1 - c0, 4)), dim3(256), 0, s, p, t, c0, c1, U, F,
+                       plan);
     return hipGetLastError();
 }
 

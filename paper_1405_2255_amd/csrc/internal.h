@@ -97,11 +97,17 @@ hipError_t launch_p2m(int p, const TreeArrays &t, const int *leaf_cell, int nlea
                       double *M, hipStream_t s);
 hipError_t launch_shift_upsilon(int p, const TreeArrays &t, int c0, int c1, double *U,
                                 hipStream_t s);
+// Output plans of the translation kernels: plan[q * 64 + lane] = the lane's
+// q-th coefficient index (or -1), q < FMM_PLAN_ROWS; m2m and l2l each hold
+// 64 * FMM_PLAN_ROWS entries.
+#define FMM_PLAN_ROWS 4
+#define FMM_PLAN_SIZE (FMM_PLAN_ROWS * 64)
+void translation_plans(int p, short *m2m, short *l2l);
 hipError_t launch_m2m_level(int p, const TreeArrays &t, int c0, int c1, const double *U,
-                            double *M, hipStream_t s);
+                            double *M, const short *plan, hipStream_t s);
 hipError_t launch_power(int p, int ncells, const double *M, double *P, hipStream_t s);
 hipError_t launch_l2l_level(int p, const TreeArrays &t, int c0, int c1, const double *U,
-                            double *F, hipStream_t s);
+                            double *F, const short *plan, hipStream_t s);
 // far field at every particle of every leaf: out4[i] = (Psi, ax, ay, az)
 hipError_t launch_l2p(int p, const TreeArrays &t, const int *leaf_of, const int *leaf_cell,
                       int64_t n, const double *x, const double *y, const double *z,
