@@ -131,6 +131,8 @@ struct fmm_ctx {
     DevBuf counters, nonfinite, walktmp, coffsets, roots, ckey, ckey2, order, order2;
     DevBuf dkey, dsort, dsort2, runstart;   // deep refinement below level 21
     DevBuf plans;                          // output plans of M2M and L2L for order plan_p
+    DevBuf M32, sig, Flow;                 // mixed-precision M2L: scaled multipoles, chunk
+                                           // scales, FP64 low-degree chunk parts
     int plan_p = -1;
     uint64_t *kdeep = nullptr;            // second key word of the sorted particles
     bool deep = false;
@@ -585,11 +587,25 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
         int4 *chunks = ensure<int4>(c->chunks, std::max(nchunks, 1));
         CK(launch_chunks(c->ncells, ptr<int64_t>(c->m2l_off), chunk, cnt, coff, tmp, total,
                          chunks, true, s));
-        double *Fpart = ensure<double>(c->Fpart, 2 * (size_t)nc * std::max(nchunks, 1));
-        if (c->opts.timing) CK(hipEventRecord(c->ev_m2l[0], s));
-        CK(launch_m2l(p, nchunks, chunks, c->m2l_sorted, c->sh, t, M, Fpart, s));
-        if (c->opts.timing) CK(hipEventRecord(c->ev_m2l[1], s));
-        CK(launch_m2l_reduce(p, c->ncells, coff, Fpart, F, s));
+        if (c->opts.precision == FMM_PREC_MIXED && p <= FMM_M2L_FIXED_MAX) {
+            float *M32 = ensure<float>(c->M32, 2 * (size_t)nc * c->ncells);
+            float *Fpart = ensure<float>(c->Fpart, 2 * (size_t)nc * std::max(nchunks, 1));
+            double *sig = ensure<double>(c->sig, std::max(nchunks, 1));
+            double *Flow = ensure<double>(c->Flow, 2 * (size_t)ncplx(FMM_M2L32_JLO) *
+                                                       std::max(nchunks, 1));
+            CK(launch_m2l32_multipoles(p, c->ncells, t, M, M32, s));
+            if (c->opts.timing) CK(hipEventRecord(c->ev_m2l[0], s));
+            CK(launch_m2l32(p, nchunks, chunks, c->m2l_sorted, c->sh, t, M, M32, Fpart, Flow, sig,
+                            s));
+            if (c->opts.timing) CK(hipEventRecord(c->ev_m2l[1], s));
+            CK(launch_m2l32_reduce(p, c->ncells, coff, Fpart, Flow, sig, F, s));
+        } else {
+            double *Fpart = ensure<double>(c->Fpart, 2 * (size_t)nc * std::max(nchunks, 1));
+            if (c->opts.timing) CK(hipEventRecord(c->ev_m2l[0], s));
+            CK(launch_m2l(p, nchunks, chunks, c->m2l_sorted, c->sh, t, M, Fpart, s));
+            if (c->opts.timing) CK(hipEventRecord(c->ev_m2l[1], s));
+            CK(launch_m2l_reduce(p, c->ncells, coff, Fpart, F, s));
+        }
     }
     mark(c, PH_M2L);
     // downward pass, far field at the particles

@@ -170,6 +170,18 @@ hipError_t launch_chunks(int ncells, const int64_t *off, int chunk, int *cnt, in
 hipError_t launch_m2l(int p, int nchunks, const int4 *chunks, const uint64_t *list, int sh,
                       const TreeArrays &t, const double *M, double *Fpart, hipStream_t s,
                       bool generic = false);
+// Mixed precision (orders up to FMM_M2L_FIXED_MAX): scaled FP32 multipoles,
+// FP32 chunk sums Fh with their scale sigma, the FP64 terms of degree
+// n + k <= FMM_M2L32_JLO per chunk (Flow: tri(min(p, JLO) + 1, 0) complex
+// each), reduction to FP64 F.
+#define FMM_M2L32_JLO 3
+hipError_t launch_m2l32_multipoles(int p, int ncells, const TreeArrays &t, const double *M,
+                                   float *M32, hipStream_t s);
+hipError_t launch_m2l32(int p, int nchunks, const int4 *chunks, const uint64_t *list, int sh,
+                        const TreeArrays &t, const double *M, const float *M32, float *Fpart,
+                        double *Flow, double *sig, hipStream_t s);
+hipError_t launch_m2l32_reduce(int p, int ncells, const int *coff, const float *Fpart,
+                               const double *Flow, const double *sig, double *F, hipStream_t s);
 hipError_t launch_m2l_reduce(int p, int ncells, const int *coff, const double *Fpart, double *F,
                              hipStream_t s);
 

@@ -12,6 +12,8 @@
 // each regenerating Theta.  Higher orders use the generic kernel below.
 // Each chunk writes its partial F; a second kernel adds the partial sums of
 // each sink in chunk order, so the result is deterministic.
+#include <algorithm>
+
 #include "internal.h"
 #include "harmonics.h"
 
@@ -22,6 +24,13 @@ namespace fmm {
 FMM_M2L_FIXED_DECL(1) FMM_M2L_FIXED_DECL(2) FMM_M2L_FIXED_DECL(3) FMM_M2L_FIXED_DECL(4)
 FMM_M2L_FIXED_DECL(5) FMM_M2L_FIXED_DECL(6) FMM_M2L_FIXED_DECL(7) FMM_M2L_FIXED_DECL(8)
 FMM_M2L_FIXED_DECL(9) FMM_M2L_FIXED_DECL(10) FMM_M2L_FIXED_DECL(11) FMM_M2L_FIXED_DECL(12)
+#define FMM_M2L32_FIXED_DECL(P)                                                                \
+    hipError_t launch_m2l32_fixed_##P(int, const int4 *, const uint64_t *, uint64_t,            \
+                                      const TreeArrays &, const double *, const float *, float *, \
+                                      double *, double *, hipStream_t);
+FMM_M2L32_FIXED_DECL(1) FMM_M2L32_FIXED_DECL(2) FMM_M2L32_FIXED_DECL(3) FMM_M2L32_FIXED_DECL(4)
+FMM_M2L32_FIXED_DECL(5) FMM_M2L32_FIXED_DECL(6) FMM_M2L32_FIXED_DECL(7) FMM_M2L32_FIXED_DECL(8)
+FMM_M2L32_FIXED_DECL(9) FMM_M2L32_FIXED_DECL(10) FMM_M2L32_FIXED_DECL(11) FMM_M2L32_FIXED_DECL(12)
 }  // namespace fmm
 
 namespace fmm {
@@ -129,6 +138,51 @@ __global__ void k_m2l_reduce(int ncells, int nc, const int *coff, const double *
     reinterpret_cast<cplx *>(F)[(size_t)c * nc + o] = s;
 }
 
+// FP32 copy of the multipoles, scaled per cell: Mh_n^m = M_n^m / s^n with
+// s = rho of the cell (1 for a point cell)
+__global__ void k_m2l32_multipoles(int ncells, int p, TreeArrays t, const double *M, float *M32) {
+    const int nc = tri(p + 1, 0);
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = (int)(gid / nc), o = (int)(gid % nc);
+    if (c >= ncells) return;
+    int n = 0;
+    while (tri(n + 1, 0) <= o) ++n;
+    const double rho = t.cen[c].w;
+    const double is = rho > 0.0 ? 1.0 / rho : 1.0;
+    double f = 1.0;
+    for (int i = 0; i < n; ++i) f *= is;
+    const cplx v = reinterpret_cast<const cplx *>(M)[(size_t)c * nc + o];
+    M32[2 * ((size_t)c * nc + o)] = (float)(v.re * f);
+    M32[2 * ((size_t)c * nc + o) + 1] = (float)(v.im * f);
+}
+
+// F_n^m of each sink = sum over its chunks (in order) of Fh_n^m sigma^{-(n+1)}
+// plus, for n <= nlo, the chunk's FP64 low-degree part
+// (Flow rows have tri(FMM_M2L32_JLO + 1, 0) entries, of which the first nclo
+// are used)
+__global__ void k_m2l32_reduce(int ncells, int nc, int nclo, const int *coff, const float *Fpart,
+                               const double *Flow, const double *sig, double *F) {
+    constexpr int LSTRIDE = tri(FMM_M2L32_JLO + 1, 0);
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = (int)(gid / nc), o = (int)(gid % nc);
+    if (c >= ncells) return;
+    int n = 0;
+    while (tri(n + 1, 0) <= o) ++n;
+    cplx s = {0.0, 0.0};
+    for (int k = coff[c]; k < coff[c + 1]; ++k) {
+        const double is = 1.0 / sig[k];
+        double f = is;
+        for (int i = 0; i < n; ++i) f *= is;
+        s.re += (double)Fpart[2 * ((size_t)k * nc + o)] * f;
+        s.im += (double)Fpart[2 * ((size_t)k * nc + o) + 1] * f;
+        if (o < nclo) {
+            s.re += Flow[2 * ((size_t)k * LSTRIDE + o)];
+            s.im += Flow[2 * ((size_t)k * LSTRIDE + o) + 1];
+        }
+    }
+    reinterpret_cast<cplx *>(F)[(size_t)c * nc + o] = s;
+}
+
 inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -174,6 +228,43 @@ hipError_t launch_m2l_reduce(int p, int ncells, const int *coff, const double *F
     const int nc = tri(p + 1, 0);
     hipLaunchKernelGGL(k_m2l_reduce, dim3(blocks((int64_t)ncells * nc, 256)), dim3(256), 0, s,
                        ncells, nc, coff, Fpart, F);
+    return hipGetLastError();
+}
+
+}  // namespace fmm
+
+namespace fmm {
+
+hipError_t launch_m2l32_multipoles(int p, int ncells, const TreeArrays &t, const double *M,
+                                   float *M32, hipStream_t s) {
+    const int nc = tri(p + 1, 0);
+    hipLaunchKernelGGL(k_m2l32_multipoles, dim3(blocks((int64_t)ncells * nc, 256)), dim3(256), 0,
+                       s, ncells, p, t, M, M32);
+    return hipGetLastError();
+}
+
+hipError_t launch_m2l32(int p, int nchunks, const int4 *chunks, const uint64_t *list, int sh,
+                        const TreeArrays &t, const double *M, const float *M32, float *Fpart,
+                        double *Flow, double *sig, hipStream_t s) {
+    if (nchunks <= 0) return hipSuccess;
+    const uint64_t mask = (1ull << sh) - 1;
+#define CALL(P)                                                                                \
+    return launch_m2l32_fixed_##P(nchunks, chunks, list, mask, t, M, M32, Fpart, Flow, sig, s)
+    switch (p) {
+    case 1: CALL(1);   case 2: CALL(2);   case 3: CALL(3);   case 4: CALL(4);
+    case 5: CALL(5);   case 6: CALL(6);   case 7: CALL(7);   case 8: CALL(8);
+    case 9: CALL(9);   case 10: CALL(10); case 11: CALL(11); case 12: CALL(12);
+    default: return hipErrorInvalidValue;
+    }
+#undef CALL
+}
+
+hipError_t launch_m2l32_reduce(int p, int ncells, const int *coff, const float *Fpart,
+                               const double *Flow, const double *sig, double *F, hipStream_t s) {
+    const int nc = tri(p + 1, 0);
+    const int nclo = tri(std::min(p, FMM_M2L32_JLO) + 1, 0);
+    hipLaunchKernelGGL(k_m2l32_reduce, dim3(blocks((int64_t)ncells * nc, 256)), dim3(256), 0, s,
+                       ncells, nc, nclo, coff, Fpart, Flow, sig, F);
     return hipGetLastError();
 }
 

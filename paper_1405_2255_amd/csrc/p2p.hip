@@ -208,7 +208,9 @@ k_p2p(int ntasks, const int2 *tasks, const int *leaf_cell, const int *nsrc_tasks
             const double4 *p = xyzm + rg.x + phase, *pe = xyzm + rg.y;
             const bool own = rg.x < sb + nb && rg.y > sb;   // overlaps the task's sinks
             if (MIXED) {
-                if (own) sum_range32<R, WANT_F, WITH_POT, true>(p, pe, S, xb, self, f);
+                // the sinks' own leaf holds their nearest neighbours, the largest
+                // terms: summed in FP64 also in mixed precision
+                if (own) sum_range<R, WANT_F, WITH_POT, true>(p, pe, S, xb, self, f);
                 else sum_range32<R, WANT_F, WITH_POT, false>(p, pe, S, xb, self, f);
             } else {
                 if (own) sum_range<R, WANT_F, WITH_POT, true>(p, pe, S, xb, self, f);

@@ -1,11 +1,14 @@
 """Mixed precision (FMM_PREC_MIXED): the same tree, estimate and walk as the
 FP64 mode, so the same accepted interactions as the FP64 oracle; the direct
-sums run in FP32 arithmetic.  Bounds derived from the arithmetic: each pair's
+sums outside the sinks' own leaves and the M2L terms of degree above 3 run in
+FP32 arithmetic.  The mode is meant for error targets of 1e-7 and above.  Bounds derived from the arithmetic: each pair's
 contribution carries a relative error below ~20 FP32 units (one rounding of
 the separation, r^2, the reciprocal square root, and the products), and the
 FP32 running sums over at most 32 terms add at most 32 units of the sum of
 magnitudes; so |a_mixed - a_fp64| <= 64 u32 sum_a mu_a / r_ab^2 <= 64 u32 f_b
-with f_b the scaled force of the exact direct sum."""
+with f_b the scaled force of the exact direct sum.  The FP32 M2L terms are
+smaller than the FP64 leading ones by theta^4 and add well below that bound
+(asserted with it; their typical size is checked statistically)."""
 import numpy as np
 import pytest
 
@@ -30,6 +33,8 @@ def _run(gpu_lib, pos, m, p, eps, precision, p2p_factor=0.5):
     ("plummer", 20011, "equal", 10, 1e-7),
     ("dehnen1.5", 12345, "salpeter", 8, 1e-6),
     ("uniform", 7777, "equal", 6, 1e-5),
+    ("plummer", 3000, "equal", 2, 1e-3),      # every degree in the FP64 part
+    ("dehnen1", 5000, "equal", 14, 1e-7),     # above the register kernels: FP64 M2L
 ])
 def test_mixed_within_fp32_bound_of_oracle(gpu_lib, kind, n, masses, p, eps):
     print(f"case {kind} n={n} p={p}", flush=True)
@@ -45,10 +50,10 @@ def test_mixed_within_fp32_bound_of_oracle(gpu_lib, kind, n, masses, p, eps):
     assert np.all(da <= bound), float(np.max(da / bound))
     # potential: the same argument with sum mu / r = |pot|
     assert np.all(np.abs(pot - ref["pot"]) <= 64 * U32 * np.abs(p0) + 1e-10 * np.abs(ref["pot"]))
-    # typical size of the FP32 rounding: well below the error target
+    # typical size of the FP32 rounding: below the 1e-7 targets the mode is for
     rel = da / np.linalg.norm(ref["acc"], axis=1)
     print("mixed vs fp64 oracle: rms", np.sqrt(np.mean(rel ** 2)), "max", rel.max(), flush=True)
-    assert np.sqrt(np.mean(rel ** 2)) < 0.5 * eps
+    assert np.sqrt(np.mean(rel ** 2)) < 0.5e-7
 
 
 def test_mixed_accuracy_against_direct_sum(gpu_lib):
