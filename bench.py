@@ -15,12 +15,18 @@ Prints ONE JSON line (rank 0): metric, value, ... plus
   roofline      for the dominant kernel (algorithmic FLOP per launch / the
                 launch's HIP-event duration on the library's stream)
   cpu_baseline  the CPU oracle (direct sum) on a bounded sample of sinks
+  mixed         the same N = 1e6 evaluation in mixed precision (FP32 pair and
+                high-degree M2L arithmetic, FP64 sums), errors on all particles
   batched       512 independent Plummer clusters, N log-uniform in [1e3, 1e5],
-                in one call, against the same clusters one call each
+                in one call (FP64 and mixed), against the same clusters one
+                call each
+  c3            Dehnen gamma = 1 cusps with power-law masses, N = 1e6 and 1e7,
+                mixed precision, targets 1e-5 and 1e-7 (errors on 4096 sinks
+                against the GPU FP64 direct sum)
   served        a Poisson stream of requests (N log-uniform in [1e4, 4e6],
                 mixed profiles and error targets, 10 drift steps each with the
-                tree recycled) through the serving loop: p50/p99 latency and
-                throughput at an offered load of 0.8
+                tree recycled, mixed precision) through the serving loop:
+                p50/p99 latency and throughput at an offered load of 0.8
 """
 from __future__ import annotations
 
@@ -58,7 +64,15 @@ def _pct(e, q):
     return float(e[min(max(int(np.ceil(q / 100.0 * e.size)) - 1, 0), e.size - 1)])
 
 
-def batched_leg(args, fmm, workloads):
+def _summary(e):
+    """rms, median and nearest-rank percentiles of per-particle errors."""
+    e = np.asarray(e, dtype=np.float64)
+    return {"rms": float(np.sqrt(np.mean(e ** 2))), "median": _pct(e, 50), "p99": _pct(e, 99),
+            "p99.9": _pct(e, 99.9), "p99.99": _pct(e, 99.99), "max": float(e.max()),
+            "n": int(e.size)}
+
+
+def batched_leg(args, fmm, workloads, precision="fp64"):
     """K independent Plummer clusters (total mass 1, scale radius 1 each,
     equal masses) with N log-uniform in [1e3, 1e5], evaluated in one call;
     errors against the GPU direct sum on every 16th cluster; the same
@@ -77,7 +91,8 @@ def batched_leg(args, fmm, workloads):
     pot = torch.empty(ntot, dtype=torch.float64, device=dev)
     acc = torch.empty((ntot, 3), dtype=torch.float64, device=dev)
     eps = args.eps if args.eps is not None else 5e-8
-    ctx = fmm.Context(device=0, leaf_size=args.leaf, p2p_factor=args.p2p_factor, timing=True)
+    ctx = fmm.Context(device=0, leaf_size=args.leaf, p2p_factor=args.p2p_factor, timing=True,
+                      precision=precision)
     ctx.forces_batched(off, P, M, 1.0, args.p, eps, pot, acc)
     torch.cuda.synchronize()
     reps = 3
@@ -87,8 +102,8 @@ def batched_leg(args, fmm, workloads):
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / reps
     st = ctx.stats()
-    print(f"batched: {k} clusters, {ntot} particles, {1e3 * t_batch:.1f} ms", file=sys.stderr,
-          flush=True)
+    print(f"batched ({precision}): {k} clusters, {ntot} particles, {1e3 * t_batch:.1f} ms",
+          file=sys.stderr, flush=True)
     errs = []
     for i in range(0, k, 16):
         a, b = int(off[i]), int(off[i + 1])
@@ -97,7 +112,8 @@ def batched_leg(args, fmm, workloads):
     e = np.concatenate(errs)
     print(f"batched: errors checked on {len(errs)} clusters", file=sys.stderr, flush=True)
     # one call per cluster (after one warm pass that sizes the workspace)
-    single = fmm.Context(device=0, leaf_size=args.leaf, p2p_factor=args.p2p_factor)
+    single = fmm.Context(device=0, leaf_size=args.leaf, p2p_factor=args.p2p_factor,
+                         precision=precision)
     for i in range(k):
         a, b = int(off[i]), int(off[i + 1])
         single.forces(P[a:b], M[a:b], 1.0, args.p, eps, pot[a:b], acc[a:b])
@@ -112,7 +128,8 @@ def batched_leg(args, fmm, workloads):
     ctx.close()
     single.close()
     return {"workload": f"{k} Plummer clusters, N log-uniform in [1e3, 1e5] (seed "
-                        f"{args.seed + 77}), {ntot} particles, FP64, eps={eps:g}, p={st['p']}",
+                        f"{args.seed + 77}), {ntot} particles, {precision}, eps={eps:g}, "
+                        f"p={st['p']}",
             "value": ntot / t_batch, "unit": "particle-forces/s", "ms_per_call": 1e3 * t_batch,
             "one_call_per_cluster": {"value": ntot / t_single, "ms": 1e3 * t_single},
             "errors_vs_gpu_direct": {"clusters_checked": len(errs), "sinks": int(e.size),
@@ -120,6 +137,50 @@ def batched_leg(args, fmm, workloads):
                                      "p99.9": _pct(e, 99.9), "max": float(e.max())},
             "phases_ms": {k_: st[k_] for k_ in ("t_tree", "t_estimate", "t_up", "t_walk",
                                                 "t_m2l", "t_down", "t_p2p", "t_total")}}
+
+
+def c3_leg(args, fmm, workloads):
+    """Dehnen gamma = 1 cusp, power-law (Salpeter) masses on [0.1, 100]
+    normalised to 1, N = 1e6 and 1e7, mixed precision, rms targets 1e-5 and
+    1e-7 (epsilon = half the target); errors on 4096 seeded sinks against the
+    GPU FP64 direct sum of those sinks."""
+    import torch
+    out = []
+    dev = torch.device("cuda:0")
+    for n in (10**6, 10**7):
+        pos, m = workloads.cluster("dehnen1", n, args.seed + 5, masses="salpeter")
+        P, M = torch.from_numpy(pos).to(dev), torch.from_numpy(m).to(dev)
+        del pos, m
+        sinks = torch.from_numpy(np.sort(np.random.default_rng(n).choice(n, 4096, replace=False))
+                                 ).to(dev)
+        ctx = fmm.Context(device=0, timing=True, precision="mixed")
+        _, ad = ctx.direct_sinks(P, M, sinks, 1.0)
+        for target in (1e-5, 1e-7):
+            eps = 0.5 * target
+            ctx.forces(P, M, 1.0, -1, eps)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(2):
+                t0 = time.perf_counter()
+                _, acc = ctx.forces(P, M, 1.0, -1, eps)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            st = ctx.stats()
+            e = _rel_err(acc[sinks], ad)
+            out.append({"n": n, "target_rms": target, "eps": eps, "p": st["p"],
+                        "value": n / min(ts), "unit": "particle-forces/s",
+                        "ms": 1e3 * min(ts), "depth": st["depth"],
+                        "rms": float(np.sqrt(np.mean(e ** 2))), "p99.9": _pct(e, 99.9),
+                        "max": float(e.max())})
+            print(f"c3: n={n} target {target:g}: {1e3 * min(ts):.1f} ms, rms {out[-1]['rms']:.2e}",
+                  file=sys.stderr, flush=True)
+        ctx.close()
+        del P, M
+        torch.cuda.empty_cache()
+    return {"workload": "Dehnen gamma=1, Salpeter masses (slope 2.35, [0.1, 100], total 1), "
+                        "mixed precision, errors on 4096 sinks vs GPU FP64 direct sum",
+            "runs": out,
+            "all_within_target": bool(all(r["rms"] <= r["target_rms"] for r in out))}
 
 
 SERVE_KINDS = ("plummer", "dehnen0", "dehnen1", "dehnen1.5", "uniform")
@@ -155,7 +216,7 @@ def serve_leg(args, fmm, workloads, capacity_pfs):
         return serve.Request(pos=pos, mass=m, target_err=0.5 * float(errs[i]), steps=steps,
                              vel=vel, dt=1e-3)
 
-    srv = serve.Server(device=0, slots=args.serve_slots)
+    srv = serve.Server(device=0, slots=args.serve_slots, precision="mixed")
     # warm every slot's workspace with the largest request
     big = int(np.argmax(sizes))
     warm = [srv.submit(make(big, 1)) for _ in range(args.serve_slots)]
@@ -202,7 +263,8 @@ def serve_leg(args, fmm, workloads, capacity_pfs):
                         f"of the single-request throughput, N log-uniform in [1e4, "
                         f"{args.serve_nmax:g}], profiles {'/'.join(SERVE_KINDS)}, rms targets "
                         f"1e-5/1e-6/1e-7, {steps} evaluations per request with drift "
-                        f"(dt=1e-3) and tree recycling, {args.serve_slots} slots",
+                        f"(dt=1e-3) and tree recycling, mixed precision, {args.serve_slots} "
+                        f"slots",
             "latency": lat, "value": work / t_all, "unit": "particle-forces/s",
             "seconds": t_all, "mean_service_s_estimate": mean_service,
             "accuracy_last_step": checks,
@@ -226,6 +288,8 @@ def main() -> int:
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--no-cpu", action="store_true", help="omit the CPU baseline field")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-c3", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--batched-clusters", type=int, default=512)
     ap.add_argument("--serve-requests", type=int, default=24)
@@ -278,11 +342,12 @@ def main() -> int:
     _, a_true, _ = oracle.direct(pos_np, m_np, sinks=sinks, threads=cores)
     t_cpu = time.perf_counter() - t1
     rel = np.linalg.norm(acc_np[sinks] - a_true, axis=1) / np.linalg.norm(a_true, axis=1)
-    err_oracle = oracle.error_summary(rel)
+    err_oracle = _summary(rel)
     print(f"errors vs oracle ({len(sinks)} sinks): {err_oracle}", file=sys.stderr, flush=True)
 
     direct = None
     err_direct = None
+    ad_all = None
     if not args.no_direct:
         torch.cuda.synchronize()
         t2 = time.perf_counter()
@@ -290,8 +355,9 @@ def main() -> int:
         torch.cuda.synchronize()
         t_direct = time.perf_counter() - t2
         ad = acc_d.cpu().numpy()
+        ad_all = ad
         rel_d = np.linalg.norm(acc_np - ad, axis=1) / np.linalg.norm(ad, axis=1)
-        err_direct = oracle.error_summary(rel_d)
+        err_direct = _summary(rel_d)
         chk = np.linalg.norm(ad[sinks] - a_true, axis=1) / np.linalg.norm(a_true, axis=1)
         direct = {"value": n / t_direct, "unit": "particle-forces/s", "ms": 1e3 * t_direct,
                   "pair_interactions_per_s": float(n) * (n - 1) / t_direct,
@@ -325,7 +391,35 @@ def main() -> int:
                "seconds": t_cpu}
 
     value = n / (ms_per_step * 1e-3)
-    batched = None if args.no_batched else batched_leg(args, fmm, workloads)
+    mixed = None
+    if not args.no_mixed:
+        ctxm = fmm.Context(device=0, leaf_size=args.leaf, p2p_factor=args.p2p_factor, timing=True,
+                           precision="mixed")
+        for _ in range(max(1, args.warmup)):
+            ctxm.forces(pos, mass, 1.0, args.p, eps, pot, acc)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctxm.forces(pos, mass, 1.0, args.p, eps, pot, acc)
+        torch.cuda.synchronize()
+        ms_m = 1e3 * (time.perf_counter() - t0) / args.steps
+        stm = ctxm.stats()
+        mixed = {"value": n / (ms_m * 1e-3), "unit": "particle-forces/s", "ms_per_step": ms_m,
+                 "vs_fp64": ms_per_step / ms_m,
+                 "phases_ms": {k: stm[k] for k in ("t_tree", "t_estimate", "t_up", "t_walk",
+                                                   "t_m2l", "t_down", "t_p2p", "t_total")},
+                 "m2l_kernel_ms": stm["t_m2l_kernel"], "p2p_kernel_ms": stm["t_p2p_kernel"]}
+        if ad_all is not None:
+            rel_m = np.linalg.norm(acc.cpu().numpy() - ad_all, axis=1) / np.linalg.norm(ad_all, axis=1)
+            mixed["errors_vs_gpu_direct_all"] = _summary(rel_m)
+            mixed["meets_target"] = bool(mixed["errors_vs_gpu_direct_all"]["rms"] <= target_rms)
+        ctxm.close()
+        print(f"mixed: {ms_m:.2f} ms/step", file=sys.stderr, flush=True)
+    batched = None
+    if not args.no_batched:
+        batched = {"fp64": batched_leg(args, fmm, workloads, "fp64"),
+                   "mixed": batched_leg(args, fmm, workloads, "mixed")}
+    c3 = None if args.no_c3 else c3_leg(args, fmm, workloads)
     served = None if args.no_serve else serve_leg(args, fmm, workloads, value)
 
     phases = {k: st[k] for k in ("t_tree", "t_estimate", "t_up", "t_walk", "t_m2l", "t_down",
@@ -354,7 +448,9 @@ def main() -> int:
         "direct": direct,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "mixed": mixed,
         "batched": batched,
+        "c3": c3,
         "served": served,
         "phases_ms": phases,
         "counts": {k: st[k] for k in ("n_cells", "n_leaves", "depth", "n_m2l", "n_p2p_lists",

@@ -146,6 +146,14 @@ fmm_status fmm_forces_refit(fmm_ctx *ctx, int64_t n, const double *pos, const do
 fmm_status fmm_direct(fmm_ctx *ctx, int64_t n, const double *pos, const double *mass,
                       double G, double *pot, double *acc);
 
+/* The same exact sum for selected sinks only: sinks[j] (device int64,
+ * 0 <= sinks[j] < n) receives pot[j] and acc[3j..3j+2] from all n sources
+ * (a != sinks[j]).  An index out of range gives FMM_E_INVAL (such entries are
+ * not read; the others are written). */
+fmm_status fmm_direct_sinks(fmm_ctx *ctx, int64_t n, const double *pos, const double *mass,
+                            double G, int64_t nsinks, const int64_t *sinks, double *pot,
+                            double *acc);
+
 /* Expansion order used when fmm_forces gets p < 0. */
 int fmm_order_for_error(double target_err);
 

@@ -887,6 +887,29 @@ fmm_status fmm_direct(fmm_ctx *c, int64_t n, const double *pos, const double *ma
     });
 }
 
+fmm_status fmm_direct_sinks(fmm_ctx *c, int64_t n, const double *pos, const double *mass,
+                            double G, int64_t nsinks, const int64_t *sinks, double *pot,
+                            double *acc) {
+    if (!c) return FMM_E_INVAL;
+    fmm::Guard g(c);
+    if (!g.ok) return FMM_E_BUSY;
+    c->err.clear();
+    if (n < 0 || nsinks < 0 || (nsinks > 0 && (!pos || !mass || !sinks || !pot || !acc)) ||
+        !std::isfinite(G))
+        return fmm::fail(c, FMM_E_INVAL, "bad argument");
+    if (nsinks == 0) return FMM_OK;
+    if (n == 0) return fmm::fail(c, FMM_E_INVAL, "sink index out of range");
+    return fmm::guarded(c, [&]() -> fmm_status {
+        int *bad = fmm::ensure<int>(c->nonfinite, 8) + 5;
+        CK(hipMemsetAsync(bad, 0, sizeof(int), c->stream));
+        CK(fmm::launch_direct_sinks(n, pos, mass, G, nsinks, sinks, pot, acc, bad, c->stream));
+        CK(hipMemcpyAsync(c->hint, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        fmm::sync(c);
+        if (c->hint[0]) return fmm::fail(c, FMM_E_INVAL, "sink index out of range");
+        return FMM_OK;
+    });
+}
+
 fmm_status fmm_stats(const fmm_ctx *c, fmm_stats_t *out) {
     if (!c || !out) return FMM_E_INVAL;
     *out = c->st;

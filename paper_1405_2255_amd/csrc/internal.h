@@ -208,6 +208,9 @@ hipError_t launch_output(int64_t n, const uint32_t *perm, const double4 *out4, d
                          double *pot, double *acc, int *nonfinite, hipStream_t s);
 hipError_t launch_scale(int want_f, int64_t n, const double4 *est4, double *scale,
                         hipStream_t s);
+hipError_t launch_direct_sinks(int64_t n, const double *pos, const double *mass, double G,
+                               int64_t nsinks, const int64_t *sinks, double *pot, double *acc,
+                               int *bad, hipStream_t s);
 hipError_t launch_direct(int64_t n, const double *pos, const double *mass, double G,
                          double *pot, double *acc, hipStream_t s);
 

@@ -290,6 +290,36 @@ k_direct(int64_t n, const double *pos, const double *mass, double G, double *pot
     acc[3 * i + 2] = G * az;
 }
 
+// the same for listed sinks; an index outside [0, n) sets *bad
+__global__ void __launch_bounds__(256)
+k_direct_sinks(int64_t n, const double *pos, const double *mass, double G, int64_t nsinks,
+               const int64_t *sinks, double *pot, double *acc, int *bad) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t ii = t < nsinks ? sinks[t] : 0;
+    const bool valid = t < nsinks && ii >= 0 && ii < n;
+    if (t < nsinks && !valid) atomicOr(bad, 1);
+    if (!valid) ii = 0;
+    const double xb = pos[3 * ii], yb = pos[3 * ii + 1], zb = pos[3 * ii + 2];
+    double p = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        const double dx = pos[3 * j] - xb, dy = pos[3 * j + 1] - yb, dz = pos[3 * j + 2] - zb;
+        const bool self = j == ii;
+        const double r2 = self ? 1.0 : fma(dx, dx, fma(dy, dy, dz * dz));
+        const double mu = self ? 0.0 : mass[j];
+        const double ri = rsqrt_nr(r2);
+        const double q = mu * ri, q3 = q * ri * ri;
+        p += q;
+        ax = fma(q3, dx, ax);
+        ay = fma(q3, dy, ay);
+        az = fma(q3, dz, az);
+    }
+    if (!valid) return;
+    pot[t] = -G * p;
+    acc[3 * t] = G * ax;
+    acc[3 * t + 1] = G * ay;
+    acc[3 * t + 2] = G * az;
+}
+
 __global__ void k_output(int64_t n, const uint32_t *perm, const double4 *out4, double G,
                          double *pot, double *acc, int *nonfinite) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -375,6 +405,14 @@ hipError_t launch_output(int64_t n, const uint32_t *perm, const double4 *out4, d
 hipError_t launch_scale(int want_f, int64_t n, const double4 *est4, double *scale,
                         hipStream_t s) {
     hipLaunchKernelGGL(k_scale, dim3(blocks(n, 256)), dim3(256), 0, s, want_f, n, est4, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_direct_sinks(int64_t n, const double *pos, const double *mass, double G,
+                               int64_t nsinks, const int64_t *sinks, double *pot, double *acc,
+                               int *bad, hipStream_t s) {
+    hipLaunchKernelGGL(k_direct_sinks, dim3(blocks(nsinks, 256)), dim3(256), 0, s, n, pos, mass,
+                       G, nsinks, sinks, pot, acc, bad);
     return hipGetLastError();
 }
 

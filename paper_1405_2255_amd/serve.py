@@ -96,7 +96,7 @@ class Request:
 
 class Server:
     def __init__(self, device: int = 0, slots: int = 4, budget_bytes: int | None = None,
-                 leaf_size: int = 0, p2p_factor: float = 0.0):
+                 leaf_size: int = 0, p2p_factor: float = 0.0, precision: str = "fp64"):
         self.device = device
         if budget_bytes is None:
             free, total = torch.cuda.mem_get_info(device)
@@ -115,7 +115,8 @@ class Server:
                 self.streams.append(st)
                 self.contexts.append(fmm.Context(device=device, stream=st, leaf_size=leaf_size,
                                                  p2p_factor=p2p_factor,
-                                                 scale_source="previous", timing=True))
+                                                 scale_source="previous", timing=True,
+                                                 precision=precision))
         self._threads = [threading.Thread(target=self._loop, daemon=True)
                          for _ in range(slots)]
         for t in self._threads:

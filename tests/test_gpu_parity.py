@@ -230,3 +230,19 @@ def test_error_paths(ctx, gpu_lib):
     pot, acc = ctx.forces(P, M, p=6, target_err=1e-6)
     torch.cuda.synchronize()
     assert torch.isfinite(acc).all()
+
+
+def test_direct_sinks_matches_oracle(ctx, gpu_lib):
+    """The exact sum for listed sinks (the reference used on large inputs)."""
+    import torch
+    pos, m = W.cluster("dehnen1", 6000, 3, masses="salpeter")
+    P, M = _to_dev(pos, m)
+    sinks = np.array([0, 5999, 17, 17, 3000, 1234], dtype=np.int64)
+    pot, acc = ctx.direct_sinks(P, M, torch.from_numpy(sinks).cuda(), G=2.0)
+    torch.cuda.synchronize()
+    p0, a0, _ = oracle.direct(pos, m, G=2.0, sinks=sinks)
+    np.testing.assert_allclose(pot.cpu().numpy(), p0, rtol=1e-12)
+    assert _rel(acc.cpu().numpy(), a0).max() < 1e-12
+    with pytest.raises(gpu_lib.FMMError) as e:
+        ctx.direct_sinks(P, M, torch.tensor([3, 6000], dtype=torch.int64, device="cuda"))
+    assert e.value.status == gpu_lib.E_INVAL
