@@ -296,6 +296,9 @@ def main() -> int:
     ap.add_argument("--serve-nmax", type=float, default=4e6)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-load", type=float, default=0.8)
+    ap.add_argument("--calib-copy", type=int, default=0,
+                    help="only copy a device buffer of this many MiB three times (the "
+                         "reference kernel for scaling HBM byte counters), then exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -303,6 +306,16 @@ def main() -> int:
         return 2
 
     import torch
+    if args.calib_copy > 0:
+        nbytes = args.calib_copy << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes_read": nbytes, "calib_copy_bytes_written": nbytes,
+                          "launches": 3}), flush=True)
+        return 0
     import oracle
     from paper_1405_2255_amd import fmm, workloads
 

@@ -74,4 +74,17 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
     return fma(y * 0.5, e, y);
 }
 
+// XCD-aware block order.  Workgroups are handed to the 8 XCDs of the chip in
+// turn (block b to XCD b % 8), and each XCD has its own L2.  Work items in
+// Morton order that are close share their inputs (neighbouring sinks read
+// mostly the same sources), so block b is given logical index
+// start(x) + b / 8 with x = b % 8: XCD x then processes one contiguous eighth
+// of the work.  A bijection of [0, nb) for any nb.
+constexpr int FMM_NXCD = 8;
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int x = b % FMM_NXCD, j = b / FMM_NXCD;
+    const int q = nb / FMM_NXCD, r = nb % FMM_NXCD;
+    return x * q + (x < r ? x : r) + j;
+}
+
 }  // namespace fmm

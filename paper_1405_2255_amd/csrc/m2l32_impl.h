@@ -182,7 +182,7 @@ template <int P>
 __global__ void __launch_bounds__(64)
 k_m2l32(int nchunks, const int4 *chunks, const uint64_t *list, uint64_t mask, TreeArrays t,
         const double *M, const float *M32, float *Fpart, double *Flow, double *sig) {
-    const int ch = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ch = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (ch >= nchunks) return;
     const int4 c = chunks[ch];
     // sigma: the smallest separation of the chunk

@@ -89,7 +89,7 @@ template <int P>
 __global__ void __launch_bounds__(64)
 k_m2l(int nchunks, const int4 *chunks, const uint64_t *list, uint64_t mask, TreeArrays t,
       const double *M, double *Fpart) {
-    const int ch = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ch = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (ch >= nchunks) return;
     const int4 c = chunks[ch];
     cplx *out = reinterpret_cast<cplx *>(Fpart) + (size_t)ch * tri(P + 1, 0);

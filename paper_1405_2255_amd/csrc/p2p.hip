@@ -166,7 +166,7 @@ k_p2p(int ntasks, const int2 *tasks, const int *leaf_cell, const int *nsrc_tasks
       const int *moff, const int64_t *off, const int2 *range, TreeArrays t, const double4 *xyzm,
       double4 *out4, double4 *partial) {
     __shared__ double4 red[4][R * FMM_WAVE];
-    const int task = blockIdx.x * 4 + threadIdx.x / FMM_WAVE;
+    const int task = xcd_block(blockIdx.x, gridDim.x) * 4 + threadIdx.x / FMM_WAVE;
     if (task >= ntasks) return;
     const int lane = lane_id(), w = threadIdx.x / FMM_WAVE;
     const int2 tk = tasks[task];
