@@ -50,6 +50,24 @@ def m2l_flops(p: int) -> float:
     return 8.0 * sum((n + 1) * (p - n + 1) ** 2 for n in range(p + 1))
 
 
+def _measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 byte-counter
+    summary, or None if the kernel's sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "fmm_plummer_1e6_hbm_bytes.md")
+    try:
+        line = next(l for l in open(path) if l.startswith("traffic-json:"))
+        rec = json.loads(line.split(":", 1)[1])[kernel]
+    except (OSError, StopIteration, KeyError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != rec["sha256"]:
+        return None
+    return rec["fetch_bytes"] + rec["write_bytes"]
+
+
 P2P_FLOPS = 20.0   # per ordered particle pair: 3 sub, 5 for r^2, rsqrt, 3 mul, 3 fma, 1 add (+ rsqrt)
 
 
@@ -390,7 +408,7 @@ def main() -> int:
     achieved = kflop / (kms * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": kname, "achieved": achieved,
                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": _measured_traffic(kname),
                 "launch_ms": kms, "algorithmic_flop_per_launch": kflop,
                 "other": {"k_m2l": {"ms": m2l_ms, "tflops": m2l_f / (m2l_ms * 1e-3) / 1e12},
                           "k_p2p": {"ms": p2p_ms, "tflops": p2p_f / (p2p_ms * 1e-3) / 1e12}}}
