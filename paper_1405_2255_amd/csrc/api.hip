@@ -126,7 +126,7 @@ struct fmm_ctx {
         rho2, smin, leaf_cell, M, F, P, U, Fe;
     // walk
     DevBuf fa, fb, m2l, m2l2, p2p, p2p2, p2pe, p2pe2, m2l_off, p2p_off, chunks, ccnt, coff, Fpart;
-    DevBuf rflag, ranges, rkey;
+    DevBuf rflag, ranges, rkey, wcode;
     DevBuf pt_n, pt_m, pt_s, pt_off, pt_moff, ptasks, ppart;
     DevBuf counters, nonfinite, walktmp, coffsets, roots, ckey, ckey2, order, order2;
     DevBuf dkey, dsort, dsort2, runstart;   // deep refinement below level 21
@@ -376,12 +376,13 @@ Lists walk(fmm_ctx *c, const WalkParams &wp0, const double *P) {
         uint2 *fa = ensure<uint2>(c->fa, cap_f), *fb = ensure<uint2>(c->fb, cap_f);
         uint64_t *ml = ensure<uint64_t>(c->m2l, cap_m), *pl = ensure<uint64_t>(c->p2p, cap_p);
         uint32_t *pe = ensure<uint32_t>(c->p2pe, cap_p);
+        uint16_t *code = ensure<uint16_t>(c->wcode, cap_f);
         CK(hipMemsetAsync(cnt, 0, (8 + sweeps) * sizeof(unsigned long long), s));
         CK(launch_root_pairs(fa, c->nroots, s));           // (r, r) for every root
         if (c->opts.timing) CK(hipEventRecord(c->ev_walk[0], s));
         for (int i = 0; i < sweeps; ++i) {
             WalkBuffers wb{(i & 1) ? fb : fa, (i & 1) ? fa : fb, cap_f, ml, cap_m, pl, pe, cap_p,
-                           cnt};
+                           cnt, code};
             CK(launch_walk(wp, t, P, wb, i, btmp, s));
         }
         if (c->opts.timing) CK(hipEventRecord(c->ev_walk[1], s));

@@ -141,6 +141,7 @@ struct WalkBuffers {
     uint64_t *p2p; uint32_t *p2p_end; int64_t cap_p2p;   // key, end of the source range
     unsigned long long *counters;   // [0] m2l, [1] direct entries, [2] direct particle
                                     // pairs, [3] overflow, [4 + i] frontier after sweep i
+    uint16_t *code;                 // cap_out: each input pair's decision (count -> write)
 };
 // sweep i reads the frontier size from counters[4 + i - 1] (1 for sweep 0);
 // btmp holds walk_tmp_u64() entries of per-block scratch

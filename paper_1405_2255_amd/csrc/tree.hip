@@ -37,11 +37,25 @@ __device__ __forceinline__ int cluster_of(const int64_t *off, int K, int64_t i) 
 }
 
 // bounding box of every cluster: bb[6k..6k+5] = min x, y, z, max x, y, z as
-// order-preserving keys
+// order-preserving keys.  A wavefront keeps the box of its current cluster
+// over its chunks of the grid-stride loop and commits it (6 atomics) only when
+// the cluster changes and at the end; a chunk that spans clusters commits
+// per lane.
+__device__ __forceinline__ void commit_box(unsigned long long *bb, int c, const double *lo,
+                                           const double *hi) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        atomicMin(&bb[6 * c + d], ordered_key(lo[d]));
+        atomicMax(&bb[6 * c + 3 + d], ordered_key(hi[d]));
+    }
+}
+
 __global__ void k_bbox(const double *pos, int64_t n, int K, const int64_t *off,
                        unsigned long long *bb) {
     const int lane = lane_id();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int run = -1;
+    double rlo[3] = {INFINITY, INFINITY, INFINITY}, rhi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(FMM_WAVE - 1));
          base < n; base += stride) {
         const int64_t i = base + lane;
@@ -65,21 +79,26 @@ __global__ void k_bbox(const double *pos, int64_t n, int K, const int64_t *off,
                     hi[d] = fmax(hi[d], __shfl_xor(hi[d], o, FMM_WAVE));
                 }
             }
-            if (lane == 0) {
+            if (c0 != run) {
+                if (run >= 0 && lane == 0) commit_box(bb, run, rlo, rhi);
+                run = c0;
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    atomicMin(&bb[6 * c0 + d], ordered_key(lo[d]));
-                    atomicMax(&bb[6 * c0 + 3 + d], ordered_key(hi[d]));
+                    rlo[d] = lo[d];
+                    rhi[d] = hi[d];
+                }
+            } else {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    rlo[d] = fmin(rlo[d], lo[d]);
+                    rhi[d] = fmax(rhi[d], hi[d]);
                 }
             }
         } else if (valid) {
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                atomicMin(&bb[6 * cl + d], ordered_key(lo[d]));
-                atomicMax(&bb[6 * cl + 3 + d], ordered_key(hi[d]));
-            }
+            commit_box(bb, cl, lo, hi);
         }
     }
+    if (run >= 0 && lane == 0) commit_box(bb, run, rlo, rhi);
 }
 
 __global__ void k_bbox_init(int K, unsigned long long *bb) {
@@ -485,7 +504,7 @@ hipError_t launch_bbox(const double *pos, int64_t n, int K, const int64_t *off,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     unsigned g = blocks(n, 256);
-    if (g > 2048) g = 2048;
+    if (g > 256) g = 256;
     hipLaunchKernelGGL(k_bbox, dim3(g), dim3(256), 0, s, pos, n, K, off, bb);
     return hipGetLastError();
 }

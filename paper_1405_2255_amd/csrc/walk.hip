@@ -154,6 +154,7 @@ k_walk_count(WalkParams wp, TreeArrays t, const double *P, WalkBuffers wb, int s
         for (int64_t i = lo + threadIdx.x; i < hi; i += WALK_THREADS) {
             const uint2 pr = wb.in[i];
             const Decision d = decide(wp, t, P, (int)pr.x, (int)pr.y);
+            wb.code[i] = (uint16_t)(d.kind | (d.nf << 3));   // kind < 8, nf <= 64
             f += d.nf;
             m += d.kind == 5;
             q += d.kind == 4;
@@ -255,11 +256,13 @@ k_walk_write(WalkParams wp, TreeArrays t, const double *P, WalkBuffers wb, int s
         const int64_t i = base + threadIdx.x;
         Decision d = {0, 0, 0.0};
         int A = 0, B = 0;
-        if (i < hi) {
+        if (i < hi) {                 // the decision the count pass took for this pair
             const uint2 pr = wb.in[i];
             A = (int)pr.x;
             B = (int)pr.y;
-            d = decide(wp, t, P, A, B);
+            const unsigned code = wb.code[i];
+            d.kind = (int)(code & 7u);
+            d.nf = (int)(code >> 3);
         }
         int sf = d.nf, sm = d.kind == 5, sp = d.kind == 4;
         int tot[3];
