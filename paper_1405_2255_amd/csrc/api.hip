@@ -131,6 +131,7 @@ struct fmm_ctx {
     DevBuf counters, nonfinite, walktmp, coffsets, roots, ckey, ckey2, order, order2;
     DevBuf dkey, dsort, dsort2, runstart;   // deep refinement below level 21
     DevBuf plans;                          // output plans of M2M and L2L for order plan_p
+    DevBuf Tsh;                            // M2M: each cell's expansion shifted to its parent
     DevBuf M32, sig, Flow;                 // mixed-precision M2L: scaled multipoles, chunk
                                            // scales, FP64 low-degree chunk parts
     int plan_p = -1;
@@ -553,8 +554,9 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
         sync(c);
         c->plan_p = p;
     }
-    for (int L = c->depth - 1; L >= 0; --L)
-        CK(launch_m2m_level(p, t, c->ls[L], c->ls[L + 1], U, M, plans, s));
+    double *Tsh = ensure<double>(c->Tsh, 2 * (size_t)nc * c->ncells);
+    for (int L = c->depth; L >= 0; --L)
+        CK(launch_m2m_level(p, t, c->ls[L], c->ls[L + 1], U, M, Tsh, plans, s));
     CK(launch_power(p, c->ncells, M, P, s));
     mark(c, PH_UP);
     // walk
@@ -924,7 +926,7 @@ size_t fmm_footprint_bytes(int64_t n, int p, const fmm_opts *o) {
     const double cells = 1.5 * (double)n / (0.3 * leaf) + 64;
     const double nc = 16.0 * (p + 1) * (p + 2) / 2.0;
     const double per_particle = 8 * 2 + 4 * 2 + 8 * 4 + 32 + 4 + 32 * 2 + 8 * 2 + 4 + 16 + 8 * 4;
-    const double per_cell = 3 * nc + 8 * (p + 1) + 4 * 10 + 32 * 2 + 8 * 9 + 16 + 16;
+    const double per_cell = 4 * nc + 8 * (p + 1) + 4 * 10 + 32 * 2 + 8 * 9 + 16 + 16;
     const double lists = 8.0 * 2 * (150.0 * cells) + 8.0 * 2 * (200.0 * cells) + 8.0 * 2 * n;
     const double part = nc * (150.0 * cells / 16 + cells);
     return (size_t)(per_particle * n + per_cell * cells + lists + part);

@@ -181,69 +181,78 @@ __device__ __forceinline__ void stage_store(cplx *dst, const StageMap &sm, int l
         if (sm.src[r] >= 0) dst[lane + r * FMM_WAVE] = sym(v[r], sm.q[r]);
 }
 
-// ---- M2M: one wavefront per parent, lanes over output coefficients ------------
-// M_n^m(z') = sum_{k=0}^{n} sum_{l=-k}^{k} Upsilon_k^l(z - z') M_{n-k}^{m-l}(z);
-// each child's M and shift Upsilon are staged (all orders) in the wavefront's
-// LDS.  plan[q * 64 + lane] is the lane's q-th output (or -1): outputs sorted
-// by their number of terms and dealt out in snake order, for balanced lanes.
+// ---- M2M: one wavefront per cell, lanes over coefficients ---------------------
+// Level by level from the bottom.  The wavefront of cell c first completes
+// M(c): for an internal cell the sum, in child order, of the children's
+// shifted expansions T(child) written by the previous level's launch (a leaf
+// keeps its P2M result); then, unless c is a root, it shifts M(c) to the
+// parent's centre,
+//   T_n^m(c) = sum_{k=0}^{n} sum_{l=-k}^{k} Upsilon_k^l(z_c - z_parent) M_{n-k}^{m-l}(c),
+// with M(c) and the shift Upsilon staged (all orders) in the wavefront's LDS.
+// plan[q * 64 + lane] is the lane's q-th output (or -1): outputs sorted by
+// their number of terms and dealt out in snake order, for balanced lanes.
 __global__ void __launch_bounds__(256)
-k_m2m_level(int p, TreeArrays t, int c0, int c1, const double *U, double *M, const short *plan) {
+k_m2m_level(int p, TreeArrays t, int c0, int c1, const double *U, double *M, double *T,
+            const short *plan) {
     __shared__ cplx sU[4][NFULL], sM[4][NFULL];
     const int w = threadIdx.x / FMM_WAVE, lane = lane_id();
     const int c = c0 + blockIdx.x * 4 + w;
     if (c >= c1) return;
-    const int nch = t.nchild[c];
-    if (nch == 0) return;
     const int nc = tri(p + 1, 0);
-    const cplx *Ub = reinterpret_cast<const cplx *>(U);
-    const cplx *Mb = reinterpret_cast<const cplx *>(M);
-    int o[OUT_PER_LANE], on[OUT_PER_LANE], om[OUT_PER_LANE];
+    const int nch = t.nchild[c];
+    const bool shift = t.parent[c] >= 0;
+    int o[OUT_PER_LANE];
 #pragma unroll
     for (int q = 0; q < OUT_PER_LANE; ++q) o[q] = plan[q * FMM_WAVE + lane];
-    cplx acc[OUT_PER_LANE];
+    const StageMap sm = stage_map(p, lane);
+    cplx ru[STAGE_R];
+    if (shift) stage_load(reinterpret_cast<const cplx *>(U) + (size_t)c * nc, sm, ru);
+    cplx *Mc = reinterpret_cast<cplx *>(M) + (size_t)c * nc;
+    const cplx *Tb = reinterpret_cast<const cplx *>(T);
+    // complete M(c) (stored half, lanes over stored coefficients) and stage it
+    for (int e = lane; e < nc; e += FMM_WAVE) {
+        int n, m;
+        nm_of(e, n, m);
+        cplx v;
+        if (nch > 0) {
+            v = {0.0, 0.0};
+            const int k0 = t.child0[c];
+            for (int ch = k0; ch < k0 + nch; ++ch) {
+                const cplx x = Tb[(size_t)ch * nc + e];
+                v.re += x.re;
+                v.im += x.im;
+            }
+            if (m == 0) v.im = 0.0;
+            Mc[e] = v;
+        } else {
+            v = Mc[e];
+        }
+        sM[w][n * n + n + m] = v;
+        if (m > 0) sM[w][n * n + n - m] = sym(v, -m);
+    }
+    if (!shift) return;
+    stage_store(sU[w], sm, lane, ru);
+    wave_lds_sync();
+    cplx *Tc = reinterpret_cast<cplx *>(T) + (size_t)c * nc;
 #pragma unroll
     for (int q = 0; q < OUT_PER_LANE; ++q) {
-        on[q] = -1;
-        om[q] = 0;
-        if (o[q] >= 0) nm_of(o[q], on[q], om[q]);
-        acc[q] = {0.0, 0.0};
-    }
-    const StageMap sm = stage_map(p, lane);
-    const int k0 = t.child0[c];
-    cplx ru[STAGE_R], rm[STAGE_R];
-    stage_load(Ub + (size_t)k0 * nc, sm, ru);
-    stage_load(Mb + (size_t)k0 * nc, sm, rm);
-    for (int ch = k0; ch < k0 + nch; ++ch) {
-        stage_store(sU[w], sm, lane, ru);
-        stage_store(sM[w], sm, lane, rm);
-        wave_lds_sync();
-        if (ch + 1 < k0 + nch) {            // next child's data in flight meanwhile
-            stage_load(Ub + (size_t)(ch + 1) * nc, sm, ru);
-            stage_load(Mb + (size_t)(ch + 1) * nc, sm, rm);
-        }
-#pragma unroll
-        for (int q = 0; q < OUT_PER_LANE; ++q) {
-            const int n = on[q], m = om[q];
-            cplx a = acc[q];
-            for (int k = 0; k <= n; ++k) {
-                const int nn = n - k;
-                const int lmin = max(-k, m - nn), lmax = min(k, m + nn);
-                const int bu = k * k + k, bv = nn * nn + nn + m;
+        if (o[q] < 0) continue;
+        int n, m;
+        nm_of(o[q], n, m);
+        cplx a = {0.0, 0.0};
+        for (int k = 0; k <= n; ++k) {
+            const int nn = n - k;
+            const int lmin = max(-k, m - nn), lmax = min(k, m + nn);
+            const int bu = k * k + k, bv = nn * nn + nn + m;
 #pragma unroll 4
-                for (int l = lmin; l <= lmax; ++l) {
-                    const cplx u = sU[w][bu + l], v = sM[w][bv - l];
-                    a.re = fma(u.re, v.re, fma(-u.im, v.im, a.re));
-                    a.im = fma(u.re, v.im, fma(u.im, v.re, a.im));
-                }
+            for (int l = lmin; l <= lmax; ++l) {
+                const cplx u = sU[w][bu + l], v = sM[w][bv - l];
+                a.re = fma(u.re, v.re, fma(-u.im, v.im, a.re));
+                a.im = fma(u.re, v.im, fma(u.im, v.re, a.im));
             }
-            acc[q] = a;
         }
-        wave_lds_sync();
+        Tc[o[q]] = {a.re, m == 0 ? 0.0 : a.im};
     }
-    cplx *Mc = reinterpret_cast<cplx *>(M) + (size_t)c * nc;
-#pragma unroll
-    for (int q = 0; q < OUT_PER_LANE; ++q)
-        if (on[q] >= 0) Mc[o[q]] = {acc[q].re, om[q] == 0 ? 0.0 : acc[q].im};
 }
 
 // ---- multipole power P_n^2 = sum_m (n-m)!(n+m)! |M_n^m|^2 ----------------------
@@ -492,10 +501,10 @@ hipError_t launch_shift_upsilon(int p, const TreeArrays &t, int c0, int c1, doub
 }
 
 hipError_t launch_m2m_level(int p, const TreeArrays &t, int c0, int c1, const double *U,
-                            double *M, const short *plan, hipStream_t s) {
+                            double *M, double *T, const short *plan, hipStream_t s) {
     if (c1 <= c0) return hipSuccess;
     hipLaunchKernelGGL(k_m2m_level, dim3(blocks(c1 - c0, 4)), dim3(256), 0, s, p, t, c0, c1, U, M,
-                       plan);
+                       T, plan);
     return hipGetLastError();
 }
 

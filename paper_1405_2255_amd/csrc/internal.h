@@ -103,8 +103,11 @@ hipError_t launch_shift_upsilon(int p, const TreeArrays &t, int c0, int c1, doub
 #define FMM_PLAN_ROWS 4
 #define FMM_PLAN_SIZE (FMM_PLAN_ROWS * 64)
 void translation_plans(int p, short *m2m, short *l2l);
+// Cells [c0, c1) of one level: complete M (internal cells: sum of the
+// children's T) and write T = M shifted to the parent's centre (not for
+// roots).  Run from the deepest level up to level 0.
 hipError_t launch_m2m_level(int p, const TreeArrays &t, int c0, int c1, const double *U,
-                            double *M, const short *plan, hipStream_t s);
+                            double *M, double *T, const short *plan, hipStream_t s);
 hipError_t launch_power(int p, int ncells, const double *M, double *P, hipStream_t s);
 hipError_t launch_l2l_level(int p, const TreeArrays &t, int c0, int c1, const double *U,
                             double *F, const short *plan, hipStream_t s);
