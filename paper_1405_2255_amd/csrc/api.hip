@@ -148,6 +148,7 @@ struct fmm_ctx {
     // last call
     int64_t n = 0;
     int ncells = 0, nleaves = 0, depth = 0, sh = 0, pb = 0, p = 0;
+    int pack = 0;   // direct-sum keys carry the range end (sh + 2 pb <= 64)
     int64_t n_m2l = 0, n_p2p = 0, n_ranges = 0;
     uint64_t *m2l_sorted = nullptr, *p2p_sorted = nullptr;
     uint32_t *p2pe_sorted = nullptr;
@@ -310,6 +311,7 @@ void build_tree(fmm_ctx *c, int64_t n, const double *pos, const double *mass, in
     c->depth = (int)c->ls.size() - 3;   // ls ends with two equal entries
     c->sh = std::max(1, bitlen((uint64_t)ncells));
     c->pb = std::max(1, bitlen((uint64_t)n));
+    c->pack = c->sh + 2 * c->pb <= 64;
     // per-cell arrays sized now that the count is known
     ensure<int>(c->leaf_lo, ncells); ensure<int>(c->leaf_hi, ncells);
     ensure<double4>(c->cen, ncells); ensure<double4>(c->com, ncells);
@@ -361,6 +363,7 @@ Lists walk(fmm_ctx *c, const WalkParams &wp0, const double *P) {
     wp.nroots = c->nroots;
     wp.sh = c->sh;
     wp.pb = c->pb;
+    wp.pack = c->pack;
     wp.binom[0] = 1.0;
     for (int k = 1; k <= std::min(wp.p, FMM_PMAX); ++k)
         wp.binom[k] = wp.binom[k - 1] * (double)(wp.p - k + 1) / (double)k;
@@ -436,7 +439,9 @@ void prepare_p2p(fmm_ctx *c, int64_t nlist) {
     uint32_t *v1 = ptr<uint32_t>(c->p2pe);
     uint32_t *v2 = ensure<uint32_t>(c->p2pe2, std::max<int64_t>(nlist, 1));
     int *tmp = tmp_ints(c, std::max(sort_tmp_ints(nlist), scan_tmp_ints(nlist + 1)));
-    CK(radix_sort(&k1, &k2, &v1, &v2, nlist, c->sh + c->pb, tmp, s));
+    // packed keys (the range end in the low pb bits) sort without a value array
+    if (c->pack) CK(radix_sort(&k1, &k2, nullptr, nullptr, nlist, c->sh + c->pb, tmp, s, c->pb));
+    else CK(radix_sort(&k1, &k2, &v1, &v2, nlist, c->sh + c->pb, tmp, s));
     c->p2p_sorted = k1;
     c->p2pe_sorted = v1;
     int *flag = ensure<int>(c->rflag, (size_t)nlist + 2);
@@ -445,9 +450,9 @@ void prepare_p2p(fmm_ctx *c, int64_t nlist) {
     int *total = ptr<int>(c->nonfinite) + 1;
     int64_t runs = 0;
     if (nlist > 0) {
-        CK(launch_range_merge(k1, v1, nlist, c->pb, flag, tmp, total, rg, rk, false, s));
+        CK(launch_range_merge(k1, v1, nlist, c->pb, c->pack, flag, tmp, total, rg, rk, false, s));
         CK(hipMemcpyAsync(c->hint, total, sizeof(int), hipMemcpyDeviceToHost, s));
-        CK(launch_range_merge(k1, v1, nlist, c->pb, flag, tmp, total, rg, rk, true, s));
+        CK(launch_range_merge(k1, v1, nlist, c->pb, c->pack, flag, tmp, total, rg, rk, true, s));
         sync(c);
         runs = c->hint[0];
     }
@@ -973,14 +978,22 @@ int64_t fmm_export(fmm_ctx *c, int what, void *dst, int64_t capacity) {
             std::vector<uint32_t> ends(cnt);
             if (cnt) {
                 CK(hipMemcpy(keys.data(), c->p2p_sorted, cnt * 8, hipMemcpyDeviceToHost));
-                CK(hipMemcpy(ends.data(), c->p2pe_sorted, cnt * 4, hipMemcpyDeviceToHost));
+                if (!c->pack)
+                    CK(hipMemcpy(ends.data(), c->p2pe_sorted, cnt * 4, hipMemcpyDeviceToHost));
             }
             int64_t *o = static_cast<int64_t *>(dst);
             const uint64_t mask = (1ull << c->pb) - 1;
             for (int64_t i = 0; i < cnt; ++i) {
-                o[3 * i] = id((int)(keys[i] >> c->pb));
-                o[3 * i + 1] = (int64_t)(keys[i] & mask);
-                o[3 * i + 2] = (int64_t)ends[i];
+                const uint64_t k = keys[i];
+                if (c->pack) {
+                    o[3 * i] = id((int)(k >> (2 * c->pb)));
+                    o[3 * i + 1] = (int64_t)((k >> c->pb) & mask);
+                    o[3 * i + 2] = (int64_t)(k & mask);
+                } else {
+                    o[3 * i] = id((int)(k >> c->pb));
+                    o[3 * i + 1] = (int64_t)(k & mask);
+                    o[3 * i + 2] = (int64_t)ends[i];
+                }
             }
             return bytes;
         }

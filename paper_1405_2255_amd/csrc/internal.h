@@ -22,8 +22,10 @@ hipError_t exclusive_scan(const int *in, int *out, int64_t n, int *tmp, int *tot
 // Buffers are ping-ponged; on return *keys/*vals point at the sorted data
 // (one of the two given buffers).  vals may be null (key-only sort).
 size_t sort_tmp_ints(int64_t n);
+// (Only key bits [lo_bit, lo_bit + bits) are sorted.)
 hipError_t radix_sort(uint64_t **keys, uint64_t **keys_alt, uint32_t **vals,
-                      uint32_t **vals_alt, int64_t n, int bits, int *tmp, hipStream_t s);
+                      uint32_t **vals_alt, int64_t n, int bits, int *tmp, hipStream_t s,
+                      int lo_bit = 0);
 
 // ---- tree.hip ---------------------------------------------------------
 struct TreeArrays {
@@ -136,6 +138,8 @@ struct WalkParams {
     int sh;            // M2L keys are (sink << sh) | source cell
     int pb;            // direct-sum keys are (sink << pb) | first source particle
     double binom[FMM_PMAX + 1];   // C(p, k)
+    int pack;          // nonzero: direct-sum keys carry the range end too,
+                       // (sink << 2pb) | (first << pb) | end (needs sh + 2 pb <= 64)
 };
 struct WalkBuffers {
     const uint2 *in;
@@ -157,10 +161,11 @@ hipError_t launch_list_offsets(const uint64_t *list, int64_t nlist, int nsinks, 
                                int64_t *off, hipStream_t s);
 // merge key-sorted direct-sum entries into maximal particle ranges per sink:
 // first call (write = false) flags and scans (flag: n + 1 ints, *total = runs);
-// second call writes range[run] = (begin, end) and rkey[run] = its key.
+// second call writes range[run] = (begin, end) and rkey[run] = (sink << pb) |
+// begin.  packed: the keys carry the ends (WalkParams::pack), end is unused.
 hipError_t launch_range_merge(const uint64_t *key, const uint32_t *end, int64_t n, int pb,
-                              int *flag, int *tmp, int *total, int2 *range, uint64_t *rkey,
-                              bool write, hipStream_t s);
+                              int packed, int *flag, int *tmp, int *total, int2 *range,
+                              uint64_t *rkey, bool write, hipStream_t s);
 
 // ---- m2l.hip ------------------------------------------------------------
 // chunk table of the sink-sorted M2L list: first call (fill = false) counts the

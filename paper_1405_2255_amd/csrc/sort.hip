@@ -174,12 +174,13 @@ size_t sort_tmp_ints(int64_t n) {
 }
 
 hipError_t radix_sort(uint64_t **keys, uint64_t **keys_alt, uint32_t **vals,
-                      uint32_t **vals_alt, int64_t n, int bits, int *tmp, hipStream_t s) {
+                      uint32_t **vals_alt, int64_t n, int bits, int *tmp, hipStream_t s,
+                      int lo_bit) {
     if (n <= 1) return hipSuccess;
     const int ntiles = (int)((n + RS_TILE - 1) / RS_TILE);
     int *hist = tmp;
     int *stmp = tmp + (size_t)256 * ntiles;
-    for (int shift = 0; shift < bits; shift += 8) {
+    for (int shift = lo_bit; shift < lo_bit + bits; shift += 8) {
         hipLaunchKernelGGL(k_rs_hist, dim3(ntiles), dim3(RS_THREADS), 0, s, *keys, n, shift, hist,
                            ntiles);
         hipError_t e = hipGetLastError();

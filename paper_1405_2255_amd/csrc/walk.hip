@@ -291,8 +291,13 @@ k_walk_write(WalkParams wp, TreeArrays t, const double *P, WalkBuffers wb, int s
         }
         case 4:     // direct sum of A's particles onto B's (B may be any cell)
             if (pp + 1 <= wb.cap_p2p) {
-                wb.p2p[pp] = ((uint64_t)B << wp.pb) | (uint64_t)t.beg[A];
-                wb.p2p_end[pp] = (uint32_t)t.end[A];
+                if (wp.pack) {
+                    wb.p2p[pp] = ((uint64_t)B << (2 * wp.pb)) | ((uint64_t)t.beg[A] << wp.pb) |
+                                 (uint64_t)t.end[A];
+                } else {
+                    wb.p2p[pp] = ((uint64_t)B << wp.pb) | (uint64_t)t.beg[A];
+                    wb.p2p_end[pp] = (uint32_t)t.end[A];
+                }
             }
             break;
         case 5:
@@ -322,38 +327,50 @@ __global__ void k_list_offsets(const uint64_t *list, int64_t nlist, int nsinks, 
     off[s] = lo;
 }
 
+// A direct-sum entry: sink cell, first and end source particle (packed keys
+// carry the end; otherwise it is in the separate array)
+struct Entry {
+    uint64_t sink;
+    uint32_t first, end;
+};
+__device__ __forceinline__ Entry entry(const uint64_t *key, const uint32_t *end, int64_t e,
+                                       int pb, int packed) {
+    const uint64_t mask = (1ull << pb) - 1, k = key[e];
+    if (packed) return {k >> (2 * pb), (uint32_t)((k >> pb) & mask), (uint32_t)(k & mask)};
+    return {k >> pb, (uint32_t)(k & mask), end[e]};
+}
+
 // Direct-sum entries sorted by (sink, source begin): an entry starts a new
 // range unless it continues the previous one (same sink, adjacent particles).
 __global__ void k_range_flags(const uint64_t *key, const uint32_t *end, int64_t n, int pb,
-                              int *flag) {
+                              int packed, int *flag) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e > n) return;
     if (e == n) {
         flag[e] = 0;
         return;
     }
-    const uint64_t mask = (1ull << pb) - 1;
     bool start = e == 0;
     if (!start) {
-        const uint64_t k = key[e], q = key[e - 1];
-        start = (k >> pb) != (q >> pb) || (uint32_t)(k & mask) != end[e - 1];
+        const Entry a = entry(key, end, e, pb, packed), b = entry(key, end, e - 1, pb, packed);
+        start = a.sink != b.sink || a.first != b.end;
     }
     flag[e] = start ? 1 : 0;
 }
 
-// run r = [first entry's begin, last entry's end) with its sink
+// run r = [first entry's begin, last entry's end) with its key (sink << pb) | begin
 __global__ void k_range_write(const uint64_t *key, const uint32_t *end, int64_t n, int pb,
-                              const int *scan, int2 *range, uint64_t *rkey) {
+                              int packed, const int *scan, int2 *range, uint64_t *rkey) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
-    const uint64_t mask = (1ull << pb) - 1;
+    const Entry a = entry(key, end, e, pb, packed);
     const int starts_here = scan[e + 1] - scan[e];
     const int run = scan[e + 1] - 1;
     if (starts_here) {
-        range[run].x = (int)(key[e] & mask);
-        rkey[run] = key[e];
+        range[run].x = (int)a.first;
+        rkey[run] = (a.sink << pb) | (uint64_t)a.first;
     }
-    if (e == n - 1 || scan[e + 2] - scan[e + 1]) range[run].y = (int)end[e];
+    if (e == n - 1 || scan[e + 2] - scan[e + 1]) range[run].y = (int)a.end;
 }
 
 inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -361,11 +378,11 @@ inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 }  // namespace
 
 hipError_t launch_range_merge(const uint64_t *key, const uint32_t *end, int64_t n, int pb,
-                              int *flag, int *tmp, int *total, int2 *range, uint64_t *rkey,
-                              bool write, hipStream_t s) {
+                              int packed, int *flag, int *tmp, int *total, int2 *range,
+                              uint64_t *rkey, bool write, hipStream_t s) {
     if (!write) {
         hipLaunchKernelGGL(k_range_flags, dim3(blocks(n + 1, 256)), dim3(256), 0, s, key, end, n,
-                           pb, flag);
+                           pb, packed, flag);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         // flag -> exclusive scan of n + 1 entries; flag[n] = 0 so scan[n] = runs
@@ -373,8 +390,8 @@ hipError_t launch_range_merge(const uint64_t *key, const uint32_t *end, int64_t 
         if (e != hipSuccess) return e;
         return hipSuccess;
     }
-    hipLaunchKernelGGL(k_range_write, dim3(blocks(n, 256)), dim3(256), 0, s, key, end, n, pb, flag,
-                       range, rkey);
+    hipLaunchKernelGGL(k_range_write, dim3(blocks(n, 256)), dim3(256), 0, s, key, end, n, pb,
+                       packed, flag, range, rkey);
     return hipGetLastError();
 }
 
