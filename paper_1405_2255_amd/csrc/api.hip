@@ -126,7 +126,7 @@ struct fmm_ctx {
         rho2, smin, leaf_cell, M, F, P, U, Fe;
     // walk
     DevBuf fa, fb, m2l, m2l2, p2p, p2p2, p2pe, p2pe2, m2l_off, p2p_off, chunks, ccnt, coff, Fpart;
-    DevBuf rflag, ranges, rkey, wcode;
+    DevBuf rflag, ranges, rkey, wcode, rup;
     DevBuf pt_n, pt_m, pt_s, pt_off, pt_moff, ptasks, ppart;
     DevBuf counters, nonfinite, walktmp, coffsets, roots, ckey, ckey2, order, order2;
     DevBuf dkey, dsort, dsort2, runstart;   // deep refinement below level 21
@@ -473,8 +473,10 @@ void run_p2p(fmm_ctx *c, int want_f, int with_pot, int mixed, double4 *out4, boo
     int *totals = ptr<int>(c->nonfinite) + 1;
     const int64_t *off = ptr<int64_t>(c->p2p_off);
     const int2 *rg = ptr<int2>(c->ranges);
-    CK(launch_p2p_plan(nl, ptr<int>(c->leaf_cell), off, rg, t, ntask, mtask, nts, toff, moff, tmp,
-                       totals, s));
+    int *up = ensure<int>(c->rup, (size_t)std::max(c->ncells, 1));
+    CK(launch_range_up(c->ncells, t.parent, off, up, s));
+    CK(launch_p2p_plan(nl, ptr<int>(c->leaf_cell), off, rg, up, t, ntask, mtask, nts, toff, moff,
+                       tmp, totals, s));
     CK(hipMemcpyAsync(c->hint, totals, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     sync(c);
     const int ntasks = c->hint[0], prows = c->hint[1];
@@ -482,8 +484,8 @@ void run_p2p(fmm_ctx *c, int want_f, int with_pot, int mixed, double4 *out4, boo
     double4 *part = ensure<double4>(c->ppart, (size_t)std::max(prows, 1) * 64);
     CK(launch_p2p_tasks(nl, toff, tasks, s));
     if (timed && c->opts.timing) CK(hipEventRecord(c->ev_p2p[0], s));
-    CK(launch_p2p(want_f, with_pot, mixed, ntasks, tasks, ptr<int>(c->leaf_cell), nts, moff, off, rg, t,
-                  ptr<double4>(c->xyzm), out4, part, s));
+    CK(launch_p2p(want_f, with_pot, mixed, ntasks, tasks, ptr<int>(c->leaf_cell), nts, moff, off,
+                  rg, up, t, ptr<double4>(c->xyzm), out4, part, s));
     if (timed && c->opts.timing) CK(hipEventRecord(c->ev_p2p[1], s));
     if (prows > 0)
         CK(launch_p2p_reduce(c->n, ptr<int>(c->leaf_of), ptr<int>(c->leaf_cell), nts, moff, t,

@@ -200,15 +200,18 @@ hipError_t launch_m2l_reduce(int p, int ncells, const int *coff, const double *F
 // the task counts (ntask, mtask, nsrc_tasks: nleaves + 1 ints each) and their
 // scans task_off, moff; totals[0] = tasks, totals[1] = partial rows.
 #define P2P_TASK 8192
-hipError_t launch_p2p_plan(int nleaves, const int *leaf_cell, const int64_t *off,
-                           const int2 *range, const TreeArrays &t, int *ntask, int *mtask,
-                           int *nsrc_tasks, int *task_off, int *moff, int *tmp, int *totals,
+// up[c]: nearest proper ancestor of c with direct-sum ranges (or -1)
+hipError_t launch_range_up(int ncells, const int *parent, const int64_t *off, int *up,
                            hipStream_t s);
+hipError_t launch_p2p_plan(int nleaves, const int *leaf_cell, const int64_t *off,
+                           const int2 *range, const int *up, const TreeArrays &t, int *ntask,
+                           int *mtask, int *nsrc_tasks, int *task_off, int *moff, int *tmp,
+                           int *totals, hipStream_t s);
 hipError_t launch_p2p_tasks(int nleaves, const int *task_off, int2 *tasks, hipStream_t s);
 // mixed != 0: FP32 pair arithmetic (separations in FP64, sums flushed to FP64)
 hipError_t launch_p2p(int want_f, int with_pot, int mixed, int ntasks, const int2 *tasks,
                       const int *leaf_cell, const int *nsrc_tasks, const int *moff,
-                      const int64_t *off, const int2 *range, const TreeArrays &t,
+                      const int64_t *off, const int2 *range, const int *up, const TreeArrays &t,
                       const double4 *xyzm, double4 *out4, double4 *partial, hipStream_t s);
 hipError_t launch_p2p_reduce(int64_t n, const int *leaf_of, const int *leaf_cell,
                              const int *nsrc_tasks, const int *moff, const TreeArrays &t,

@@ -25,12 +25,27 @@ namespace {
 // more costs occupancy)
 constexpr int P2P_R = 2;
 
+// up[c] = the nearest proper ancestor of c that has direct-sum ranges (or -1),
+// so that a leaf visits only the cells of its chain that hold work instead of
+// every ancestor (each step is a dependent load).
+__global__ void k_range_up(int ncells, const int *parent, const int64_t *off, int *up) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncells) return;
+    int a = parent[c];
+    while (a >= 0 && off[a + 1] == off[a]) a = parent[a];
+    up[c] = a;
+}
+
+__device__ __forceinline__ int first_with_ranges(int c, const int *up, const int64_t *off) {
+    return off[c + 1] > off[c] ? c : up[c];
+}
+
 // Work of one sink leaf: its direct-sum ranges and those of its ancestors,
 // read as one concatenated list of source particles.
-__device__ __forceinline__ int64_t leaf_sources(int c, const int *parent, const int64_t *off,
+__device__ __forceinline__ int64_t leaf_sources(int c, const int *up, const int64_t *off,
                                                 const int2 *range) {
     int64_t s = 0;
-    for (int anc = c; anc >= 0; anc = parent[anc])
+    for (int anc = first_with_ranges(c, up, off); anc >= 0; anc = up[anc])
         for (int64_t r = off[anc]; r < off[anc + 1]; ++r) s += range[r].y - range[r].x;
     return s;
 }
@@ -38,8 +53,8 @@ __device__ __forceinline__ int64_t leaf_sources(int c, const int *parent, const 
 // per leaf: tasks = sink chunks of 64 x source chunks of P2P_TASK sources;
 // mtask = tasks that need a partial-sum row (leaves with more than one task)
 __global__ void k_p2p_count(int nleaves, const int *leaf_cell, const int64_t *off,
-                            const int2 *range, TreeArrays t, int *ntask, int *mtask,
-                            int *nsrc_tasks) {
+                            const int2 *range, const int *up, TreeArrays t, int *ntask,
+                            int *mtask, int *nsrc_tasks) {
     const int leaf = blockIdx.x * blockDim.x + threadIdx.x;
     if (leaf > nleaves) return;
     if (leaf == nleaves) {
@@ -48,7 +63,7 @@ __global__ void k_p2p_count(int nleaves, const int *leaf_cell, const int64_t *of
         return;
     }
     const int c = leaf_cell[leaf];
-    const int64_t S = leaf_sources(c, t.parent, off, range);
+    const int64_t S = leaf_sources(c, up, off, range);
     const int nsc = (t.end[c] - t.beg[c] + FMM_WAVE - 1) / FMM_WAVE;
     const int nts = (int)max((int64_t)1, (S + P2P_TASK - 1) / P2P_TASK);
     nsrc_tasks[leaf] = nts;
@@ -163,8 +178,8 @@ __device__ __forceinline__ void sum_range(const double4 *p, const double4 *pe, i
 template <int R, int WANT_F, int WITH_POT, int MIXED>
 __global__ void __launch_bounds__(256)
 k_p2p(int ntasks, const int2 *tasks, const int *leaf_cell, const int *nsrc_tasks,
-      const int *moff, const int64_t *off, const int2 *range, TreeArrays t, const double4 *xyzm,
-      double4 *out4, double4 *partial) {
+      const int *moff, const int64_t *off, const int2 *range, const int *up, TreeArrays t,
+      const double4 *xyzm, double4 *out4, double4 *partial) {
     __shared__ double4 red[4][R * FMM_WAVE];
     const int task = xcd_block(blockIdx.x, gridDim.x) * 4 + threadIdx.x / FMM_WAVE;
     if (task >= ntasks) return;
@@ -192,7 +207,7 @@ k_p2p(int ntasks, const int2 *tasks, const int *leaf_cell, const int *nsrc_tasks
     }
     // sources [ts * P2P_TASK, (ts + 1) * P2P_TASK) of the leaf's list
     int64_t skip = (int64_t)ts * P2P_TASK, left = P2P_TASK;
-    for (int anc = c; anc >= 0 && left > 0; anc = t.parent[anc]) {
+    for (int anc = first_with_ranges(c, up, off); anc >= 0 && left > 0; anc = up[anc]) {
         for (int64_t r = off[anc]; r < off[anc + 1] && left > 0; ++r) {
             int2 rg = range[r];
             const int len = rg.y - rg.x;
@@ -346,12 +361,19 @@ inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
 
-hipError_t launch_p2p_plan(int nleaves, const int *leaf_cell, const int64_t *off,
-                           const int2 *range, const TreeArrays &t, int *ntask, int *mtask,
-                           int *nsrc_tasks, int *task_off, int *moff, int *tmp, int *totals,
+hipError_t launch_range_up(int ncells, const int *parent, const int64_t *off, int *up,
                            hipStream_t s) {
+    hipLaunchKernelGGL(k_range_up, dim3(blocks(ncells, 256)), dim3(256), 0, s, ncells, parent,
+                       off, up);
+    return hipGetLastError();
+}
+
+hipError_t launch_p2p_plan(int nleaves, const int *leaf_cell, const int64_t *off,
+                           const int2 *range, const int *up, const TreeArrays &t, int *ntask,
+                           int *mtask, int *nsrc_tasks, int *task_off, int *moff, int *tmp,
+                           int *totals, hipStream_t s) {
     hipLaunchKernelGGL(k_p2p_count, dim3(blocks(nleaves + 1, 256)), dim3(256), 0, s, nleaves,
-                       leaf_cell, off, range, t, ntask, mtask, nsrc_tasks);
+                       leaf_cell, off, range, up, t, ntask, mtask, nsrc_tasks);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = exclusive_scan(ntask, task_off, nleaves + 1, tmp, totals, s);
@@ -367,13 +389,13 @@ hipError_t launch_p2p_tasks(int nleaves, const int *task_off, int2 *tasks, hipSt
 
 hipError_t launch_p2p(int want_f, int with_pot, int mixed, int ntasks, const int2 *tasks,
                       const int *leaf_cell, const int *nsrc_tasks, const int *moff,
-                      const int64_t *off, const int2 *range, const TreeArrays &t,
+                      const int64_t *off, const int2 *range, const int *up, const TreeArrays &t,
                       const double4 *xyzm, double4 *out4, double4 *partial, hipStream_t s) {
     if (ntasks <= 0) return hipSuccess;
     const dim3 g(blocks(ntasks, 4)), b(256);
 #define FMM_P2P_LAUNCH(F, P, X)                                                                  \
     hipLaunchKernelGGL((k_p2p<P2P_R, F, P, X>), g, b, 0, s, ntasks, tasks, leaf_cell, nsrc_tasks, \
-                       moff, off, range, t, xyzm, out4, partial)
+                       moff, off, range, up, t, xyzm, out4, partial)
     if (mixed) {
         if (want_f) FMM_P2P_LAUNCH(1, 0, 1);
         else if (with_pot) FMM_P2P_LAUNCH(0, 1, 1);
