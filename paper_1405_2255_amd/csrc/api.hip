@@ -149,6 +149,7 @@ struct fmm_ctx {
     int64_t n = 0;
     int ncells = 0, nleaves = 0, depth = 0, sh = 0, pb = 0, p = 0;
     int pack = 0;   // direct-sum keys carry the range end (sh + 2 pb <= 64)
+    int walk_used[3] = {0, 0, 0};   // sweeps the last walk of each mode needed
     int64_t n_m2l = 0, n_p2p = 0, n_ranges = 0;
     uint64_t *m2l_sorted = nullptr, *p2p_sorted = nullptr;
     uint32_t *p2pe_sorted = nullptr;
@@ -384,15 +385,25 @@ Lists walk(fmm_ctx *c, const WalkParams &wp0, const double *P) {
         CK(hipMemsetAsync(cnt, 0, (8 + sweeps) * sizeof(unsigned long long), s));
         CK(launch_root_pairs(fa, c->nroots, s));           // (r, r) for every root
         if (c->opts.timing) CK(hipEventRecord(c->ev_walk[0], s));
-        for (int i = 0; i < sweeps; ++i) {
-            WalkBuffers wb{(i & 1) ? fb : fa, (i & 1) ? fa : fb, cap_f, ml, cap_m, pl, pe, cap_p,
-                           cnt, code};
-            CK(launch_walk(wp, t, P, wb, i, btmp, s));
+        // as many sweeps as the last walk of this kind needed (plus one), more
+        // only while the frontier is not empty; at most `sweeps`
+        int target = c->walk_used[wp.mode] > 0 ? std::min(sweeps, c->walk_used[wp.mode] + 1)
+                                               : sweeps;
+        int launched = 0;
+        for (;;) {
+            for (int i = launched; i < target; ++i) {
+                WalkBuffers wb{(i & 1) ? fb : fa, (i & 1) ? fa : fb, cap_f, ml, cap_m, pl, pe,
+                               cap_p, cnt, code};
+                CK(launch_walk(wp, t, P, wb, i, btmp, s));
+            }
+            launched = target;
+            if (c->opts.timing) CK(hipEventRecord(c->ev_walk[1], s));
+            CK(hipMemcpyAsync(c->hcnt, cnt, (4 + sweeps) * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, s));
+            sync(c);
+            if (c->hcnt[4 + launched - 1] == 0 || launched >= sweeps) break;
+            target = std::min(sweeps, launched + 4);
         }
-        if (c->opts.timing) CK(hipEventRecord(c->ev_walk[1], s));
-        CK(hipMemcpyAsync(c->hcnt, cnt, (4 + sweeps) * sizeof(unsigned long long),
-                          hipMemcpyDeviceToHost, s));
-        sync(c);
         const unsigned long long *h = c->hcnt;
         int64_t maxf = 0, visited = 1;
         int used = 0;
@@ -414,7 +425,8 @@ Lists walk(fmm_ctx *c, const WalkParams &wp0, const double *P) {
             if ((int64_t)h[1] > cap_p) cap_p = (int64_t)h[1] + (int64_t)h[1] / 2;
             continue;
         }
-        if (h[4 + sweeps - 1] != 0) throw HipFail{hipErrorUnknown, "walk did not terminate"};
+        if (h[4 + launched - 1] != 0) throw HipFail{hipErrorUnknown, "walk did not terminate"};
+        c->walk_used[wp.mode] = used + 1;
         return Lists{ml, (int64_t)h[0], pl, pe, (int64_t)h[1], (int64_t)h[2], used + 1};
     }
 }
