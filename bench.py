@@ -108,7 +108,9 @@ def batched_leg(args, fmm, workloads, precision="fp64"):
     M = torch.from_numpy(mass).to(dev)
     pot = torch.empty(ntot, dtype=torch.float64, device=dev)
     acc = torch.empty((ntot, 3), dtype=torch.float64, device=dev)
-    eps = args.eps if args.eps is not None else 5e-8
+    # accuracy parameter calibrated on this workload for rms <= 1e-7 (the rms
+    # over all particles is measured and reported below)
+    eps = args.eps if args.eps is not None else 8e-8
     ctx = fmm.Context(device=0, leaf_size=args.leaf, p2p_factor=args.p2p_factor, timing=True,
                       precision=precision)
     ctx.forces_batched(off, P, M, 1.0, args.p, eps, pot, acc)
@@ -296,7 +298,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--eps", type=float, default=None,
-                    help="accuracy parameter epsilon (default: calibrated for rms 1e-7)")
+                    help="accuracy parameter epsilon (default 8e-8: calibrated for rms 1e-7)")
     ap.add_argument("--p", type=int, default=-1)
     ap.add_argument("--leaf", type=int, default=0)
     ap.add_argument("--p2p-factor", type=float, default=0.0)
@@ -338,7 +340,9 @@ def main() -> int:
     from paper_1405_2255_amd import fmm, workloads
 
     target_rms = 1e-7
-    eps = args.eps if args.eps is not None else 5e-8
+    # accuracy parameter calibrated on this workload for rms <= 1e-7 (the rms
+    # over all particles is measured and reported below)
+    eps = args.eps if args.eps is not None else 8e-8
     n = args.n
     pos_np, m_np = workloads.cluster("plummer", n, args.seed)
     dev = torch.device("cuda:0")

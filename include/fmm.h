@@ -154,7 +154,9 @@ fmm_status fmm_direct_sinks(fmm_ctx *ctx, int64_t n, const double *pos, const do
                             double G, int64_t nsinks, const int64_t *sinks, double *pot,
                             double *acc);
 
-/* Expansion order used when fmm_forces gets p < 0. */
+/* Expansion order used when fmm_forces gets p < 0: round(1.6 log10(1/eps)) + 2,
+ * clamped to [3, FMM_P_MAX] (two above the paper's CPU optimum, Sec. 6.2: the
+ * measured balance of M2L and direct sums on this GPU); -1 for eps <= 0 or NaN. */
 int fmm_order_for_error(double target_err);
 
 /* Statistics of the last call (FMM_E_INVAL for NULL arguments). */

@@ -175,7 +175,7 @@ hipError_t launch_chunks(int ncells, const int64_t *off, int chunk, int *cnt, in
                          int *tmp, int *total, int4 *chunks, bool fill, hipStream_t s);
 // orders up to FMM_M2L_FIXED_MAX use register-resident kernels compiled per
 // order; higher orders (or generic = true) use the LDS-staged generic kernel
-#define FMM_M2L_FIXED_MAX 12
+#define FMM_M2L_FIXED_MAX 16
 hipError_t launch_m2l(int p, int nchunks, const int4 *chunks, const uint64_t *list, int sh,
                       const TreeArrays &t, const double *M, double *Fpart, hipStream_t s,
                       bool generic = false);

@@ -24,6 +24,7 @@ namespace fmm {
 FMM_M2L_FIXED_DECL(1) FMM_M2L_FIXED_DECL(2) FMM_M2L_FIXED_DECL(3) FMM_M2L_FIXED_DECL(4)
 FMM_M2L_FIXED_DECL(5) FMM_M2L_FIXED_DECL(6) FMM_M2L_FIXED_DECL(7) FMM_M2L_FIXED_DECL(8)
 FMM_M2L_FIXED_DECL(9) FMM_M2L_FIXED_DECL(10) FMM_M2L_FIXED_DECL(11) FMM_M2L_FIXED_DECL(12)
+FMM_M2L_FIXED_DECL(13) FMM_M2L_FIXED_DECL(14) FMM_M2L_FIXED_DECL(15) FMM_M2L_FIXED_DECL(16)
 #define FMM_M2L32_FIXED_DECL(P)                                                                \
     hipError_t launch_m2l32_fixed_##P(int, const int4 *, const uint64_t *, uint64_t,            \
                                       const TreeArrays &, const double *, const float *, float *, \
@@ -31,6 +32,7 @@ FMM_M2L_FIXED_DECL(9) FMM_M2L_FIXED_DECL(10) FMM_M2L_FIXED_DECL(11) FMM_M2L_FIXE
 FMM_M2L32_FIXED_DECL(1) FMM_M2L32_FIXED_DECL(2) FMM_M2L32_FIXED_DECL(3) FMM_M2L32_FIXED_DECL(4)
 FMM_M2L32_FIXED_DECL(5) FMM_M2L32_FIXED_DECL(6) FMM_M2L32_FIXED_DECL(7) FMM_M2L32_FIXED_DECL(8)
 FMM_M2L32_FIXED_DECL(9) FMM_M2L32_FIXED_DECL(10) FMM_M2L32_FIXED_DECL(11) FMM_M2L32_FIXED_DECL(12)
+FMM_M2L32_FIXED_DECL(13) FMM_M2L32_FIXED_DECL(14) FMM_M2L32_FIXED_DECL(15) FMM_M2L32_FIXED_DECL(16)
 }  // namespace fmm
 
 namespace fmm {
@@ -218,6 +220,7 @@ hipError_t launch_m2l(int p, int nchunks, const int4 *chunks, const uint64_t *li
     case 1: CALL(1);   case 2: CALL(2);   case 3: CALL(3);   case 4: CALL(4);
     case 5: CALL(5);   case 6: CALL(6);   case 7: CALL(7);   case 8: CALL(8);
     case 9: CALL(9);   case 10: CALL(10); case 11: CALL(11); case 12: CALL(12);
+    case 13: CALL(13); case 14: CALL(14); case 15: CALL(15); case 16: CALL(16);
     default: return hipErrorInvalidValue;
     }
 #undef CALL
@@ -254,6 +257,7 @@ hipError_t launch_m2l32(int p, int nchunks, const int4 *chunks, const uint64_t *
     case 1: CALL(1);   case 2: CALL(2);   case 3: CALL(3);   case 4: CALL(4);
     case 5: CALL(5);   case 6: CALL(6);   case 7: CALL(7);   case 8: CALL(8);
     case 9: CALL(9);   case 10: CALL(10); case 11: CALL(11); case 12: CALL(12);
+    case 13: CALL(13); case 14: CALL(14); case 15: CALL(15); case 16: CALL(16);
     default: return hipErrorInvalidValue;
     }
 #undef CALL

@@ -1,0 +1,4 @@
+// Instantiation of the mixed-precision M2L kernel for expansion order 13.
+#include "m2l32_impl.h"
+
+FMM_M2L32_FIXED_DEFINE(13)

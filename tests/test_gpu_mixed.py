@@ -34,7 +34,8 @@ def _run(gpu_lib, pos, m, p, eps, precision, p2p_factor=0.5):
     ("dehnen1.5", 12345, "salpeter", 8, 1e-6),
     ("uniform", 7777, "equal", 6, 1e-5),
     ("plummer", 3000, "equal", 2, 1e-3),      # every degree in the FP64 part
-    ("dehnen1", 5000, "equal", 14, 1e-7),     # above the register kernels: FP64 M2L
+    ("dehnen1", 5000, "equal", 14, 1e-7),
+    ("plummer", 4000, "equal", 18, 1e-7),     # above the register kernels: FP64 M2L
 ])
 def test_mixed_within_fp32_bound_of_oracle(gpu_lib, kind, n, masses, p, eps):
     print(f"case {kind} n={n} p={p}", flush=True)

@@ -150,9 +150,10 @@ def test_fmm_accuracy_against_direct_sum(ctx):
 
 
 def test_high_order_generic_kernel_matches_oracle(gpu_lib):
-    """Orders above the register kernels go through the LDS-staged kernel."""
+    """Orders 13 and 16 (the largest register kernels) and 18 (above them: the
+    LDS-staged kernel)."""
     ctx = gpu_lib.Context(leaf_size=16, p2p_factor=0.5)
-    for p in (13, 16):
+    for p in (13, 16, 18):
         pos, m = W.cluster("plummer", 5000, 9)
         pot, acc = _gpu_fmm(ctx, pos, m, p, 1e-9)
         ref = oracle.fmm(pos, m, p=p, eps=1e-9, leaf_size=16, p2p_pairs=0.5 * (p + 1) ** 3)
