@@ -205,11 +205,17 @@ k_p2p(int ntasks, const int2 *tasks, const int *leaf_cell, const int *nsrc_tasks
         xb[k] = *self[k];
         f[k] = make_double4(0.0, 0.0, 0.0, 0.0);
     }
-    // sources [ts * P2P_TASK, (ts + 1) * P2P_TASK) of the leaf's list
+    // sources [ts * P2P_TASK, (ts + 1) * P2P_TASK) of the leaf's list; the range
+    // descriptors are read 64 at a time (one per lane) and broadcast in turn
     int64_t skip = (int64_t)ts * P2P_TASK, left = P2P_TASK;
     for (int anc = first_with_ranges(c, up, off); anc >= 0 && left > 0; anc = up[anc]) {
-        for (int64_t r = off[anc]; r < off[anc + 1] && left > 0; ++r) {
-            int2 rg = range[r];
+        const int64_t r1 = off[anc + 1];
+        for (int64_t rb = off[anc]; rb < r1 && left > 0; rb += FMM_WAVE) {
+          const int2 mine = rb + lane < r1 ? range[rb + lane] : make_int2(0, 0);
+          const int nbat = (int)min((int64_t)FMM_WAVE, r1 - rb);
+          for (int j = 0; j < nbat && left > 0; ++j) {
+            int2 rg = make_int2(__builtin_amdgcn_readlane(mine.x, j),
+                                __builtin_amdgcn_readlane(mine.y, j));
             const int len = rg.y - rg.x;
             if (skip >= len) {
                 skip -= len;
@@ -231,6 +237,7 @@ k_p2p(int ntasks, const int2 *tasks, const int *leaf_cell, const int *nsrc_tasks
                 if (own) sum_range<R, WANT_F, WITH_POT, true>(p, pe, S, xb, self, f);
                 else sum_range<R, WANT_F, WITH_POT, false>(p, pe, S, xb, self, f);
             }
+          }
         }
     }
     // sum the phases of each sink through LDS: red[w][slot + phase * R * ng];
