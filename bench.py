@@ -1,9 +1,11 @@
 """Benchmark: particle-forces/s of one full FMM force evaluation on one GPU.
 
 Workload (default): Plummer sphere, N = 10^6 equal masses (total 1, G = 1,
-scale radius 1, seeded, untruncated), FP64, criterion a (relative force error)
-with the accuracy parameter chosen so that the measured rms relative force
-error stays at or below 1e-7.  One step = one fmm_forces call: tree build,
+scale radius 1, seeded, untruncated), FP64, criterion a (relative force error).
+Leaf size, direct-sum threshold, order and accuracy parameter are picked by
+the autotuner for rms <= 1e-7 on a calibration sample (the same workload with
+another seed, before the timed region); the rms relative force error of the
+measured run is then measured on every particle.  One step = one fmm_forces call: tree build,
 low-order estimate, upward pass, walk, M2L, P2P, downward pass, output -
 inputs resident in HBM before the timed region.
 
@@ -18,8 +20,8 @@ Prints ONE JSON line (rank 0): metric, value, ... plus
   mixed         the same N = 1e6 evaluation in mixed precision (FP32 pair and
                 high-degree M2L arithmetic, FP64 sums), errors on all particles
   batched       512 independent Plummer clusters, N log-uniform in [1e3, 1e5],
-                in one call (FP64 and mixed), against the same clusters one
-                call each
+                in one call (FP64 and mixed, parameters autotuned on every 8th
+                cluster), against the same clusters one call each
   c3            Dehnen gamma = 1 cusps with power-law masses, N = 1e6 and 1e7,
                 mixed precision, targets 1e-5 and 1e-7 (errors on 4096 sinks
                 against the GPU FP64 direct sum)
@@ -31,6 +33,7 @@ Prints ONE JSON line (rank 0): metric, value, ... plus
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -111,14 +114,38 @@ def batched_leg(args, fmm, workloads, precision="fp64"):
     # accuracy parameter calibrated on this workload for rms <= 1e-7 (the rms
     # over all particles is measured and reported below)
     eps = args.eps if args.eps is not None else 8e-8
-    ctx = fmm.Context(device=0, leaf_size=args.leaf, p2p_factor=args.p2p_factor, timing=True,
+    leaf, pf, p = args.leaf, args.p2p_factor, args.p
+    tuned = None
+    explicit = bool(args.leaf or args.p2p_factor or args.p >= 0 or args.eps is not None)
+    if not (args.no_tune or explicit):
+        # n_L, threshold factor, p and eps picked by the autotuner on every 8th
+        # cluster (its own timing and sampled errors), outside the timed region
+        from paper_1405_2255_amd import autotune
+        sub = list(range(0, k, 8))
+        sub_off = np.concatenate([[0], np.cumsum(sizes[sub])]).astype(np.int64)
+        sub_P = torch.cat([P[int(off[i]):int(off[i + 1])] for i in sub]).contiguous()
+        sub_M = torch.cat([M[int(off[i]):int(off[i + 1])] for i in sub]).contiguous()
+        t0 = time.perf_counter()
+        res = autotune.tune(sub_P, sub_M, 1e-7, offsets=sub_off, precision=precision,
+                            seed=args.seed)
+        t_tune = time.perf_counter() - t0
+        del sub_P, sub_M
+        if res.best is not None:
+            b = res.best
+            leaf, pf, p, eps = b.leaf_size, b.p2p_factor, b.p, b.eps
+        tuned = {"picked": None if res.best is None else dataclasses.asdict(res.best),
+                 "sample_clusters": len(sub), "candidates": len(res.table),
+                 "rms_on_sample": res.rms, "reference_rms_vs_direct": res.ref_rms,
+                 "ms_on_sample": res.ms, "tune_s": t_tune}
+        print(f"batched ({precision}): tuned {tuned}", file=sys.stderr, flush=True)
+    ctx = fmm.Context(device=0, leaf_size=leaf, p2p_factor=pf, timing=True,
                       precision=precision)
-    ctx.forces_batched(off, P, M, 1.0, args.p, eps, pot, acc)
+    ctx.forces_batched(off, P, M, 1.0, p, eps, pot, acc)
     torch.cuda.synchronize()
     reps = 3
     t0 = time.perf_counter()
     for _ in range(reps):
-        ctx.forces_batched(off, P, M, 1.0, args.p, eps, pot, acc)
+        ctx.forces_batched(off, P, M, 1.0, p, eps, pot, acc)
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / reps
     st = ctx.stats()
@@ -132,16 +159,15 @@ def batched_leg(args, fmm, workloads, precision="fp64"):
     e = np.concatenate(errs)
     print(f"batched: errors checked on {len(errs)} clusters", file=sys.stderr, flush=True)
     # one call per cluster (after one warm pass that sizes the workspace)
-    single = fmm.Context(device=0, leaf_size=args.leaf, p2p_factor=args.p2p_factor,
-                         precision=precision)
+    single = fmm.Context(device=0, leaf_size=leaf, p2p_factor=pf, precision=precision)
     for i in range(k):
         a, b = int(off[i]), int(off[i + 1])
-        single.forces(P[a:b], M[a:b], 1.0, args.p, eps, pot[a:b], acc[a:b])
+        single.forces(P[a:b], M[a:b], 1.0, p, eps, pot[a:b], acc[a:b])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(k):
         a, b = int(off[i]), int(off[i + 1])
-        single.forces(P[a:b], M[a:b], 1.0, args.p, eps, pot[a:b], acc[a:b])
+        single.forces(P[a:b], M[a:b], 1.0, p, eps, pot[a:b], acc[a:b])
     torch.cuda.synchronize()
     t_single = time.perf_counter() - t0
     print(f"batched: one call per cluster {1e3 * t_single:.1f} ms", file=sys.stderr, flush=True)
@@ -149,7 +175,8 @@ def batched_leg(args, fmm, workloads, precision="fp64"):
     single.close()
     return {"workload": f"{k} Plummer clusters, N log-uniform in [1e3, 1e5] (seed "
                         f"{args.seed + 77}), {ntot} particles, {precision}, eps={eps:g}, "
-                        f"p={st['p']}",
+                        f"p={st['p']}, n_L={leaf or 32}, p2p_factor={pf or 2:g}",
+            "autotune": tuned,
             "value": ntot / t_batch, "unit": "particle-forces/s", "ms_per_call": 1e3 * t_batch,
             "one_call_per_cluster": {"value": ntot / t_single, "ms": 1e3 * t_single},
             "errors_vs_gpu_direct": {"clusters_checked": len(errs), "sinks": int(e.size),
@@ -308,6 +335,8 @@ def main() -> int:
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--no-cpu", action="store_true", help="omit the CPU baseline field")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batched legs: library defaults instead of autotuned parameters")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-c3", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
@@ -340,26 +369,51 @@ def main() -> int:
     from paper_1405_2255_amd import fmm, workloads
 
     target_rms = 1e-7
-    # accuracy parameter calibrated on this workload for rms <= 1e-7 (the rms
-    # over all particles is measured and reported below)
-    eps = args.eps if args.eps is not None else 8e-8
     n = args.n
-    pos_np, m_np = workloads.cluster("plummer", n, args.seed)
     dev = torch.device("cuda:0")
+    explicit = bool(args.leaf or args.p2p_factor or args.p >= 0 or args.eps is not None)
+
+    def params(precision):
+        """(leaf, p2p_factor, p, eps, autotune record): the autotuner's choice
+        for rms <= target on a calibration sample (the same workload with
+        another seed), or the library defaults and eps = 8e-8 (calibrated on
+        this workload) when parameters are given or --no-tune."""
+        if args.no_tune or explicit:
+            return (args.leaf, args.p2p_factor, args.p,
+                    args.eps if args.eps is not None else 8e-8, None)
+        from paper_1405_2255_amd import autotune
+        cp, cm = workloads.cluster("plummer", n, args.seed + 1000)
+        cp, cm = torch.from_numpy(cp).to(dev), torch.from_numpy(cm).to(dev)
+        t0 = time.perf_counter()
+        res = autotune.tune(cp, cm, target_rms, precision=precision, seed=args.seed)
+        t_tune = time.perf_counter() - t0
+        del cp, cm
+        rec = {"calibration_sample": f"Plummer N={n}, seed {args.seed + 1000}",
+               "candidates": len(res.table), "tune_s": t_tune, "rms_on_sample": res.rms,
+               "ms_on_sample": res.ms, "reference_rms_vs_direct": res.ref_rms,
+               "picked": None if res.best is None else dataclasses.asdict(res.best)}
+        print(f"autotune ({precision}): {rec}", file=sys.stderr, flush=True)
+        if res.best is None:
+            return args.leaf, args.p2p_factor, args.p, 8e-8, rec
+        b = res.best
+        return b.leaf_size, b.p2p_factor, b.p, b.eps, rec
+
+    leaf, pf, p_arg, eps, tuned = params("fp64")
+    pos_np, m_np = workloads.cluster("plummer", n, args.seed)
     pos = torch.from_numpy(pos_np).to(dev)
     mass = torch.from_numpy(m_np).to(dev)
     pot = torch.empty(n, dtype=torch.float64, device=dev)
     acc = torch.empty((n, 3), dtype=torch.float64, device=dev)
-    ctx = fmm.Context(device=0, leaf_size=args.leaf, p2p_factor=args.p2p_factor, timing=True)
+    ctx = fmm.Context(device=0, leaf_size=leaf, p2p_factor=pf, timing=True)
 
     for _ in range(args.warmup):
-        ctx.forces(pos, mass, 1.0, args.p, eps, pot, acc)
+        ctx.forces(pos, mass, 1.0, p_arg, eps, pot, acc)
         print(f"warmup step done: {ctx.stats()['t_total']:.2f} ms", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     kstats = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        ctx.forces(pos, mass, 1.0, args.p, eps, pot, acc)
+        ctx.forces(pos, mass, 1.0, p_arg, eps, pot, acc)
         kstats.append(ctx.stats())
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -428,19 +482,23 @@ def main() -> int:
     value = n / (ms_per_step * 1e-3)
     mixed = None
     if not args.no_mixed:
-        ctxm = fmm.Context(device=0, leaf_size=args.leaf, p2p_factor=args.p2p_factor, timing=True,
+        leaf_m, pf_m, p_m, eps_m, tuned_m = params("mixed")
+        ctxm = fmm.Context(device=0, leaf_size=leaf_m, p2p_factor=pf_m, timing=True,
                            precision="mixed")
         for _ in range(max(1, args.warmup)):
-            ctxm.forces(pos, mass, 1.0, args.p, eps, pot, acc)
+            ctxm.forces(pos, mass, 1.0, p_m, eps_m, pot, acc)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            ctxm.forces(pos, mass, 1.0, args.p, eps, pot, acc)
+            ctxm.forces(pos, mass, 1.0, p_m, eps_m, pot, acc)
         torch.cuda.synchronize()
         ms_m = 1e3 * (time.perf_counter() - t0) / args.steps
         stm = ctxm.stats()
         mixed = {"value": n / (ms_m * 1e-3), "unit": "particle-forces/s", "ms_per_step": ms_m,
                  "vs_fp64": ms_per_step / ms_m,
+                 "params": {"leaf_size": leaf_m or 32, "p2p_factor": pf_m or 2.0, "p": stm["p"],
+                            "eps": eps_m},
+                 "autotune": tuned_m,
                  "phases_ms": {k: stm[k] for k in ("t_tree", "t_estimate", "t_up", "t_walk",
                                                    "t_m2l", "t_down", "t_p2p", "t_total")},
                  "m2l_kernel_ms": stm["t_m2l_kernel"], "p2p_kernel_ms": stm["t_p2p_kernel"]}
@@ -474,9 +532,11 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"Plummer sphere N={n}, equal masses, G=1, untruncated, seed "
                                f"{args.seed}; FP64 FMM, criterion a (eq:mac:better:a), "
-                               f"eps={eps:g}, p={p}",
-                   "n": n, "p": p, "eps": eps, "leaf_size": args.leaf or 32,
-                   "parallelism": "single GPU"},
+                               f"eps={eps:g}, p={p}, n_L={leaf or 32}, "
+                               f"p2p_factor={pf or 2.0:g}",
+                   "n": n, "p": p, "eps": eps, "leaf_size": leaf or 32,
+                   "p2p_factor": pf or 2.0, "parallelism": "single GPU"},
+        "autotune": tuned,
         "errors": {"vs_oracle_sampled": err_oracle, "vs_gpu_direct_all": err_direct,
                    "target_rms": target_rms,
                    "meets_target": bool((err_direct or err_oracle)["rms"] <= target_rms)},
