@@ -53,9 +53,10 @@ def m2l_flops(p: int) -> float:
     return 8.0 * sum((n + 1) * (p - n + 1) ** 2 for n in range(p + 1))
 
 
-def _measured_traffic(kernel: str):
+def _measured_traffic(kernel: str, config: dict):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 byte-counter
-    summary, or None if the kernel's sources changed since it was taken."""
+    summary, or None if the kernel's sources changed since it was taken or the
+    counters were taken with other workload parameters."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "fmm_plummer_1e6_hbm_bytes.md")
     try:
@@ -67,6 +68,10 @@ def _measured_traffic(kernel: str):
     for f in rec["sources"]:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     if h.hexdigest() != rec["sha256"]:
+        return None
+    want = rec.get("config", {})
+    if any(k not in config or abs(float(config[k]) - float(v)) > 1e-12 * abs(float(v))
+           for k, v in want.items()) or not want:
         return None
     return rec["fetch_bytes"] + rec["write_bytes"]
 
@@ -466,7 +471,10 @@ def main() -> int:
     achieved = kflop / (kms * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": kname, "achieved": achieved,
                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": _measured_traffic(kname),
+                "frac": achieved / FP64_PEAK_TFLOPS,
+                "traffic": _measured_traffic(kname, {"n": n, "leaf_size": leaf or 32,
+                                                     "p2p_factor": pf or 2.0, "p": p,
+                                                     "eps": eps}),
                 "launch_ms": kms, "algorithmic_flop_per_launch": kflop,
                 "other": {"k_m2l": {"ms": m2l_ms, "tflops": m2l_f / (m2l_ms * 1e-3) / 1e12},
                           "k_p2p": {"ms": p2p_ms, "tflops": p2p_f / (p2p_ms * 1e-3) / 1e12}}}
