@@ -38,6 +38,10 @@ def _load():
         _lib.or_p2m.argtypes = [i64, P, P, P, ip, P]
         _lib.or_m2m.argtypes = [P, P, ip, P]
         _lib.or_m2l.argtypes = [P, P, ip, P]
+        _lib.or_m2l_rot.argtypes = [P, P, ip, P]
+        _lib.or_m2l_rot.restype = None
+        _lib.or_swap_matrix.argtypes = [ip, P]
+        _lib.or_swap_matrix.restype = None
         _lib.or_l2l.argtypes = [P, P, ip, P]
         _lib.or_l2p.argtypes = [P, P, ip, P, P]
         _lib.or_power.argtypes = [P, ip, P]
@@ -132,6 +136,21 @@ def m2l(M, sB_minus_zA, p: int) -> np.ndarray:
     M = np.ascontiguousarray(M, dtype=np.complex128)
     out = np.zeros(ncoef(p), dtype=np.complex128)
     _load().or_m2l(_ptr(M), _ptr(_f64(sB_minus_zA, (3,))), p, _ptr(out))
+    return out
+
+
+def m2l_rot(M, sB_minus_zA, p: int) -> np.ndarray:
+    """eq:M2L by the rotation-accelerated kernel of App. A (eq:M2L:z)."""
+    M = np.ascontiguousarray(M, dtype=np.complex128)
+    out = np.zeros(ncoef(p), dtype=np.complex128)
+    _load().or_m2l_rot(_ptr(M), _ptr(_f64(sB_minus_zA, (3,))), p, _ptr(out))
+    return out
+
+
+def swap_matrix(n: int) -> np.ndarray:
+    """B_n of eq:Ylm:swap (x <-> z), rows and columns m = -n..n."""
+    out = np.zeros((2 * n + 1, 2 * n + 1))
+    _load().or_swap_matrix(n, _ptr(out))
     return out
 
 

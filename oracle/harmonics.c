@@ -177,3 +177,104 @@ double or_etilde_factor(double rho_zA, double rho_sB) {
     if (!(sum > 0.0)) return 8.0;
     return 8.0 * fmax(rho_zA, rho_sB) / sum;
 }
+
+/* Swap matrix B_n for exchanging the x and z axes (App. A, fast rotations,
+ * eq:Ylm:swap): Theta_n^m(z, y, x) = sum_l B_n^{ml} Theta_n^l(x, y, z).
+ * Built from B_0 = 1 by the recurrences given there, read as: rows |m| <= n-1
+ * of B_n from 2 B_n^{ml} = B_{n-1}^{m,l-1} - B_{n-1}^{m,l+1}, and the two new
+ * rows m = +-n from 2 B_n^{+-n,l} = B_{n-1}^{+-(n-1),l-1} + B_{n-1}^{+-(n-1),l+1}
+ * +- 2 B_{n-1}^{+-(n-1),l}; entries with |l| > n-1 of B_{n-1} are zero.
+ * Output: (2n+1)^2 doubles, row m = -n..n, column l = -n..n, row-major. */
+void or_swap_matrix(int n, double *B) {
+    double *prev = (double *)malloc(sizeof(double) * (size_t)(2 * n + 1) * (2 * n + 1));
+    double *cur = (double *)malloc(sizeof(double) * (size_t)(2 * n + 1) * (2 * n + 1));
+    cur[0] = 1.0;                                  /* B_0 */
+    for (int k = 0; k < n; ++k) {                  /* B_k (in cur) -> B_{k+1} */
+        const int w = 2 * k + 1, W = 2 * k + 3;
+        for (int i = 0; i < w * w; ++i) prev[i] = cur[i];
+#define PB(m, l) (((m) < -k || (m) > k || (l) < -k || (l) > k) ? 0.0 : prev[((m) + k) * w + (l) + k])
+        for (int m = -(k + 1); m <= k + 1; ++m)
+            for (int l = -(k + 1); l <= k + 1; ++l) {
+                double v;
+                if (m >= -k && m <= k)
+                    v = 0.5 * (PB(m, l - 1) - PB(m, l + 1));
+                else if (m == k + 1)
+                    v = 0.5 * (PB(k, l - 1) + PB(k, l + 1) + 2.0 * PB(k, l));
+                else
+                    v = 0.5 * (PB(-k, l - 1) + PB(-k, l + 1) - 2.0 * PB(-k, l));
+                cur[(m + k + 1) * W + l + k + 1] = v;
+            }
+#undef PB
+    }
+    for (int i = 0; i < (2 * n + 1) * (2 * n + 1); ++i) B[i] = cur[i];
+    free(prev);
+    free(cur);
+}
+
+/* X_n^m *= w^{-m} for every n <= p (a rotation of the frame about z by the
+ * angle of the unit complex number w, eq:Ylm:rot:z) */
+static void rot_z(double complex *X, int p, double complex w) {
+    for (int n = 0; n <= p; ++n)
+        for (int m = -n; m <= n; ++m) X[OR_IDX(n, m)] *= cpow(w, -m);
+}
+
+/* X_n <- B_n X_n (Theta-type coefficients) or B_n^T X_n (Upsilon-type: the
+ * swap matrices of Upsilon_n^m are the transposes), every degree n <= p */
+static void swap_xz(double complex *X, int p, int transpose) {
+    double complex *y = (double complex *)malloc(sizeof(double complex) * (size_t)(2 * p + 1));
+    double *B = (double *)malloc(sizeof(double) * (size_t)(2 * p + 1) * (2 * p + 1));
+    for (int n = 0; n <= p; ++n) {
+        const int w = 2 * n + 1;
+        or_swap_matrix(n, B);
+        for (int m = -n; m <= n; ++m) {
+            double complex s = 0.0;
+            for (int l = -n; l <= n; ++l)
+                s += (transpose ? B[(l + n) * w + m + n] : B[(m + n) * w + l + n]) *
+                     X[OR_IDX(n, l)];
+            y[m + n] = s;
+        }
+        for (int m = -n; m <= n; ++m) X[OR_IDX(n, m)] = y[m + n];
+    }
+    free(y);
+    free(B);
+}
+
+/* The rotation-accelerated M2L of App. A (a fast M2L kernel), same result as
+ * or_m2l up to rounding.  With r = (x, y, z) = s_B - z_A, rho = |(x, y)|:
+ * rotate the multipoles about z so that r lies in the y-z plane (angle
+ * phi - pi/2, phi the azimuth of r), swap x and z, rotate about the new z axis
+ * by atan2(rho, z) so that r lies on the (swapped) x axis, swap back: r is now
+ * along +z.  Apply the z-axis kernel eq:M2L:z
+ *     Ft_n^m = sum_{k=|m|}^{p-n} (-1)^m Mt_k^m (n+k)! / r^{n+k+1},
+ * then undo the rotations in reverse order and add to F. */
+void or_m2l_rot(const double complex *M, const double r3[3], int p, double complex *F) {
+    const int nc = (p + 1) * (p + 1);
+    double complex *X = (double complex *)malloc(sizeof(double complex) * (size_t)nc);
+    double complex *Y = (double complex *)malloc(sizeof(double complex) * (size_t)nc);
+    const double x = r3[0], y = r3[1], z = r3[2];
+    const double rho = sqrt(x * x + y * y), r = sqrt(x * x + y * y + z * z);
+    /* e^{i alpha} with alpha = phi - pi/2; any angle when r is on the z axis */
+    const double complex wa = rho > 0.0 ? (x + I * y) / rho * (-I) : 1.0;
+    const double complex wb = (z + I * rho) / r;   /* e^{i beta}, beta = atan2(rho, z) */
+    for (int i = 0; i < nc; ++i) X[i] = M[i];
+    rot_z(X, p, wa);
+    swap_xz(X, p, 1);
+    rot_z(X, p, wb);
+    swap_xz(X, p, 1);
+    for (int n = 0; n <= p; ++n)
+        for (int m = -n; m <= n; ++m) {
+            double complex s = 0.0;
+            if (abs(m) <= p - n)
+                for (int k = abs(m); k <= p - n; ++k)
+                    s += ((m & 1) ? -1.0 : 1.0) * X[OR_IDX(k, m)] * factorial(n + k) /
+                         pow(r, n + k + 1);
+            Y[OR_IDX(n, m)] = s;
+        }
+    swap_xz(Y, p, 0);
+    rot_z(Y, p, 1.0 / wb);
+    swap_xz(Y, p, 0);
+    rot_z(Y, p, 1.0 / wa);
+    for (int i = 0; i < nc; ++i) F[i] += Y[i];
+    free(X);
+    free(Y);
+}

@@ -12,8 +12,9 @@
  *                 sinks (result independent of the thread count).
  *   harmonics.c - complex solid harmonics Theta_n^m, Upsilon_n^m (Sec. 2.1,
  *                 App. A.3, A.5) and the FMM kernels P2M, M2M, M2L, L2L, L2P
- *                 (eqs:fmm), multipole power P_n (eq:def:PA) and the error
- *                 estimate E_{A->B} (eq:def:EAB, eq:err:tilde).
+ *                 (eqs:fmm), multipole power P_n (eq:def:PA), the error
+ *                 estimate E_{A->B} (eq:def:EAB, eq:err:tilde), the x <-> z
+ *                 swap matrices and the rotation-accelerated M2L (App. A).
  *   fmm.c       - a plain recursive FMM following the paper's phases: tree,
  *                 low-order estimate of the sink scale (Sec. 5.4.2), upward
  *                 pass, one-sided dual tree walk with the error-balancing
@@ -64,6 +65,13 @@ void or_l2l(const double complex *F, const double s_minus_sp[3], int p,
 /* Psi_0^0 and a = -(Re Psi_1^1, Im Psi_1^1, Psi_1^0) at x_b     eq:L2P:Psi, eq:L2P */
 void or_l2p(const double complex *F, const double sB_minus_x[3], int p,
             double *psi, double acc[3]);
+/* Swap matrix B_n (x <-> z) of eq:Ylm:swap by its recurrence (App. A):
+ * (2n+1)^2 doubles, row m = -n..n, column l = -n..n, row-major. */
+void or_swap_matrix(int n, double *B);
+/* The same F += M2L as or_m2l by the rotation-accelerated kernel of App. A:
+ * rotate M so that s_B - z_A points along z, eq:M2L:z, rotate back. */
+void or_m2l_rot(const double complex *M, const double sB_minus_zA[3], int p,
+                double complex *F);
 /* P_n = sqrt(sum_m (n-m)!(n+m)! |M_n^m|^2), n = 0..p              eq:def:PA */
 void or_power(const double complex *M, int p, double *P);
 /* E_{A->B} of eq:def:EAB times M_A (i.e. without the 1/M_A factor) */
