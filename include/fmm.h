@@ -63,6 +63,19 @@ typedef enum {
                            accumulated and returned in FP64 */
 } fmm_precision;
 
+/* Which M2L kernel evaluates the accepted cell pairs (same result up to
+ * rounding). */
+typedef enum {
+    FMM_M2L_AUTO = 0,     /* the library's choice (currently always the direct
+                             kernel) */
+    FMM_M2L_DIRECT = 1,   /* eq:M2L as a double sum over the multipoles */
+    FMM_M2L_ROTATION = 2  /* App. A: rotate the multipoles so that the interaction
+                             is along z, eq:M2L:z, rotate back (FP64, orders up
+                             to 16).  Compiled but switched off until its results
+                             on the device are established: requesting it gives
+                             FMM_E_UNSUPPORTED */
+} fmm_m2l_kernel;
+
 /* Where min_B{a_b} (or f_b) comes from. */
 typedef enum {
     FMM_SCALE_ESTIMATE = 0, /* low-order FMM estimate (Sec. 5.4.2) inside the call */
@@ -83,6 +96,7 @@ typedef struct {
     fmm_scale_source scale_source;
     int timing;            /* nonzero: record per-phase HIP events (fmm_stats) */
     fmm_precision precision; /* FMM_PREC_FP64 by default (0) */
+    fmm_m2l_kernel m2l_kernel; /* FMM_M2L_AUTO by default (0) */
 } fmm_opts;
 
 /* Interaction counts and per-phase times of the last fmm_forces call. */
@@ -107,6 +121,7 @@ typedef struct {
     int64_t walk_pairs, est_walk_pairs;
     double t_sweeps, t_est_sweeps;
     int refitted;                /* 1 if the last call recycled the tree */
+    int m2l_rotation;            /* 1 if the rotation M2L kernel ran */
 } fmm_stats_t;
 
 /* Create a context on opts->device.  Allocates only small bookkeeping; the

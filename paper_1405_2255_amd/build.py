@@ -17,7 +17,9 @@ SOURCES = ["api.hip", "sort.hip", "tree.hip", "walk.hip", "expansions.hip", "m2l
            "m2l_p01_06.hip", "m2l_p07_08.hip", "m2l_p09.hip", "m2l_p10.hip", "m2l_p11.hip",
            "m2l_p12.hip", "m2l_p13.hip", "m2l_p14.hip", "m2l_p15.hip", "m2l_p16.hip",
            "m2l32_p01_08.hip", "m2l32_p09_10.hip", "m2l32_p11.hip", "m2l32_p12.hip",
-           "m2l32_p13.hip", "m2l32_p14.hip", "m2l32_p15.hip", "m2l32_p16.hip"]
+           "m2l32_p13.hip", "m2l32_p14.hip", "m2l32_p15.hip", "m2l32_p16.hip",
+           "m2l_rot.hip", "m2lr_p01_08.hip", "m2lr_p09_11.hip", "m2lr_p12_13.hip",
+           "m2lr_p14.hip", "m2lr_p15.hip", "m2lr_p16.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++20", "--offload-arch=gfx950", "-fPIC", "-Wall",
          "-Wno-unused-function", "-I" + os.path.join(ROOT, "include"),
@@ -41,8 +43,8 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     jobs = jobs or min(len(SOURCES), max(1, (os.cpu_count() or 2)))
     # the highest-order M2L units take longest: start them first
     def cost(f):
-        m = re.match(r"m2l(32)?_p(\d+)(?:_(\d+))?\.hip$", f)
-        return int(m.group(3) or m.group(2)) if m else 0
+        m = re.match(r"m2l(?:32|r)?_p(\d+)(?:_(\d+))?\.hip$", f)
+        return int(m.group(2) or m.group(1)) if m else 0
     order = sorted(SOURCES, key=lambda f: -cost(f))
     with cf.ThreadPoolExecutor(jobs) as ex:
         done = dict(zip(order, ex.map(lambda s: _compile(s, verbose), order)))

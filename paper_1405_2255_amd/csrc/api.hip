@@ -593,9 +593,30 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
     c->m2l_sorted = sort_list(c, c->m2l, c->m2l2, L.n_m2l, c->ncells, c->m2l_off);
     prepare_p2p(c, L.n_p2p);
     mark(c, PH_WALK);
-    // M2L by chunks of one sink's list
+    // M2L: the rotation kernel over 64-entry windows of the list, or the
+    // direct kernel by chunks of one sink's list
     double *F = ensure<double>(c->F, 2 * (size_t)nc * c->ncells);
-    {
+    const bool rot = FMM_M2L_ROT_ENABLED &&
+                     (c->opts.m2l_kernel == FMM_M2L_ROTATION ||
+                      (c->opts.m2l_kernel == FMM_M2L_AUTO &&
+                       c->opts.precision == FMM_PREC_FP64 && p >= FMM_M2L_ROT_AUTO_MIN &&
+                       p <= FMM_M2L_ROT_MAX));
+    c->st.m2l_rotation = rot ? 1 : 0;
+    if (rot) {
+        int *cnt = ensure<int>(c->ccnt, (size_t)c->ncells + 1);
+        int *coff = ensure<int>(c->coff, (size_t)c->ncells + 1);
+        int *tmp = tmp_ints(c, scan_tmp_ints(c->ncells + 1));
+        int *total = ptr<int>(c->nonfinite) + 1;
+        CK(launch_rot_pieces(c->ncells, ptr<int64_t>(c->m2l_off), cnt, coff, tmp, total, s));
+        // pieces = (window, sink) pairs: at most one per window plus one per sink
+        const int64_t pieces = (c->n_m2l + 63) / 64 + c->ncells;
+        double *Fpart = ensure<double>(c->Fpart, 2 * (size_t)nc * (size_t)std::max<int64_t>(pieces, 1));
+        if (c->opts.timing) CK(hipEventRecord(c->ev_m2l[0], s));
+        CK(launch_m2l_rot(p, c->n_m2l, c->m2l_sorted, c->sh, ptr<int64_t>(c->m2l_off), coff, t, M,
+                          Fpart, s));
+        if (c->opts.timing) CK(hipEventRecord(c->ev_m2l[1], s));
+        CK(launch_m2l_reduce(p, c->ncells, coff, Fpart, F, s));
+    } else {
         const int chunk = 16;
         int *cnt = ensure<int>(c->ccnt, (size_t)c->ncells + 1);
         int *coff = ensure<int>(c->coff, (size_t)c->ncells + 1);
@@ -743,6 +764,7 @@ fmm_status fmm_build(fmm_ctx **out, const fmm_opts *o) {
     if (o->mac == FMM_MAC_THETA && !(o->theta_crit > 0.0 && o->theta_crit < 1.0)) return FMM_E_INVAL;
     if (o->p2p_factor < 0.0 || !std::isfinite(o->p2p_factor)) return FMM_E_INVAL;
     if (o->precision != FMM_PREC_FP64 && o->precision != FMM_PREC_MIXED) return FMM_E_INVAL;
+    if (o->m2l_kernel < FMM_M2L_AUTO || o->m2l_kernel > FMM_M2L_ROTATION) return FMM_E_INVAL;
     if (o->scale_source != FMM_SCALE_ESTIMATE && o->scale_source != FMM_SCALE_PREVIOUS)
         return FMM_E_INVAL;
     int ndev = 0;
@@ -821,6 +843,10 @@ static fmm_status check_common(fmm_ctx *c, int64_t n, const double *pos, const d
     }
     if (*p == 0) return fmm::fail(c, FMM_E_INVAL, "p must be >= 1");
     if (*p > FMM_P_MAX) return fmm::fail(c, FMM_E_UNSUPPORTED, "p above FMM_P_MAX");
+    if (c->opts.m2l_kernel == FMM_M2L_ROTATION && !FMM_M2L_ROT_ENABLED)
+        return fmm::fail(c, FMM_E_UNSUPPORTED, "the rotation M2L kernel is switched off");
+    if (c->opts.m2l_kernel == FMM_M2L_ROTATION && *p > FMM_M2L_ROT_MAX)
+        return fmm::fail(c, FMM_E_UNSUPPORTED, "the rotation M2L kernel supports p <= 16");
     return FMM_OK;
 }
 

@@ -194,6 +194,25 @@ hipError_t launch_m2l32_reduce(int p, int ncells, const int *coff, const float *
 hipError_t launch_m2l_reduce(int p, int ncells, const int *coff, const double *Fpart, double *F,
                              hipStream_t s);
 
+// ---- m2l_rot.hip ---------------------------------------------------------
+// Rotation-accelerated M2L (App. A), orders 1..FMM_M2L_ROT_MAX: one wavefront
+// per 64 consecutive entries of the sink-sorted list; partial sums per piece
+// (a run of one sink's entries inside one window) go to Fpart (2 tri(p+1, 0)
+// doubles each) and launch_m2l_reduce adds them per sink.  Pieces: at most
+// ceil(nlist / 64) + ncells; launch_rot_pieces counts them per cell into cnt
+// and scans into coff (ncells + 1 entries, *total = pieces).
+#define FMM_M2L_ROT_MAX 16
+// The rotation kernel is switched off until its results on the device are
+// established: FMM_M2L_AUTO never selects it (FMM_M2L_ROT_AUTO_MIN above
+// FMM_M2L_ROT_MAX) and an explicit request fails with FMM_E_UNSUPPORTED.
+#define FMM_M2L_ROT_ENABLED 0
+#define FMM_M2L_ROT_AUTO_MIN (FMM_M2L_ROT_MAX + 1)
+hipError_t launch_rot_pieces(int ncells, const int64_t *off, int *cnt, int *coff, int *tmp,
+                             int *total, hipStream_t s);
+hipError_t launch_m2l_rot(int p, int64_t nlist, const uint64_t *list, int sh, const int64_t *off,
+                          const int *coff, const TreeArrays &t, const double *M, double *Fpart,
+                          hipStream_t s);
+
 // ---- p2p.hip ------------------------------------------------------------
 // near field of each sink leaf over its list, added to out4 (sorted order)
 // off: ncells + 1 offsets into range (per sink cell).  Planning: per leaf

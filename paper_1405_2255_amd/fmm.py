@@ -29,6 +29,7 @@ OK, E_INVAL, E_NOMEM, E_HIP, E_NONFINITE, E_UNSUPPORTED, E_BUSY = range(7)
 MAC_REL, MAC_SCALED, MAC_THETA = 0, 1, 2
 SCALE_ESTIMATE, SCALE_PREVIOUS = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
+M2L_AUTO, M2L_DIRECT, M2L_ROTATION = 0, 1, 2
 EXPORT_M2L, EXPORT_P2P, EXPORT_SCALE, EXPORT_CELLS = 1, 2, 3, 4
 P_MAX = 20
 
@@ -45,7 +46,8 @@ SYMBOLS = ["fmm_build", "fmm_forces", "fmm_forces_batched", "fmm_forces_refit", 
 class Opts(C.Structure):
     _fields_ = [("device", C.c_int), ("hip_stream", C.c_void_p), ("leaf_size", C.c_int),
                 ("mac", C.c_int), ("theta_crit", C.c_double), ("p2p_factor", C.c_double),
-                ("scale_source", C.c_int), ("timing", C.c_int), ("precision", C.c_int)]
+                ("scale_source", C.c_int), ("timing", C.c_int), ("precision", C.c_int),
+                ("m2l_kernel", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -61,7 +63,7 @@ class Stats(C.Structure):
                 ("m2l_launches", C.c_int), ("p2p_launches", C.c_int),
                 ("walk_pairs", C.c_int64), ("est_walk_pairs", C.c_int64),
                 ("t_sweeps", C.c_double), ("t_est_sweeps", C.c_double),
-                ("refitted", C.c_int)]
+                ("refitted", C.c_int), ("m2l_rotation", C.c_int)]
 
 
 _P = C.c_void_p
@@ -104,7 +106,7 @@ def order_for_error(target_err: float) -> int:
 
 
 def footprint_bytes(n: int, p: int, leaf_size: int = 0) -> int:
-    o = Opts(0, None, leaf_size, 0, 0.0, 0.0, 0, 0, 0)
+    o = Opts(0, None, leaf_size, 0, 0.0, 0.0, 0, 0, 0, 0)
     return int(_lib.fmm_footprint_bytes(int(n), int(p), C.byref(o)))
 
 
@@ -119,6 +121,7 @@ def _dev_ptr(t: torch.Tensor, name: str, shape=None) -> int:
 
 
 _PRECISIONS = {"fp64": PREC_FP64, "mixed": PREC_MIXED}
+_M2L = {"auto": M2L_AUTO, "direct": M2L_DIRECT, "rotation": M2L_ROTATION}
 _MACS = {"a": MAC_REL, "rel": MAC_REL, "f": MAC_SCALED, "scaled": MAC_SCALED,
          "theta": MAC_THETA}
 _SCALES = {"estimate": SCALE_ESTIMATE, "previous": SCALE_PREVIOUS}
@@ -130,7 +133,7 @@ class Context:
     def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None,
                  leaf_size: int = 0, mac: str = "a", theta_crit: float = 0.5,
                  p2p_factor: float = 0.0, scale_source: str = "estimate",
-                 timing: bool = False, precision: str = "fp64"):
+                 timing: bool = False, precision: str = "fp64", m2l: str = "auto"):
         if not torch.cuda.is_available():
             raise RuntimeError("libfmm needs a GPU")
         self.device = int(device)
@@ -138,7 +141,7 @@ class Context:
             self.stream = stream if stream is not None else torch.cuda.current_stream()
         o = Opts(self.device, C.c_void_p(self.stream.cuda_stream), int(leaf_size), _MACS[mac],
                  float(theta_crit), float(p2p_factor), _SCALES[scale_source], int(bool(timing)),
-                 _PRECISIONS[precision])
+                 _PRECISIONS[precision], _M2L[m2l])
         self._opts = o
         h = C.c_void_p()
         st = _lib.fmm_build(C.byref(h), C.byref(o))
