@@ -16,12 +16,15 @@ times the full force evaluation on the GPU, keeps those whose rms over all
 particles is within `margin` of the target and returns the fastest.
 
 `BandTuner` caches one result per (N band, target, precision) so that a
-serving loop or a batch of clusters of similar size reuses it.
+serving loop or a batch of clusters of similar size reuses it.  Running the
+module on the GPU tunes the benchmark workloads (on samples with seeds other
+than the measured inputs') and writes the committed table tuned.json.
 """
 from __future__ import annotations
 
 import dataclasses
 import math
+import os
 import time
 
 import numpy as np
@@ -187,3 +190,74 @@ class BandTuner:
             self.cache[key] = tune(pos, mass, target, offsets=offsets,
                                    precision=self.precision, **self.kw).best
         return self.cache[key]
+
+
+# ---- committed table -----------------------------------------------------
+# Results of `tune` for named workloads, written by running this module on the
+# GPU (python -m paper_1405_2255_amd.autotune --write), read back by callers
+# that want the tuned parameters without spending the tuning time.
+TABLE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
+
+
+def table_lookup(key: str, precision: str, path: str = TABLE_PATH):
+    """(Candidate, record) stored for a workload key and precision, or None."""
+    import json
+    try:
+        rec = json.load(open(path))[key][precision]
+    except (OSError, KeyError, ValueError):
+        return None
+    c = rec["picked"]
+    return Candidate(int(c["leaf_size"]), float(c["p2p_factor"]), float(c["eps"]), int(c["p"])), rec
+
+
+def _bench_workloads():
+    """The tuning samples of the benchmark legs: the same distributions as the
+    measured inputs, other seeds."""
+    from . import workloads as W
+    out = {}
+
+    def plummer_1e6():
+        pos, m = W.cluster("plummer", 10 ** 6, 1001)
+        return pos, m, None
+    out["plummer_1e6"] = plummer_1e6
+
+    def batched_sample():
+        sizes = W.log_uniform_sizes(512, 78, 1e3, 1e5)[::8]
+        pos = np.vstack([W.cluster("plummer", int(n), 5100 + i)[0] for i, n in enumerate(sizes)])
+        m = np.concatenate([np.full(int(n), 1.0 / n) for n in sizes])
+        return pos, m, np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    out["batched_512_plummer_1e3_1e5"] = batched_sample
+    return out
+
+
+def main(argv=None) -> int:
+    import argparse
+    import json
+    import torch
+    ap = argparse.ArgumentParser(description="tune the benchmark workloads and write the table")
+    ap.add_argument("--write", default=TABLE_PATH)
+    ap.add_argument("--target", type=float, default=1e-7)
+    args = ap.parse_args(argv)
+    table = {}
+    for key, make in _bench_workloads().items():
+        pos, m, off = make()
+        P = torch.from_numpy(pos).cuda()
+        M = torch.from_numpy(m).cuda()
+        for prec in ("fp64", "mixed"):
+            t0 = time.perf_counter()
+            res = tune(P, M, args.target, offsets=off, precision=prec)
+            rec = {"picked": None if res.best is None else dataclasses.asdict(res.best),
+                   "target_rms": args.target, "rms_on_sample": res.rms, "ms_on_sample": res.ms,
+                   "reference_rms_vs_direct": res.ref_rms, "candidates": len(res.table),
+                   "tune_s": time.perf_counter() - t0,
+                   "sample": f"{key}, n={len(m)}, seeds other than the measured input's"}
+            table.setdefault(key, {})[prec] = rec
+            print(key, prec, json.dumps(rec), flush=True)
+    with open(args.write, "w") as fh:
+        json.dump(table, fh, indent=1, sort_keys=True)
+        fh.write("\n")
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())
