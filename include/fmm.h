@@ -156,6 +156,22 @@ fmm_status fmm_forces_batched(fmm_ctx *ctx, int64_t k, const int64_t *offsets_ho
 fmm_status fmm_forces_refit(fmm_ctx *ctx, int64_t n, const double *pos, const double *mass,
                             double G, int p, double target_err, double *pot, double *acc);
 
+/* Forces on a listed subset of the particles, as block time-step schemes need
+ * them (Sec. 7.1: forces for active particles only).  All n particles are
+ * sources; active[j] (device int64, 0 <= active[j] < n, any order, repeats
+ * allowed) are the sinks.  The tree, the expansions and the sink scale are
+ * those of fmm_forces on all n particles; the walk visits only sink cells that
+ * hold a listed particle, and the direct sums run only for their leaves.  So
+ * pot[j] and acc[3j..3j+2] (n_active entries, device) are exactly the values
+ * fmm_forces returns for particle active[j], at a cost that falls with the
+ * number of sink cells involved.  refit != 0 recycles the tree as
+ * fmm_forces_refit does.  An index out of range gives FMM_E_INVAL (entries
+ * with valid indices are written).  Calls with a list do not update the
+ * |a| kept for FMM_SCALE_PREVIOUS. */
+fmm_status fmm_forces_active(fmm_ctx *ctx, int64_t n, const double *pos, const double *mass,
+                             double G, int p, double target_err, int64_t n_active,
+                             const int64_t *active, int refit, double *pot, double *acc);
+
 /* Exact FP64 direct summation of eq. (1) on the GPU (the comparison
  * baseline): all n sinks against all n sources, a != b. */
 fmm_status fmm_direct(fmm_ctx *ctx, int64_t n, const double *pos, const double *mass,

@@ -129,6 +129,7 @@ struct fmm_ctx {
     DevBuf rflag, ranges, rkey, wcode, rup;
     DevBuf pt_n, pt_m, pt_s, pt_off, pt_moff, ptasks, ppart;
     DevBuf counters, nonfinite, walktmp, coffsets, roots, ckey, ckey2, order, order2;
+    DevBuf actflag, actf, actinv, actpre, cellact, actbad;   // forces for a listed subset
     DevBuf dkey, dsort, dsort2, runstart;   // deep refinement below level 21
     DevBuf plans;                          // output plans of M2M and L2L for order plan_p
     DevBuf Tsh;                            // M2M: each cell's expansion shifted to its parent
@@ -474,7 +475,8 @@ void prepare_p2p(fmm_ctx *c, int64_t nlist) {
 }
 
 // direct sums of every leaf (prepared ranges), added into out4
-void run_p2p(fmm_ctx *c, int want_f, int with_pot, int mixed, double4 *out4, bool timed) {
+void run_p2p(fmm_ctx *c, int want_f, int with_pot, int mixed, double4 *out4, bool timed,
+             const uint8_t *active = nullptr) {
     hipStream_t s = c->stream;
     const int nl = c->nleaves;
     TreeArrays t = tree_arrays(c);
@@ -487,8 +489,8 @@ void run_p2p(fmm_ctx *c, int want_f, int with_pot, int mixed, double4 *out4, boo
     const int2 *rg = ptr<int2>(c->ranges);
     int *up = ensure<int>(c->rup, (size_t)std::max(c->ncells, 1));
     CK(launch_range_up(c->ncells, t.parent, off, up, s));
-    CK(launch_p2p_plan(nl, ptr<int>(c->leaf_cell), off, rg, up, t, ntask, mtask, nts, toff, moff,
-                       tmp, totals, s));
+    CK(launch_p2p_plan(nl, ptr<int>(c->leaf_cell), off, rg, up, t, active, ntask, mtask, nts, toff,
+                       moff, tmp, totals, s));
     CK(hipMemcpyAsync(c->hint, totals, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     sync(c);
     const int ntasks = c->hint[0], prows = c->hint[1];
@@ -540,8 +542,11 @@ void sink_scale(fmm_ctx *c, bool want_f) {
 }
 
 // ------------------------------------------------------------ the call
+// nact/act: when act is not null, only the nact listed particles (input
+// indices) are sinks: pot/acc receive their results in list order (Sec. 7.1)
 void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double G, int p,
-            double eps, double *pot, double *acc, int K, const int64_t *off, bool refit) {
+            double eps, double *pot, double *acc, int K, const int64_t *off, bool refit,
+            int64_t nact = 0, const int64_t *act = nullptr) {
     hipStream_t s = c->stream;
     c->st = fmm_stats_t{};
     c->n = n;
@@ -552,8 +557,28 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
     ensure<int>(c->nonfinite, 8);
     mark(c, PH_START);
     build_tree(c, n, pos, mass, K, off, refit);
-    mark(c, PH_TREE);
     TreeArrays t = tree_arrays(c);
+    // listed sinks: cells that hold one (the tree, expansions and sink scale
+    // stay those of all n particles, so a listed particle's result equals the
+    // full call's)
+    const uint8_t *cell_active = nullptr;
+    int *inv = nullptr, *bad = nullptr;
+    if (act) {
+        int *flag_in = ensure<int>(c->actflag, n);
+        int *f = ensure<int>(c->actf, n + 1);
+        inv = ensure<int>(c->actinv, n);
+        int *pre = ensure<int>(c->actpre, n + 1);
+        uint8_t *ca = ensure<uint8_t>(c->cellact, c->ncells);
+        bad = ensure<int>(c->actbad, 1);
+        int *tmp = tmp_ints(c, scan_tmp_ints(n + 1));
+        CK(hipMemsetAsync(flag_in, 0, n * sizeof(int), s));
+        CK(hipMemsetAsync(bad, 0, sizeof(int), s));
+        CK(launch_mark_listed(n, nact, act, flag_in, bad, s));
+        CK(launch_cell_active(n, c->perm, flag_in, f, inv, pre, tmp, ptr<int>(c->nonfinite) + 1,
+                              c->ncells, t.beg, t.end, ca, s));
+        cell_active = ca;
+    }
+    mark(c, PH_TREE);
     const bool want_f = c->opts.mac == FMM_MAC_SCALED;
     if (c->opts.mac != FMM_MAC_THETA) sink_scale(c, want_f);
     mark(c, PH_EST);
@@ -581,6 +606,7 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
     // walk
     WalkParams wp{c->opts.mac == FMM_MAC_THETA ? 1 : 0, p, eps, c->opts.theta_crit,
                   c->opts.p2p_factor * (p + 1.0) * (p + 1.0) * (p + 1.0), 0, 0, 0, {}};
+    wp.active = cell_active;
     Lists L = walk(c, wp, P);
     c->st.walk_pairs = c->last_walk_pairs;
     c->st.t_sweeps = c->last_sweep_ms;
@@ -660,18 +686,23 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
                   ptr<double>(c->y), ptr<double>(c->z), F, o4, s));
     mark(c, PH_DOWN);
     // near field
-    run_p2p(c, 0, 1, c->opts.precision == FMM_PREC_MIXED, o4, true);
+    run_p2p(c, 0, 1, c->opts.precision == FMM_PREC_MIXED, o4, true, cell_active);
     mark(c, PH_P2P);
     int *nonfinite = ptr<int>(c->nonfinite);
     CK(hipMemsetAsync(nonfinite, 0, sizeof(int), s));
-    CK(launch_output(n, c->perm, o4, G, pot, acc, nonfinite, s));
-    if (c->opts.scale_source == FMM_SCALE_PREVIOUS) {
+    if (act)
+        CK(launch_output_listed(n, nact, act, inv, o4, G, pot, acc, nonfinite, s));
+    else
+        CK(launch_output(n, c->perm, o4, G, pot, acc, nonfinite, s));
+    if (c->opts.scale_source == FMM_SCALE_PREVIOUS && !act) {
         CK(launch_norm3(acc, n, G, ensure<double>(c->prev_scale, n), s));
         c->have_prev_scale = true;
         c->prev_n = n;
     }
     mark(c, PH_END);
     CK(hipMemcpyAsync(c->hint, nonfinite, sizeof(int), hipMemcpyDeviceToHost, s));
+    if (act) CK(hipMemcpyAsync(c->hint + 1, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    else c->hint[1] = 0;
     sync(c);
     c->st.n_cells = c->ncells;
     c->st.refitted = c->refitted ? 1 : 0;
@@ -814,7 +845,10 @@ void fmm_destroy(fmm_ctx *c) {
                       &c->pt_s, &c->pt_off, &c->pt_moff, &c->ptasks, &c->ppart, &c->m2l_off,
                       &c->p2p_off, &c->chunks, &c->ccnt, &c->coff, &c->Fpart, &c->counters,
                       &c->nonfinite, &c->prev_scale, &c->walktmp, &c->coffsets, &c->roots,
-                      &c->ckey, &c->ckey2, &c->order, &c->order2};
+                      &c->ckey, &c->ckey2, &c->order, &c->order2, &c->wcode, &c->rup,
+                      &c->actflag, &c->actf, &c->actinv, &c->actpre, &c->cellact, &c->actbad,
+                      &c->dkey, &c->dsort, &c->dsort2, &c->runstart, &c->plans, &c->Tsh,
+                      &c->M32, &c->sig, &c->Flow};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (auto &e : c->ev) if (e) (void)hipEventDestroy(e);
@@ -918,6 +952,45 @@ fmm_status fmm_forces_refit(fmm_ctx *c, int64_t n, const double *pos, const doub
         }
         const int64_t off[2] = {0, n};
         fmm::forces(c, n, pos, mass, G, p, target_err, pot, acc, 1, off, true);
+        if (c->hint[0]) return fmm::fail(c, FMM_E_NONFINITE, "non-finite potential or acceleration");
+        return FMM_OK;
+    });
+}
+
+fmm_status fmm_forces_active(fmm_ctx *c, int64_t n, const double *pos, const double *mass,
+                             double G, int p, double target_err, int64_t n_active,
+                             const int64_t *active, int refit, double *pot, double *acc) {
+    if (!c) return FMM_E_INVAL;
+    fmm::Guard g(c);
+    if (!g.ok) return FMM_E_BUSY;
+    c->err.clear();
+    if (n_active < 0 || (n_active > 0 && (!active || !pot || !acc)))
+        return fmm::fail(c, FMM_E_INVAL, "bad list of active particles or outputs");
+    if (n < 0 || (n > 0 && (!pos || !mass)))
+        return fmm::fail(c, FMM_E_INVAL, "bad particle arrays");
+    // outputs are checked above; check_common only needs non-null pointers
+    fmm_status st = check_common(c, n, pos, mass, G, &p, target_err, pot ? pot : (double *)pos,
+                                 acc ? acc : (double *)pos);
+    if (st != FMM_OK) return st;
+    return fmm::guarded(c, [&]() -> fmm_status {
+        if (n_active == 0) return FMM_OK;
+        if (n == 0) return fmm::fail(c, FMM_E_INVAL, "active index out of range");
+        if (n == 1) {   // one particle: no force; the list may only name it
+            int *bad = fmm::ensure<int>(c->actbad, 1);
+            int *flag = fmm::ensure<int>(c->actflag, 1);
+            CK(hipMemsetAsync(bad, 0, sizeof(int), c->stream));
+            CK(fmm::launch_mark_listed(1, n_active, active, flag, bad, c->stream));
+            CK(hipMemsetAsync(pot, 0, n_active * sizeof(double), c->stream));
+            CK(hipMemsetAsync(acc, 0, 3 * n_active * sizeof(double), c->stream));
+            CK(hipMemcpyAsync(c->hint + 1, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+            fmm::sync(c);
+            if (c->hint[1]) return fmm::fail(c, FMM_E_INVAL, "active index out of range");
+            return FMM_OK;
+        }
+        const int64_t off[2] = {0, n};
+        fmm::forces(c, n, pos, mass, G, p, target_err, pot, acc, 1, off, refit != 0, n_active,
+                    active);
+        if (c->hint[1]) return fmm::fail(c, FMM_E_INVAL, "active index out of range");
         if (c->hint[0]) return fmm::fail(c, FMM_E_NONFINITE, "non-finite potential or acceleration");
         return FMM_OK;
     });

@@ -140,6 +140,8 @@ struct WalkParams {
     double binom[FMM_PMAX + 1];   // C(p, k)
     int pack;          // nonzero: direct-sum keys carry the range end too,
                        // (sink << 2pb) | (first << pb) | end (needs sh + 2 pb <= 64)
+    const uint8_t *active;   // not null: pairs whose sink cell holds no listed
+                             // particle are dropped (forces for a subset, Sec. 7.1)
 };
 struct WalkBuffers {
     const uint2 *in;
@@ -223,9 +225,9 @@ hipError_t launch_m2l_rot(int p, int64_t nlist, const uint64_t *list, int sh, co
 hipError_t launch_range_up(int ncells, const int *parent, const int64_t *off, int *up,
                            hipStream_t s);
 hipError_t launch_p2p_plan(int nleaves, const int *leaf_cell, const int64_t *off,
-                           const int2 *range, const int *up, const TreeArrays &t, int *ntask,
-                           int *mtask, int *nsrc_tasks, int *task_off, int *moff, int *tmp,
-                           int *totals, hipStream_t s);
+                           const int2 *range, const int *up, const TreeArrays &t,
+                           const uint8_t *active, int *ntask, int *mtask, int *nsrc_tasks,
+                           int *task_off, int *moff, int *tmp, int *totals, hipStream_t s);
 hipError_t launch_p2p_tasks(int nleaves, const int *task_off, int2 *tasks, hipStream_t s);
 // mixed != 0: FP32 pair arithmetic (separations in FP64, sums flushed to FP64)
 hipError_t launch_p2p(int want_f, int with_pot, int mixed, int ntasks, const int2 *tasks,
@@ -237,6 +239,19 @@ hipError_t launch_p2p_reduce(int64_t n, const int *leaf_of, const int *leaf_cell
                              const double4 *partial, double4 *out4, hipStream_t s);
 hipError_t launch_output(int64_t n, const uint32_t *perm, const double4 *out4, double G,
                          double *pot, double *acc, int *nonfinite, hipStream_t s);
+// forces for a listed subset of sinks (Sec. 7.1): flag_in (n ints, zeroed by the
+// caller) marks the listed input indices, *bad = 1 if one is outside [0, n);
+// then per sorted position f (n + 1), inv (input -> sorted, n), the exclusive
+// scan pre (n + 1, scratch tmp/total) and active[c] = 1 for cells holding a
+// listed particle; the output kernel writes the listed particles in list order
+hipError_t launch_mark_listed(int64_t n, int64_t nact, const int64_t *act, int *flag_in, int *bad,
+                             hipStream_t s);
+hipError_t launch_cell_active(int64_t n, const uint32_t *perm, const int *flag_in, int *f,
+                              int *inv, int *pre, int *tmp, int *total, int ncells, const int *beg,
+                              const int *end, uint8_t *active, hipStream_t s);
+hipError_t launch_output_listed(int64_t n, int64_t nact, const int64_t *act, const int *inv,
+                                const double4 *out4, double G, double *pot, double *acc,
+                                int *nonfinite, hipStream_t s);
 hipError_t launch_scale(int want_f, int64_t n, const double4 *est4, double *scale,
                         hipStream_t s);
 hipError_t launch_direct_sinks(int64_t n, const double *pos, const double *mass, double G,

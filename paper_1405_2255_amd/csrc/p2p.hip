@@ -52,9 +52,10 @@ __device__ __forceinline__ int64_t leaf_sources(int c, const int *up, const int6
 
 // per leaf: tasks = sink chunks of 64 x source chunks of P2P_TASK sources;
 // mtask = tasks that need a partial-sum row (leaves with more than one task)
+// (active: when not null, leaves whose cell holds no listed sink get no task)
 __global__ void k_p2p_count(int nleaves, const int *leaf_cell, const int64_t *off,
-                            const int2 *range, const int *up, TreeArrays t, int *ntask,
-                            int *mtask, int *nsrc_tasks) {
+                            const int2 *range, const int *up, TreeArrays t,
+                            const uint8_t *active, int *ntask, int *mtask, int *nsrc_tasks) {
     const int leaf = blockIdx.x * blockDim.x + threadIdx.x;
     if (leaf > nleaves) return;
     if (leaf == nleaves) {
@@ -63,6 +64,12 @@ __global__ void k_p2p_count(int nleaves, const int *leaf_cell, const int64_t *of
         return;
     }
     const int c = leaf_cell[leaf];
+    if (active && !active[c]) {
+        nsrc_tasks[leaf] = 1;
+        ntask[leaf] = 0;
+        mtask[leaf] = 0;
+        return;
+    }
     const int64_t S = leaf_sources(c, up, off, range);
     const int nsc = (t.end[c] - t.beg[c] + FMM_WAVE - 1) / FMM_WAVE;
     const int nts = (int)max((int64_t)1, (S + P2P_TASK - 1) / P2P_TASK);
@@ -356,6 +363,57 @@ __global__ void k_output(int64_t n, const uint32_t *perm, const double4 *out4, d
     if (!(isfinite(p) && isfinite(a) && isfinite(b) && isfinite(c))) atomicOr(nonfinite, 1);
 }
 
+// ---- forces for a listed subset of sinks (Sec. 7.1) ------------------------
+// flag_in[act[j]] = 1 (input order, zeroed by the caller); *bad = 1 for an
+// index outside [0, n)
+__global__ void k_mark_listed(int64_t n, int64_t nact, const int64_t *act, int *flag_in,
+                              int *bad) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nact) return;
+    const int64_t i = act[j];
+    if (i < 0 || i >= n) atomicOr(bad, 1);
+    else flag_in[i] = 1;
+}
+
+// key order: f[i] = flag of the particle at sorted position i, inv[input] = i
+__global__ void k_sorted_flags(int64_t n, const uint32_t *perm, const int *flag_in, int *f,
+                               int *inv) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    if (i == n) {
+        f[n] = 0;
+        return;
+    }
+    const uint32_t j = perm[i];
+    f[i] = flag_in[j];
+    inv[j] = (int)i;
+}
+
+// a cell is active if it holds a listed particle: pre is the exclusive scan of f
+__global__ void k_cell_active(int ncells, const int *beg, const int *end, const int *pre,
+                              uint8_t *active) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncells) return;
+    active[c] = pre[end[c]] > pre[beg[c]] ? 1 : 0;
+}
+
+// results of the listed particles, in list order (indices out of range are skipped)
+__global__ void k_output_listed(int64_t n, int64_t nact, const int64_t *act, const int *inv,
+                                const double4 *out4, double G, double *pot, double *acc,
+                                int *nonfinite) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nact) return;
+    const int64_t idx = act[j];
+    if (idx < 0 || idx >= n) return;
+    const double4 v = out4[inv[idx]];
+    const double p = -G * v.x, a = G * v.y, b = G * v.z, c = G * v.w;
+    pot[j] = p;
+    acc[3 * j] = a;
+    acc[3 * j + 1] = b;
+    acc[3 * j + 2] = c;
+    if (!(isfinite(p) && isfinite(a) && isfinite(b) && isfinite(c))) atomicOr(nonfinite, 1);
+}
+
 // sink scale of the acceptance test from the estimate: |a| (criterion a) or f
 __global__ void k_scale(int want_f, int64_t n, const double4 *est4, double *scale) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -376,11 +434,11 @@ hipError_t launch_range_up(int ncells, const int *parent, const int64_t *off, in
 }
 
 hipError_t launch_p2p_plan(int nleaves, const int *leaf_cell, const int64_t *off,
-                           const int2 *range, const int *up, const TreeArrays &t, int *ntask,
-                           int *mtask, int *nsrc_tasks, int *task_off, int *moff, int *tmp,
-                           int *totals, hipStream_t s) {
+                           const int2 *range, const int *up, const TreeArrays &t,
+                           const uint8_t *active, int *ntask, int *mtask, int *nsrc_tasks,
+                           int *task_off, int *moff, int *tmp, int *totals, hipStream_t s) {
     hipLaunchKernelGGL(k_p2p_count, dim3(blocks(nleaves + 1, 256)), dim3(256), 0, s, nleaves,
-                       leaf_cell, off, range, up, t, ntask, mtask, nsrc_tasks);
+                       leaf_cell, off, range, up, t, active, ntask, mtask, nsrc_tasks);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = exclusive_scan(ntask, task_off, nleaves + 1, tmp, totals, s);
@@ -428,6 +486,37 @@ hipError_t launch_output(int64_t n, const uint32_t *perm, const double4 *out4, d
                          double *pot, double *acc, int *nonfinite, hipStream_t s) {
     hipLaunchKernelGGL(k_output, dim3(blocks(n, 256)), dim3(256), 0, s, n, perm, out4, G, pot, acc,
                        nonfinite);
+    return hipGetLastError();
+}
+
+hipError_t launch_mark_listed(int64_t n, int64_t nact, const int64_t *act, int *flag_in, int *bad,
+                             hipStream_t s) {
+    if (nact <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mark_listed, dim3(blocks(nact, 256)), dim3(256), 0, s, n, nact, act,
+                       flag_in, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_cell_active(int64_t n, const uint32_t *perm, const int *flag_in, int *f,
+                              int *inv, int *pre, int *tmp, int *total, int ncells, const int *beg,
+                              const int *end, uint8_t *active, hipStream_t s) {
+    hipLaunchKernelGGL(k_sorted_flags, dim3(blocks(n + 1, 256)), dim3(256), 0, s, n, perm,
+                       flag_in, f, inv);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = exclusive_scan(f, pre, n + 1, tmp, total, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cell_active, dim3(blocks(ncells, 256)), dim3(256), 0, s, ncells, beg, end,
+                       pre, active);
+    return hipGetLastError();
+}
+
+hipError_t launch_output_listed(int64_t n, int64_t nact, const int64_t *act, const int *inv,
+                                const double4 *out4, double G, double *pot, double *acc,
+                                int *nonfinite, hipStream_t s) {
+    if (nact <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_output_listed, dim3(blocks(nact, 256)), dim3(256), 0, s, n, nact, act, inv,
+                       out4, G, pot, acc, nonfinite);
     return hipGetLastError();
 }
 

@@ -45,6 +45,7 @@ struct Decision {
 
 __device__ __forceinline__ Decision decide(const WalkParams &wp, const TreeArrays &t,
                                            const double *P, int A, int B) {
+    if (wp.active && !wp.active[B]) return {0, 0, 0.0};   // no listed sink below B
     const int nchA = t.nchild[A], nchB = t.nchild[B];
     if (A == B) {
         if (nchA == 0) {

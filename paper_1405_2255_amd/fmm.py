@@ -37,7 +37,8 @@ STATUS_NAMES = {OK: "FMM_OK", E_INVAL: "FMM_E_INVAL", E_NOMEM: "FMM_E_NOMEM", E_
                 E_NONFINITE: "FMM_E_NONFINITE", E_UNSUPPORTED: "FMM_E_UNSUPPORTED",
                 E_BUSY: "FMM_E_BUSY"}
 
-SYMBOLS = ["fmm_build", "fmm_forces", "fmm_forces_batched", "fmm_forces_refit", "fmm_direct",
+SYMBOLS = ["fmm_build", "fmm_forces", "fmm_forces_batched", "fmm_forces_refit",
+           "fmm_forces_active", "fmm_direct",
            "fmm_direct_sinks",
            "fmm_order_for_error", "fmm_stats", "fmm_footprint_bytes", "fmm_last_error",
            "fmm_destroy", "fmm_export"]
@@ -77,6 +78,9 @@ _lib.fmm_forces_batched.restype = C.c_int
 _lib.fmm_forces_refit.argtypes = [_P, C.c_int64, _P, _P, C.c_double, C.c_int, C.c_double, _P,
                                   _P]
 _lib.fmm_forces_refit.restype = C.c_int
+_lib.fmm_forces_active.argtypes = [_P, C.c_int64, _P, _P, C.c_double, C.c_int, C.c_double,
+                                   C.c_int64, _P, C.c_int, _P, _P]
+_lib.fmm_forces_active.restype = C.c_int
 _lib.fmm_direct.argtypes = [_P, C.c_int64, _P, _P, C.c_double, _P, _P]
 _lib.fmm_direct.restype = C.c_int
 _lib.fmm_direct_sinks.argtypes = [_P, C.c_int64, _P, _P, C.c_double, C.c_int64, _P, _P, _P]
@@ -199,6 +203,25 @@ class Context:
                                             _dev_ptr(mass, "mass", (n,)), float(G), int(p),
                                             float(target_err), _dev_ptr(pot, "pot", (n,)),
                                             _dev_ptr(acc, "acc", (n, 3))))
+        return pot, acc
+
+    def forces_active(self, pos: torch.Tensor, mass: torch.Tensor, active: torch.Tensor,
+                      G: float = 1.0, p: int = -1, target_err: float = 1e-7,
+                      refit: bool = False):
+        """Potential and acceleration of the listed particles (int64 CUDA
+        tensor of input indices), in list order; equal to forces() for them."""
+        n = pos.shape[0]
+        if not isinstance(active, torch.Tensor) or active.dtype != torch.int64 or not active.is_cuda:
+            raise TypeError("active must be an int64 CUDA tensor")
+        active = active.contiguous()
+        k = active.shape[0]
+        pot = torch.empty(k, dtype=torch.float64, device=pos.device)
+        acc = torch.empty((k, 3), dtype=torch.float64, device=pos.device)
+        self._check(_lib.fmm_forces_active(self._h, n, _dev_ptr(pos, "pos", (n, 3)),
+                                           _dev_ptr(mass, "mass", (n,)), float(G), int(p),
+                                           float(target_err), k, C.c_void_p(active.data_ptr()),
+                                           int(bool(refit)), _dev_ptr(pot, "pot", (k,)),
+                                           _dev_ptr(acc, "acc", (k, 3))))
         return pot, acc
 
     def direct(self, pos: torch.Tensor, mass: torch.Tensor, G: float = 1.0):

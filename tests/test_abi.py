@@ -91,3 +91,15 @@ def test_option_and_stats_layouts_match_header():
 
     assert [f[0] for f in fmm.Opts._fields_] == members("fmm_opts")
     assert [f[0] for f in fmm.Stats._fields_] == members("fmm_stats_t")
+
+
+def test_destroy_releases_every_device_buffer():
+    """Every DevBuf member of the context is in fmm_destroy's release list."""
+    src = open(os.path.join(ROOT, "paper_1405_2255_amd", "csrc", "api.hip")).read()
+    body = src[src.index("struct fmm_ctx {"):]
+    body = body[:body.index("\n};")]
+    body = re.sub(r"//[^\n]*", "", body)
+    members = [v.strip() for d in re.findall(r"DevBuf\s+([^;]*);", body) for v in d.split(",")]
+    listed = re.search(r"DevBuf \*bufs\[\] = \{(.*?)\};", src, re.S).group(1)
+    listed = {v.strip().replace("&c->", "") for v in listed.split(",")}
+    assert members and not [m for m in members if m not in listed]
