@@ -19,6 +19,8 @@ Prints ONE JSON line (rank 0): metric, value, ... plus
   cpu_baseline  the CPU oracle (direct sum) on a bounded sample of sinks
   mixed         the same N = 1e6 evaluation in mixed precision (FP32 pair and
                 high-degree M2L arithmetic, FP64 sums), errors on all particles
+  active        forces for subsets of sinks (innermost 1e3..1e5, random 1%) of
+                the same input, fresh and with a recycled tree (Sec. 7.1)
   batched       512 independent Plummer clusters, N log-uniform in [1e3, 1e5],
                 in one call (FP64 and mixed, parameters autotuned on every 8th
                 cluster), against the same clusters one call each
@@ -198,6 +200,64 @@ def batched_leg(args, fmm, workloads, precision="fp64"):
                                                 "t_m2l", "t_down", "t_p2p", "t_total")}}
 
 
+def active_leg(args, fmm, pos, mass, params, full_ms):
+    """Forces for a subset of sinks (Sec. 7.1) on the N = 1e6 Plummer input
+    with the main leg's parameters: the innermost N_a particles (the paper's
+    block time-step experiment) and a random 1%; a fresh call (tree, estimate)
+    and a call that recycles the tree with the previous |a| as the scale, as a
+    block time-step scheme would.  Each result is compared with the full call's
+    values for the same particles (equal bitwise by construction)."""
+    import torch
+    leaf, pf, p, eps = params
+    n = pos.shape[0]
+    full = fmm.Context(device=0, leaf_size=leaf, p2p_factor=pf)
+    _, acc_full = full.forces(pos, mass, 1.0, p, eps)
+    order = torch.argsort(torch.linalg.norm(pos, dim=1))
+    rng = np.random.default_rng(args.seed + 9)
+    subsets = [("innermost", int(k), order[:int(k)].contiguous()) for k in (1e3, 1e4, 1e5)]
+    subsets.append(("random", n // 100, torch.from_numpy(
+        np.sort(rng.choice(n, n // 100, replace=False))).to(pos.device)))
+    # reference of the recycled calls: a full call on a recycled tree with the
+    # previous call's |a| as the scale
+    prev = fmm.Context(device=0, leaf_size=leaf, p2p_factor=pf, scale_source="previous")
+    prev.forces(pos, mass, 1.0, p, eps)
+    _, acc_prev = prev.forces(pos, mass, 1.0, p, eps, refit=True)
+    torch.cuda.synchronize()
+    prev.close()
+    runs = []
+    for mode in ("fresh", "recycled"):
+        ref = acc_prev if mode == "recycled" else acc_full
+        ctx = fmm.Context(device=0, leaf_size=leaf, p2p_factor=pf, timing=True,
+                          scale_source="previous" if mode == "recycled" else "estimate")
+        for kind, k, idx in subsets:
+            if mode == "recycled":
+                ctx.forces(pos, mass, 1.0, p, eps)          # the step that built the tree
+            ctx.forces_active(pos, mass, idx, 1.0, p, eps, refit=mode == "recycled")
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                _, acc = ctx.forces_active(pos, mass, idx, 1.0, p, eps, refit=mode == "recycled")
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            st = ctx.stats()
+            t = float(np.median(ts))
+            runs.append({"mode": mode, "sinks": kind, "n_active": k, "ms": 1e3 * t,
+                         "value": k / t, "unit": "particle-forces/s",
+                         "time_vs_full_call": 1e3 * t / full_ms,
+                         "equal_to_full_call": bool(torch.equal(acc, ref[idx])),
+                         "n_m2l": st["n_m2l"], "n_p2p_pairs": st["n_p2p_pairs"],
+                         "phases_ms": {k_: st[k_] for k_ in ("t_tree", "t_estimate", "t_up",
+                                                             "t_walk", "t_m2l", "t_down",
+                                                             "t_p2p", "t_total")}})
+            print(f"active ({mode}): {kind} {k}: {1e3 * t:.2f} ms", file=sys.stderr, flush=True)
+        ctx.close()
+    full.close()
+    return {"workload": f"Plummer N={n} (the main leg's input and parameters), listed sinks",
+            "full_call_ms": full_ms, "runs": runs,
+            "all_equal_to_full_call": all(r["equal_to_full_call"] for r in runs)}
+
+
 def c3_leg(args, fmm, workloads):
     """Dehnen gamma = 1 cusp, power-law (Salpeter) masses on [0.1, 100]
     normalised to 1, N = 1e6 and 1e7, mixed precision, rms targets 1e-5 and
@@ -347,6 +407,7 @@ def main() -> int:
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--no-cpu", action="store_true", help="omit the CPU baseline field")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-active", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="library defaults instead of autotuned parameters")
     ap.add_argument("--retune", action="store_true",
@@ -531,6 +592,8 @@ def main() -> int:
             mixed["meets_target"] = bool(mixed["errors_vs_gpu_direct_all"]["rms"] <= target_rms)
         ctxm.close()
         print(f"mixed: {ms_m:.2f} ms/step", file=sys.stderr, flush=True)
+    active = None if args.no_active else active_leg(args, fmm, pos, mass,
+                                                    (leaf, pf, p_arg, eps), ms_per_step)
     batched = None
     if not args.no_batched:
         batched = {"fp64": batched_leg(args, fmm, workloads, "fp64"),
@@ -567,6 +630,7 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "mixed": mixed,
+        "active": active,
         "batched": batched,
         "c3": c3,
         "served": served,

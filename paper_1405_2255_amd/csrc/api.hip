@@ -680,10 +680,10 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
     // downward pass, far field at the particles
     for (int Lv = 1; Lv <= c->depth; ++Lv)
         CK(launch_l2l_level(p, t, c->ls[Lv], c->ls[Lv + 1], U, F,
-                            ptr<short>(c->plans) + FMM_PLAN_SIZE, s));
+                            ptr<short>(c->plans) + FMM_PLAN_SIZE, s, cell_active));
     double4 *o4 = ensure<double4>(c->out4, n);
     CK(launch_l2p(p, t, ptr<int>(c->leaf_of), ptr<int>(c->leaf_cell), n, ptr<double>(c->x),
-                  ptr<double>(c->y), ptr<double>(c->z), F, o4, s));
+                  ptr<double>(c->y), ptr<double>(c->z), F, o4, s, cell_active));
     mark(c, PH_DOWN);
     // near field
     run_p2p(c, 0, 1, c->opts.precision == FMM_PREC_MIXED, o4, true, cell_active);

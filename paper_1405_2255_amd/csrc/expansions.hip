@@ -281,11 +281,13 @@ __global__ void k_power(int p, int ncells, const double *M, double *P) {
 // the parent's F and the child's shift are staged (all orders) in LDS; plan
 // as for M2M.
 __global__ void __launch_bounds__(256)
-k_l2l_level(int p, TreeArrays t, int c0, int c1, const double *U, double *F, const short *plan) {
+k_l2l_level(int p, TreeArrays t, int c0, int c1, const double *U, double *F, const short *plan,
+            const uint8_t *active) {
     __shared__ cplx sU[4][NFULL], sF[4][NFULL];
     const int w = threadIdx.x / FMM_WAVE, lane = lane_id();
     const int c = c0 + blockIdx.x * 4 + w;
     if (c >= c1) return;
+    if (active && !active[c]) return;      // no listed sink below c
     const int pc = t.parent[c];
     if (pc < 0) return;
     const int nc = tri(p + 1, 0);
@@ -334,10 +336,11 @@ k_l2l_level(int p, TreeArrays t, int c0, int c1, const double *U, double *F, con
 template <int P>
 __global__ void __launch_bounds__(256)
 k_l2p(TreeArrays t, const int *leaf_of, const int *leaf_cell, int64_t n, const double *x,
-      const double *y, const double *z, const double *F, double4 *out4) {
+      const double *y, const double *z, const double *F, double4 *out4, const uint8_t *active) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int c = leaf_cell[leaf_of[i]];
+    if (active && !active[c]) return;      // a leaf without listed sinks
     const double4 cen = t.cen[c];
     const cplx *Fc = reinterpret_cast<const cplx *>(F) + (size_t)c * tri(P + 1, 0);
     RowGen<P> g;
@@ -514,18 +517,18 @@ hipError_t launch_power(int p, int ncells, const double *M, double *P, hipStream
 }
 
 hipError_t launch_l2l_level(int p, const TreeArrays &t, int c0, int c1, const double *U,
-                            double *F, const short *plan, hipStream_t s) {
+                            double *F, const short *plan, hipStream_t s, const uint8_t *active) {
     if (c1 <= c0) return hipSuccess;
     hipLaunchKernelGGL(k_l2l_level, dim3(blocks(c1 - c0, 4)), dim3(256), 0, s, p, t, c0, c1, U, F,
-                       plan);
+                       plan, active);
     return hipGetLastError();
 }
 
 hipError_t launch_l2p(int p, const TreeArrays &t, const int *leaf_of, const int *leaf_cell,
                       int64_t n, const double *x, const double *y, const double *z,
-                      const double *F, double4 *out4, hipStream_t s) {
+                      const double *F, double4 *out4, hipStream_t s, const uint8_t *active) {
 #define CALL(P) hipLaunchKernelGGL(k_l2p<P>, dim3(blocks(n, 256)), dim3(256), 0, s, t, leaf_of, \
-                                   leaf_cell, n, x, y, z, F, out4)
+                                   leaf_cell, n, x, y, z, F, out4, active)
     FMM_DISPATCH_P(p, CALL)
 #undef CALL
     return hipGetLastError();

@@ -111,12 +111,15 @@ void translation_plans(int p, short *m2m, short *l2l);
 hipError_t launch_m2m_level(int p, const TreeArrays &t, int c0, int c1, const double *U,
                             double *M, double *T, const short *plan, hipStream_t s);
 hipError_t launch_power(int p, int ncells, const double *M, double *P, hipStream_t s);
+// (active: when not null, cells / leaves without listed sinks are skipped)
 hipError_t launch_l2l_level(int p, const TreeArrays &t, int c0, int c1, const double *U,
-                            double *F, const short *plan, hipStream_t s);
+                            double *F, const short *plan, hipStream_t s,
+                            const uint8_t *active = nullptr);
 // far field at every particle of every leaf: out4[i] = (Psi, ax, ay, az)
 hipError_t launch_l2p(int p, const TreeArrays &t, const int *leaf_of, const int *leaf_cell,
                       int64_t n, const double *x, const double *y, const double *z,
-                      const double *F, double4 *out4, hipStream_t s);
+                      const double *F, double4 *out4, hipStream_t s,
+                      const uint8_t *active = nullptr);
 // low-order estimate: monopole M2L into per-cell (Psi, a) at com (gravity)
 // or the 1/r^2 sum (f); L2L of the same; evaluation at particles.
 hipError_t launch_est_m2l(int want_f, const TreeArrays &t, int nsinks, const int64_t *off,
