@@ -194,7 +194,8 @@ MAC_A, MAC_F, MAC_THETA = 0, 1, 2
 class _Params(C.Structure):
     _fields_ = [("p", C.c_int), ("eps", C.c_double), ("leaf_size", C.c_int),
                 ("mac", C.c_int), ("theta_crit", C.c_double), ("p2p_pairs", C.c_double),
-                ("scale_source", C.c_int), ("scale", C.c_void_p), ("G", C.c_double)]
+                ("scale_source", C.c_int), ("scale", C.c_void_p), ("G", C.c_double),
+                ("eps_particle", C.c_void_p)]
 
 
 class _Stats(C.Structure):
@@ -211,7 +212,7 @@ class _Lists(C.Structure):
 
 def fmm(pos, mass, *, p: int, eps: float, leaf_size: int, G: float = 1.0,
         mac: int = MAC_A, theta_crit: float = 0.5, p2p_pairs: float = 0.0,
-        scale=None, want_lists: bool = False, list_cap: int = 1 << 22):
+        scale=None, want_lists: bool = False, list_cap: int = 1 << 22, eps_particle=None):
     """Plain CPU FMM.  Returns dict with pot, acc, stats and (optionally) the
     interaction lists (arrays of (source id, sink id), id = level<<40 | begin)
     and the per-particle sink scale used by the acceptance test."""
@@ -220,10 +221,13 @@ def fmm(pos, mass, *, p: int, eps: float, leaf_size: int, G: float = 1.0,
     mass = _f64(mass)
     n = mass.shape[0]
     prm = _Params(p, eps, leaf_size, mac, theta_crit, p2p_pairs,
-                  1 if scale is not None else 0, None, G)
+                  1 if scale is not None else 0, None, G, None)
     if scale is not None:
         scale = _f64(scale)
         prm.scale = scale.ctypes.data
+    if eps_particle is not None:      # individual accuracy parameters (Sec. 7)
+        eps_particle = _f64(eps_particle)
+        prm.eps_particle = eps_particle.ctypes.data
     pot = np.zeros(n)
     acc = np.zeros((n, 3))
     st = _Stats()
@@ -246,7 +250,8 @@ def fmm(pos, mass, *, p: int, eps: float, leaf_size: int, G: float = 1.0,
             return fmm(pos, mass, p=p, eps=eps, leaf_size=leaf_size, G=G, mac=mac,
                        theta_crit=theta_crit, p2p_pairs=p2p_pairs, scale=scale,
                        want_lists=True,
-                       list_cap=int(max(lists.m2l_count, lists.p2p_count)) + 1)
+                       list_cap=int(max(lists.m2l_count, lists.p2p_count)) + 1,
+                       eps_particle=eps_particle)
         out["m2l"] = m2l_buf[: lists.m2l_count].copy()
         out["p2p"] = p2p_buf[: lists.p2p_count].copy()
         out["scale"] = sc

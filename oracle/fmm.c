@@ -348,7 +348,8 @@ static int accept(fmm_t *t, const cell_t *A, const cell_t *B, const double d[3])
     if (!(A->rho + B->rho < r)) return 0;                        /* theta < 1 */
     const double err = or_etilde_factor(A->rho, B->rho) * or_eab_times_mass(A->P, t->p, B->rho, r)
                        / (r * r);                                /* Etilde M_A / r^2 */
-    return err < q->eps * B->smin;
+    /* individual eps_b are already folded into smin = min_B{eps_b a_b} (Sec. 7) */
+    return err < (q->eps_particle ? 1.0 : q->eps) * B->smin;
 }
 
 static void walk(fmm_t *t, int64_t ia, int64_t ib) {
@@ -511,6 +512,8 @@ int or_fmm(const or_fmm_params *prm, int64_t n, const double *pos,
                                                    : sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
             }
         }
+        if (prm->eps_particle)               /* min_B{eps_b a_b} (Sec. 7) */
+            for (int64_t i = 0; i < n; ++i) t->scale[i] *= prm->eps_particle[t->orig[i]];
         if (lists && lists->scale_est)
             for (int64_t i = 0; i < n; ++i) lists->scale_est[t->orig[i]] = t->scale[i];
         subtree_min(t, 0);

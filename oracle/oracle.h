@@ -93,6 +93,9 @@ typedef struct {
     int scale_source;  /* OR_SCALE_ESTIMATE or OR_SCALE_GIVEN */
     const double *scale; /* OR_SCALE_GIVEN: per-particle a_b or f_b (input order, G=1 units) */
     double G;
+    const double *eps_particle; /* NULL, or individual accuracy parameters eps_b (input
+                                   order): the criterion compares with min_B{eps_b a_b}
+                                   instead of eps min_B{a_b} (Sec. 7) */
 } or_fmm_params;
 
 typedef struct {

@@ -199,3 +199,46 @@ def test_lists_partition_all_pairs():
 
     m2l_pairs = sum(size(a) * size(b) for a, b in r["m2l"])
     assert m2l_pairs + st["n_p2p_pairs"] == n * (n - 1)
+
+
+def test_individual_eps_constant_equals_global():
+    """eps_b = eps for every particle: min_B{eps_b a_b} = eps min_B{a_b} exactly
+    (scaling by a positive constant commutes with the minimum under rounding), so
+    lists and results equal the global criterion (Sec. 7)."""
+    from paper_1405_2255_amd import workloads as W
+    pos, m = W.cluster("plummer", 3000, 41)
+    a = oracle.fmm(pos, m, p=6, eps=1e-6, leaf_size=16, want_lists=True)
+    b = oracle.fmm(pos, m, p=6, eps=1e-6, leaf_size=16, want_lists=True,
+                   eps_particle=np.full(3000, 1e-6))
+    assert np.array_equal(a["m2l"], b["m2l"]) and np.array_equal(a["p2p"], b["p2p"])
+    assert np.array_equal(a["acc"], b["acc"]) and np.array_equal(a["pot"], b["pot"])
+
+
+def test_individual_eps_sets_each_particles_accuracy():
+    """Inner half at eps_b = 1e-8, outer half at 1e-6: each half gets the
+    accuracy of a global run at its own eps (criterion with min_B{eps_b a_b},
+    Sec. 7), and a vanishing eps_b makes that particle's force exact (every cell
+    holding it rejects every approximation)."""
+    from paper_1405_2255_amd import workloads as W
+    n = 6000
+    pos, m = W.cluster("plummer", n, 42)
+    r = np.linalg.norm(pos, axis=1)
+    inner = r < np.median(r)
+    eps_b = np.where(inner, 1e-8, 1e-6)
+    one = int(np.argsort(r)[n // 3])
+    eps_b[one] = 1e-300
+    _, a_true, _ = oracle.direct(pos, m)
+
+    def err(out):
+        return np.linalg.norm(out["acc"] - a_true, axis=1) / np.linalg.norm(a_true, axis=1)
+
+    def rms(e):
+        return np.sqrt(np.mean(e ** 2))
+
+    e = err(oracle.fmm(pos, m, p=8, eps=1e-6, leaf_size=16, eps_particle=eps_b))
+    e_lo = err(oracle.fmm(pos, m, p=8, eps=1e-8, leaf_size=16))
+    e_hi = err(oracle.fmm(pos, m, p=8, eps=1e-6, leaf_size=16))
+    assert rms(e[inner]) < 1.5 * rms(e_lo[inner])
+    assert rms(e[~inner]) < 1.5 * rms(e_hi[~inner])
+    assert rms(e[inner]) < rms(e_hi[inner]) / 10
+    assert e[one] < 1e-13
