@@ -172,6 +172,14 @@ fmm_status fmm_forces_active(fmm_ctx *ctx, int64_t n, const double *pos, const d
                              double G, int p, double target_err, int64_t n_active,
                              const int64_t *active, int refit, double *pot, double *acc);
 
+/* fmm_forces with an individual accuracy parameter per particle (Sec. 7): the
+ * acceptance test compares with min_{b in B}{eps_b a_b} (criterion a; f_b for
+ * criterion f) instead of eps min_B{a_b}.  eps_particle: device, n FP64 in
+ * input order, each > 0 and finite (FMM_E_INVAL otherwise, nothing written).
+ * p < 0 takes the order for the smallest eps_b.  Not for FMM_MAC_THETA. */
+fmm_status fmm_forces_eps(fmm_ctx *ctx, int64_t n, const double *pos, const double *mass,
+                          double G, int p, const double *eps_particle, double *pot, double *acc);
+
 /* Exact FP64 direct summation of eq. (1) on the GPU (the comparison
  * baseline): all n sinks against all n sources, a != b. */
 fmm_status fmm_direct(fmm_ctx *ctx, int64_t n, const double *pos, const double *mass,

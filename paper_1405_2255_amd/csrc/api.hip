@@ -130,6 +130,7 @@ struct fmm_ctx {
     DevBuf pt_n, pt_m, pt_s, pt_off, pt_moff, ptasks, ppart;
     DevBuf counters, nonfinite, walktmp, coffsets, roots, ckey, ckey2, order, order2;
     DevBuf actflag, actf, actinv, actpre, cellact, actbad;   // forces for a listed subset
+    DevBuf epsmin;                                           // smallest individual eps
     DevBuf dkey, dsort, dsort2, runstart;   // deep refinement below level 21
     DevBuf plans;                          // output plans of M2M and L2L for order plan_p
     DevBuf Tsh;                            // M2M: each cell's expansion shifted to its parent
@@ -507,7 +508,9 @@ void run_p2p(fmm_ctx *c, int want_f, int with_pot, int mixed, double4 *out4, boo
 }
 
 // ------------------------------------------------------------ sink scale
-void sink_scale(fmm_ctx *c, bool want_f) {
+// eps_b (input order, device) when not null: individual accuracy parameters
+// folded into the scale, min_B{eps_b a_b} (Sec. 7)
+void sink_scale(fmm_ctx *c, bool want_f, const double *eps_b) {
     hipStream_t s = c->stream;
     const int64_t n = c->n;
     TreeArrays t = tree_arrays(c);
@@ -537,6 +540,7 @@ void sink_scale(fmm_ctx *c, bool want_f) {
         run_p2p(c, want_f, 0, 0, e4, false);
         CK(launch_scale(want_f, n, e4, scale, s));
     }
+    if (eps_b) CK(launch_scale_eps(n, c->perm, eps_b, scale, s));
     for (int Lv = c->depth; Lv >= 0; --Lv)
         CK(launch_smin_level(t, c->ls[Lv], c->ls[Lv + 1], scale, s));
 }
@@ -546,7 +550,7 @@ void sink_scale(fmm_ctx *c, bool want_f) {
 // indices) are sinks: pot/acc receive their results in list order (Sec. 7.1)
 void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double G, int p,
             double eps, double *pot, double *acc, int K, const int64_t *off, bool refit,
-            int64_t nact = 0, const int64_t *act = nullptr) {
+            int64_t nact = 0, const int64_t *act = nullptr, const double *eps_b = nullptr) {
     hipStream_t s = c->stream;
     c->st = fmm_stats_t{};
     c->n = n;
@@ -580,7 +584,7 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
     }
     mark(c, PH_TREE);
     const bool want_f = c->opts.mac == FMM_MAC_SCALED;
-    if (c->opts.mac != FMM_MAC_THETA) sink_scale(c, want_f);
+    if (c->opts.mac != FMM_MAC_THETA) sink_scale(c, want_f, eps_b);
     mark(c, PH_EST);
     // upward pass
     const int nc = ncplx(p);
@@ -607,6 +611,7 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
     WalkParams wp{c->opts.mac == FMM_MAC_THETA ? 1 : 0, p, eps, c->opts.theta_crit,
                   c->opts.p2p_factor * (p + 1.0) * (p + 1.0) * (p + 1.0), 0, 0, 0, {}};
     wp.active = cell_active;
+    if (eps_b) wp.eps = 1.0;      // eps_b is in the cell minimum of the scale
     Lists L = walk(c, wp, P);
     c->st.walk_pairs = c->last_walk_pairs;
     c->st.t_sweeps = c->last_sweep_ms;
@@ -848,7 +853,7 @@ void fmm_destroy(fmm_ctx *c) {
                       &c->ckey, &c->ckey2, &c->order, &c->order2, &c->wcode, &c->rup,
                       &c->actflag, &c->actf, &c->actinv, &c->actpre, &c->cellact, &c->actbad,
                       &c->dkey, &c->dsort, &c->dsort2, &c->runstart, &c->plans, &c->Tsh,
-                      &c->M32, &c->sig, &c->Flow};
+                      &c->M32, &c->sig, &c->Flow, &c->epsmin};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (auto &e : c->ev) if (e) (void)hipEventDestroy(e);
@@ -991,6 +996,49 @@ fmm_status fmm_forces_active(fmm_ctx *c, int64_t n, const double *pos, const dou
         fmm::forces(c, n, pos, mass, G, p, target_err, pot, acc, 1, off, refit != 0, n_active,
                     active);
         if (c->hint[1]) return fmm::fail(c, FMM_E_INVAL, "active index out of range");
+        if (c->hint[0]) return fmm::fail(c, FMM_E_NONFINITE, "non-finite potential or acceleration");
+        return FMM_OK;
+    });
+}
+
+fmm_status fmm_forces_eps(fmm_ctx *c, int64_t n, const double *pos, const double *mass,
+                          double G, int p, const double *eps_particle, double *pot, double *acc) {
+    if (!c) return FMM_E_INVAL;
+    fmm::Guard g(c);
+    if (!g.ok) return FMM_E_BUSY;
+    c->err.clear();
+    if (n > 0 && !eps_particle) return fmm::fail(c, FMM_E_INVAL, "eps_particle is null");
+    if (c->opts.mac == FMM_MAC_THETA)
+        return fmm::fail(c, FMM_E_INVAL, "individual eps need criterion a or f");
+    if (n < 0 || (n > 0 && (!pos || !mass || !pot || !acc)))
+        return fmm::fail(c, FMM_E_INVAL, "bad argument");
+    if (n == 0) return FMM_OK;
+    return fmm::guarded(c, [&]() -> fmm_status {
+        // every eps_b > 0 and finite; the smallest sets the order when p < 0
+        unsigned long long *mb = fmm::ensure<unsigned long long>(c->epsmin, 1);
+        int *bad = fmm::ensure<int>(c->actbad, 1);
+        CK(hipMemsetAsync(mb, 0xff, sizeof(unsigned long long), c->stream));
+        CK(hipMemsetAsync(bad, 0, sizeof(int), c->stream));
+        CK(fmm::launch_eps_min(n, eps_particle, mb, bad, c->stream));
+        unsigned long long *h = reinterpret_cast<unsigned long long *>(c->hint + 2);
+        CK(hipMemcpyAsync(h, mb, sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
+        CK(hipMemcpyAsync(c->hint + 1, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        fmm::sync(c);
+        if (c->hint[1]) return fmm::fail(c, FMM_E_INVAL, "every eps_b must be > 0 and finite");
+        double emin;
+        std::memcpy(&emin, h, sizeof(double));
+        int pp = p;
+        fmm_status st = check_common(c, n, pos, mass, G, &pp, emin, pot, acc);
+        if (st != FMM_OK) return st;
+        if (n == 1) {
+            CK(hipMemsetAsync(pot, 0, sizeof(double), c->stream));
+            CK(hipMemsetAsync(acc, 0, 3 * sizeof(double), c->stream));
+            fmm::sync(c);
+            return FMM_OK;
+        }
+        const int64_t off[2] = {0, n};
+        fmm::forces(c, n, pos, mass, G, pp, emin, pot, acc, 1, off, false, 0, nullptr,
+                    eps_particle);
         if (c->hint[0]) return fmm::fail(c, FMM_E_NONFINITE, "non-finite potential or acceleration");
         return FMM_OK;
     });

@@ -252,6 +252,13 @@ hipError_t launch_mark_listed(int64_t n, int64_t nact, const int64_t *act, int *
 hipError_t launch_cell_active(int64_t n, const uint32_t *perm, const int *flag_in, int *f,
                               int *inv, int *pre, int *tmp, int *total, int ncells, const int *beg,
                               const int *end, uint8_t *active, hipStream_t s);
+// individual accuracy parameters (Sec. 7): *bad = 1 unless every eps_b is
+// > 0 and finite; *minbits (set to all ones by the caller) = bit pattern of the
+// smallest; launch_scale_eps multiplies the key-ordered sink scale by eps_b
+hipError_t launch_eps_min(int64_t n, const double *eps_b, unsigned long long *minbits, int *bad,
+                         hipStream_t s);
+hipError_t launch_scale_eps(int64_t n, const uint32_t *perm, const double *eps_b, double *scale,
+                           hipStream_t s);
 hipError_t launch_output_listed(int64_t n, int64_t nact, const int64_t *act, const int *inv,
                                 const double4 *out4, double G, double *pot, double *acc,
                                 int *nonfinite, hipStream_t s);

@@ -14,6 +14,8 @@
 // adds into the output directly; otherwise each task writes a row of partial
 // sums that a second kernel adds in task order (deterministic).
 // Source particles are read as (x, y, z, m) double4 from the key-sorted copy.
+#include <algorithm>
+
 #include "internal.h"
 #include "dev.h"
 
@@ -414,6 +416,40 @@ __global__ void k_output_listed(int64_t n, int64_t nact, const int64_t *act, con
     if (!(isfinite(p) && isfinite(a) && isfinite(b) && isfinite(c))) atomicOr(nonfinite, 1);
 }
 
+// ---- individual accuracy parameters (Sec. 7) ------------------------------
+// every eps_b must be > 0 and finite (*bad = 1 otherwise); the smallest one as
+// the bit pattern of a positive double (which orders like the value)
+__global__ void __launch_bounds__(256)
+k_eps_min(int64_t n, const double *eps_b, unsigned long long *minbits, int *bad) {
+    __shared__ unsigned long long red[256 / FMM_WAVE];
+    unsigned long long mine = ~0ull;
+    int fail = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = eps_b[i];
+        if (!(v > 0.0 && isfinite(v))) fail = 1;
+        else mine = min(mine, (unsigned long long)__double_as_longlong(v));
+    }
+    if (__any(fail) && lane_id() == 0) atomicOr(bad, 1);
+#pragma unroll
+    for (int off = FMM_WAVE / 2; off > 0; off >>= 1) mine = min(mine, __shfl_xor(mine, off));
+    if (lane_id() == 0) red[threadIdx.x / FMM_WAVE] = mine;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long b = red[0];
+        for (int w = 1; w < 256 / FMM_WAVE; ++w) b = min(b, red[w]);
+        atomicMin(minbits, b);
+    }
+}
+
+// scale[i] *= eps_b of the particle at sorted position i: the cell minimum
+// then is min_B{eps_b a_b} (or f_b) and the criterion compares with it alone
+__global__ void k_scale_eps(int64_t n, const uint32_t *perm, const double *eps_b, double *scale) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    scale[i] *= eps_b[perm[i]];
+}
+
 // sink scale of the acceptance test from the estimate: |a| (criterion a) or f
 __global__ void k_scale(int want_f, int64_t n, const double4 *est4, double *scale) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -517,6 +553,20 @@ hipError_t launch_output_listed(int64_t n, int64_t nact, const int64_t *act, con
     if (nact <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_output_listed, dim3(blocks(nact, 256)), dim3(256), 0, s, n, nact, act, inv,
                        out4, G, pot, acc, nonfinite);
+    return hipGetLastError();
+}
+
+hipError_t launch_eps_min(int64_t n, const double *eps_b, unsigned long long *minbits, int *bad,
+                         hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const unsigned nb = (unsigned)std::min<int64_t>(256, (n + 255) / 256);
+    hipLaunchKernelGGL(k_eps_min, dim3(nb), dim3(256), 0, s, n, eps_b, minbits, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_eps(int64_t n, const uint32_t *perm, const double *eps_b, double *scale,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_eps, dim3(blocks(n, 256)), dim3(256), 0, s, n, perm, eps_b, scale);
     return hipGetLastError();
 }
 

@@ -38,7 +38,7 @@ STATUS_NAMES = {OK: "FMM_OK", E_INVAL: "FMM_E_INVAL", E_NOMEM: "FMM_E_NOMEM", E_
                 E_BUSY: "FMM_E_BUSY"}
 
 SYMBOLS = ["fmm_build", "fmm_forces", "fmm_forces_batched", "fmm_forces_refit",
-           "fmm_forces_active", "fmm_direct",
+           "fmm_forces_active", "fmm_forces_eps", "fmm_direct",
            "fmm_direct_sinks",
            "fmm_order_for_error", "fmm_stats", "fmm_footprint_bytes", "fmm_last_error",
            "fmm_destroy", "fmm_export"]
@@ -81,6 +81,8 @@ _lib.fmm_forces_refit.restype = C.c_int
 _lib.fmm_forces_active.argtypes = [_P, C.c_int64, _P, _P, C.c_double, C.c_int, C.c_double,
                                    C.c_int64, _P, C.c_int, _P, _P]
 _lib.fmm_forces_active.restype = C.c_int
+_lib.fmm_forces_eps.argtypes = [_P, C.c_int64, _P, _P, C.c_double, C.c_int, _P, _P, _P]
+_lib.fmm_forces_eps.restype = C.c_int
 _lib.fmm_direct.argtypes = [_P, C.c_int64, _P, _P, C.c_double, _P, _P]
 _lib.fmm_direct.restype = C.c_int
 _lib.fmm_direct_sinks.argtypes = [_P, C.c_int64, _P, _P, C.c_double, C.c_int64, _P, _P, _P]
@@ -222,6 +224,19 @@ class Context:
                                            float(target_err), k, C.c_void_p(active.data_ptr()),
                                            int(bool(refit)), _dev_ptr(pot, "pot", (k,)),
                                            _dev_ptr(acc, "acc", (k, 3))))
+        return pot, acc
+
+    def forces_eps(self, pos: torch.Tensor, mass: torch.Tensor, eps_particle: torch.Tensor,
+                   G: float = 1.0, p: int = -1):
+        """forces() with an individual accuracy parameter per particle (float64
+        CUDA tensor, input order)."""
+        n = pos.shape[0]
+        pot = torch.empty(n, dtype=torch.float64, device=pos.device)
+        acc = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+        self._check(_lib.fmm_forces_eps(self._h, n, _dev_ptr(pos, "pos", (n, 3)),
+                                        _dev_ptr(mass, "mass", (n,)), float(G), int(p),
+                                        _dev_ptr(eps_particle, "eps_particle", (n,)),
+                                        _dev_ptr(pot, "pot", (n,)), _dev_ptr(acc, "acc", (n, 3))))
         return pot, acc
 
     def direct(self, pos: torch.Tensor, mass: torch.Tensor, G: float = 1.0):
