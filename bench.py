@@ -21,6 +21,7 @@ Prints ONE JSON line (rank 0): metric, value, ... plus
                 high-degree M2L arithmetic, FP64 sums), errors on all particles
   active        forces for subsets of sinks (innermost 1e3..1e5, random 1%) of
                 the same input, fresh and with a recycled tree (Sec. 7.1)
+  individual_eps  individual accuracy parameters (inner 10% at 1e-7, rest 1e-5)
   batched       512 independent Plummer clusters, N log-uniform in [1e3, 1e5],
                 in one call (FP64 and mixed, parameters autotuned on every 8th
                 cluster), against the same clusters one call each
@@ -258,6 +259,44 @@ def active_leg(args, fmm, pos, mass, params, full_ms):
             "all_equal_to_full_call": all(r["equal_to_full_call"] for r in runs)}
 
 
+def eps_leg(args, fmm, pos, mass, params, full_ms, acc_direct):
+    """Individual accuracy parameters (Sec. 7) on the N = 1e6 Plummer input: the
+    innermost 10% at eps_b = 1e-7 and the rest at 1e-5 (the main leg's order,
+    leaf size and threshold), timed against the main leg's global-eps call; rms
+    relative force error of each group against the GPU direct sum."""
+    import torch
+    leaf, pf, p, eps = params
+    n = pos.shape[0]
+    r = torch.linalg.norm(pos, dim=1)
+    inner = r <= torch.quantile(r[::97], 0.1)
+    eps_b = torch.where(inner, torch.tensor(1e-7, dtype=torch.float64, device=pos.device),
+                        torch.tensor(1e-5, dtype=torch.float64, device=pos.device)).contiguous()
+    ctx = fmm.Context(device=0, leaf_size=leaf, p2p_factor=pf, timing=True)
+    ctx.forces_eps(pos, mass, eps_b, 1.0, p)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        _, acc = ctx.forces_eps(pos, mass, eps_b, 1.0, p)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    st = ctx.stats()
+    ctx.close()
+    t = float(np.median(ts))
+    out = {"workload": f"Plummer N={n}, innermost 10% eps_b=1e-7, the rest 1e-5, p={p}, "
+                       f"n_L={leaf or 32}, p2p_factor={pf or 2.0:g}",
+           "value": n / t, "unit": "particle-forces/s", "ms": 1e3 * t,
+           "time_vs_main_call": 1e3 * t / full_ms,
+           "n_m2l": st["n_m2l"], "n_p2p_pairs": st["n_p2p_pairs"]}
+    if acc_direct is not None:
+        ad = torch.from_numpy(acc_direct).to(pos.device)
+        e = torch.linalg.norm(acc - ad, dim=1) / torch.linalg.norm(ad, dim=1)
+        out["rms_inner"] = float(torch.sqrt(torch.mean(e[inner] ** 2)))
+        out["rms_outer"] = float(torch.sqrt(torch.mean(e[~inner] ** 2)))
+    print(f"eps_b: {1e3 * t:.2f} ms", file=sys.stderr, flush=True)
+    return out
+
+
 def c3_leg(args, fmm, workloads):
     """Dehnen gamma = 1 cusp, power-law (Salpeter) masses on [0.1, 100]
     normalised to 1, N = 1e6 and 1e7, mixed precision, rms targets 1e-5 and
@@ -408,6 +447,7 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="omit the CPU baseline field")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-active", action="store_true")
+    ap.add_argument("--no-eps", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="library defaults instead of autotuned parameters")
     ap.add_argument("--retune", action="store_true",
@@ -594,6 +634,8 @@ def main() -> int:
         print(f"mixed: {ms_m:.2f} ms/step", file=sys.stderr, flush=True)
     active = None if args.no_active else active_leg(args, fmm, pos, mass,
                                                     (leaf, pf, p_arg, eps), ms_per_step)
+    eps_b = None if args.no_eps else eps_leg(args, fmm, pos, mass, (leaf, pf, st["p"], eps),
+                                             ms_per_step, ad_all)
     batched = None
     if not args.no_batched:
         batched = {"fp64": batched_leg(args, fmm, workloads, "fp64"),
@@ -631,6 +673,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "mixed": mixed,
         "active": active,
+        "individual_eps": eps_b,
         "batched": batched,
         "c3": c3,
         "served": served,
