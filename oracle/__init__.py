@@ -195,13 +195,13 @@ class _Params(C.Structure):
     _fields_ = [("p", C.c_int), ("eps", C.c_double), ("leaf_size", C.c_int),
                 ("mac", C.c_int), ("theta_crit", C.c_double), ("p2p_pairs", C.c_double),
                 ("scale_source", C.c_int), ("scale", C.c_void_p), ("G", C.c_double),
-                ("eps_particle", C.c_void_p)]
+                ("eps_particle", C.c_void_p), ("adaptive_order", C.c_int)]
 
 
 class _Stats(C.Structure):
     _fields_ = [(k, C.c_int64) for k in (
         "n_cells", "n_leaves", "depth", "n_m2l", "n_p2p_cells", "n_p2p_pairs",
-        "n_est_m2l", "n_est_p2p_pairs")]
+        "n_est_m2l", "n_est_p2p_pairs", "m2l_order_sum")]
 
 
 class _Lists(C.Structure):
@@ -212,16 +212,19 @@ class _Lists(C.Structure):
 
 def fmm(pos, mass, *, p: int, eps: float, leaf_size: int, G: float = 1.0,
         mac: int = MAC_A, theta_crit: float = 0.5, p2p_pairs: float = 0.0,
-        scale=None, want_lists: bool = False, list_cap: int = 1 << 22, eps_particle=None):
+        scale=None, want_lists: bool = False, list_cap: int = 1 << 22, eps_particle=None,
+        adaptive_order: int = 0):
     """Plain CPU FMM.  Returns dict with pot, acc, stats and (optionally) the
     interaction lists (arrays of (source id, sink id), id = level<<40 | begin)
-    and the per-particle sink scale used by the acceptance test."""
+    and the per-particle sink scale used by the acceptance test.
+    adaptive_order = q_min > 0: each M2L pair at the lowest order in [q_min, p]
+    that passes the criterion (Sec. 7); stats["m2l_order_sum"] sums the orders."""
     lib = _load()
     pos = _f64(pos)
     mass = _f64(mass)
     n = mass.shape[0]
     prm = _Params(p, eps, leaf_size, mac, theta_crit, p2p_pairs,
-                  1 if scale is not None else 0, None, G, None)
+                  1 if scale is not None else 0, None, G, None, int(adaptive_order))
     if scale is not None:
         scale = _f64(scale)
         prm.scale = scale.ctypes.data
@@ -251,7 +254,7 @@ def fmm(pos, mass, *, p: int, eps: float, leaf_size: int, G: float = 1.0,
                        theta_crit=theta_crit, p2p_pairs=p2p_pairs, scale=scale,
                        want_lists=True,
                        list_cap=int(max(lists.m2l_count, lists.p2p_count)) + 1,
-                       eps_particle=eps_particle)
+                       eps_particle=eps_particle, adaptive_order=adaptive_order)
         out["m2l"] = m2l_buf[: lists.m2l_count].copy()
         out["p2p"] = p2p_buf[: lists.p2p_count].copy()
         out["scale"] = sc

@@ -341,15 +341,21 @@ static void record(int64_t *buf, int64_t cap, int64_t *cnt, const cell_t *A, con
     ++*cnt;
 }
 
-static int accept(fmm_t *t, const cell_t *A, const cell_t *B, const double d[3]) {
+/* the criterion for an expansion of order `order` (E_{A->B} of eq:def:EAB at
+ * that order) */
+static int accept_order(fmm_t *t, const cell_t *A, const cell_t *B, const double d[3], int order) {
     const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     const or_fmm_params *q = t->prm;
     if (q->mac == OR_MAC_THETA) return A->rho + B->rho < q->theta_crit * r;
     if (!(A->rho + B->rho < r)) return 0;                        /* theta < 1 */
-    const double err = or_etilde_factor(A->rho, B->rho) * or_eab_times_mass(A->P, t->p, B->rho, r)
+    const double err = or_etilde_factor(A->rho, B->rho) * or_eab_times_mass(A->P, order, B->rho, r)
                        / (r * r);                                /* Etilde M_A / r^2 */
     /* individual eps_b are already folded into smin = min_B{eps_b a_b} (Sec. 7) */
     return err < (q->eps_particle ? 1.0 : q->eps) * B->smin;
+}
+
+static int accept(fmm_t *t, const cell_t *A, const cell_t *B, const double d[3]) {
+    return accept_order(t, A, B, d, t->p);
 }
 
 static void walk(fmm_t *t, int64_t ia, int64_t ib) {
@@ -369,8 +375,15 @@ static void walk(fmm_t *t, int64_t ia, int64_t ib) {
     const double d[3] = {B->c[0] - A->c[0], B->c[1] - A->c[1], B->c[2] - A->c[2]};
     const int ok = accept(t, A, B, d);
     if (ok && (double)(A->end - A->begin) * (double)(B->end - B->begin) >= t->prm->p2p_pairs) {
-        or_m2l(A->M, d, t->p, t->cells[ib].F);
+        /* adaptive order (Sec. 7): the lowest order in [q_min, p] that passes the
+         * criterion, q_min = adaptive_order */
+        int q = t->p;
+        if (t->prm->adaptive_order > 0 && t->prm->mac != OR_MAC_THETA)
+            for (q = t->prm->adaptive_order; q < t->p; ++q)
+                if (accept_order(t, A, B, d, q)) break;
+        or_m2l(A->M, d, q, t->cells[ib].F);
         ++t->st->n_m2l;
+        t->st->m2l_order_sum += q;
         record(t->lists ? t->lists->m2l : NULL, t->lists ? t->lists->m2l_cap : 0,
                &t->nm2l_rec, A, B);
         return;

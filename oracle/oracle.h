@@ -96,6 +96,11 @@ typedef struct {
     const double *eps_particle; /* NULL, or individual accuracy parameters eps_b (input
                                    order): the criterion compares with min_B{eps_b a_b}
                                    instead of eps min_B{a_b} (Sec. 7) */
+    int adaptive_order; /* q_min > 0: each cell pair evaluated by M2L uses the
+                           lowest order q in [q_min, p] that passes the criterion
+                           (Sec. 7); 0: every pair at order p.  About the centre of
+                           mass the dipole power vanishes, so the estimate at q = 1
+                           can be zero while the error is not: q_min >= 2 */
 } or_fmm_params;
 
 typedef struct {
@@ -104,6 +109,7 @@ typedef struct {
     int64_t n_p2p_cells;    /* cell->cell interactions done by direct summation */
     int64_t n_p2p_pairs;    /* particle pairs summed directly (ordered, a != b) */
     int64_t n_est_m2l, n_est_p2p_pairs; /* the same for the estimate pass */
+    int64_t m2l_order_sum;  /* sum over M2L pairs of the order used */
 } or_fmm_stats;
 
 /* Optional outputs for list comparison.  A cell is identified by
