@@ -32,6 +32,14 @@ def _load():
         P = C.c_void_p
         _lib.or_direct.argtypes = [i64, P, P, d, i64, P, ip, P, P, P]
         _lib.or_direct.restype = ip
+        _lib.or_direct_jerk.argtypes = [i64, P, P, P, d, i64, P, ip, P]
+        _lib.or_direct_jerk.restype = ip
+        _lib.or_upsilon_dot.argtypes = [P, P, ip, P]
+        _lib.or_upsilon_dot.restype = None
+        _lib.or_p2m_dot.argtypes = [i64, P, P, P, P, ip, P]
+        _lib.or_p2m_dot.restype = None
+        _lib.or_l2p_dot.argtypes = [P, P, P, P, ip, P]
+        _lib.or_l2p_dot.restype = None
         for name in ("or_theta", "or_upsilon"):
             getattr(_lib, name).argtypes = [P, ip, P]
             getattr(_lib, name).restype = None
@@ -100,6 +108,30 @@ def direct(pos, mass, G: float = 1.0, sinks=None, threads: int | None = None):
     return pot, acc, f
 
 
+def direct_jerk(pos, vel, mass, G: float = 1.0, sinks=None, threads: int | None = None):
+    """Exact FP64 jerk (time derivative of the direct-sum acceleration for
+    particles moving with vel), compensated sums; (nsinks, 3)."""
+    lib = _load()
+    pos = _f64(pos)
+    vel = _f64(vel)
+    mass = _f64(mass)
+    n = mass.shape[0]
+    assert pos.shape == (n, 3) and vel.shape == (n, 3)
+    if sinks is not None:
+        sinks = np.ascontiguousarray(sinks, dtype=np.int64)
+        ns = sinks.shape[0]
+    else:
+        ns = n
+    if threads is None:
+        threads = max(1, len(os.sched_getaffinity(0)))
+    jerk = np.empty((ns, 3))
+    rc = lib.or_direct_jerk(n, _ptr(pos), _ptr(vel), _ptr(mass), float(G), ns, _ptr(sinks),
+                            int(threads), _ptr(jerk))
+    if rc != 0:
+        raise ValueError("or_direct_jerk: bad arguments")
+    return jerk
+
+
 # ----------------------------------------------------------- harmonics/kernels
 
 def theta(r, p: int) -> np.ndarray:
@@ -154,6 +186,34 @@ def swap_matrix(n: int) -> np.ndarray:
     return out
 
 
+def upsilon_dot(r, v, p: int) -> np.ndarray:
+    r = _f64(r, (3,))
+    v = _f64(v, (3,))
+    out = np.zeros(ncoef(p), dtype=np.complex128)
+    _load().or_upsilon_dot(_ptr(r), _ptr(v), p, _ptr(out))
+    return out
+
+
+def p2m_dot(pos, vel, mass, z, p: int) -> np.ndarray:
+    pos = _f64(pos)
+    vel = _f64(vel)
+    mass = _f64(mass)
+    z = _f64(z, (3,))
+    out = np.zeros(ncoef(p), dtype=np.complex128)
+    _load().or_p2m_dot(mass.shape[0], _ptr(pos), _ptr(vel), _ptr(mass), _ptr(z), p, _ptr(out))
+    return out
+
+
+def l2p_dot(F, Fd, sB_minus_x, v, p: int) -> np.ndarray:
+    F = np.ascontiguousarray(F, dtype=np.complex128)
+    Fd = np.ascontiguousarray(Fd, dtype=np.complex128)
+    d = _f64(sB_minus_x, (3,))
+    v = _f64(v, (3,))
+    j = np.zeros(3)
+    _load().or_l2p_dot(_ptr(F), _ptr(Fd), _ptr(d), _ptr(v), p, _ptr(j))
+    return j
+
+
 def l2l(F, s_minus_sp, p: int) -> np.ndarray:
     F = np.ascontiguousarray(F, dtype=np.complex128)
     out = np.zeros(ncoef(p), dtype=np.complex128)
@@ -195,7 +255,8 @@ class _Params(C.Structure):
     _fields_ = [("p", C.c_int), ("eps", C.c_double), ("leaf_size", C.c_int),
                 ("mac", C.c_int), ("theta_crit", C.c_double), ("p2p_pairs", C.c_double),
                 ("scale_source", C.c_int), ("scale", C.c_void_p), ("G", C.c_double),
-                ("eps_particle", C.c_void_p), ("adaptive_order", C.c_int)]
+                ("eps_particle", C.c_void_p), ("adaptive_order", C.c_int),
+                ("vel", C.c_void_p), ("jerk", C.c_void_p)]
 
 
 class _Stats(C.Structure):
@@ -213,12 +274,13 @@ class _Lists(C.Structure):
 def fmm(pos, mass, *, p: int, eps: float, leaf_size: int, G: float = 1.0,
         mac: int = MAC_A, theta_crit: float = 0.5, p2p_pairs: float = 0.0,
         scale=None, want_lists: bool = False, list_cap: int = 1 << 22, eps_particle=None,
-        adaptive_order: int = 0):
+        adaptive_order: int = 0, vel=None):
     """Plain CPU FMM.  Returns dict with pot, acc, stats and (optionally) the
     interaction lists (arrays of (source id, sink id), id = level<<40 | begin)
     and the per-particle sink scale used by the acceptance test.
     adaptive_order = q_min > 0: each M2L pair at the lowest order in [q_min, p]
-    that passes the criterion (Sec. 7); stats["m2l_order_sum"] sums the orders."""
+    that passes the criterion (Sec. 7); stats["m2l_order_sum"] sums the orders.
+    vel (n, 3): also out["jerk"], the time derivative of acc (Sec. 7, jerk)."""
     lib = _load()
     pos = _f64(pos)
     mass = _f64(mass)
@@ -231,11 +293,20 @@ def fmm(pos, mass, *, p: int, eps: float, leaf_size: int, G: float = 1.0,
     if eps_particle is not None:      # individual accuracy parameters (Sec. 7)
         eps_particle = _f64(eps_particle)
         prm.eps_particle = eps_particle.ctypes.data
+    jerk = None
+    if vel is not None:               # jerk (Sec. 7)
+        vel = _f64(vel)
+        assert vel.shape == (n, 3)
+        jerk = np.zeros((n, 3))
+        prm.vel = vel.ctypes.data
+        prm.jerk = jerk.ctypes.data
     pot = np.zeros(n)
     acc = np.zeros((n, 3))
     st = _Stats()
     lists = None
     out = {}
+    if jerk is not None:
+        out["jerk"] = jerk
     if want_lists:
         m2l_buf = np.zeros((list_cap, 2), dtype=np.int64)
         p2p_buf = np.zeros((list_cap, 2), dtype=np.int64)
@@ -254,7 +325,7 @@ def fmm(pos, mass, *, p: int, eps: float, leaf_size: int, G: float = 1.0,
                        theta_crit=theta_crit, p2p_pairs=p2p_pairs, scale=scale,
                        want_lists=True,
                        list_cap=int(max(lists.m2l_count, lists.p2p_count)) + 1,
-                       eps_particle=eps_particle, adaptive_order=adaptive_order)
+                       eps_particle=eps_particle, adaptive_order=adaptive_order, vel=vel)
         out["m2l"] = m2l_buf[: lists.m2l_count].copy()
         out["p2p"] = p2p_buf[: lists.p2p_count].copy()
         out["scale"] = sc

@@ -7,6 +7,11 @@
  * and division, sources in index order, every sum Neumaier-compensated.
  * Threads split the sink list; each sink's sums are independent of the
  * split, so the result is bitwise the same for any thread count.
+ *
+ * The jerk j_b = d a_b / dt (Sec. 7, jerk) is the time derivative of the same
+ * sum for particles moving with velocities v:
+ *   j_b = G sum_{a != b} mu_a [ v_ab / r^3 - 3 (r . v_ab) r / r^5 ],
+ *   r = x_a - x_b, v_ab = v_a - v_b.
  */
 #include "oracle.h"
 
@@ -28,6 +33,7 @@ typedef struct {
     int64_t n; const double *pos, *mass; double G;
     const int64_t *sinks; int64_t lo, hi;
     double *pot, *acc, *f;
+    const double *vel; double *jerk;   /* jerk jobs: vel in, jerk out */
 } job;
 
 static void one_sink(const job *j, int64_t i) {
@@ -59,15 +65,55 @@ static void one_sink(const job *j, int64_t i) {
     if (j->f) j->f[i] = j->G * ks_val(&sf);
 }
 
+static void one_sink_jerk(const job *j, int64_t i) {
+    const int64_t b = j->sinks ? j->sinks[i] : i;
+    const double *xb = &j->pos[3 * b], *vb = &j->vel[3 * b];
+    ksum s[3] = {{0, 0}, {0, 0}, {0, 0}};
+    for (int64_t a = 0; a < j->n; ++a) {
+        if (a == b) continue;
+        double r[3], v[3];
+        for (int d = 0; d < 3; ++d) {
+            r[d] = j->pos[3 * a + d] - xb[d];
+            v[d] = j->vel[3 * a + d] - vb[d];
+        }
+        const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        const double rr = sqrt(r2);
+        const double q3 = j->mass[a] / (r2 * rr);            /* mu/r^3 */
+        const double rv = (r[0] * v[0] + r[1] * v[1] + r[2] * v[2]) / r2;
+        for (int d = 0; d < 3; ++d) ks_add(&s[d], q3 * (v[d] - 3.0 * rv * r[d]));
+    }
+    for (int d = 0; d < 3; ++d) j->jerk[3 * i + d] = j->G * ks_val(&s[d]);
+}
+
 static void *worker(void *arg) {
     const job *j = (const job *)arg;
-    for (int64_t i = j->lo; i < j->hi; ++i) one_sink(j, i);
+    for (int64_t i = j->lo; i < j->hi; ++i) {
+        if (j->jerk) one_sink_jerk(j, i);
+        else one_sink(j, i);
+    }
     return NULL;
 }
+
+static int run_jobs(int64_t n, const double *pos, const double *mass, double G,
+                    int64_t n_sinks, const int64_t *sinks, int threads,
+                    double *pot, double *acc, double *f, const double *vel, double *jerk);
 
 int or_direct(int64_t n, const double *pos, const double *mass, double G,
               int64_t n_sinks, const int64_t *sinks, int threads,
               double *pot, double *acc, double *f) {
+    return run_jobs(n, pos, mass, G, n_sinks, sinks, threads, pot, acc, f, NULL, NULL);
+}
+
+int or_direct_jerk(int64_t n, const double *pos, const double *vel, const double *mass,
+                   double G, int64_t n_sinks, const int64_t *sinks, int threads,
+                   double *jerk) {
+    if (!jerk || (n > 0 && !vel)) return -1;
+    return run_jobs(n, pos, mass, G, n_sinks, sinks, threads, NULL, NULL, NULL, vel, jerk);
+}
+
+static int run_jobs(int64_t n, const double *pos, const double *mass, double G,
+                    int64_t n_sinks, const int64_t *sinks, int threads,
+                    double *pot, double *acc, double *f, const double *vel, double *jerk) {
     if (n < 0 || (n > 0 && (!pos || !mass))) return -1;
     if (!sinks) n_sinks = n;
     if (n_sinks < 0) return -1;
@@ -80,7 +126,7 @@ int or_direct(int64_t n, const double *pos, const double *mass, double G,
     pthread_t tid[256];
     for (int t = 0; t < threads; ++t) {
         jobs[t] = (job){n, pos, mass, G, sinks, n_sinks * t / threads,
-                        n_sinks * (t + 1) / threads, pot, acc, f};
+                        n_sinks * (t + 1) / threads, pot, acc, f, vel, jerk};
     }
     int started = 0;
     for (int t = 1; t < threads; ++t) {

@@ -27,6 +27,10 @@
  *                Acceptance: theta < 1 and Etilde M_A / r^2 < eps min_B{a_b}
  *                (eq:mac:better:a) or min_B{f_b} (eq:mac:better:f).
  *   5. down:     L2L (eq:L2L) top down, L2P (eq:L2P) at leaf particles.
+ * With velocities the same passes also carry the time derivatives for the
+ * jerk (Sec. 7, eqs:fmm:dot): centres at rest, Mdot by eq:P2M:dot and M2M,
+ * Fdot by M2L of Mdot (same pairs, same order) and L2L, eq:L2P:dot at the
+ * particles, and the time derivative of every direct pair.
  *
  * Expansion centre of every cell: z = s = the midpoint of the bounding box of
  * its particles; rho = max distance of its particles from that centre
@@ -52,6 +56,7 @@ typedef struct {
     double c[3], rho;
     double smin;
     double complex *M, *F;   /* order p at c */
+    double complex *Md, *Fd; /* their time derivatives (jerk only) */
     double complex Me[4], Fe[4]; /* order 1 at com (estimate of a) */
     double fe;               /* 1/r^2 monopole sum (estimate of f) */
     double *P;
@@ -64,6 +69,7 @@ typedef struct {
     /* particles in Morton order */
     double *x;      /* 3n */
     double *m;
+    double *v;      /* 3n velocities (jerk only) */
     int64_t *orig;  /* Morton position -> input index */
     uint64_t *key;  /* levels 1..21 */
     uint64_t *key2; /* levels 22..42 (only inside overfull level-21 cells) */
@@ -71,6 +77,7 @@ typedef struct {
     cell_t *cells; int64_t ncells, cap;
     /* accumulators, Morton order */
     double *pot, *acc;      /* near + far */
+    double *jerk;           /* 3n (jerk only) */
     double *est_acc, *est_f;
     double *scale;          /* per particle sink scale, Morton order */
     or_fmm_stats *st;
@@ -208,8 +215,9 @@ static void cell_geometry(fmm_t *t, cell_t *C) {
 
 /* ------------------------------------------------------------ direct sums */
 
+/* jerk (not NULL): also the time derivative of each pair's acceleration */
 static void p2p(fmm_t *t, const cell_t *A, const cell_t *B, double *pot, double *acc,
-                int64_t *count) {
+                double *jerk, int64_t *count) {
     for (int64_t b = B->begin; b < B->end; ++b) {
         const double *xb = &t->x[3 * b];
         for (int64_t a = A->begin; a < A->end; ++a) {
@@ -221,6 +229,14 @@ static void p2p(fmm_t *t, const cell_t *A, const cell_t *B, double *pot, double 
             const double q = t->m[a] * ir, q3 = q * ir * ir;
             if (pot) pot[b] += q;
             acc[3 * b] += q3 * dx; acc[3 * b + 1] += q3 * dy; acc[3 * b + 2] += q3 * dz;
+            if (jerk) {
+                const double *va = &t->v[3 * a], *vb = &t->v[3 * b];
+                const double vx = va[0] - vb[0], vy = va[1] - vb[1], vz = va[2] - vb[2];
+                const double rv = (dx * vx + dy * vy + dz * vz) * ir * ir;
+                jerk[3 * b] += q3 * (vx - 3.0 * rv * dx);
+                jerk[3 * b + 1] += q3 * (vy - 3.0 * rv * dy);
+                jerk[3 * b + 2] += q3 * (vz - 3.0 * rv * dz);
+            }
             ++*count;
         }
     }
@@ -252,7 +268,7 @@ static void est_walk(fmm_t *t, int64_t ia, int64_t ib) {
     if (ia == ib) {
         if (is_leaf(A)) {
             if (want_f) p2p_f(t, A, A, t->est_f, &t->st->n_est_p2p_pairs);
-            else p2p(t, A, A, NULL, t->est_acc, &t->st->n_est_p2p_pairs);
+            else p2p(t, A, A, NULL, t->est_acc, NULL, &t->st->n_est_p2p_pairs);
         } else {
             for (int i = 0; i < A->nchild; ++i)
                 for (int j = 0; j < A->nchild; ++j) est_walk(t, A->child[i], A->child[j]);
@@ -269,7 +285,7 @@ static void est_walk(fmm_t *t, int64_t ia, int64_t ib) {
     }
     if (is_leaf(A) && is_leaf(B)) {
         if (want_f) p2p_f(t, A, B, t->est_f, &t->st->n_est_p2p_pairs);
-        else p2p(t, A, B, NULL, t->est_acc, &t->st->n_est_p2p_pairs);
+        else p2p(t, A, B, NULL, t->est_acc, NULL, &t->st->n_est_p2p_pairs);
         return;
     }
     if (split_choice(A, B, A->rho_com, B->rho_com) == 0) {
@@ -325,12 +341,16 @@ static void up(fmm_t *t, int64_t ic) {
     cell_t *C = &t->cells[ic];
     if (is_leaf(C)) {
         or_p2m(C->end - C->begin, &t->x[3 * C->begin], &t->m[C->begin], C->c, t->p, C->M);
+        if (t->v)   /* eq:P2M:dot */
+            or_p2m_dot(C->end - C->begin, &t->x[3 * C->begin], &t->v[3 * C->begin],
+                       &t->m[C->begin], C->c, t->p, C->Md);
     } else {
         for (int i = 0; i < C->nchild; ++i) {
             up(t, C->child[i]);
             const cell_t *D = &t->cells[C->child[i]];
             const double d[3] = {D->c[0] - C->c[0], D->c[1] - C->c[1], D->c[2] - C->c[2]};
             or_m2m(D->M, d, t->p, C->M);
+            if (t->v) or_m2m(D->Md, d, t->p, C->Md);   /* centres at rest */
         }
     }
     or_power(C->M, t->p, C->P);
@@ -362,7 +382,7 @@ static void walk(fmm_t *t, int64_t ia, int64_t ib) {
     const cell_t *A = &t->cells[ia], *B = &t->cells[ib];
     if (ia == ib) {
         if (is_leaf(A)) {
-            p2p(t, A, A, t->pot, t->acc, &t->st->n_p2p_pairs);
+            p2p(t, A, A, t->pot, t->acc, t->jerk, &t->st->n_p2p_pairs);
             ++t->st->n_p2p_cells;
             record(t->lists ? t->lists->p2p : NULL, t->lists ? t->lists->p2p_cap : 0,
                    &t->np2p_rec, A, A);
@@ -382,6 +402,7 @@ static void walk(fmm_t *t, int64_t ia, int64_t ib) {
             for (q = t->prm->adaptive_order; q < t->p; ++q)
                 if (accept_order(t, A, B, d, q)) break;
         or_m2l(A->M, d, q, t->cells[ib].F);
+        if (t->v) or_m2l(A->Md, d, q, t->cells[ib].Fd);   /* eq:M2L:dot */
         ++t->st->n_m2l;
         t->st->m2l_order_sum += q;
         record(t->lists ? t->lists->m2l : NULL, t->lists ? t->lists->m2l_cap : 0,
@@ -389,7 +410,7 @@ static void walk(fmm_t *t, int64_t ia, int64_t ib) {
         return;
     }
     if (ok || (is_leaf(A) && is_leaf(B))) {
-        p2p(t, A, B, t->pot, t->acc, &t->st->n_p2p_pairs);
+        p2p(t, A, B, t->pot, t->acc, t->jerk, &t->st->n_p2p_pairs);
         ++t->st->n_p2p_cells;
         record(t->lists ? t->lists->p2p : NULL, t->lists ? t->lists->p2p_cap : 0,
                &t->np2p_rec, A, B);
@@ -412,6 +433,11 @@ static void down(fmm_t *t, int64_t ic) {
             or_l2p(C->F, d, t->p, &psi, a);
             t->pot[b] += psi;
             for (int k = 0; k < 3; ++k) t->acc[3 * b + k] += a[k];
+            if (t->v) {   /* eq:L2P:dot */
+                double j[3];
+                or_l2p_dot(C->F, C->Fd, d, &t->v[3 * b], t->p, j);
+                for (int k = 0; k < 3; ++k) t->jerk[3 * b + k] += j[k];
+            }
         }
         return;
     }
@@ -419,6 +445,7 @@ static void down(fmm_t *t, int64_t ic) {
         cell_t *D = &t->cells[C->child[i]];
         const double d[3] = {C->c[0] - D->c[0], C->c[1] - D->c[1], C->c[2] - D->c[2]};
         or_l2l(C->F, d, t->p, D->F);
+        if (t->v) or_l2l(C->Fd, d, t->p, D->Fd);   /* centres at rest */
         down(t, C->child[i]);
     }
 }
@@ -437,7 +464,9 @@ static double subtree_min(fmm_t *t, int64_t ic) {
 static void release(fmm_t *t) {
     for (int64_t i = 0; i < t->ncells; ++i) {
         free(t->cells[i].M); free(t->cells[i].F); free(t->cells[i].P);
+        free(t->cells[i].Md); free(t->cells[i].Fd);
     }
+    free(t->v); free(t->jerk);
     free(t->cells); free(t->x); free(t->m); free(t->orig); free(t->key); free(t->key2);
     free(t->pot); free(t->acc); free(t->est_acc); free(t->est_f); free(t->scale);
 }
@@ -452,6 +481,7 @@ int or_fmm(const or_fmm_params *prm, int64_t n, const double *pos,
     if (n == 0) return 0;
     if (!pos || !mass || !pot || !acc) return -1;
     if (prm->scale_source == OR_SCALE_GIVEN && prm->mac != OR_MAC_THETA && !prm->scale) return -1;
+    if (prm->vel && !prm->jerk) return -1;
 
     fmm_t T; memset(&T, 0, sizeof(T));
     fmm_t *t = &T;
@@ -506,10 +536,22 @@ int or_fmm(const or_fmm_params *prm, int64_t n, const double *pos,
         C->F = (double complex *)calloc((size_t)t->ncoef, sizeof(double complex));
         C->P = (double *)calloc((size_t)t->p + 1, sizeof(double));
         if (!C->M || !C->F || !C->P) { release(t); return -2; }
+        if (prm->vel) {
+            C->Md = (double complex *)calloc((size_t)t->ncoef, sizeof(double complex));
+            C->Fd = (double complex *)calloc((size_t)t->ncoef, sizeof(double complex));
+            if (!C->Md || !C->Fd) { release(t); return -2; }
+        }
         if (is_leaf(C)) ++stats->n_leaves;
         if (C->level > stats->depth) stats->depth = C->level;
     }
     stats->n_cells = t->ncells;
+    if (prm->vel) {   /* velocities in the final particle order */
+        t->v = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+        t->jerk = (double *)calloc(3 * (size_t)n, sizeof(double));
+        if (!t->v || !t->jerk) { release(t); return -2; }
+        for (int64_t i = 0; i < n; ++i)
+            for (int d = 0; d < 3; ++d) t->v[3 * i + d] = prm->vel[3 * t->orig[i] + d];
+    }
 
     /* 2. sink scale */
     if (prm->mac != OR_MAC_THETA) {
@@ -542,6 +584,8 @@ int or_fmm(const or_fmm_params *prm, int64_t n, const double *pos,
         const int64_t j = t->orig[i];
         pot[j] = -prm->G * t->pot[i];
         for (int d = 0; d < 3; ++d) acc[3 * j + d] = prm->G * t->acc[3 * i + d];
+        if (t->v)
+            for (int d = 0; d < 3; ++d) prm->jerk[3 * j + d] = prm->G * t->jerk[3 * i + d];
     }
     release(t);
     return 0;

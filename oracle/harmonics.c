@@ -141,6 +141,63 @@ void or_l2p(const double complex *F, const double sB_minus_x[3], int p,
     acc[2] = -creal(Psi[1][0]);
 }
 
+/* Time derivatives (App. A.5).  In xi = (x+iy)/2, eta = -(x-iy)/2 and z
+ * (eq:xi:eta) the first derivatives of the regular harmonics follow from
+ * eq:dUnm with the first-order operators d/dxi (Delta_1^{-1}), d/deta
+ * (Delta_1^1) and -d/dz (Delta_1^0):
+ *   d/dxi Upsilon_n^m = Upsilon_{n-1}^{m-1},  d/deta Upsilon_n^m = Upsilon_{n-1}^{m+1},
+ *   d/dz Upsilon_n^m = Upsilon_{n-1}^m,
+ * and the chain rule gives d/dt = xidot d/dxi + etadot d/deta + zdot d/dz.
+ * Upsilon_1^1 = xi, whose derivative is xidot, fixes this pairing of xidot
+ * with m-1 (the relation as printed pairs xidot with m+1). */
+void or_upsilon_dot(const double r[3], const double v[3], int p, double complex *Ud) {
+    double complex *U = scratch(p);
+    or_upsilon(r, p, U);
+    const double complex xid = 0.5 * (v[0] + I * v[1]);
+    const double complex etad = -0.5 * (v[0] - I * v[1]);
+    Ud[OR_IDX(0, 0)] = 0.0;
+    for (int n = 1; n <= p; ++n)
+        for (int m = -n; m <= n; ++m)
+            Ud[OR_IDX(n, m)] = xid * get(U, n - 1, m - 1) + v[2] * get(U, n - 1, m)
+                               + etad * get(U, n - 1, m + 1);
+    free(U);
+}
+
+/* eq:P2M:dot */
+void or_p2m_dot(int64_t n, const double *pos, const double *vel, const double *mass,
+                const double z[3], int p, double complex *Md) {
+    double complex *Ud = scratch(p);
+    for (int64_t a = 0; a < n; ++a) {
+        const double d[3] = {pos[3 * a] - z[0], pos[3 * a + 1] - z[1], pos[3 * a + 2] - z[2]};
+        or_upsilon_dot(d, &vel[3 * a], p, Ud);
+        for (int k = 0; k < (p + 1) * (p + 1); ++k) Md[k] += mass[a] * Ud[k];
+    }
+    free(Ud);
+}
+
+/* eq:L2P:dot with n = 1: s_B is at rest, so d/dt (s_B - x) = -v */
+void or_l2p_dot(const double complex *F, const double complex *Fd, const double sB_minus_x[3],
+                const double v[3], int p, double jerk[3]) {
+    double complex *U = scratch(p), *Ud = scratch(p);
+    const double mv[3] = {-v[0], -v[1], -v[2]};
+    or_upsilon(sB_minus_x, p, U);
+    or_upsilon_dot(sB_minus_x, mv, p, Ud);
+    double complex Psid[2] = {0.0, 0.0};
+    for (int m = 0; m <= 1; ++m) {
+        double complex s = 0.0;
+        for (int k = 0; k <= p - 1; ++k)
+            for (int l = -k; l <= k; ++l)
+                s += conj(get(U, k, l)) * get(Fd, 1 + k, m + l)
+                     + conj(get(Ud, k, l)) * get(F, 1 + k, m + l);
+        Psid[m] = s;
+    }
+    free(U);
+    free(Ud);
+    jerk[0] = -creal(Psid[1]);
+    jerk[1] = -cimag(Psid[1]);
+    jerk[2] = -creal(Psid[0]);
+}
+
 static double factorial(int k) {
     double f = 1.0;
     for (int i = 2; i <= k; ++i) f *= i;

@@ -47,6 +47,13 @@ int or_direct(int64_t n, const double *pos, const double *mass, double G,
               int64_t n_sinks, const int64_t *sinks, int threads,
               double *pot, double *acc, double *f);
 
+/* jerk[3i..] = G sum_{a != b} mu_a [v_ab/r^3 - 3 (r.v_ab) r/r^5] with r = x_a - x_b,
+ * v_ab = v_a - v_b (the time derivative of acc above; Sec. 7, jerk), same sink
+ * list, summation order and compensation as or_direct. */
+int or_direct_jerk(int64_t n, const double *pos, const double *vel, const double *mass,
+                   double G, int64_t n_sinks, const int64_t *sinks, int threads,
+                   double *jerk);
+
 /* ---- harmonics and kernels (harmonics.c), complex, all m ------------- */
 void or_theta(const double r[3], int p, double complex *T);
 void or_upsilon(const double r[3], int p, double complex *U);
@@ -65,6 +72,19 @@ void or_l2l(const double complex *F, const double s_minus_sp[3], int p,
 /* Psi_0^0 and a = -(Re Psi_1^1, Im Psi_1^1, Psi_1^0) at x_b     eq:L2P:Psi, eq:L2P */
 void or_l2p(const double complex *F, const double sB_minus_x[3], int p,
             double *psi, double acc[3]);
+/* d/dt Upsilon_n^m(r) for dr/dt = v, n = 0..p (App. A.5, time derivatives):
+ * xidot Upsilon_{n-1}^{m-1} + zdot Upsilon_{n-1}^m + etadot Upsilon_{n-1}^{m+1}
+ * with xi = (x+iy)/2, eta = -(x-iy)/2 (eq:xi:eta) */
+void or_upsilon_dot(const double r[3], const double v[3], int p, double complex *Ud);
+/* Mdot_n^m(z) += sum_a mu_a d/dt Upsilon_n^m(x_a - z) with dx_a/dt = v_a   eq:P2M:dot */
+void or_p2m_dot(int64_t n, const double *pos, const double *vel, const double *mass,
+                const double z[3], int p, double complex *Md);
+/* jerk contribution of a local expansion F and its time derivative Fd at a
+ * particle moving with v: j = -(Re Psidot_1^1, Im Psidot_1^1, Psidot_1^0) with
+ * Psidot_1^m = sum_{k<=p-1,l} [conj(Upsilon_k^l(s_B - x)) Fd_{1+k}^{m+l}
+ *             + conj(d/dt Upsilon_k^l(s_B - x, -v)) F_{1+k}^{m+l}]   eq:L2P:dot */
+void or_l2p_dot(const double complex *F, const double complex *Fd, const double sB_minus_x[3],
+                const double v[3], int p, double jerk[3]);
 /* Swap matrix B_n (x <-> z) of eq:Ylm:swap by its recurrence (App. A):
  * (2n+1)^2 doubles, row m = -n..n, column l = -n..n, row-major. */
 void or_swap_matrix(int n, double *B);
@@ -101,6 +121,12 @@ typedef struct {
                            (Sec. 7); 0: every pair at order p.  About the centre of
                            mass the dipole power vanishes, so the estimate at q = 1
                            can be zero while the error is not: q_min >= 2 */
+    const double *vel;  /* NULL, or velocities (input order, 3n): then jerk (3n,
+                           input order) receives the jerk (Sec. 7, jerk), with the
+                           expansion centres at rest: Mdot by eq:P2M:dot and M2M,
+                           Fdot by M2L of Mdot and L2L, eq:L2P:dot at the particles,
+                           and the time derivative of the direct sums */
+    double *jerk;
 } or_fmm_params;
 
 typedef struct {
