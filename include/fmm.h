@@ -180,6 +180,21 @@ fmm_status fmm_forces_active(fmm_ctx *ctx, int64_t n, const double *pos, const d
 fmm_status fmm_forces_eps(fmm_ctx *ctx, int64_t n, const double *pos, const double *mass,
                           double G, int p, const double *eps_particle, double *pot, double *acc);
 
+/* Forces and jerk j = da/dt of every particle (Sec. 7, jerk; eqs:fmm:dot), for
+ * particles moving with velocities vel (device, n x 3 FP64, input order).
+ * pot and acc are those of fmm_forces with the same arguments; jerk (device,
+ * n x 3) receives G sum_a mu_a d/dt[(x_a - x_b)/|x_a - x_b|^3] with the
+ * expansion centres held at rest: multipole rates from the time derivative of
+ * eq:P2M (P2M:dot) and M2M, field-tensor rates from M2L of the multipole rates
+ * over the same interaction list and order (in FP64 whatever the precision
+ * option) and L2L, eq:L2P:dot at the particles, and the time derivative of
+ * every direct pair.  The acceptance test is that of the acceleration; the
+ * jerk's relative error is typically the order p times the force error.
+ * A non-finite jerk gives FMM_E_NONFINITE. */
+fmm_status fmm_forces_jerk(fmm_ctx *ctx, int64_t n, const double *pos, const double *vel,
+                           const double *mass, double G, int p, double target_err, double *pot,
+                           double *acc, double *jerk);
+
 /* Exact FP64 direct summation of eq. (1) on the GPU (the comparison
  * baseline): all n sinks against all n sources, a != b. */
 fmm_status fmm_direct(fmm_ctx *ctx, int64_t n, const double *pos, const double *mass,

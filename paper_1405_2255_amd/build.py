@@ -14,6 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfmm.so")
 SOURCES = ["api.hip", "sort.hip", "tree.hip", "walk.hip", "expansions.hip", "m2l.hip", "p2p.hip",
+           "jerk.hip",
            "m2l_p01_06.hip", "m2l_p07_08.hip", "m2l_p09.hip", "m2l_p10.hip", "m2l_p11.hip",
            "m2l_p12.hip", "m2l_p13.hip", "m2l_p14.hip", "m2l_p15.hip", "m2l_p16.hip",
            "m2l32_p01_08.hip", "m2l32_p09_10.hip", "m2l32_p11.hip", "m2l32_p12.hip",

@@ -11,6 +11,7 @@
 // (cells per tree level, pairs per walk sweep) to size the next launch.
 #include "../../include/fmm.h"
 #include "internal.h"
+#include "jerk.h"
 
 #include <algorithm>
 #include <atomic>
@@ -131,6 +132,8 @@ struct fmm_ctx {
     DevBuf counters, nonfinite, walktmp, coffsets, roots, ckey, ckey2, order, order2;
     DevBuf actflag, actf, actinv, actpre, cellact, actbad;   // forces for a listed subset
     DevBuf epsmin;                                           // smallest individual eps
+    DevBuf vel4, Md, Fd, jFpart, jo4;    // jerk: velocities, rates of M and F, M2L chunk
+                                         // parts of the rates, jerk per particle
     DevBuf dkey, dsort, dsort2, runstart;   // deep refinement below level 21
     DevBuf plans;                          // output plans of M2M and L2L for order plan_p
     DevBuf Tsh;                            // M2M: each cell's expansion shifted to its parent
@@ -153,6 +156,7 @@ struct fmm_ctx {
     int pack = 0;   // direct-sum keys carry the range end (sh + 2 pb <= 64)
     int walk_used[3] = {0, 0, 0};   // sweeps the last walk of each mode needed
     int64_t n_m2l = 0, n_p2p = 0, n_ranges = 0;
+    int p2p_ntasks = 0;       // direct-sum tasks of the last run_p2p
     uint64_t *m2l_sorted = nullptr, *p2p_sorted = nullptr;
     uint32_t *p2pe_sorted = nullptr;
     std::vector<int> ls;  // first cell of each level
@@ -495,6 +499,7 @@ void run_p2p(fmm_ctx *c, int want_f, int with_pot, int mixed, double4 *out4, boo
     CK(hipMemcpyAsync(c->hint, totals, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     sync(c);
     const int ntasks = c->hint[0], prows = c->hint[1];
+    c->p2p_ntasks = ntasks;
     int2 *tasks = ensure<int2>(c->ptasks, std::max(ntasks, 1));
     double4 *part = ensure<double4>(c->ppart, (size_t)std::max(prows, 1) * 64);
     CK(launch_p2p_tasks(nl, toff, tasks, s));
@@ -548,9 +553,12 @@ void sink_scale(fmm_ctx *c, bool want_f, const double *eps_b) {
 // ------------------------------------------------------------ the call
 // nact/act: when act is not null, only the nact listed particles (input
 // indices) are sinks: pot/acc receive their results in list order (Sec. 7.1)
+// vel/jerk (device, input order, 3n each) when not null: the jerk as well
+// (Sec. 7), with the expansion centres at rest
 void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double G, int p,
             double eps, double *pot, double *acc, int K, const int64_t *off, bool refit,
-            int64_t nact = 0, const int64_t *act = nullptr, const double *eps_b = nullptr) {
+            int64_t nact = 0, const int64_t *act = nullptr, const double *eps_b = nullptr,
+            const double *vel = nullptr, double *jerk = nullptr) {
     hipStream_t s = c->stream;
     c->st = fmm_stats_t{};
     c->n = n;
@@ -606,6 +614,19 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
     for (int L = c->depth; L >= 0; --L)
         CK(launch_m2m_level(p, t, c->ls[L], c->ls[L + 1], U, M, Tsh, plans, s));
     CK(launch_power(p, c->ncells, M, P, s));
+    // jerk: rates of the multipoles (eq:P2M:dot, then the same M2M with the
+    // centres at rest; Tsh is free again once M is complete)
+    double4 *v4 = nullptr;
+    double *Md = nullptr;
+    if (vel) {
+        v4 = ensure<double4>(c->vel4, n);
+        Md = ensure<double>(c->Md, 2 * (size_t)nc * c->ncells);
+        CK(launch_gather_vel(n, c->perm, vel, v4, s));
+        CK(launch_p2m_dot(p, t, ptr<int>(c->leaf_cell), c->nleaves, ptr<double>(c->x),
+                          ptr<double>(c->y), ptr<double>(c->z), ptr<double>(c->m), v4, Md, s));
+        for (int L = c->depth; L >= 0; --L)
+            CK(launch_m2m_level(p, t, c->ls[L], c->ls[L + 1], U, Md, Tsh, plans, s));
+    }
     mark(c, PH_UP);
     // walk
     WalkParams wp{c->opts.mac == FMM_MAC_THETA ? 1 : 0, p, eps, c->opts.theta_crit,
@@ -627,7 +648,7 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
     // M2L: the rotation kernel over 64-entry windows of the list, or the
     // direct kernel by chunks of one sink's list
     double *F = ensure<double>(c->F, 2 * (size_t)nc * c->ncells);
-    const bool rot = FMM_M2L_ROT_ENABLED &&
+    const bool rot = FMM_M2L_ROT_ENABLED && !vel &&
                      (c->opts.m2l_kernel == FMM_M2L_ROTATION ||
                       (c->opts.m2l_kernel == FMM_M2L_AUTO &&
                        c->opts.precision == FMM_PREC_FP64 && p >= FMM_M2L_ROT_AUTO_MIN &&
@@ -680,18 +701,44 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
             if (c->opts.timing) CK(hipEventRecord(c->ev_m2l[1], s));
             CK(launch_m2l_reduce(p, c->ncells, coff, Fpart, F, s));
         }
+        if (vel) {   // eq:M2L:dot: the same pairs applied to the rates, FP64
+            double *Fd = ensure<double>(c->Fd, 2 * (size_t)nc * c->ncells);
+            double *Fp = ensure<double>(c->jFpart, 2 * (size_t)nc * std::max(nchunks, 1));
+            CK(launch_m2l(p, nchunks, chunks, c->m2l_sorted, c->sh, t, Md, Fp, s));
+            CK(launch_m2l_reduce(p, c->ncells, coff, Fp, Fd, s));
+        }
     }
     mark(c, PH_M2L);
     // downward pass, far field at the particles
-    for (int Lv = 1; Lv <= c->depth; ++Lv)
+    for (int Lv = 1; Lv <= c->depth; ++Lv) {
         CK(launch_l2l_level(p, t, c->ls[Lv], c->ls[Lv + 1], U, F,
                             ptr<short>(c->plans) + FMM_PLAN_SIZE, s, cell_active));
+        if (vel)
+            CK(launch_l2l_level(p, t, c->ls[Lv], c->ls[Lv + 1], U, ptr<double>(c->Fd),
+                                ptr<short>(c->plans) + FMM_PLAN_SIZE, s));
+    }
     double4 *o4 = ensure<double4>(c->out4, n);
     CK(launch_l2p(p, t, ptr<int>(c->leaf_of), ptr<int>(c->leaf_cell), n, ptr<double>(c->x),
                   ptr<double>(c->y), ptr<double>(c->z), F, o4, s, cell_active));
+    double4 *jo4 = nullptr;
+    if (vel) {   // eq:L2P:dot, assigns the far-field jerk of every particle
+        jo4 = ensure<double4>(c->jo4, n);
+        CK(launch_l2p_dot(p, t, ptr<int>(c->leaf_of), ptr<int>(c->leaf_cell), n,
+                          ptr<double>(c->x), ptr<double>(c->y), ptr<double>(c->z), v4, F,
+                          ptr<double>(c->Fd), jo4, s));
+    }
     mark(c, PH_DOWN);
     // near field
     run_p2p(c, 0, 1, c->opts.precision == FMM_PREC_MIXED, o4, true, cell_active);
+    if (vel) {   // near-field jerk over the same tasks
+        TreeArrays tt = tree_arrays(c);
+        CK(launch_p2p_jerk(c->p2p_ntasks, ptr<int2>(c->ptasks), ptr<int>(c->leaf_cell),
+                           ptr<int>(c->pt_s), ptr<int>(c->pt_moff), ptr<int64_t>(c->p2p_off),
+                           ptr<int2>(c->ranges), ptr<int>(c->rup), tt, ptr<double4>(c->xyzm), v4,
+                           jo4, ptr<double4>(c->ppart), s));
+        CK(launch_p2p_reduce(n, ptr<int>(c->leaf_of), ptr<int>(c->leaf_cell), ptr<int>(c->pt_s),
+                             ptr<int>(c->pt_moff), tt, ptr<double4>(c->ppart), jo4, s));
+    }
     mark(c, PH_P2P);
     int *nonfinite = ptr<int>(c->nonfinite);
     CK(hipMemsetAsync(nonfinite, 0, sizeof(int), s));
@@ -699,6 +746,7 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
         CK(launch_output_listed(n, nact, act, inv, o4, G, pot, acc, nonfinite, s));
     else
         CK(launch_output(n, c->perm, o4, G, pot, acc, nonfinite, s));
+    if (vel) CK(launch_output_jerk(n, c->perm, jo4, G, jerk, nonfinite, s));
     if (c->opts.scale_source == FMM_SCALE_PREVIOUS && !act) {
         CK(launch_norm3(acc, n, G, ensure<double>(c->prev_scale, n), s));
         c->have_prev_scale = true;
@@ -853,7 +901,8 @@ void fmm_destroy(fmm_ctx *c) {
                       &c->ckey, &c->ckey2, &c->order, &c->order2, &c->wcode, &c->rup,
                       &c->actflag, &c->actf, &c->actinv, &c->actpre, &c->cellact, &c->actbad,
                       &c->dkey, &c->dsort, &c->dsort2, &c->runstart, &c->plans, &c->Tsh,
-                      &c->M32, &c->sig, &c->Flow, &c->epsmin};
+                      &c->M32, &c->sig, &c->Flow, &c->epsmin, &c->vel4, &c->Md, &c->Fd,
+                      &c->jFpart, &c->jo4};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (auto &e : c->ev) if (e) (void)hipEventDestroy(e);
@@ -1040,6 +1089,37 @@ fmm_status fmm_forces_eps(fmm_ctx *c, int64_t n, const double *pos, const double
         fmm::forces(c, n, pos, mass, G, pp, emin, pot, acc, 1, off, false, 0, nullptr,
                     eps_particle);
         if (c->hint[0]) return fmm::fail(c, FMM_E_NONFINITE, "non-finite potential or acceleration");
+        return FMM_OK;
+    });
+}
+
+fmm_status fmm_forces_jerk(fmm_ctx *c, int64_t n, const double *pos, const double *vel,
+                           const double *mass, double G, int p, double target_err, double *pot,
+                           double *acc, double *jerk) {
+    if (!c) return FMM_E_INVAL;
+    fmm::Guard g(c);
+    if (!g.ok) return FMM_E_BUSY;
+    c->err.clear();
+    if (n > 0 && (!vel || !jerk)) return fmm::fail(c, FMM_E_INVAL, "null velocity or jerk array");
+    fmm_status st = check_common(c, n, pos, mass, G, &p, target_err, pot, acc);
+    if (st != FMM_OK) return st;
+    return fmm::guarded(c, [&]() -> fmm_status {
+        if (n == 0) return FMM_OK;
+        if (n == 1) {
+            CK(hipMemsetAsync(pot, 0, sizeof(double), c->stream));
+            CK(hipMemsetAsync(acc, 0, 3 * sizeof(double), c->stream));
+            CK(hipMemsetAsync(jerk, 0, 3 * sizeof(double), c->stream));
+            fmm::sync(c);
+            c->st = fmm_stats_t{};
+            c->st.n = 1;
+            c->st.p = p;
+            return FMM_OK;
+        }
+        const int64_t off[2] = {0, n};
+        fmm::forces(c, n, pos, mass, G, p, target_err, pot, acc, 1, off, false, 0, nullptr,
+                    nullptr, vel, jerk);
+        if (c->hint[0])
+            return fmm::fail(c, FMM_E_NONFINITE, "non-finite potential, acceleration or jerk");
         return FMM_OK;
     });
 }

@@ -1,0 +1,38 @@
+// Launchers of the jerk kernels (Sec. 7, jerk; eqs:fmm:dot): with the
+// expansion centres at rest, the rates Mdot come from eq:P2M:dot and the
+// ordinary M2M, the rates Fdot from the ordinary M2L of Mdot (same list, same
+// order) and L2L, and eq:L2P:dot evaluates the far-field jerk at each particle;
+// the near field adds the time derivative of every direct pair.
+#pragma once
+
+#include "internal.h"
+
+namespace fmm {
+
+// v4[i] = (v_x, v_y, v_z, 0) of sorted particle i: vel (input order, 3n doubles)
+// gathered through perm
+hipError_t launch_gather_vel(int64_t n, const uint32_t *perm, const double *vel, double4 *v4,
+                             hipStream_t s);
+// Mdot_n^m of every leaf (same layout as M): sum_a mu_a d/dt Upsilon_n^m(x_a - z)
+hipError_t launch_p2m_dot(int p, const TreeArrays &t, const int *leaf_cell, int nleaves,
+                          const double *x, const double *y, const double *z, const double *m,
+                          const double4 *v4, double *Md, hipStream_t s);
+// far-field jerk of every particle: jo4[i] = (0, j_x, j_y, j_z) (G = 1), from
+// the leaf's F and Fdot (assigned, not added)
+hipError_t launch_l2p_dot(int p, const TreeArrays &t, const int *leaf_of, const int *leaf_cell,
+                          int64_t n, const double *x, const double *y, const double *z,
+                          const double4 *v4, const double *F, const double *Fd, double4 *jo4,
+                          hipStream_t s);
+// near-field jerk over the prepared direct-sum tasks (the same tasks, ranges
+// and partial-row layout as launch_p2p), added into jo4; rows of multi-task
+// leaves go to partial and launch_p2p_reduce adds them
+hipError_t launch_p2p_jerk(int ntasks, const int2 *tasks, const int *leaf_cell,
+                           const int *nsrc_tasks, const int *moff, const int64_t *off,
+                           const int2 *range, const int *up, const TreeArrays &t,
+                           const double4 *xyzm, const double4 *v4, double4 *jo4,
+                           double4 *partial, hipStream_t s);
+// jerk[3 perm[i] + d] = G jo4[i].(y, z, w); *nonfinite = 1 on a non-finite value
+hipError_t launch_output_jerk(int64_t n, const uint32_t *perm, const double4 *jo4, double G,
+                              double *jerk, int *nonfinite, hipStream_t s);
+
+}  // namespace fmm

@@ -38,7 +38,7 @@ STATUS_NAMES = {OK: "FMM_OK", E_INVAL: "FMM_E_INVAL", E_NOMEM: "FMM_E_NOMEM", E_
                 E_BUSY: "FMM_E_BUSY"}
 
 SYMBOLS = ["fmm_build", "fmm_forces", "fmm_forces_batched", "fmm_forces_refit",
-           "fmm_forces_active", "fmm_forces_eps", "fmm_direct",
+           "fmm_forces_active", "fmm_forces_eps", "fmm_forces_jerk", "fmm_direct",
            "fmm_direct_sinks",
            "fmm_order_for_error", "fmm_stats", "fmm_footprint_bytes", "fmm_last_error",
            "fmm_destroy", "fmm_export"]
@@ -83,6 +83,9 @@ _lib.fmm_forces_active.argtypes = [_P, C.c_int64, _P, _P, C.c_double, C.c_int, C
 _lib.fmm_forces_active.restype = C.c_int
 _lib.fmm_forces_eps.argtypes = [_P, C.c_int64, _P, _P, C.c_double, C.c_int, _P, _P, _P]
 _lib.fmm_forces_eps.restype = C.c_int
+_lib.fmm_forces_jerk.argtypes = [_P, C.c_int64, _P, _P, _P, C.c_double, C.c_int, C.c_double,
+                                 _P, _P, _P]
+_lib.fmm_forces_jerk.restype = C.c_int
 _lib.fmm_direct.argtypes = [_P, C.c_int64, _P, _P, C.c_double, _P, _P]
 _lib.fmm_direct.restype = C.c_int
 _lib.fmm_direct_sinks.argtypes = [_P, C.c_int64, _P, _P, C.c_double, C.c_int64, _P, _P, _P]
@@ -238,6 +241,22 @@ class Context:
                                         _dev_ptr(eps_particle, "eps_particle", (n,)),
                                         _dev_ptr(pot, "pot", (n,)), _dev_ptr(acc, "acc", (n, 3))))
         return pot, acc
+
+    def forces_jerk(self, pos: torch.Tensor, vel: torch.Tensor, mass: torch.Tensor,
+                    G: float = 1.0, p: int = -1, target_err: float = 1e-6):
+        """forces() plus the jerk da/dt for particles moving with vel (float64
+        CUDA tensor (n, 3)): returns (pot, acc, jerk)."""
+        n = pos.shape[0]
+        pot = torch.empty(n, dtype=torch.float64, device=pos.device)
+        acc = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+        jerk = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+        self._check(_lib.fmm_forces_jerk(self._h, n, _dev_ptr(pos, "pos", (n, 3)),
+                                         _dev_ptr(vel, "vel", (n, 3)),
+                                         _dev_ptr(mass, "mass", (n,)), float(G), int(p),
+                                         float(target_err), _dev_ptr(pot, "pot", (n,)),
+                                         _dev_ptr(acc, "acc", (n, 3)),
+                                         _dev_ptr(jerk, "jerk", (n, 3))))
+        return pot, acc, jerk
 
     def direct(self, pos: torch.Tensor, mass: torch.Tensor, G: float = 1.0):
         """Exact FP64 all-pairs direct summation on the GPU."""

@@ -1,0 +1,117 @@
+"""Jerk (Sec. 7, eqs:fmm:dot) through the C ABI, against the oracle's FMM
+with the same parameters and against the exact direct jerk.
+
+Tolerances (FP64): the GPU and the oracle build the same tree and lists, so
+pot and acc agree as in the force parity tests (relative 1e-10).  The jerk's
+far field is a sum of rate terms that are up to ~1/eps larger than the
+result, like the force's, plus one more factor of the order from the
+derivative: bound 1e-9 relative per particle.  Against the exact jerk the
+oracle pins the error to about the order times the force error
+(rms_jerk < 4 (p + 1) rms_acc)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1405_2255_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)
+
+
+def _plummer(n, seed):
+    pos, vel = W.plummer(n, seed, with_velocities=True)
+    return pos, vel, np.full(n, 1.0 / n)
+
+
+@pytest.mark.parametrize("n,p,eps,leaf", [(6000, 8, 1e-6, 16), (12000, 12, 1e-8, 32),
+                                          (3001, 3, 1e-3, 8)])
+def test_jerk_matches_oracle(gpu_lib, n, p, eps, leaf):
+    import torch
+    pos, vel, m = _plummer(n, 100 + p)
+    print(f"jerk parity n={n} p={p} eps={eps} leaf={leaf}", flush=True)
+    ctx = gpu_lib.Context(leaf_size=leaf, p2p_factor=0.5)
+    P, V, M = _dev(pos), _dev(vel), _dev(m)
+    pot, acc, jerk = ctx.forces_jerk(P, V, M, G=1.3, p=p, target_err=eps)
+    pot0, acc0 = ctx.forces(P, M, G=1.3, p=p, target_err=eps)
+    torch.cuda.synchronize()
+    st = ctx.stats()
+    ref = oracle.fmm(pos, m, p=p, eps=eps, leaf_size=leaf, p2p_pairs=0.5 * (p + 1) ** 3,
+                     G=1.3, vel=vel)
+    assert st["n_m2l"] == ref["stats"]["n_m2l"]
+    assert st["n_p2p_pairs"] == ref["stats"]["n_p2p_pairs"]
+    # the jerk passes leave the force path untouched
+    assert np.array_equal(pot.cpu().numpy(), pot0.cpu().numpy())
+    assert np.array_equal(acc.cpu().numpy(), acc0.cpu().numpy())
+    assert _rel(acc.cpu().numpy(), ref["acc"]).max() < 1e-10
+    assert _rel(jerk.cpu().numpy(), ref["jerk"]).max() < 1e-9
+
+
+def test_jerk_accuracy_against_direct(gpu_lib):
+    import torch
+    n = 100000
+    pos, vel, m = _plummer(n, 7)
+    ctx = gpu_lib.Context()
+    _, acc, jerk = ctx.forces_jerk(_dev(pos), _dev(vel), _dev(m), p=10, target_err=1e-6)
+    torch.cuda.synchronize()
+    sinks = np.random.default_rng(7).choice(n, 512, replace=False)
+    j0 = oracle.direct_jerk(pos, vel, m, sinks=sinks)
+    _, a0, _ = oracle.direct(pos, m, sinks=sinks)
+    ej = _rel(jerk.cpu().numpy()[sinks], j0)
+    ea = _rel(acc.cpu().numpy()[sinks], a0)
+    rj, ra = np.sqrt(np.mean(ej ** 2)), np.sqrt(np.mean(ea ** 2))
+    print(f"jerk rms {rj:.3e} acc rms {ra:.3e}", flush=True)
+    assert rj < 4 * 11 * ra and rj < 1e-3
+
+
+def test_jerk_full_size_sampled(gpu_lib):
+    """10^6 Plummer particles in the benchmark's configuration: sampled jerks
+    against the exact ones."""
+    import torch
+    from paper_1405_2255_amd import autotune
+    n = 1000000
+    pos, vel, m = _plummer(n, 1)
+    cfg, _ = autotune.table_lookup("plummer_1e6", "fp64")
+    ctx = gpu_lib.Context(leaf_size=cfg.leaf_size, p2p_factor=cfg.p2p_factor)
+    _, acc, jerk = ctx.forces_jerk(_dev(pos), _dev(vel), _dev(m), p=cfg.p, target_err=cfg.eps)
+    torch.cuda.synchronize()
+    sinks = np.random.default_rng(1).choice(n, 128, replace=False)
+    j0 = oracle.direct_jerk(pos, vel, m, sinks=sinks)
+    _, a0, _ = oracle.direct(pos, m, sinks=sinks)
+    ej = _rel(jerk.cpu().numpy()[sinks], j0)
+    ea = _rel(acc.cpu().numpy()[sinks], a0)
+    rj, ra = np.sqrt(np.mean(ej ** 2)), np.sqrt(np.mean(ea ** 2))
+    print(f"N=1e6 jerk rms {rj:.3e} acc rms {ra:.3e}", flush=True)
+    assert np.all(np.isfinite(jerk.cpu().numpy()))
+    assert rj < 4 * (cfg.p + 1) * max(ra, 1e-9)
+
+
+def test_jerk_edge_cases(gpu_lib):
+    import torch
+    ctx = gpu_lib.Context()
+    # no particles, one particle, one pair (exact), particles at rest (zero jerk)
+    e = torch.empty((0, 3), dtype=torch.float64, device="cuda")
+    pot, acc, jerk = ctx.forces_jerk(e, e, torch.empty(0, dtype=torch.float64, device="cuda"))
+    assert jerk.shape == (0, 3)
+    one = _dev(np.array([[0.1, 0.2, 0.3]]))
+    _, _, j1 = ctx.forces_jerk(one, one, _dev(np.array([2.0])))
+    torch.cuda.synchronize()
+    assert np.all(j1.cpu().numpy() == 0)
+    x2 = np.array([[0.0, 0.0, 0.0], [1.0, 0.5, -0.2]])
+    v2 = np.array([[0.1, -0.3, 0.2], [-0.4, 0.0, 0.7]])
+    m2 = np.array([1.0, 3.0])
+    _, _, j2 = ctx.forces_jerk(_dev(x2), _dev(v2), _dev(m2), G=2.0, p=4, target_err=1e-6)
+    torch.cuda.synchronize()
+    assert _rel(j2.cpu().numpy(), oracle.direct_jerk(x2, v2, m2, G=2.0)).max() < 1e-14
+    pos, m = W.cluster("dehnen1", 20000, 5)
+    _, _, j0 = ctx.forces_jerk(_dev(pos), _dev(np.zeros_like(pos)), _dev(m), p=8,
+                               target_err=1e-6)
+    torch.cuda.synchronize()
+    assert np.all(j0.cpu().numpy() == 0)
