@@ -297,6 +297,49 @@ def eps_leg(args, fmm, pos, mass, params, full_ms, acc_direct):
     return out
 
 
+def jerk_leg(args, fmm, workloads, pos, mass, params, main_stats):
+    """Jerk (Sec. 7, eqs:fmm:dot) on the N = 1e6 Plummer input moving with its
+    equilibrium velocities (the main leg's order, eps, leaf size and
+    threshold): time of the force-and-jerk call against the force-only call
+    with the phase times of both (the paper: M2L work doubles), and the rms
+    relative jerk and force errors on 2048 seeded sinks against the GPU
+    direct sums."""
+    import torch
+    leaf, pf, p, eps = params
+    n = pos.shape[0]
+    _, vel = workloads.plummer(n, args.seed, with_velocities=True)
+    V = torch.from_numpy(vel).to(pos.device)
+    del vel
+    ctx = fmm.Context(device=0, leaf_size=leaf, p2p_factor=pf, timing=True)
+    ctx.forces_jerk(pos, V, mass, 1.0, p, eps)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        _, acc, jerk = ctx.forces_jerk(pos, V, mass, 1.0, p, eps)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    st = ctx.stats()
+    sinks = torch.from_numpy(np.sort(np.random.default_rng(2024).choice(n, 2048, replace=False))
+                             ).to(pos.device)
+    jd = ctx.direct_jerk_sinks(pos, V, mass, sinks, 1.0)
+    _, ad = ctx.direct_sinks(pos, mass, sinks, 1.0)
+    ej = torch.linalg.norm(jerk[sinks] - jd, dim=1) / torch.linalg.norm(jd, dim=1)
+    ea = torch.linalg.norm(acc[sinks] - ad, dim=1) / torch.linalg.norm(ad, dim=1)
+    ctx.close()
+    t = float(np.median(ts))
+    phases = ("t_tree", "t_estimate", "t_up", "t_walk", "t_m2l", "t_down", "t_p2p", "t_total")
+    out = {"workload": f"Plummer N={n} with equilibrium velocities, p={st['p']}, eps={eps:g}, "
+                       f"n_L={leaf or 32}, p2p_factor={pf or 2.0:g}",
+           "value": n / t, "unit": "particle-jerks/s", "ms": 1e3 * t,
+           "phases_ms": {k: st[k] for k in phases},
+           "phases_ms_forces_only": {k: main_stats[k] for k in phases},
+           "errors_vs_gpu_direct_2048": {"jerk": _summary(ej.cpu().numpy()),
+                                         "acc": _summary(ea.cpu().numpy())}}
+    print(f"jerk: {1e3 * t:.2f} ms", file=sys.stderr, flush=True)
+    return out
+
+
 def c3_leg(args, fmm, workloads):
     """Dehnen gamma = 1 cusp, power-law (Salpeter) masses on [0.1, 100]
     normalised to 1, N = 1e6 and 1e7, mixed precision, rms targets 1e-5 and
@@ -448,6 +491,7 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-active", action="store_true")
     ap.add_argument("--no-eps", action="store_true")
+    ap.add_argument("--no-jerk", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="library defaults instead of autotuned parameters")
     ap.add_argument("--retune", action="store_true",
@@ -636,6 +680,8 @@ def main() -> int:
                                                     (leaf, pf, p_arg, eps), ms_per_step)
     eps_b = None if args.no_eps else eps_leg(args, fmm, pos, mass, (leaf, pf, st["p"], eps),
                                              ms_per_step, ad_all)
+    jerk = None if args.no_jerk else jerk_leg(args, fmm, workloads, pos, mass,
+                                              (leaf, pf, st["p"], eps), st)
     batched = None
     if not args.no_batched:
         batched = {"fp64": batched_leg(args, fmm, workloads, "fp64"),
@@ -674,6 +720,7 @@ def main() -> int:
         "mixed": mixed,
         "active": active,
         "individual_eps": eps_b,
+        "jerk": jerk,
         "batched": batched,
         "c3": c3,
         "served": served,

@@ -182,13 +182,14 @@ fmm_status fmm_forces_eps(fmm_ctx *ctx, int64_t n, const double *pos, const doub
 
 /* Forces and jerk j = da/dt of every particle (Sec. 7, jerk; eqs:fmm:dot), for
  * particles moving with velocities vel (device, n x 3 FP64, input order).
- * pot and acc are those of fmm_forces with the same arguments; jerk (device,
- * n x 3) receives G sum_a mu_a d/dt[(x_a - x_b)/|x_a - x_b|^3] with the
- * expansion centres held at rest: multipole rates from the time derivative of
- * eq:P2M (P2M:dot) and M2M, field-tensor rates from M2L of the multipole rates
- * over the same interaction list and order (in FP64 whatever the precision
- * option) and L2L, eq:L2P:dot at the particles, and the time derivative of
- * every direct pair.  The acceptance test is that of the acceleration; the
+ * pot and acc are those of fmm_forces with the same arguments (bit for bit
+ * in FP64; with FMM_PREC_MIXED the direct sums of this call are FP64); jerk
+ * (device, n x 3) receives G sum_a mu_a d/dt[(x_a - x_b)/|x_a - x_b|^3] with
+ * the expansion centres held at rest: multipole rates from the time
+ * derivative of eq:P2M (P2M:dot) and M2M, field-tensor rates from M2L of the
+ * multipole rates over the same interaction list and order (FP64) and L2L,
+ * eq:L2P:dot at the particles, and the time derivative of every direct pair,
+ * summed in the same pass as its force.  The acceptance test is that of the acceleration; the
  * jerk's relative error is typically the order p times the force error.
  * A non-finite jerk gives FMM_E_NONFINITE. */
 fmm_status fmm_forces_jerk(fmm_ctx *ctx, int64_t n, const double *pos, const double *vel,
@@ -207,6 +208,15 @@ fmm_status fmm_direct(fmm_ctx *ctx, int64_t n, const double *pos, const double *
 fmm_status fmm_direct_sinks(fmm_ctx *ctx, int64_t n, const double *pos, const double *mass,
                             double G, int64_t nsinks, const int64_t *sinks, double *pot,
                             double *acc);
+
+/* The exact jerk of selected sinks (the comparison baseline of
+ * fmm_forces_jerk): sinks[j] (device int64, 0 <= sinks[j] < n) receives
+ * jerk[3j..3j+2] = G sum_{a != b} mu_a [v_ab/r^3 - 3 (r . v_ab) r/r^5],
+ * r = x_a - x_b, v_ab = v_a - v_b, from all n sources (vel: device, n x 3).
+ * An index out of range gives FMM_E_INVAL (such entries are not read). */
+fmm_status fmm_direct_jerk_sinks(fmm_ctx *ctx, int64_t n, const double *pos, const double *vel,
+                                 const double *mass, double G, int64_t nsinks,
+                                 const int64_t *sinks, double *jerk);
 
 /* Expansion order used when fmm_forces gets p < 0: round(1.6 log10(1/eps)) + 2,
  * clamped to [3, FMM_P_MAX] (two above the paper's CPU optimum, Sec. 6.2: the

@@ -132,8 +132,9 @@ struct fmm_ctx {
     DevBuf counters, nonfinite, walktmp, coffsets, roots, ckey, ckey2, order, order2;
     DevBuf actflag, actf, actinv, actpre, cellact, actbad;   // forces for a listed subset
     DevBuf epsmin;                                           // smallest individual eps
-    DevBuf vel4, Md, Fd, jFpart, jo4;    // jerk: velocities, rates of M and F, M2L chunk
-                                         // parts of the rates, jerk per particle
+    DevBuf vel4, Md, Fd, jFpart, jo4, jpart;   // jerk: velocities, rates of M and F, M2L
+                                               // chunk parts of the rates, jerk per
+                                               // particle, direct-sum partial rows
     DevBuf dkey, dsort, dsort2, runstart;   // deep refinement below level 21
     DevBuf plans;                          // output plans of M2M and L2L for order plan_p
     DevBuf Tsh;                            // M2M: each cell's expansion shifted to its parent
@@ -156,7 +157,6 @@ struct fmm_ctx {
     int pack = 0;   // direct-sum keys carry the range end (sh + 2 pb <= 64)
     int walk_used[3] = {0, 0, 0};   // sweeps the last walk of each mode needed
     int64_t n_m2l = 0, n_p2p = 0, n_ranges = 0;
-    int p2p_ntasks = 0;       // direct-sum tasks of the last run_p2p
     uint64_t *m2l_sorted = nullptr, *p2p_sorted = nullptr;
     uint32_t *p2pe_sorted = nullptr;
     std::vector<int> ls;  // first cell of each level
@@ -479,9 +479,11 @@ void prepare_p2p(fmm_ctx *c, int64_t nlist) {
     CK(launch_list_offsets(rk, runs, c->ncells, c->pb, off, s));
 }
 
-// direct sums of every leaf (prepared ranges), added into out4
+// direct sums of every leaf (prepared ranges), added into out4; with v4 (sorted
+// velocities) the FP64 kernel that also adds each pair's jerk into jo4
 void run_p2p(fmm_ctx *c, int want_f, int with_pot, int mixed, double4 *out4, bool timed,
-             const uint8_t *active = nullptr) {
+             const uint8_t *active = nullptr, const double4 *v4 = nullptr,
+             double4 *jo4 = nullptr) {
     hipStream_t s = c->stream;
     const int nl = c->nleaves;
     TreeArrays t = tree_arrays(c);
@@ -499,17 +501,27 @@ void run_p2p(fmm_ctx *c, int want_f, int with_pot, int mixed, double4 *out4, boo
     CK(hipMemcpyAsync(c->hint, totals, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     sync(c);
     const int ntasks = c->hint[0], prows = c->hint[1];
-    c->p2p_ntasks = ntasks;
     int2 *tasks = ensure<int2>(c->ptasks, std::max(ntasks, 1));
     double4 *part = ensure<double4>(c->ppart, (size_t)std::max(prows, 1) * 64);
     CK(launch_p2p_tasks(nl, toff, tasks, s));
     if (timed && c->opts.timing) CK(hipEventRecord(c->ev_p2p[0], s));
-    CK(launch_p2p(want_f, with_pot, mixed, ntasks, tasks, ptr<int>(c->leaf_cell), nts, moff, off,
-                  rg, up, t, ptr<double4>(c->xyzm), out4, part, s));
+    double4 *jpart = nullptr;
+    if (v4) {
+        jpart = ensure<double4>(c->jpart, (size_t)std::max(prows, 1) * 64);
+        CK(launch_p2p_jerk(ntasks, tasks, ptr<int>(c->leaf_cell), nts, moff, off, rg, up, t,
+                           ptr<double4>(c->xyzm), v4, out4, jo4, part, jpart, s));
+    } else {
+        CK(launch_p2p(want_f, with_pot, mixed, ntasks, tasks, ptr<int>(c->leaf_cell), nts, moff,
+                      off, rg, up, t, ptr<double4>(c->xyzm), out4, part, s));
+    }
     if (timed && c->opts.timing) CK(hipEventRecord(c->ev_p2p[1], s));
-    if (prows > 0)
+    if (prows > 0) {
         CK(launch_p2p_reduce(c->n, ptr<int>(c->leaf_of), ptr<int>(c->leaf_cell), nts, moff, t,
                              part, out4, s));
+        if (v4)
+            CK(launch_p2p_reduce(c->n, ptr<int>(c->leaf_of), ptr<int>(c->leaf_cell), nts, moff, t,
+                                 jpart, jo4, s));
+    }
 }
 
 // ------------------------------------------------------------ sink scale
@@ -729,16 +741,10 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
     }
     mark(c, PH_DOWN);
     // near field
-    run_p2p(c, 0, 1, c->opts.precision == FMM_PREC_MIXED, o4, true, cell_active);
-    if (vel) {   // near-field jerk over the same tasks
-        TreeArrays tt = tree_arrays(c);
-        CK(launch_p2p_jerk(c->p2p_ntasks, ptr<int2>(c->ptasks), ptr<int>(c->leaf_cell),
-                           ptr<int>(c->pt_s), ptr<int>(c->pt_moff), ptr<int64_t>(c->p2p_off),
-                           ptr<int2>(c->ranges), ptr<int>(c->rup), tt, ptr<double4>(c->xyzm), v4,
-                           jo4, ptr<double4>(c->ppart), s));
-        CK(launch_p2p_reduce(n, ptr<int>(c->leaf_of), ptr<int>(c->leaf_cell), ptr<int>(c->pt_s),
-                             ptr<int>(c->pt_moff), tt, ptr<double4>(c->ppart), jo4, s));
-    }
+    // near field (with the jerk: FP64, potential and acceleration as the force-only
+    // FP64 kernel sums them)
+    run_p2p(c, 0, 1, c->opts.precision == FMM_PREC_MIXED && !vel, o4, true, cell_active, v4,
+            jo4);
     mark(c, PH_P2P);
     int *nonfinite = ptr<int>(c->nonfinite);
     CK(hipMemsetAsync(nonfinite, 0, sizeof(int), s));
@@ -902,7 +908,7 @@ void fmm_destroy(fmm_ctx *c) {
                       &c->actflag, &c->actf, &c->actinv, &c->actpre, &c->cellact, &c->actbad,
                       &c->dkey, &c->dsort, &c->dsort2, &c->runstart, &c->plans, &c->Tsh,
                       &c->M32, &c->sig, &c->Flow, &c->epsmin, &c->vel4, &c->Md, &c->Fd,
-                      &c->jFpart, &c->jo4};
+                      &c->jFpart, &c->jo4, &c->jpart};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (auto &e : c->ev) if (e) (void)hipEventDestroy(e);
@@ -1156,6 +1162,30 @@ fmm_status fmm_direct_sinks(fmm_ctx *c, int64_t n, const double *pos, const doub
         int *bad = fmm::ensure<int>(c->nonfinite, 8) + 5;
         CK(hipMemsetAsync(bad, 0, sizeof(int), c->stream));
         CK(fmm::launch_direct_sinks(n, pos, mass, G, nsinks, sinks, pot, acc, bad, c->stream));
+        CK(hipMemcpyAsync(c->hint, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        fmm::sync(c);
+        if (c->hint[0]) return fmm::fail(c, FMM_E_INVAL, "sink index out of range");
+        return FMM_OK;
+    });
+}
+
+fmm_status fmm_direct_jerk_sinks(fmm_ctx *c, int64_t n, const double *pos, const double *vel,
+                                 const double *mass, double G, int64_t nsinks,
+                                 const int64_t *sinks, double *jerk) {
+    if (!c) return FMM_E_INVAL;
+    fmm::Guard g(c);
+    if (!g.ok) return FMM_E_BUSY;
+    c->err.clear();
+    if (n < 0 || nsinks < 0 ||
+        (nsinks > 0 && (!pos || !vel || !mass || !sinks || !jerk)) || !std::isfinite(G))
+        return fmm::fail(c, FMM_E_INVAL, "bad argument");
+    if (nsinks == 0) return FMM_OK;
+    if (n == 0) return fmm::fail(c, FMM_E_INVAL, "sink index out of range");
+    return fmm::guarded(c, [&]() -> fmm_status {
+        int *bad = fmm::ensure<int>(c->nonfinite, 8) + 5;
+        CK(hipMemsetAsync(bad, 0, sizeof(int), c->stream));
+        CK(fmm::launch_direct_jerk_sinks(n, pos, vel, mass, G, nsinks, sinks, jerk, bad,
+                                         c->stream));
         CK(hipMemcpyAsync(c->hint, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
         fmm::sync(c);
         if (c->hint[0]) return fmm::fail(c, FMM_E_INVAL, "sink index out of range");

@@ -23,14 +23,21 @@ hipError_t launch_l2p_dot(int p, const TreeArrays &t, const int *leaf_of, const 
                           int64_t n, const double *x, const double *y, const double *z,
                           const double4 *v4, const double *F, const double *Fd, double4 *jo4,
                           hipStream_t s);
-// near-field jerk over the prepared direct-sum tasks (the same tasks, ranges
-// and partial-row layout as launch_p2p), added into jo4; rows of multi-task
-// leaves go to partial and launch_p2p_reduce adds them
+// near field with jerk, FP64, in place of launch_p2p (same prepared tasks,
+// ranges and partial-row layout, same summation order, so out4 receives the
+// same values launch_p2p would add): (pot, a) added into out4, the jerk into
+// jo4; rows of multi-task leaves go to partial / jpartial and
+// launch_p2p_reduce adds each into its output
 hipError_t launch_p2p_jerk(int ntasks, const int2 *tasks, const int *leaf_cell,
                            const int *nsrc_tasks, const int *moff, const int64_t *off,
                            const int2 *range, const int *up, const TreeArrays &t,
-                           const double4 *xyzm, const double4 *v4, double4 *jo4,
-                           double4 *partial, hipStream_t s);
+                           const double4 *xyzm, const double4 *v4, double4 *out4, double4 *jo4,
+                           double4 *partial, double4 *jpartial, hipStream_t s);
+// exact jerk of listed sinks (input indices) against all n sources, written in
+// list order; *bad (zeroed by the caller) = 1 for an index outside [0, n)
+hipError_t launch_direct_jerk_sinks(int64_t n, const double *pos, const double *vel,
+                                   const double *mass, double G, int64_t nsinks,
+                                   const int64_t *sinks, double *jerk, int *bad, hipStream_t s);
 // jerk[3 perm[i] + d] = G jo4[i].(y, z, w); *nonfinite = 1 on a non-finite value
 hipError_t launch_output_jerk(int64_t n, const uint32_t *perm, const double4 *jo4, double G,
                               double *jerk, int *nonfinite, hipStream_t s);

@@ -175,21 +175,73 @@ k_l2p_dot(TreeArrays t, const int *leaf_of, const int *leaf_cell, int64_t n, con
     jo4[i] = make_double4(0.0, -p11.re, -p11.im, -p10.re);
 }
 
-// ---- near-field jerk ---------------------------------------------------------
+// ---- near field: potential, acceleration and jerk in one pass ---------------
 // d/dt [mu (x_a - x_b)/r^3] = mu [v_ab/r^3 - 3 (r . v_ab) r/r^5],
-// r = x_a - x_b, v_ab = v_a - v_b.  Same tasks as the acceleration kernel: a
-// task is up to 64 sinks of a leaf against one slice of P2P_TASK sources of
-// the leaf's direct-sum list; one sink per lane group, the phases of a group
-// stride through each range and are added through LDS at the end.
+// r = x_a - x_b, v_ab = v_a - v_b.  Same tasks, lane layout and summation
+// order as the force-only direct-sum kernel (a task is up to 64 sinks of a
+// leaf against one slice of P2P_TASK sources of the leaf's list; two sinks per
+// lane, lanes are (sink group, phase) pairs, phases added through LDS), so
+// the potential and acceleration are bit for bit those of the force-only
+// call; the jerk reuses each pair's separation and 1/r^3.
+constexpr int JR = 2;   // sinks per lane
+
 __device__ __forceinline__ int first_ranges(int c, const int *up, const int64_t *off) {
     return off[c + 1] > off[c] ? c : up[c];
+}
+
+struct Sink {
+    double4 x, v;            // position (w: mass, unused), velocity
+    double4 f;               // (pot, ax, ay, az)
+    double jx, jy, jz;
+};
+
+__device__ __forceinline__ void pair_jerk(const double4 s, const double4 va, bool skip, Sink &k) {
+    const double dx = s.x - k.x.x, dy = s.y - k.x.y, dz = s.z - k.x.z;
+    const double r2 = skip ? 1.0 : fma(dx, dx, fma(dy, dy, dz * dz));
+    const double mu = skip ? 0.0 : s.w;
+    const double ri = rsqrt_nr(r2);
+    const double q = mu * ri;
+    const double q3 = q * ri * ri;
+    k.f.x += q;
+    k.f.y = fma(q3, dx, k.f.y);
+    k.f.z = fma(q3, dy, k.f.z);
+    k.f.w = fma(q3, dz, k.f.w);
+    const double ux = va.x - k.v.x, uy = va.y - k.v.y, uz = va.z - k.v.z;
+    const double rv = 3.0 * fma(dx, ux, fma(dy, uy, dz * uz)) * (ri * ri);
+    k.jx = fma(q3, fma(-rv, dx, ux), k.jx);
+    k.jy = fma(q3, fma(-rv, dy, uy), k.jy);
+    k.jz = fma(q3, fma(-rv, dz, uz), k.jz);
+}
+
+// one lane's share of a source range: sources a, a + stride, ... below e, the
+// next source loaded before the current one is summed; CHECK: the range may
+// hold the sinks themselves (skipped by index)
+template <bool CHECK>
+__device__ __forceinline__ void sum_range_jerk(const double4 *xyzm, const double4 *v4, int a,
+                                               int e, int stride, const int (&self)[JR],
+                                               Sink (&k)[JR]) {
+    if (a >= e) return;
+    double4 s = xyzm[a], va = v4[a];
+    for (;;) {
+        const int b = a + stride;
+        const bool more = b < e;
+        const double4 s2 = xyzm[more ? b : a], vb = v4[more ? b : a];
+#pragma unroll
+        for (int r = 0; r < JR; ++r) pair_jerk(s, va, CHECK && a == self[r], k[r]);
+        if (!more) break;
+        a = b;
+        s = s2;
+        va = vb;
+    }
 }
 
 __global__ void __launch_bounds__(256)
 k_p2p_jerk(int ntasks, const int2 *tasks, const int *leaf_cell, const int *nsrc_tasks,
            const int *moff, const int64_t *off, const int2 *range, const int *up, TreeArrays t,
-           const double4 *xyzm, const double4 *v4, double4 *jo4, double4 *partial) {
-    __shared__ double4 red[4][FMM_WAVE];
+           const double4 *xyzm, const double4 *v4, double4 *out4, double4 *jo4,
+           double4 *partial, double4 *jpartial) {
+    __shared__ double4 red[4][JR * FMM_WAVE];
+    __shared__ double4 jred[4][JR * FMM_WAVE];
     const int task = xcd_block(blockIdx.x, gridDim.x) * 4 + threadIdx.x / FMM_WAVE;
     if (task >= ntasks) return;                // whole wavefronts leave together
     const int lane = lane_id(), w = threadIdx.x / FMM_WAVE;
@@ -200,62 +252,77 @@ k_p2p_jerk(int ntasks, const int2 *tasks, const int *leaf_cell, const int *nsrc_
     const int sc = tk.y / nts, ts = tk.y % nts;
     const int sb = t.beg[c] + sc * FMM_WAVE;
     const int nb = min(t.end[c] - sb, FMM_WAVE);
-    const int S = FMM_WAVE / nb;               // phases per sink
-    const int g = lane % nb, phase = lane / nb;
+    const int ng = (nb + JR - 1) / JR;
+    const int S = FMM_WAVE / ng;               // phases per lane group
+    const int g = lane % ng, phase = lane / ng;
     const bool active = phase < S;
-    const int bi = sb + g;
-    const double4 xb = xyzm[bi], vb = v4[bi];
-    double jx = 0.0, jy = 0.0, jz = 0.0;
+    Sink k[JR];
+    int self[JR];
+#pragma unroll
+    for (int r = 0; r < JR; ++r) {
+        const int slot = g + r * ng < nb ? g + r * ng : g;
+        self[r] = sb + slot;
+        k[r].x = xyzm[self[r]];
+        k[r].v = v4[self[r]];
+        k[r].f = make_double4(0.0, 0.0, 0.0, 0.0);
+        k[r].jx = k[r].jy = k[r].jz = 0.0;
+    }
     int64_t skip = (int64_t)ts * P2P_TASK, left = P2P_TASK;
     for (int anc = first_ranges(c, up, off); anc >= 0 && left > 0; anc = up[anc]) {
-        for (int64_t r = off[anc]; r < off[anc + 1] && left > 0; ++r) {
-            int2 rg = range[r];
-            const int len = rg.y - rg.x;
-            if (skip >= len) {
-                skip -= len;
-                continue;
-            }
-            rg.x += (int)skip;
-            skip = 0;
-            if (rg.y - rg.x > left) rg.y = rg.x + (int)left;
-            left -= rg.y - rg.x;
-            if (!active) continue;
-            for (int a = rg.x + phase; a < rg.y; a += S) {
-                const double4 s = xyzm[a], va = v4[a];
-                const bool self = a == bi;
-                const double dx = s.x - xb.x, dy = s.y - xb.y, dz = s.z - xb.z;
-                const double ux = va.x - vb.x, uy = va.y - vb.y, uz = va.z - vb.z;
-                const double r2 = self ? 1.0 : fma(dx, dx, fma(dy, dy, dz * dz));
-                const double mu = self ? 0.0 : s.w;
-                const double ri = rsqrt_nr(r2);
-                const double ri2 = ri * ri;
-                const double q3 = mu * ri * ri2;
-                const double rv = 3.0 * fma(dx, ux, fma(dy, uy, dz * uz)) * ri2;
-                jx = fma(q3, fma(-rv, dx, ux), jx);
-                jy = fma(q3, fma(-rv, dy, uy), jy);
-                jz = fma(q3, fma(-rv, dz, uz), jz);
+        const int64_t r1 = off[anc + 1];
+        for (int64_t rb = off[anc]; rb < r1 && left > 0; rb += FMM_WAVE) {
+            const int2 mine = rb + lane < r1 ? range[rb + lane] : make_int2(0, 0);
+            const int nbat = (int)min((int64_t)FMM_WAVE, r1 - rb);
+            for (int j = 0; j < nbat && left > 0; ++j) {
+                int2 rg = make_int2(__builtin_amdgcn_readlane(mine.x, j),
+                                    __builtin_amdgcn_readlane(mine.y, j));
+                const int len = rg.y - rg.x;
+                if (skip >= len) {
+                    skip -= len;
+                    continue;
+                }
+                rg.x += (int)skip;
+                skip = 0;
+                if (rg.y - rg.x > left) rg.y = rg.x + (int)left;
+                left -= rg.y - rg.x;
+                if (!active) continue;
+                const bool own = rg.x < sb + nb && rg.y > sb;   // overlaps the task's sinks
+                if (own) sum_range_jerk<true>(xyzm, v4, rg.x + phase, rg.y, S, self, k);
+                else sum_range_jerk<false>(xyzm, v4, rg.x + phase, rg.y, S, self, k);
             }
         }
     }
-    // phases of sink g sit at red[w][g + phase * nb]; active lanes cover every
-    // index below nb * S <= 64 exactly once
-    if (active) red[w][g + phase * nb] = make_double4(0.0, jx, jy, jz);
+    // phases of slot q sit at red[w][q + phase * JR * ng]; active lanes cover
+    // every index below JR * ng * S <= JR * 64 exactly once
+    if (active) {
+#pragma unroll
+        for (int r = 0; r < JR; ++r) {
+            red[w][g + r * ng + phase * JR * ng] = k[r].f;
+            jred[w][g + r * ng + phase * JR * ng] = make_double4(0.0, k[r].jx, k[r].jy, k[r].jz);
+        }
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (lane >= nb) return;
-    double4 sum = red[w][lane];
+    double4 v = red[w][lane], jv = jred[w][lane];
     for (int ph = 1; ph < S; ++ph) {
-        const double4 q = red[w][lane + ph * nb];
-        sum.y += q.y; sum.z += q.z; sum.w += q.w;
+        const double4 q = red[w][lane + ph * JR * ng], qj = jred[w][lane + ph * JR * ng];
+        v.x += q.x; v.y += q.y; v.z += q.z; v.w += q.w;
+        jv.y += qj.y; jv.z += qj.z; jv.w += qj.w;
     }
     const int bo = sb + lane;
     if (moff[leaf + 1] == moff[leaf]) {        // the leaf's only task
-        double4 o = jo4[bo];
-        o.y += sum.y; o.z += sum.z; o.w += sum.w;
-        jo4[bo] = o;
+        double4 o = out4[bo];
+        o.x += v.x; o.y += v.y; o.z += v.z; o.w += v.w;
+        out4[bo] = o;
+        double4 oj = jo4[bo];
+        oj.y += jv.y; oj.z += jv.z; oj.w += jv.w;
+        jo4[bo] = oj;
     } else {
-        partial[((int64_t)moff[leaf] + tk.y) * FMM_WAVE + lane] = sum;
+        const int64_t row = ((int64_t)moff[leaf] + tk.y) * FMM_WAVE + lane;
+        partial[row] = v;
+        jpartial[row] = jv;
     }
 }
 
@@ -270,6 +337,39 @@ __global__ void k_output_jerk(int64_t n, const uint32_t *perm, const double4 *jo
     jerk[3 * j + 1] = b;
     jerk[3 * j + 2] = c;
     if (!(isfinite(a) && isfinite(b) && isfinite(c))) atomicOr(nonfinite, 1);
+}
+
+// exact jerk of listed sinks against all n sources, one thread per sink;
+// *bad = 1 for an index outside [0, n)
+__global__ void __launch_bounds__(256)
+k_direct_jerk_sinks(int64_t n, const double *pos, const double *vel, const double *mass,
+                    double G, int64_t nsinks, const int64_t *sinks, double *jerk, int *bad) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t ii = t < nsinks ? sinks[t] : 0;
+    const bool valid = t < nsinks && ii >= 0 && ii < n;
+    if (t < nsinks && !valid) atomicOr(bad, 1);
+    if (!valid) ii = 0;
+    const double xb = pos[3 * ii], yb = pos[3 * ii + 1], zb = pos[3 * ii + 2];
+    const double ub = vel[3 * ii], vb = vel[3 * ii + 1], wb = vel[3 * ii + 2];
+    double jx = 0.0, jy = 0.0, jz = 0.0;
+    for (int64_t a = 0; a < n; ++a) {
+        const double dx = pos[3 * a] - xb, dy = pos[3 * a + 1] - yb, dz = pos[3 * a + 2] - zb;
+        const double ux = vel[3 * a] - ub, uy = vel[3 * a + 1] - vb, uz = vel[3 * a + 2] - wb;
+        const bool self = a == ii;
+        const double r2 = self ? 1.0 : fma(dx, dx, fma(dy, dy, dz * dz));
+        const double mu = self ? 0.0 : mass[a];
+        const double ri = rsqrt_nr(r2);
+        const double ri2 = ri * ri;
+        const double q3 = mu * ri * ri2;
+        const double rv = 3.0 * fma(dx, ux, fma(dy, uy, dz * uz)) * ri2;
+        jx = fma(q3, fma(-rv, dx, ux), jx);
+        jy = fma(q3, fma(-rv, dy, uy), jy);
+        jz = fma(q3, fma(-rv, dz, uz), jz);
+    }
+    if (!valid) return;
+    jerk[3 * t] = G * jx;
+    jerk[3 * t + 1] = G * jy;
+    jerk[3 * t + 2] = G * jz;
 }
 
 #define FMM_JERK_DISPATCH_P(p, CALL)                                                   \
@@ -319,11 +419,21 @@ hipError_t launch_l2p_dot(int p, const TreeArrays &t, const int *leaf_of, const 
 hipError_t launch_p2p_jerk(int ntasks, const int2 *tasks, const int *leaf_cell,
                            const int *nsrc_tasks, const int *moff, const int64_t *off,
                            const int2 *range, const int *up, const TreeArrays &t,
-                           const double4 *xyzm, const double4 *v4, double4 *jo4,
-                           double4 *partial, hipStream_t s) {
+                           const double4 *xyzm, const double4 *v4, double4 *out4, double4 *jo4,
+                           double4 *partial, double4 *jpartial, hipStream_t s) {
     if (ntasks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_p2p_jerk, dim3(blocks(ntasks, 4)), dim3(256), 0, s, ntasks, tasks,
-                       leaf_cell, nsrc_tasks, moff, off, range, up, t, xyzm, v4, jo4, partial);
+                       leaf_cell, nsrc_tasks, moff, off, range, up, t, xyzm, v4, out4, jo4,
+                       partial, jpartial);
+    return hipGetLastError();
+}
+
+hipError_t launch_direct_jerk_sinks(int64_t n, const double *pos, const double *vel,
+                                   const double *mass, double G, int64_t nsinks,
+                                   const int64_t *sinks, double *jerk, int *bad, hipStream_t s) {
+    if (nsinks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_direct_jerk_sinks, dim3(blocks(nsinks, 256)), dim3(256), 0, s, n, pos,
+                       vel, mass, G, nsinks, sinks, jerk, bad);
     return hipGetLastError();
 }
 

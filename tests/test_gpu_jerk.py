@@ -115,3 +115,17 @@ def test_jerk_edge_cases(gpu_lib):
                                target_err=1e-6)
     torch.cuda.synchronize()
     assert np.all(j0.cpu().numpy() == 0)
+
+
+def test_direct_jerk_sinks_matches_oracle(gpu_lib):
+    import torch
+    n = 5000
+    pos, vel, m = _plummer(n, 11)
+    m = m * np.random.default_rng(11).random(n)
+    sinks = np.array([0, 1, 17, 4999, 2500, 17], dtype=np.int64)
+    ctx = gpu_lib.Context()
+    j = ctx.direct_jerk_sinks(_dev(pos), _dev(vel), _dev(m), _dev(sinks), G=0.9)
+    torch.cuda.synchronize()
+    assert _rel(j.cpu().numpy(), oracle.direct_jerk(pos, vel, m, G=0.9, sinks=sinks)).max() < 1e-12
+    with pytest.raises(gpu_lib.FMMError):
+        ctx.direct_jerk_sinks(_dev(pos), _dev(vel), _dev(m), _dev(np.array([3, n], np.int64)))
