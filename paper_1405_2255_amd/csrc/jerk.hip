@@ -19,6 +19,19 @@ namespace {
 
 inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// 1 / (n^2 - m^2) for 0 <= m < n <= FMM_PMAX: the divisor of the column
+// recurrence eq:Ups:rec, read per lane instead of divided
+struct RecipTable {
+    double v[FMM_PMAX + 1][FMM_PMAX + 1];
+};
+constexpr RecipTable make_recip_table() {
+    RecipTable r{};
+    for (int n = 0; n <= FMM_PMAX; ++n)
+        for (int m = 0; m <= FMM_PMAX; ++m) r.v[n][m] = n > m ? 1.0 / (double)(n * n - m * m) : 0.0;
+    return r;
+}
+__constant__ RecipTable kRecip = make_recip_table();
+
 // xidot X + etadot Y for the velocity (vx, vy)
 __device__ __forceinline__ cplx rate_xy(double vx, double vy, cplx X, cplx Y) {
     // (vx + i vy)/2 X - (vx - i vy)/2 Y
@@ -94,7 +107,7 @@ k_p2m_dot(TreeArrays t, const int *leaf_cell, int nleaves, const double *x, cons
             } else if (n == col + 1) {
                 u = {dz * u1.re, dz * u1.im};
             } else {
-                const double inv = 1.0 / (double)(n * n - col * col);
+                const double inv = kRecip.v[n][col < FMM_PMAX ? col : FMM_PMAX];
                 const double s = (2.0 * n - 1.0) * dz;
                 u = {(s * u1.re - r2 * u2.re) * inv, (s * u1.im - r2 * u2.im) * inv};
             }
