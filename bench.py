@@ -391,7 +391,9 @@ def serve_leg(args, fmm, workloads, capacity_pfs):
     """Poisson arrivals at an offered load of args.serve_load times the
     single-request throughput measured above; every request takes 10 force
     evaluations with drift steps x += v dt (dt = 1e-3) in between, the tree
-    recycled and the previous step's |a| as the sink scale."""
+    recycled and the previous step's |a| as the sink scale.  The same requests
+    are then replayed at each load of args.serve_other_loads (latency and
+    throughput only)."""
     import torch
     from paper_1405_2255_amd import serve
     rng = np.random.default_rng(args.seed + 2000)
@@ -425,24 +427,35 @@ def serve_leg(args, fmm, workloads, capacity_pfs):
         w.result(600)
     print("serve: slots warmed", file=sys.stderr, flush=True)
     mean_service = float(np.mean(sizes)) * steps / capacity_pfs
-    gaps = rng.exponential(mean_service / args.serve_load, r)
-    reqs = []
-    t0 = time.perf_counter()
-    t_next = t0
-    for i in range(r):
-        t_next += gaps[i]
-        dt = t_next - time.perf_counter()
-        if dt > 0:
-            time.sleep(dt)
-        reqs.append(srv.submit(make(i)))
-    for i, q in enumerate(reqs):
-        q.result(600)
-        print(f"serve: request {i} n={sizes[i]} {kinds[i]} done, latency "
-              f"{1e3 * q.latency:.1f} ms", file=sys.stderr, flush=True)
-    t_all = max(q.t_end for q in reqs) - t0
-    srv.close()
+    unit_gaps = rng.exponential(mean_service, r)
+
+    def run_at(load):
+        reqs = []
+        t0 = time.perf_counter()
+        t_next = t0
+        for i in range(r):
+            t_next += unit_gaps[i] / load
+            dt = t_next - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            reqs.append(srv.submit(make(i)))
+        for i, q in enumerate(reqs):
+            q.result(600)
+            print(f"serve: load {load} request {i} n={sizes[i]} {kinds[i]} done, latency "
+                  f"{1e3 * q.latency:.1f} ms", file=sys.stderr, flush=True)
+        return reqs, max(q.t_end for q in reqs) - t0
+
+    reqs, t_all = run_at(args.serve_load)
     lat = serve.latency_summary(reqs)
     print(f"served {r} requests in {t_all:.2f} s: {lat}", file=sys.stderr, flush=True)
+    work = float(np.sum(sizes)) * steps
+    others = []
+    for load in args.serve_other_loads:
+        rq, ta = run_at(load)
+        others.append({"offered_load": load, "latency": serve.latency_summary(rq),
+                       "value": work / ta, "unit": "particle-forces/s", "seconds": ta})
+        print(f"served at load {load}: {others[-1]['latency']}", file=sys.stderr, flush=True)
+    srv.close()
     # accuracy of the last step of every request with N <= 3e5 against the GPU
     # direct sum on the same drifted positions
     checks = []
@@ -459,7 +472,6 @@ def serve_leg(args, fmm, workloads, capacity_pfs):
         checks.append({"n": int(sizes[i]), "kind": kinds[i], "target_rms": float(errs[i]),
                        "rms": float(np.sqrt(np.mean(e ** 2))), "p99.9": _pct(e, 99.9)})
     ctx.close()
-    work = float(np.sum(sizes)) * steps
     return {"workload": f"{r} requests, Poisson arrivals at offered load {args.serve_load} "
                         f"of the single-request throughput, N log-uniform in [1e4, "
                         f"{args.serve_nmax:g}], profiles {'/'.join(SERVE_KINDS)}, rms targets "
@@ -468,7 +480,7 @@ def serve_leg(args, fmm, workloads, capacity_pfs):
                         f"slots",
             "latency": lat, "value": work / t_all, "unit": "particle-forces/s",
             "seconds": t_all, "mean_service_s_estimate": mean_service,
-            "accuracy_last_step": checks,
+            "accuracy_last_step": checks, "other_loads": others,
             "all_within_target": bool(all(c["rms"] <= c["target_rms"] for c in checks))}
 
 
@@ -504,6 +516,8 @@ def main() -> int:
     ap.add_argument("--serve-nmax", type=float, default=4e6)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-load", type=float, default=0.8)
+    ap.add_argument("--serve-other-loads", type=lambda s: [float(x) for x in s.split(",") if x],
+                    default=[0.5, 0.95])
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="only copy a device buffer of this many MiB three times (the "
                          "reference kernel for scaling HBM byte counters), then exit")
