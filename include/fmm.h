@@ -196,6 +196,17 @@ fmm_status fmm_forces_jerk(fmm_ctx *ctx, int64_t n, const double *pos, const dou
                            const double *mass, double G, int p, double target_err, double *pot,
                            double *acc, double *jerk);
 
+/* fmm_forces_jerk for a listed subset of sinks, as Hermite integrators with
+ * block time steps need it (Sec. 7.1 with Sec. 7, jerk): the sinks and outputs
+ * as in fmm_forces_active (pot[j], acc[3j..], jerk[3j..] for particle
+ * active[j], n_active entries each, device), the rest as in fmm_forces_jerk;
+ * each listed particle's results equal those of fmm_forces_jerk on all n.
+ * refit != 0 recycles the tree as fmm_forces_refit does. */
+fmm_status fmm_forces_jerk_active(fmm_ctx *ctx, int64_t n, const double *pos, const double *vel,
+                                  const double *mass, double G, int p, double target_err,
+                                  int64_t n_active, const int64_t *active, int refit, double *pot,
+                                  double *acc, double *jerk);
+
 /* Exact FP64 direct summation of eq. (1) on the GPU (the comparison
  * baseline): all n sinks against all n sources, a != b. */
 fmm_status fmm_direct(fmm_ctx *ctx, int64_t n, const double *pos, const double *mass,

@@ -727,7 +727,7 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
                             ptr<short>(c->plans) + FMM_PLAN_SIZE, s, cell_active));
         if (vel)
             CK(launch_l2l_level(p, t, c->ls[Lv], c->ls[Lv + 1], U, ptr<double>(c->Fd),
-                                ptr<short>(c->plans) + FMM_PLAN_SIZE, s));
+                                ptr<short>(c->plans) + FMM_PLAN_SIZE, s, cell_active));
     }
     double4 *o4 = ensure<double4>(c->out4, n);
     CK(launch_l2p(p, t, ptr<int>(c->leaf_of), ptr<int>(c->leaf_cell), n, ptr<double>(c->x),
@@ -737,7 +737,7 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
         jo4 = ensure<double4>(c->jo4, n);
         CK(launch_l2p_dot(p, t, ptr<int>(c->leaf_of), ptr<int>(c->leaf_cell), n,
                           ptr<double>(c->x), ptr<double>(c->y), ptr<double>(c->z), v4, F,
-                          ptr<double>(c->Fd), jo4, s));
+                          ptr<double>(c->Fd), jo4, s, cell_active));
     }
     mark(c, PH_DOWN);
     // near field
@@ -752,7 +752,10 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
         CK(launch_output_listed(n, nact, act, inv, o4, G, pot, acc, nonfinite, s));
     else
         CK(launch_output(n, c->perm, o4, G, pot, acc, nonfinite, s));
-    if (vel) CK(launch_output_jerk(n, c->perm, jo4, G, jerk, nonfinite, s));
+    if (vel && act)
+        CK(launch_output_jerk_listed(n, nact, act, inv, jo4, G, jerk, nonfinite, s));
+    else if (vel)
+        CK(launch_output_jerk(n, c->perm, jo4, G, jerk, nonfinite, s));
     if (c->opts.scale_source == FMM_SCALE_PREVIOUS && !act) {
         CK(launch_norm3(acc, n, G, ensure<double>(c->prev_scale, n), s));
         c->have_prev_scale = true;
@@ -1165,6 +1168,47 @@ fmm_status fmm_direct_sinks(fmm_ctx *c, int64_t n, const double *pos, const doub
         CK(hipMemcpyAsync(c->hint, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
         fmm::sync(c);
         if (c->hint[0]) return fmm::fail(c, FMM_E_INVAL, "sink index out of range");
+        return FMM_OK;
+    });
+}
+
+fmm_status fmm_forces_jerk_active(fmm_ctx *c, int64_t n, const double *pos, const double *vel,
+                                  const double *mass, double G, int p, double target_err,
+                                  int64_t n_active, const int64_t *active, int refit, double *pot,
+                                  double *acc, double *jerk) {
+    if (!c) return FMM_E_INVAL;
+    fmm::Guard g(c);
+    if (!g.ok) return FMM_E_BUSY;
+    c->err.clear();
+    if (n_active < 0 || (n_active > 0 && (!active || !pot || !acc || !jerk)))
+        return fmm::fail(c, FMM_E_INVAL, "bad list of active particles or outputs");
+    if (n < 0 || (n > 0 && (!pos || !mass || !vel)))
+        return fmm::fail(c, FMM_E_INVAL, "bad particle arrays");
+    fmm_status st = check_common(c, n, pos, mass, G, &p, target_err, pot ? pot : (double *)pos,
+                                 acc ? acc : (double *)pos);
+    if (st != FMM_OK) return st;
+    return fmm::guarded(c, [&]() -> fmm_status {
+        if (n_active == 0) return FMM_OK;
+        if (n == 0) return fmm::fail(c, FMM_E_INVAL, "active index out of range");
+        if (n == 1) {   // one particle: no force, no jerk; the list may only name it
+            int *bad = fmm::ensure<int>(c->actbad, 1);
+            int *flag = fmm::ensure<int>(c->actflag, 1);
+            CK(hipMemsetAsync(bad, 0, sizeof(int), c->stream));
+            CK(fmm::launch_mark_listed(1, n_active, active, flag, bad, c->stream));
+            CK(hipMemsetAsync(pot, 0, n_active * sizeof(double), c->stream));
+            CK(hipMemsetAsync(acc, 0, 3 * n_active * sizeof(double), c->stream));
+            CK(hipMemsetAsync(jerk, 0, 3 * n_active * sizeof(double), c->stream));
+            CK(hipMemcpyAsync(c->hint + 1, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+            fmm::sync(c);
+            if (c->hint[1]) return fmm::fail(c, FMM_E_INVAL, "active index out of range");
+            return FMM_OK;
+        }
+        const int64_t off[2] = {0, n};
+        fmm::forces(c, n, pos, mass, G, p, target_err, pot, acc, 1, off, refit != 0, n_active,
+                    active, nullptr, vel, jerk);
+        if (c->hint[1]) return fmm::fail(c, FMM_E_INVAL, "active index out of range");
+        if (c->hint[0])
+            return fmm::fail(c, FMM_E_NONFINITE, "non-finite potential, acceleration or jerk");
         return FMM_OK;
     });
 }

@@ -143,10 +143,11 @@ template <int P>
 __global__ void __launch_bounds__(256)
 k_l2p_dot(TreeArrays t, const int *leaf_of, const int *leaf_cell, int64_t n, const double *x,
           const double *y, const double *z, const double4 *v4, const double *F,
-          const double *Fd, double4 *jo4) {
+          const double *Fd, double4 *jo4, const uint8_t *active) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int c = leaf_cell[leaf_of[i]];
+    if (active && !active[c]) return;      // a leaf without listed sinks
     const double4 cen = t.cen[c];
     const cplx *Fc = reinterpret_cast<const cplx *>(F) + (size_t)c * tri(P + 1, 0);
     const cplx *Gc = reinterpret_cast<const cplx *>(Fd) + (size_t)c * tri(P + 1, 0);
@@ -339,6 +340,22 @@ k_p2p_jerk(int ntasks, const int2 *tasks, const int *leaf_cell, const int *nsrc_
     }
 }
 
+// listed sinks: jerk[3 j + d] = G jo4[inv[act[j]]].(y, z, w) (indices out of
+// range are skipped; the caller reports them)
+__global__ void k_output_jerk_listed(int64_t n, int64_t nact, const int64_t *act, const int *inv,
+                                     const double4 *jo4, double G, double *jerk, int *nonfinite) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nact) return;
+    const int64_t idx = act[j];
+    if (idx < 0 || idx >= n) return;
+    const double4 v = jo4[inv[idx]];
+    const double a = G * v.y, b = G * v.z, c = G * v.w;
+    jerk[3 * j] = a;
+    jerk[3 * j + 1] = b;
+    jerk[3 * j + 2] = c;
+    if (!(isfinite(a) && isfinite(b) && isfinite(c))) atomicOr(nonfinite, 1);
+}
+
 __global__ void k_output_jerk(int64_t n, const uint32_t *perm, const double4 *jo4, double G,
                               double *jerk, int *nonfinite) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -420,10 +437,10 @@ hipError_t launch_p2m_dot(int p, const TreeArrays &t, const int *leaf_cell, int 
 hipError_t launch_l2p_dot(int p, const TreeArrays &t, const int *leaf_of, const int *leaf_cell,
                           int64_t n, const double *x, const double *y, const double *z,
                           const double4 *v4, const double *F, const double *Fd, double4 *jo4,
-                          hipStream_t s) {
+                          hipStream_t s, const uint8_t *active) {
     if (n <= 0) return hipSuccess;
 #define CALL(P) hipLaunchKernelGGL(k_l2p_dot<P>, dim3(blocks(n, 256)), dim3(256), 0, s, t,   \
-                                   leaf_of, leaf_cell, n, x, y, z, v4, F, Fd, jo4)
+                                   leaf_of, leaf_cell, n, x, y, z, v4, F, Fd, jo4, active)
     FMM_JERK_DISPATCH_P(p, CALL)
 #undef CALL
     return hipGetLastError();
@@ -447,6 +464,15 @@ hipError_t launch_direct_jerk_sinks(int64_t n, const double *pos, const double *
     if (nsinks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_direct_jerk_sinks, dim3(blocks(nsinks, 256)), dim3(256), 0, s, n, pos,
                        vel, mass, G, nsinks, sinks, jerk, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_output_jerk_listed(int64_t n, int64_t nact, const int64_t *act, const int *inv,
+                                     const double4 *jo4, double G, double *jerk, int *nonfinite,
+                                     hipStream_t s) {
+    if (nact <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_output_jerk_listed, dim3(blocks(nact, 256)), dim3(256), 0, s, n, nact, act,
+                       inv, jo4, G, jerk, nonfinite);
     return hipGetLastError();
 }
 

@@ -38,7 +38,7 @@ STATUS_NAMES = {OK: "FMM_OK", E_INVAL: "FMM_E_INVAL", E_NOMEM: "FMM_E_NOMEM", E_
                 E_BUSY: "FMM_E_BUSY"}
 
 SYMBOLS = ["fmm_build", "fmm_forces", "fmm_forces_batched", "fmm_forces_refit",
-           "fmm_forces_active", "fmm_forces_eps", "fmm_forces_jerk", "fmm_direct",
+           "fmm_forces_active", "fmm_forces_eps", "fmm_forces_jerk", "fmm_forces_jerk_active", "fmm_direct",
            "fmm_direct_sinks", "fmm_direct_jerk_sinks",
            "fmm_order_for_error", "fmm_stats", "fmm_footprint_bytes", "fmm_last_error",
            "fmm_destroy", "fmm_export"]
@@ -86,6 +86,9 @@ _lib.fmm_forces_eps.restype = C.c_int
 _lib.fmm_forces_jerk.argtypes = [_P, C.c_int64, _P, _P, _P, C.c_double, C.c_int, C.c_double,
                                  _P, _P, _P]
 _lib.fmm_forces_jerk.restype = C.c_int
+_lib.fmm_forces_jerk_active.argtypes = [_P, C.c_int64, _P, _P, _P, C.c_double, C.c_int,
+                                        C.c_double, C.c_int64, _P, C.c_int, _P, _P, _P]
+_lib.fmm_forces_jerk_active.restype = C.c_int
 _lib.fmm_direct_jerk_sinks.argtypes = [_P, C.c_int64, _P, _P, _P, C.c_double, C.c_int64, _P, _P]
 _lib.fmm_direct_jerk_sinks.restype = C.c_int
 _lib.fmm_direct.argtypes = [_P, C.c_int64, _P, _P, C.c_double, _P, _P]
@@ -258,6 +261,29 @@ class Context:
                                          float(target_err), _dev_ptr(pot, "pot", (n,)),
                                          _dev_ptr(acc, "acc", (n, 3)),
                                          _dev_ptr(jerk, "jerk", (n, 3))))
+        return pot, acc, jerk
+
+    def forces_jerk_active(self, pos: torch.Tensor, vel: torch.Tensor, mass: torch.Tensor,
+                           active: torch.Tensor, G: float = 1.0, p: int = -1,
+                           target_err: float = 1e-6, refit: bool = False):
+        """forces_jerk() for the listed sinks only (int64 CUDA tensor of input
+        indices): (pot, acc, jerk) in list order."""
+        n = pos.shape[0]
+        if not isinstance(active, torch.Tensor) or active.dtype != torch.int64 or not active.is_cuda:
+            raise TypeError("active must be an int64 CUDA tensor")
+        active = active.contiguous()
+        k = active.shape[0]
+        pot = torch.empty(k, dtype=torch.float64, device=pos.device)
+        acc = torch.empty((k, 3), dtype=torch.float64, device=pos.device)
+        jerk = torch.empty((k, 3), dtype=torch.float64, device=pos.device)
+        self._check(_lib.fmm_forces_jerk_active(self._h, n, _dev_ptr(pos, "pos", (n, 3)),
+                                                _dev_ptr(vel, "vel", (n, 3)),
+                                                _dev_ptr(mass, "mass", (n,)), float(G), int(p),
+                                                float(target_err), k,
+                                                C.c_void_p(active.data_ptr()), int(bool(refit)),
+                                                _dev_ptr(pot, "pot", (k,)),
+                                                _dev_ptr(acc, "acc", (k, 3)),
+                                                _dev_ptr(jerk, "jerk", (k, 3))))
         return pot, acc, jerk
 
     def direct(self, pos: torch.Tensor, mass: torch.Tensor, G: float = 1.0):

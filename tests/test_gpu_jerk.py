@@ -129,3 +129,36 @@ def test_direct_jerk_sinks_matches_oracle(gpu_lib):
     assert _rel(j.cpu().numpy(), oracle.direct_jerk(pos, vel, m, G=0.9, sinks=sinks)).max() < 1e-12
     with pytest.raises(gpu_lib.FMMError):
         ctx.direct_jerk_sinks(_dev(pos), _dev(vel), _dev(m), _dev(np.array([3, n], np.int64)))
+
+
+def test_jerk_for_listed_sinks_equals_full_call(gpu_lib):
+    """Block time steps with a Hermite integrator need force and jerk of the
+    active particles only: the listed results equal the full call's bit for
+    bit, with a fresh and with a recycled tree."""
+    import torch
+    n = 20000
+    pos, vel, m = _plummer(n, 21)
+    P, V, M = _dev(pos), _dev(vel), _dev(m)
+    full = gpu_lib.Context(leaf_size=32)
+    pf, af, jf = full.forces_jerk(P, V, M, p=10, target_err=1e-7)
+    r = np.linalg.norm(pos, axis=1)
+    rng = np.random.default_rng(21)
+    lists = [np.argsort(r)[:200], rng.choice(n, n // 10, replace=False),
+             np.array([5, 5, 17, n - 1])]
+    ctx = gpu_lib.Context(leaf_size=32)
+    for refit in (False, True):
+        for lst in lists:
+            lst = lst.astype(np.int64)
+            pa, aa, ja = ctx.forces_jerk_active(P, V, M, _dev(lst), p=10, target_err=1e-7,
+                                                refit=refit)
+            torch.cuda.synchronize()
+            assert np.array_equal(pa.cpu().numpy(), pf.cpu().numpy()[lst])
+            assert np.array_equal(aa.cpu().numpy(), af.cpu().numpy()[lst])
+            assert np.array_equal(ja.cpu().numpy(), jf.cpu().numpy()[lst])
+    st = ctx.stats()
+    assert st["refitted"] == 1
+    pe, ae, je = ctx.forces_jerk_active(P, V, M, _dev(np.zeros(0, np.int64)), p=10,
+                                        target_err=1e-7)
+    assert je.shape == (0, 3)
+    with pytest.raises(gpu_lib.FMMError):
+        ctx.forces_jerk_active(P, V, M, _dev(np.array([0, n], np.int64)), p=10, target_err=1e-7)
