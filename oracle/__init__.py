@@ -262,7 +262,7 @@ class _Params(C.Structure):
 class _Stats(C.Structure):
     _fields_ = [(k, C.c_int64) for k in (
         "n_cells", "n_leaves", "depth", "n_m2l", "n_p2p_cells", "n_p2p_pairs",
-        "n_est_m2l", "n_est_p2p_pairs", "m2l_order_sum")]
+        "n_est_m2l", "n_est_p2p_pairs", "m2l_order_sum", "m2l_macs")]
 
 
 class _Lists(C.Structure):

@@ -405,6 +405,8 @@ static void walk(fmm_t *t, int64_t ia, int64_t ib) {
         if (t->v) or_m2l(A->Md, d, q, t->cells[ib].Fd);   /* eq:M2L:dot */
         ++t->st->n_m2l;
         t->st->m2l_order_sum += q;
+        for (int n = 0; n <= q; ++n)
+            t->st->m2l_macs += (int64_t)(n + 1) * (q - n + 1) * (q - n + 1);
         record(t->lists ? t->lists->m2l : NULL, t->lists ? t->lists->m2l_cap : 0,
                &t->nm2l_rec, A, B);
         return;

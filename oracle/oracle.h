@@ -136,6 +136,8 @@ typedef struct {
     int64_t n_p2p_pairs;    /* particle pairs summed directly (ordered, a != b) */
     int64_t n_est_m2l, n_est_p2p_pairs; /* the same for the estimate pass */
     int64_t m2l_order_sum;  /* sum over M2L pairs of the order used */
+    int64_t m2l_macs;       /* complex multiply-adds of eq:M2L over all pairs:
+                               sum_{n<=q} (n+1)(q-n+1)^2 per pair of order q */
 } or_fmm_stats;
 
 /* Optional outputs for list comparison.  A cell is identified by

@@ -271,6 +271,7 @@ def test_adaptive_order_two_clusters():
     assert st["n_m2l"] == 2 and st["m2l_order_sum"] % 2 == 0
     q = st["m2l_order_sum"] // 2
     assert 3 <= q < p - 1
+    assert st["m2l_macs"] == 2 * sum((n + 1) * (q - n + 1) ** 2 for n in range(q + 1))
     fixed = oracle.fmm(pos, m, p=q, eps=eps, leaf_size=64)
     assert fixed["stats"]["n_m2l"] == 2
     np.testing.assert_allclose(r["acc"], fixed["acc"], rtol=1e-13, atol=0)
