@@ -210,3 +210,48 @@ def test_hermite_steps_follow_the_direct_integration(gpu_lib):
     print(f"energy drift fmm {def_:.2e} direct {ded:.2e}", flush=True)
     assert np.max(np.linalg.norm(xf - xd, axis=1)) < 1e-9 * np.max(np.linalg.norm(xd, axis=1))
     assert abs(def_ - ded) < 1e-9
+
+
+@pytest.mark.parametrize("mac", ["f", "theta"])
+def test_jerk_other_criteria_match_oracle(gpu_lib, mac):
+    """The jerk follows whatever lists the criterion builds: criterion f and
+    the theta criterion against the oracle with the same criterion."""
+    import torch
+    n, p, eps = 5000, 8, 1e-6
+    pos, vel, m = _plummer(n, 51)
+    kw = dict(leaf_size=16, p2p_factor=0.5, mac=mac)
+    if mac == "theta":
+        kw["theta_crit"] = 0.5
+    ctx = gpu_lib.Context(**kw)
+    _, acc, jerk = ctx.forces_jerk(_dev(pos), _dev(vel), _dev(m), p=p, target_err=eps)
+    torch.cuda.synchronize()
+    ref = oracle.fmm(pos, m, p=p, eps=eps, leaf_size=16, p2p_pairs=0.5 * (p + 1) ** 3,
+                     mac=oracle.MAC_F if mac == "f" else oracle.MAC_THETA, theta_crit=0.5,
+                     vel=vel)
+    assert ctx.stats()["n_m2l"] == ref["stats"]["n_m2l"]
+    assert _rel(acc.cpu().numpy(), ref["acc"]).max() < 1e-10
+    assert _rel(jerk.cpu().numpy(), ref["jerk"]).max() < 1e-9
+
+
+def test_jerk_in_a_mixed_precision_context(gpu_lib):
+    """With FMM_PREC_MIXED the force's M2L is the mixed kernel while the rates,
+    their M2L and the direct sums are FP64: the jerk stays within the mixed
+    force bound of the FP64 context's jerk, and the accuracy against the exact
+    jerk is unchanged."""
+    import torch
+    n = 30000
+    pos, vel, m = _plummer(n, 61)
+    P, V, M = _dev(pos), _dev(vel), _dev(m)
+    c64 = gpu_lib.Context()
+    cmx = gpu_lib.Context(precision="mixed")
+    _, a64, j64 = c64.forces_jerk(P, V, M, p=10, target_err=1e-7)
+    _, amx, jmx = cmx.forces_jerk(P, V, M, p=10, target_err=1e-7)
+    torch.cuda.synchronize()
+    dj = _rel(jmx.cpu().numpy(), j64.cpu().numpy())
+    da = _rel(amx.cpu().numpy(), a64.cpu().numpy())
+    assert np.sqrt(np.mean(dj ** 2)) < 1e-6 and np.sqrt(np.mean(da ** 2)) < 1e-6
+    sinks = np.random.default_rng(61).choice(n, 256, replace=False)
+    j0 = oracle.direct_jerk(pos, vel, m, sinks=sinks)
+    e64 = np.sqrt(np.mean(_rel(j64.cpu().numpy()[sinks], j0) ** 2))
+    emx = np.sqrt(np.mean(_rel(jmx.cpu().numpy()[sinks], j0) ** 2))
+    assert emx < 1.5 * e64 + 1e-7
