@@ -255,3 +255,24 @@ def test_jerk_in_a_mixed_precision_context(gpu_lib):
     e64 = np.sqrt(np.mean(_rel(j64.cpu().numpy()[sinks], j0) ** 2))
     emx = np.sqrt(np.mean(_rel(jmx.cpu().numpy()[sinks], j0) ** 2))
     assert emx < 1.5 * e64 + 1e-7
+
+
+def test_jerk_deep_tree_matches_oracle(gpu_lib):
+    """A Plummer sphere with one particle 1e7 away: the tree refines below
+    level 21 (second key word), so M2M and L2L of the rates run over more than
+    21 levels."""
+    import torch
+    n, p, eps = 6000, 8, 1e-7
+    pos, vel, m = _plummer(n, 71)
+    pos = np.vstack([pos, [[1e7, 0.0, 0.0]]])
+    vel = np.vstack([vel, [[0.0, 1e-3, 0.0]]])
+    m = np.concatenate([m, [m[0]]])
+    ctx = gpu_lib.Context(leaf_size=32, p2p_factor=0.5)
+    _, acc, jerk = ctx.forces_jerk(_dev(pos), _dev(vel), _dev(m), p=p, target_err=eps)
+    torch.cuda.synchronize()
+    st = ctx.stats()
+    ref = oracle.fmm(pos, m, p=p, eps=eps, leaf_size=32, p2p_pairs=0.5 * (p + 1) ** 3, vel=vel)
+    assert st["depth"] > 21 and st["depth"] == ref["stats"]["depth"]
+    assert st["n_m2l"] == ref["stats"]["n_m2l"]
+    assert _rel(acc.cpu().numpy(), ref["acc"]).max() < 1e-10
+    assert _rel(jerk.cpu().numpy(), ref["jerk"]).max() < 1e-9
