@@ -7,18 +7,23 @@
  * with the HIP library: no headers, helpers, tables or kernels.
  *
  * Contents
- *   direct.c    - the exact result: direct summation of eq. (1) (eq:P2P) and
- *                 of the scale f (eq:f), Neumaier-compensated, threaded over
- *                 sinks (result independent of the thread count).
+ *   direct.c    - the exact result: direct summation of eq. (1) (eq:P2P), of
+ *                 the scale f (eq:f) and of the jerk (the time derivative of
+ *                 the acceleration, Sec. 7), Neumaier-compensated, threaded
+ *                 over sinks (result independent of the thread count).
  *   harmonics.c - complex solid harmonics Theta_n^m, Upsilon_n^m (Sec. 2.1,
  *                 App. A.3, A.5) and the FMM kernels P2M, M2M, M2L, L2L, L2P
  *                 (eqs:fmm), multipole power P_n (eq:def:PA), the error
  *                 estimate E_{A->B} (eq:def:EAB, eq:err:tilde), the x <-> z
- *                 swap matrices and the rotation-accelerated M2L (App. A).
+ *                 swap matrices and the rotation-accelerated M2L (App. A), the
+ *                 time derivatives of Upsilon and the P2M and L2P rates of the
+ *                 jerk (App. A.5, eqs:fmm:dot).
  *   fmm.c       - a plain recursive FMM following the paper's phases: tree,
  *                 low-order estimate of the sink scale (Sec. 5.4.2), upward
  *                 pass, one-sided dual tree walk with the error-balancing
- *                 acceptance criterion (eqs:mac:better), downward pass.
+ *                 acceptance criterion (eqs:mac:better), downward pass;
+ *                 optionally individual eps_b, an adaptive order per pair
+ *                 and the jerk (Sec. 7).
  *
  * Complex arrays are stored interleaved (re, im) with index n*n + n + m for
  * 0 <= n <= p, -n <= m <= n, i.e. (p+1)^2 complex numbers.
