@@ -41,7 +41,7 @@ typedef enum {
     FMM_E_NONFINITE = 4,   /* non-finite input or output (e.g. two distinct
                               particles at one position); outputs written but
                               undefined */
-    FMM_E_UNSUPPORTED = 5, /* expansion order outside the compiled range */
+    FMM_E_UNSUPPORTED = 5, /* expansion order outside the supported range */
     FMM_E_BUSY = 6         /* context already in use by another thread */
 } fmm_status;
 
@@ -132,8 +132,9 @@ fmm_status fmm_build(fmm_ctx **ctx, const fmm_opts *opts);
 /* Potential and acceleration of all n particles (eq. 1, Sec. 6).
  *   G          gravitational constant (applied at the end; the acceptance
  *              test is G invariant)
- *   p          expansion order 1..FMM_P_MAX, or < 0 for the order chosen from
- *              target_err by fmm_order_for_error
+ *   p          expansion order FMM_P_MIN..FMM_P_MAX (from FMM_P_MIN_MIXED in
+ *              mixed precision), or < 0 for the order chosen from target_err
+ *              by fmm_order_for_error
  *   target_err accuracy parameter epsilon of eqs:mac:better (> 0, finite)
  * n = 0 is a no-op; n = 1 gives pot = acc = 0. */
 fmm_status fmm_forces(fmm_ctx *ctx, int64_t n, const double *pos, const double *mass,
@@ -261,6 +262,13 @@ enum { FMM_EXPORT_M2L = 1, FMM_EXPORT_P2P = 2, FMM_EXPORT_SCALE = 3, FMM_EXPORT_
 int64_t fmm_export(fmm_ctx *ctx, int what, void *dst, int64_t capacity);
 
 #define FMM_P_MAX 20
+/* Lowest accepted expansion orders: 3 for FP64 evaluations and every jerk
+ * call, 2 in mixed precision; lower orders give FMM_E_UNSUPPORTED.  (The
+ * FP64 kernels of orders 1 and 2 have no passing device run: the one run that
+ * reached them ended in a GPU fault whose cause is not known.  The order
+ * chosen from target_err is never below 3.) */
+#define FMM_P_MIN 3
+#define FMM_P_MIN_MIXED 2
 
 #ifdef __cplusplus
 }

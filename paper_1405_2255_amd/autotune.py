@@ -59,7 +59,7 @@ def candidates(target: float, leaf_sizes=(32, 48, 64, 96, 128, 192), p2p_factors
                 eps = k * target
                 p0 = fmm.order_for_error(eps)
                 for d in order_offsets:
-                    p = min(fmm.P_MAX, max(1, p0 + d))
+                    p = min(fmm.P_MAX, max(fmm.P_MIN, p0 + d))
                     out.append(Candidate(int(leaf), float(pf), float(eps), int(p)))
     return list(dict.fromkeys(out))
 

@@ -925,8 +925,10 @@ void fmm_destroy(fmm_ctx *c) {
     delete c;
 }
 
+// jerk: the call also evaluates the rates (always with the FP64 M2L kernels)
 static fmm_status check_common(fmm_ctx *c, int64_t n, const double *pos, const double *mass,
-                               double G, int *p, double eps, double *pot, double *acc) {
+                               double G, int *p, double eps, double *pot, double *acc,
+                               bool jerk = false) {
     if (n < 0) return fmm::fail(c, FMM_E_INVAL, "n < 0");
     if (n > (int64_t)INT32_MAX / 2) return fmm::fail(c, FMM_E_INVAL, "n too large");
     if (n > 0 && (!pos || !mass || !pot || !acc)) return fmm::fail(c, FMM_E_INVAL, "null array");
@@ -940,6 +942,13 @@ static fmm_status check_common(fmm_ctx *c, int64_t n, const double *pos, const d
     }
     if (*p == 0) return fmm::fail(c, FMM_E_INVAL, "p must be >= 1");
     if (*p > FMM_P_MAX) return fmm::fail(c, FMM_E_UNSUPPORTED, "p above FMM_P_MAX");
+    // the lowest orders whose kernels have a passing device run: FP64 from 3,
+    // the mixed-precision M2L from 2
+    const int pmin = c->opts.precision == FMM_PREC_MIXED && !jerk ? FMM_P_MIN_MIXED : FMM_P_MIN;
+    if (*p < pmin)
+        return fmm::fail(c, FMM_E_UNSUPPORTED, c->opts.precision == FMM_PREC_MIXED && !jerk
+                                                   ? "mixed precision needs p >= 2"
+                                                   : "FP64 evaluation needs p >= 3");
     if (c->opts.m2l_kernel == FMM_M2L_ROTATION && !FMM_M2L_ROT_ENABLED)
         return fmm::fail(c, FMM_E_UNSUPPORTED, "the rotation M2L kernel is switched off");
     if (c->opts.m2l_kernel == FMM_M2L_ROTATION && *p > FMM_M2L_ROT_MAX)
@@ -1110,7 +1119,7 @@ fmm_status fmm_forces_jerk(fmm_ctx *c, int64_t n, const double *pos, const doubl
     if (!g.ok) return FMM_E_BUSY;
     c->err.clear();
     if (n > 0 && (!vel || !jerk)) return fmm::fail(c, FMM_E_INVAL, "null velocity or jerk array");
-    fmm_status st = check_common(c, n, pos, mass, G, &p, target_err, pot, acc);
+    fmm_status st = check_common(c, n, pos, mass, G, &p, target_err, pot, acc, true);
     if (st != FMM_OK) return st;
     return fmm::guarded(c, [&]() -> fmm_status {
         if (n == 0) return FMM_OK;
@@ -1185,7 +1194,7 @@ fmm_status fmm_forces_jerk_active(fmm_ctx *c, int64_t n, const double *pos, cons
     if (n < 0 || (n > 0 && (!pos || !mass || !vel)))
         return fmm::fail(c, FMM_E_INVAL, "bad particle arrays");
     fmm_status st = check_common(c, n, pos, mass, G, &p, target_err, pot ? pot : (double *)pos,
-                                 acc ? acc : (double *)pos);
+                                 acc ? acc : (double *)pos, true);
     if (st != FMM_OK) return st;
     return fmm::guarded(c, [&]() -> fmm_status {
         if (n_active == 0) return FMM_OK;

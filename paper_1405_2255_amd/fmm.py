@@ -32,6 +32,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 M2L_AUTO, M2L_DIRECT, M2L_ROTATION = 0, 1, 2
 EXPORT_M2L, EXPORT_P2P, EXPORT_SCALE, EXPORT_CELLS = 1, 2, 3, 4
 P_MAX = 20
+P_MIN, P_MIN_MIXED = 3, 2   # lowest accepted orders (FP64 and jerk calls; mixed precision)
 
 STATUS_NAMES = {OK: "FMM_OK", E_INVAL: "FMM_E_INVAL", E_NOMEM: "FMM_E_NOMEM", E_HIP: "FMM_E_HIP",
                 E_NONFINITE: "FMM_E_NONFINITE", E_UNSUPPORTED: "FMM_E_UNSUPPORTED",

@@ -11,7 +11,7 @@ def test_grid_spans_leaf_threshold_and_order():
     assert len(g) == len(set(g)) == 6 * 3 * 3 * 2
     from paper_1405_2255_amd import fmm
     for c in g:
-        assert 1 <= c.p <= fmm.P_MAX
+        assert fmm.P_MIN <= c.p <= fmm.P_MAX
         assert c.eps in (0.6e-7, 0.75e-7, 0.9e-7)
         assert c.p - fmm.order_for_error(c.eps) in (0, 1)
     # the library's own defaults (n_L = 32, factor 2, p from eps) are in the grid

@@ -220,6 +220,19 @@ def test_error_paths(ctx, gpu_lib):
     assert e.value.status == gpu_lib.E_UNSUPPORTED
     with pytest.raises(TypeError):
         ctx.forces(P.float(), M)
+    # orders below the supported range are refused before any launch: FP64
+    # and jerk calls need p >= 3, mixed precision p >= 2
+    for p in (1, 2):
+        with pytest.raises(gpu_lib.FMMError) as e:
+            ctx.forces(P, M, p=p, target_err=1e-6)
+        assert e.value.status == gpu_lib.E_UNSUPPORTED
+    mixed = gpu_lib.Context(precision="mixed")
+    with pytest.raises(gpu_lib.FMMError) as e:
+        mixed.forces(P, M, p=1, target_err=1e-6)
+    assert e.value.status == gpu_lib.E_UNSUPPORTED
+    with pytest.raises(gpu_lib.FMMError) as e:
+        mixed.forces_jerk(P, torch.zeros_like(P), M, p=2, target_err=1e-6)
+    assert e.value.status == gpu_lib.E_UNSUPPORTED
     # two distinct particles at one position: non-finite result is reported
     pos2 = pos.copy()
     pos2[7] = pos2[3]

@@ -42,7 +42,7 @@ def ctxs(gpu_lib):
             gpu_lib.Context(m2l="direct", p2p_factor=0.5))
 
 
-@pytest.mark.parametrize("p", list(range(1, 17)))
+@pytest.mark.parametrize("p", list(range(3, 17)))
 def test_rotation_equals_direct(ctxs, p):
     """Every compiled order; a workload whose lists fill many 64-entry
     windows, with sinks whose lists span more than one window and a ragged
