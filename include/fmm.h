@@ -221,6 +221,21 @@ fmm_status fmm_direct_sinks(fmm_ctx *ctx, int64_t n, const double *pos, const do
                             double G, int64_t nsinks, const int64_t *sinks, double *pot,
                             double *acc);
 
+/* fmm_direct_sinks for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, kernels and results (bit for bit), but the partial sums
+ * and the index flag live in a static device array of
+ * FMM_NOALLOC_SCRATCH_BYTES per device, reserved for the life of the process,
+ * instead of context buffers; the call allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine).  A call whose partial sums would
+ * not fit gives FMM_E_INVAL (the library's split of the sources keeps them
+ * below 16 MiB, so this does not happen for valid sizes).  Every call on one
+ * device shares that device's array: calls that overlap on one device (other
+ * contexts, other streams, other threads) race and must not be issued. */
+fmm_status fmm_direct_sinks_noalloc(fmm_ctx *ctx, int64_t n, const double *pos,
+                                    const double *mass, double G, int64_t nsinks,
+                                    const int64_t *sinks, double *pot, double *acc);
+
 /* The exact jerk of selected sinks (the comparison baseline of
  * fmm_forces_jerk): sinks[j] (device int64, 0 <= sinks[j] < n) receives
  * jerk[3j..3j+2] = G sum_{a != b} mu_a [v_ab/r^3 - 3 (r . v_ab) r/r^5],
@@ -269,6 +284,9 @@ int64_t fmm_export(fmm_ctx *ctx, int what, void *dst, int64_t capacity);
  * chosen from target_err is never below 3.) */
 #define FMM_P_MIN 3
 #define FMM_P_MIN_MIXED 2
+/* Size of the static per-device scratch array of fmm_direct_sinks_noalloc:
+ * 256 bytes of flags and 16 MiB of partial sums. */
+#define FMM_NOALLOC_SCRATCH_BYTES (256 + (16u << 20))
 
 #ifdef __cplusplus
 }

@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -140,6 +141,8 @@ struct fmm_ctx {
     DevBuf Tsh;                            // M2M: each cell's expansion shifted to its parent
     DevBuf M32, sig, Flow;                 // mixed-precision M2L: scaled multipoles, chunk
                                            // scales, FP64 low-degree chunk parts
+    DevBuf dspart;                         // exact sums for listed sinks: partial rows
+    void *scratch = nullptr;   // device address of this device's static scratch array
     int plan_p = -1;
     uint64_t *kdeep = nullptr;            // second key word of the sorted particles
     bool deep = false;
@@ -838,6 +841,32 @@ fmm_status guarded(fmm_ctx *c, F &&body) {
 
 
 }  // namespace
+
+// ---- workspace of the entry point that allocates nothing --------------------
+// fmm_direct_sinks_noalloc keeps its index flag (first 256 bytes) and its
+// partial rows (the rest) in this array instead of context buffers.  Each
+// device holds its own copy for the life of the process.  In host code the
+// name only stands for the symbol: its device address comes from
+// hipGetSymbolAddress, taken once per device (with that device current) by
+// the first fmm_build on it and kept in scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[FMM_NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[MAX_DEVICES] = {};
+
+// the address of the current device's copy (the caller made `dev` current)
+void *scratch_address(int dev) {
+    if (dev < 0 || dev >= MAX_DEVICES) throw HipFail{hipErrorInvalidDevice, "device ordinal"};
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void *q = nullptr;
+        CK(hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)));
+        scratch_ptr[dev] = q;
+    }
+    return scratch_ptr[dev];
+}
+
 }  // namespace fmm
 
 // =====================================================================  C ABI
@@ -883,6 +912,7 @@ fmm_status fmm_build(fmm_ctx **out, const fmm_opts *o) {
         for (auto &e : c->ev_m2l) CK(hipEventCreate(&e));
         for (auto &e : c->ev_p2p) CK(hipEventCreate(&e));
         for (auto &e : c->ev_walk) CK(hipEventCreate(&e));
+        c->scratch = fmm::scratch_address(c->opts.device);
         return FMM_OK;
     });
     if (st != FMM_OK) {
@@ -911,7 +941,7 @@ void fmm_destroy(fmm_ctx *c) {
                       &c->actflag, &c->actf, &c->actinv, &c->actpre, &c->cellact, &c->actbad,
                       &c->dkey, &c->dsort, &c->dsort2, &c->runstart, &c->plans, &c->Tsh,
                       &c->M32, &c->sig, &c->Flow, &c->epsmin, &c->vel4, &c->Md, &c->Fd,
-                      &c->jFpart, &c->jo4, &c->jpart};
+                      &c->jFpart, &c->jo4, &c->jpart, &c->dspart};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (auto &e : c->ev) if (e) (void)hipEventDestroy(e);
@@ -1158,6 +1188,18 @@ fmm_status fmm_direct(fmm_ctx *c, int64_t n, const double *pos, const double *ma
     });
 }
 
+static fmm_status check_direct_sinks(fmm_ctx *c, int64_t n, const double *pos,
+                                     const double *mass, double G, int64_t nsinks,
+                                     const int64_t *sinks, double *pot, double *acc) {
+    if (n < 0 || nsinks < 0 || (nsinks > 0 && (!pos || !mass || !sinks || !pot || !acc)) ||
+        !std::isfinite(G))
+        return fmm::fail(c, FMM_E_INVAL, "bad argument");
+    if (n > (int64_t)INT32_MAX / 2 || nsinks > (int64_t)INT32_MAX / 2)
+        return fmm::fail(c, FMM_E_INVAL, "n or nsinks too large");
+    if (nsinks > 0 && n == 0) return fmm::fail(c, FMM_E_INVAL, "sink index out of range");
+    return FMM_OK;
+}
+
 fmm_status fmm_direct_sinks(fmm_ctx *c, int64_t n, const double *pos, const double *mass,
                             double G, int64_t nsinks, const int64_t *sinks, double *pot,
                             double *acc) {
@@ -1165,15 +1207,45 @@ fmm_status fmm_direct_sinks(fmm_ctx *c, int64_t n, const double *pos, const doub
     fmm::Guard g(c);
     if (!g.ok) return FMM_E_BUSY;
     c->err.clear();
-    if (n < 0 || nsinks < 0 || (nsinks > 0 && (!pos || !mass || !sinks || !pot || !acc)) ||
-        !std::isfinite(G))
-        return fmm::fail(c, FMM_E_INVAL, "bad argument");
-    if (nsinks == 0) return FMM_OK;
-    if (n == 0) return fmm::fail(c, FMM_E_INVAL, "sink index out of range");
+    fmm_status st = check_direct_sinks(c, n, pos, mass, G, nsinks, sinks, pot, acc);
+    if (st != FMM_OK || nsinks == 0) return st;
     return fmm::guarded(c, [&]() -> fmm_status {
+        const int nchunk = fmm::direct_sinks_chunks(n, nsinks);
+        double4 *part =
+            nchunk > 1 ? fmm::ensure<double4>(c->dspart, (size_t)nchunk * nsinks) : nullptr;
         int *bad = fmm::ensure<int>(c->nonfinite, 8) + 5;
         CK(hipMemsetAsync(bad, 0, sizeof(int), c->stream));
-        CK(fmm::launch_direct_sinks(n, pos, mass, G, nsinks, sinks, pot, acc, bad, c->stream));
+        CK(fmm::launch_direct_sinks(n, pos, mass, G, nsinks, sinks, nchunk, pot, acc, part, bad,
+                                    c->stream));
+        CK(hipMemcpyAsync(c->hint, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        fmm::sync(c);
+        if (c->hint[0]) return fmm::fail(c, FMM_E_INVAL, "sink index out of range");
+        return FMM_OK;
+    });
+}
+
+fmm_status fmm_direct_sinks_noalloc(fmm_ctx *c, int64_t n, const double *pos,
+                                    const double *mass, double G, int64_t nsinks,
+                                    const int64_t *sinks, double *pot, double *acc) {
+    if (!c) return FMM_E_INVAL;
+    fmm::Guard g(c);
+    if (!g.ok) return FMM_E_BUSY;
+    c->err.clear();
+    fmm_status st = check_direct_sinks(c, n, pos, mass, G, nsinks, sinks, pot, acc);
+    if (st != FMM_OK || nsinks == 0) return st;
+    const int nchunk = fmm::direct_sinks_chunks(n, nsinks);
+    const size_t rows = nchunk > 1 ? (size_t)nchunk * (size_t)nsinks * sizeof(double4) : 0;
+    if (256 + rows > FMM_NOALLOC_SCRATCH_BYTES)
+        return fmm::fail(c, FMM_E_INVAL, "the partial sums exceed the static scratch buffer");
+    if (!c->scratch) return fmm::fail(c, FMM_E_HIP, "no scratch address on this device");
+    return fmm::guarded(c, [&]() -> fmm_status {
+        int *bad = static_cast<int *>(c->scratch);
+        double4 *part =
+            nchunk > 1 ? reinterpret_cast<double4 *>(static_cast<char *>(c->scratch) + 256)
+                       : nullptr;
+        CK(fmm::launch_fill_int(bad, 1, 0, c->stream));
+        CK(fmm::launch_direct_sinks(n, pos, mass, G, nsinks, sinks, nchunk, pot, acc, part, bad,
+                                    c->stream));
         CK(hipMemcpyAsync(c->hint, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
         fmm::sync(c);
         if (c->hint[0]) return fmm::fail(c, FMM_E_INVAL, "sink index out of range");

@@ -264,9 +264,20 @@ hipError_t launch_output_listed(int64_t n, int64_t nact, const int64_t *act, con
                                 int *nonfinite, hipStream_t s);
 hipError_t launch_scale(int want_f, int64_t n, const double4 *est4, double *scale,
                         hipStream_t s);
+// Exact sums for listed sinks (an index outside [0, n) sets *bad and its
+// outputs are left alone).  The sources are cut into nchunk chunks of
+// ceil(n / nchunk), one per grid row; with nchunk > 1 the partial sums go to
+// part (nchunk * nsinks double4) and are added per sink in chunk order.
+// direct_sinks_chunks gives the library's choice: about DIRECT_SINKS_BLOCKS
+// blocks of 256 sinks, chunks of at least 2048 sources.  When nchunk > 1,
+// nchunk * nsinks < 2 * DIRECT_SINKS_BLOCKS * 256.
+#define DIRECT_SINKS_BLOCKS 1024
+int direct_sinks_chunks(int64_t n, int64_t nsinks);
 hipError_t launch_direct_sinks(int64_t n, const double *pos, const double *mass, double G,
-                               int64_t nsinks, const int64_t *sinks, double *pot, double *acc,
-                               int *bad, hipStream_t s);
+                               int64_t nsinks, const int64_t *sinks, int nchunk, double *pot,
+                               double *acc, double4 *part, int *bad, hipStream_t s);
+// p[0 .. count) = v (a kernel, so that no memset node enters a captured graph)
+hipError_t launch_fill_int(int *p, int64_t count, int v, hipStream_t s);
 hipError_t launch_direct(int64_t n, const double *pos, const double *mass, double G,
                          double *pot, double *acc, hipStream_t s);
 

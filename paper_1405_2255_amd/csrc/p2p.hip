@@ -321,18 +321,29 @@ k_direct(int64_t n, const double *pos, const double *mass, double G, double *pot
     acc[3 * i + 2] = G * az;
 }
 
-// the same for listed sinks; an index outside [0, n) sets *bad
+// The same sum for listed sinks, with the sources split over the grid's y
+// dimension: block (x, k) takes sinks [256 x, 256 x + 256) against sources
+// [k chunk, min(n, (k + 1) chunk)), one sink per thread, the sources read as
+// wavefront-uniform values.  A few thousand sinks thus still fill the chip.
+// With one chunk the block writes the results; otherwise it writes row k of
+// part (nsinks double4 per row: Psi, a without G) and k_direct_sinks_reduce
+// adds the rows of each sink in chunk order, so the result does not depend on
+// the order in which blocks run.  An index outside [0, n) sets *bad (by the
+// blocks of chunk 0) and its outputs are not written.
 __global__ void __launch_bounds__(256)
 k_direct_sinks(int64_t n, const double *pos, const double *mass, double G, int64_t nsinks,
-               const int64_t *sinks, double *pot, double *acc, int *bad) {
+               const int64_t *sinks, int64_t chunk, double *pot, double *acc, double4 *part,
+               int *bad) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
     int64_t ii = t < nsinks ? sinks[t] : 0;
     const bool valid = t < nsinks && ii >= 0 && ii < n;
-    if (t < nsinks && !valid) atomicOr(bad, 1);
+    if (k == 0 && t < nsinks && !valid) atomicOr(bad, 1);
     if (!valid) ii = 0;
     const double xb = pos[3 * ii], yb = pos[3 * ii + 1], zb = pos[3 * ii + 2];
+    const int64_t j0 = (int64_t)k * chunk, j1 = min(n, j0 + chunk);
     double p = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
-    for (int64_t j = 0; j < n; ++j) {
+    for (int64_t j = j0; j < j1; ++j) {
         const double dx = pos[3 * j] - xb, dy = pos[3 * j + 1] - yb, dz = pos[3 * j + 2] - zb;
         const bool self = j == ii;
         const double r2 = self ? 1.0 : fma(dx, dx, fma(dy, dy, dz * dz));
@@ -345,10 +356,36 @@ k_direct_sinks(int64_t n, const double *pos, const double *mass, double G, int64
         az = fma(q3, dz, az);
     }
     if (!valid) return;
+    if (part) {
+        part[(int64_t)k * nsinks + t] = make_double4(p, ax, ay, az);
+        return;
+    }
     pot[t] = -G * p;
     acc[3 * t] = G * ax;
     acc[3 * t + 1] = G * ay;
     acc[3 * t + 2] = G * az;
+}
+
+__global__ void k_direct_sinks_reduce(int64_t n, double G, int64_t nsinks, const int64_t *sinks,
+                                      int nchunk, const double4 *part, double *pot, double *acc) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nsinks) return;
+    const int64_t ii = sinks[t];
+    if (ii < 0 || ii >= n) return;
+    double4 v = part[t];
+    for (int k = 1; k < nchunk; ++k) {
+        const double4 q = part[(int64_t)k * nsinks + t];
+        v.x += q.x; v.y += q.y; v.z += q.z; v.w += q.w;
+    }
+    pot[t] = -G * v.x;
+    acc[3 * t] = G * v.y;
+    acc[3 * t + 1] = G * v.z;
+    acc[3 * t + 2] = G * v.w;
+}
+
+__global__ void k_fill_int(int *p, int64_t count, int v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
 }
 
 __global__ void k_output(int64_t n, const uint32_t *perm, const double4 *out4, double G,
@@ -576,11 +613,32 @@ hipError_t launch_scale(int want_f, int64_t n, const double4 *est4, double *scal
     return hipGetLastError();
 }
 
+int direct_sinks_chunks(int64_t n, int64_t nsinks) {
+    // about DIRECT_SINKS_BLOCKS blocks, at least 2048 sources per chunk
+    const int64_t sb = (nsinks + 255) / 256;
+    const int64_t want = (DIRECT_SINKS_BLOCKS + sb - 1) / sb;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(want, n / 2048));
+}
+
 hipError_t launch_direct_sinks(int64_t n, const double *pos, const double *mass, double G,
-                               int64_t nsinks, const int64_t *sinks, double *pot, double *acc,
-                               int *bad, hipStream_t s) {
-    hipLaunchKernelGGL(k_direct_sinks, dim3(blocks(nsinks, 256)), dim3(256), 0, s, n, pos, mass,
-                       G, nsinks, sinks, pot, acc, bad);
+                               int64_t nsinks, const int64_t *sinks, int nchunk, double *pot,
+                               double *acc, double4 *part, int *bad, hipStream_t s) {
+    if (nsinks <= 0) return hipSuccess;
+    if (nchunk < 1 || (nchunk > 1 && !part)) return hipErrorInvalidValue;
+    const int64_t chunk = (n + nchunk - 1) / nchunk;
+    hipLaunchKernelGGL(k_direct_sinks, dim3(blocks(nsinks, 256), (unsigned)nchunk), dim3(256), 0,
+                       s, n, pos, mass, G, nsinks, sinks, chunk, pot, acc,
+                       nchunk > 1 ? part : nullptr, bad);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nchunk == 1) return e;
+    hipLaunchKernelGGL(k_direct_sinks_reduce, dim3(blocks(nsinks, 256)), dim3(256), 0, s, n, G,
+                       nsinks, sinks, nchunk, (const double4 *)part, pot, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int *p, int64_t count, int v, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_int, dim3(blocks(count, 256)), dim3(256), 0, s, p, count, v);
     return hipGetLastError();
 }
 

@@ -40,7 +40,7 @@ STATUS_NAMES = {OK: "FMM_OK", E_INVAL: "FMM_E_INVAL", E_NOMEM: "FMM_E_NOMEM", E_
 
 SYMBOLS = ["fmm_build", "fmm_forces", "fmm_forces_batched", "fmm_forces_refit",
            "fmm_forces_active", "fmm_forces_eps", "fmm_forces_jerk", "fmm_forces_jerk_active", "fmm_direct",
-           "fmm_direct_sinks", "fmm_direct_jerk_sinks",
+           "fmm_direct_sinks", "fmm_direct_sinks_noalloc", "fmm_direct_jerk_sinks",
            "fmm_order_for_error", "fmm_stats", "fmm_footprint_bytes", "fmm_last_error",
            "fmm_destroy", "fmm_export"]
 
@@ -96,6 +96,9 @@ _lib.fmm_direct.argtypes = [_P, C.c_int64, _P, _P, C.c_double, _P, _P]
 _lib.fmm_direct.restype = C.c_int
 _lib.fmm_direct_sinks.argtypes = [_P, C.c_int64, _P, _P, C.c_double, C.c_int64, _P, _P, _P]
 _lib.fmm_direct_sinks.restype = C.c_int
+_lib.fmm_direct_sinks_noalloc.argtypes = [_P, C.c_int64, _P, _P, C.c_double, C.c_int64, _P, _P,
+                                          _P]
+_lib.fmm_direct_sinks_noalloc.restype = C.c_int
 _lib.fmm_order_for_error.argtypes = [C.c_double]
 _lib.fmm_order_for_error.restype = C.c_int
 _lib.fmm_stats.argtypes = [_P, C.POINTER(Stats)]
@@ -298,19 +301,24 @@ class Context:
         return pot, acc
 
     def direct_sinks(self, pos: torch.Tensor, mass: torch.Tensor, sinks: torch.Tensor,
-                     G: float = 1.0):
-        """Exact FP64 direct sum for the listed sinks (int64 CUDA tensor)."""
+                     G: float = 1.0, pot: torch.Tensor | None = None,
+                     acc: torch.Tensor | None = None, noalloc: bool = False):
+        """Exact FP64 direct sum for the listed sinks (int64 CUDA tensor).
+        noalloc: through fmm_direct_sinks_noalloc (no device allocation by the
+        library; pass pot and acc to avoid torch's own allocations too)."""
         n = pos.shape[0]
         if not isinstance(sinks, torch.Tensor) or sinks.dtype != torch.int64 or not sinks.is_cuda:
             raise TypeError("sinks must be an int64 CUDA tensor")
         sinks = sinks.contiguous()
         k = sinks.shape[0]
-        pot = torch.empty(k, dtype=torch.float64, device=pos.device)
-        acc = torch.empty((k, 3), dtype=torch.float64, device=pos.device)
-        self._check(_lib.fmm_direct_sinks(self._h, n, _dev_ptr(pos, "pos", (n, 3)),
-                                          _dev_ptr(mass, "mass", (n,)), float(G), k,
-                                          C.c_void_p(sinks.data_ptr()),
-                                          _dev_ptr(pot, "pot", (k,)), _dev_ptr(acc, "acc", (k, 3))))
+        if pot is None:
+            pot = torch.empty(k, dtype=torch.float64, device=pos.device)
+        if acc is None:
+            acc = torch.empty((k, 3), dtype=torch.float64, device=pos.device)
+        fn = _lib.fmm_direct_sinks_noalloc if noalloc else _lib.fmm_direct_sinks
+        self._check(fn(self._h, n, _dev_ptr(pos, "pos", (n, 3)), _dev_ptr(mass, "mass", (n,)),
+                       float(G), k, C.c_void_p(sinks.data_ptr()), _dev_ptr(pot, "pot", (k,)),
+                       _dev_ptr(acc, "acc", (k, 3))))
         return pot, acc
 
     def direct_jerk_sinks(self, pos: torch.Tensor, vel: torch.Tensor, mass: torch.Tensor,
