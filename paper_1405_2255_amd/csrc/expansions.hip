@@ -376,16 +376,20 @@ k_l2p(TreeArrays t, const int *leaf_of, const int *leaf_cell, int64_t n, const d
 }
 
 // ---- low-order estimate (p = 1 at the centre of mass, or the 1/r^2 monopole) --
-// Fe = (Psi, F_1^0, Re F_1^1, Im F_1^1); for f only .x is used.
-__global__ void k_est_m2l(int want_f, TreeArrays t, int nsinks, const int64_t *off,
-                          const uint64_t *list, int sh, double4 *Fe) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+// Fe = (Psi, F_1^0, Re F_1^1, Im F_1^1); for f only .x is used.  One wavefront
+// per sink cell: lane j adds entries j, j + 64, ... of the cell's list, then
+// the lanes are added in a fixed butterfly order (deterministic).
+__global__ void __launch_bounds__(256)
+k_est_m2l(int want_f, TreeArrays t, int nsinks, const int64_t *off, const uint64_t *list, int sh,
+          double4 *Fe) {
+    const int b = blockIdx.x * 4 + threadIdx.x / FMM_WAVE;
     if (b >= nsinks) return;
+    const int lane = lane_id();
     const int64_t e0 = off[b], e1 = off[b + 1];
     const double4 sb = t.com[b];
     const uint64_t mask = (1ull << sh) - 1;
     double f0 = 0.0, f10 = 0.0, f11r = 0.0, f11i = 0.0;
-    for (int64_t e = e0; e < e1; ++e) {
+    for (int64_t e = e0 + lane; e < e1; e += FMM_WAVE) {
         const int a = (int)(list[e] & mask);
         const double4 za = t.com[a];
         const double M = t.mass[a];
@@ -402,7 +406,11 @@ __global__ void k_est_m2l(int want_f, TreeArrays t, int nsinks, const int64_t *o
             f11i = fma(q3, dy, f11i);
         }
     }
-    Fe[b] = make_double4(f0, f10, f11r, f11i);
+    f0 = wave_sum(f0);
+    f10 = wave_sum(f10);
+    f11r = wave_sum(f11r);
+    f11i = wave_sum(f11i);
+    if (lane == 0) Fe[b] = make_double4(f0, f10, f11r, f11i);
 }
 
 // p = 1 shift: F_1^m is unchanged and F_0^0 is not needed for |a|; so the
@@ -536,7 +544,7 @@ hipError_t launch_l2p(int p, const TreeArrays &t, const int *leaf_of, const int 
 
 hipError_t launch_est_m2l(int want_f, const TreeArrays &t, int nsinks, const int64_t *off,
                           const uint64_t *list, int sh, double4 *Fe, hipStream_t s) {
-    hipLaunchKernelGGL(k_est_m2l, dim3(blocks(nsinks, 128)), dim3(128), 0, s, want_f, t, nsinks,
+    hipLaunchKernelGGL(k_est_m2l, dim3(blocks(nsinks, 4)), dim3(256), 0, s, want_f, t, nsinks,
                        off, list, sh, Fe);
     return hipGetLastError();
 }
