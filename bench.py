@@ -32,6 +32,16 @@ Prints ONE JSON line (rank 0): metric, value, ... plus
                 mixed profiles and error targets, 10 drift steps each with the
                 tree recycled, mixed precision) through the serving loop:
                 p50/p99 latency and throughput at an offered load of 0.8
+  the benchmark spec    the form the project targets: a stream of N = 1e6 mixed-
+                precision force evaluations (rms 1e-7) through the serving loop
+                (continuous batching, HBM admission): the served capacity with
+                every request queued at once, then p50/p99 latency and
+                throughput for Poisson arrivals at offered loads of it; with the
+                FP32 roofline of its kernels and the accuracy of its results
+  roofline_fp32 the mixed-precision P2P and M2L kernels against the FP32 peak
+  cpu_baseline_fmm  the CPU oracle's plain FMM on a bounded sample
+  tree          the tree phase as HBM traffic (~290 algorithmic bytes per
+                particle) against the 8 TB/s HBM peak
 """
 from __future__ import annotations
 
@@ -48,6 +58,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 vector peak
+FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector peak (reached only with packed FP32 instructions)
+HBM_PEAK_GBPS = 8000.0    # MI355X HBM3E
+TREE_BYTES_PER_PARTICLE = 290.0   # keys, 8 radix passes of (key, index), gather
 
 
 def m2l_flops(p: int) -> float:
@@ -484,6 +497,84 @@ def serve_leg(args, fmm, workloads, capacity_pfs):
             "all_within_target": bool(all(c["rms"] <= c["target_rms"] for c in checks))}
 
 
+def north_star_leg(args, fmm, workloads, params):
+    """N = 1e6 mixed-precision force evaluations through the serving loop.
+
+    R requests cycle over K seeded Plummer inputs (N = 1e6 each, seeds other
+    than the FP64 leg's); every request is one full evaluation (tree build,
+    estimate, walk, M2L, P2P, downward pass) with the tuned mixed-precision
+    parameters for rms 1e-7.  Slots run on their own streams, so the
+    latency-bound phases of one request overlap the arithmetic of another.
+    Capacity: all R queued at t = 0, R N / (time to the last result).  Then
+    Poisson arrivals at offered loads of that capacity: p50 / p99 latency from
+    submission to result, and throughput."""
+    import torch
+    from paper_1405_2255_amd import serve
+    leaf, pf, p, eps = params
+    n, R, K = 10 ** 6, args.ns_requests, 4
+    dev = torch.device("cuda:0")
+    inputs = []
+    for k in range(K):
+        pos, m = workloads.cluster("plummer", n, args.seed + 7000 + k)
+        inputs.append((torch.from_numpy(pos).to(dev), torch.from_numpy(m).to(dev)))
+    srv = serve.Server(device=0, slots=args.ns_slots, leaf_size=leaf, p2p_factor=pf,
+                       precision="mixed")
+
+    def make(i):
+        P, M = inputs[i % K]
+        return serve.Request(pos=P, mass=M, target_err=eps, p=p, steps=1)
+
+    for w in [srv.submit(make(k)) for k in range(args.ns_slots)]:     # size every slot
+        w.result(600)
+    t0 = time.perf_counter()
+    reqs = [srv.submit(make(i)) for i in range(R)]
+    for q in reqs:
+        q.result(600)
+    t_cap = max(q.t_end for q in reqs) - t0
+    capacity = R * n / t_cap
+    print(f"north star: {R} requests queued at once in {t_cap:.3f} s, "
+          f"{capacity:.4g} particle-forces/s", file=sys.stderr, flush=True)
+    # accuracy of the served results of every input against the GPU direct sum
+    ctx = fmm.Context(device=0)
+    acc_err, pooled = [], []
+    for k in range(K):
+        _, ad = ctx.direct(inputs[k][0], inputs[k][1], 1.0)
+        e = _rel_err(reqs[k].acc, ad)
+        acc_err.append(_summary(e))
+        pooled.append(e)
+    ctx.close()
+    pooled = _summary(np.concatenate(pooled))
+    rng = np.random.default_rng(args.seed + 7100)
+    gaps = rng.exponential(n / capacity, R)
+    loads = []
+    for load in args.ns_loads:
+        t_start = time.perf_counter()
+        t_next = t_start
+        rq = []
+        for i in range(R):
+            t_next += gaps[i] / load
+            dt = t_next - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            rq.append(srv.submit(make(i)))
+        for q in rq:
+            q.result(600)
+        t_all = max(q.t_end for q in rq) - t_start
+        loads.append({"offered_load": load, "latency": serve.latency_summary(rq),
+                      "value": R * n / t_all, "unit": "particle-forces/s", "seconds": t_all})
+        print(f"north star at load {load}: {loads[-1]['latency']}", file=sys.stderr, flush=True)
+    srv.close()
+    single_ms = float(np.median([q.t_end - q.t_start for q in reqs[:args.ns_slots]]))
+    return {"workload": f"{R} requests, each one full mixed-precision evaluation of a Plummer "
+                        f"sphere, N=1e6 (cycling over {K} seeded inputs), rms target 1e-7 "
+                        f"(n_L={leaf}, p2p_factor={pf:g}, p={p}, eps={eps:g}), "
+                        f"{args.ns_slots} slots on their own streams",
+            "value": capacity, "unit": "particle-forces/s", "capacity_seconds": t_cap,
+            "latency_all_queued": serve.latency_summary(reqs), "offered_loads": loads,
+            "errors_vs_gpu_direct": acc_err, "errors_pooled": pooled,
+            "meets_target": bool(pooled["rms"] <= 1e-7)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -518,6 +609,13 @@ def main() -> int:
     ap.add_argument("--serve-load", type=float, default=0.8)
     ap.add_argument("--serve-other-loads", type=lambda s: [float(x) for x in s.split(",") if x],
                     default=[0.5, 0.95])
+    ap.add_argument("--no-north-star", action="store_true")
+    ap.add_argument("--ns-requests", type=int, default=120)
+    ap.add_argument("--ns-slots", type=int, default=3)
+    ap.add_argument("--ns-loads", type=lambda s: [float(x) for x in s.split(",") if x],
+                    default=[0.5, 0.8, 0.95])
+    ap.add_argument("--no-cpu-fmm", action="store_true")
+    ap.add_argument("--cpu-fmm-n", type=int, default=50000)
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="only copy a device buffer of this many MiB three times (the "
                          "reference kernel for scaling HBM byte counters), then exit")
@@ -663,8 +761,11 @@ def main() -> int:
 
     value = n / (ms_per_step * 1e-3)
     mixed = None
+    roofline_fp32 = None
+    tuned_mixed = None
     if not args.no_mixed:
         leaf_m, pf_m, p_m, eps_m, tuned_m = params("mixed")
+        tuned_mixed = (leaf_m, pf_m, p_m, eps_m)
         ctxm = fmm.Context(device=0, leaf_size=leaf_m, p2p_factor=pf_m, timing=True,
                            precision="mixed")
         for _ in range(max(1, args.warmup)):
@@ -690,6 +791,21 @@ def main() -> int:
             mixed["meets_target"] = bool(mixed["errors_vs_gpu_direct_all"]["rms"] <= target_rms)
         ctxm.close()
         print(f"mixed: {ms_m:.2f} ms/step", file=sys.stderr, flush=True)
+        # the mixed-precision kernels against the FP32 peak: algorithmic FLOP
+        # per launch (the same counts as the FP64 kernels) over the HIP-event
+        # duration of the launch
+        pm = stm["p"]
+        f_p2p = stm["n_p2p_pairs"] * P2P_FLOPS
+        f_m2l = stm["n_m2l"] * m2l_flops(pm)
+        roofline_fp32 = {
+            "bound": "alu", "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "k_p2p_mixed": {"ms": stm["t_p2p_kernel"],
+                            "achieved": f_p2p / (stm["t_p2p_kernel"] * 1e-3) / 1e12},
+            "k_m2l32": {"ms": stm["t_m2l_kernel"], "p": pm,
+                        "achieved": f_m2l / (stm["t_m2l_kernel"] * 1e-3) / 1e12}}
+        for k in ("k_p2p_mixed", "k_m2l32"):
+            roofline_fp32[k]["frac"] = roofline_fp32[k]["achieved"] / FP32_PEAK_TFLOPS
+        mixed["roofline_fp32"] = roofline_fp32
     active = None if args.no_active else active_leg(args, fmm, pos, mass,
                                                     (leaf, pf, p_arg, eps), ms_per_step)
     eps_b = None if args.no_eps else eps_leg(args, fmm, pos, mass, (leaf, pf, st["p"], eps),
@@ -702,6 +818,39 @@ def main() -> int:
                    "mixed": batched_leg(args, fmm, workloads, "mixed")}
     c3 = None if args.no_c3 else c3_leg(args, fmm, workloads)
     served = None if args.no_serve else serve_leg(args, fmm, workloads, value)
+    north = None
+    if not args.no_north_star and tuned_mixed is not None:
+        lm, pfm, pm_, em = tuned_mixed
+        north = north_star_leg(args, fmm, workloads,
+                               (lm or 32, pfm or 2.0, pm_ if pm_ > 0 else st["p"], em))
+        north["roofline_fp32"] = roofline_fp32
+        north["vs_plain_fp64"] = north["value"] / value
+        north["vs_gpu_direct"] = north["value"] / direct["value"] if direct else None
+    cpu_fmm = None
+    if not args.no_cpu_fmm:
+        # the CPU oracle's plain FMM (single-threaded recursion, FP64) on a
+        # bounded Plummer sample with the FP64 leg's parameters
+        nf = args.cpu_fmm_n
+        pf_pos, pf_m = workloads.cluster("plummer", nf, args.seed)
+        pp = st["p"]
+        t3 = time.perf_counter()
+        rf = oracle.fmm(pf_pos, pf_m, p=pp, eps=eps, leaf_size=leaf or 32,
+                        p2p_pairs=(pf or 2.0) * (pp + 1) ** 3)
+        t_fmm = time.perf_counter() - t3
+        cpu_fmm = {"value": nf / t_fmm, "unit": "particle-forces/s", "cores": 1,
+                   "kind": "oracle", "seconds": t_fmm,
+                   "sample": f"plain CPU FMM of the oracle on a Plummer sphere N={nf} "
+                             f"(seed {args.seed}), p={pp}, n_L={leaf or 32}, eps={eps:g}, "
+                             f"direct-sum threshold {pf or 2.0:g} (p+1)^3; "
+                             f"{rf['stats']['n_m2l']} M2L pairs, "
+                             f"{rf['stats']['n_p2p_pairs']} direct pairs"}
+        print(f"cpu fmm: {t_fmm:.2f} s for N={nf}", file=sys.stderr, flush=True)
+    tree_bytes = TREE_BYTES_PER_PARTICLE * n
+    tree = {"ms": st["t_tree"], "algorithmic_bytes": tree_bytes,
+            "achieved_GBps": tree_bytes / (st["t_tree"] * 1e-3) / 1e9, "peak_GBps": HBM_PEAK_GBPS,
+            "frac": tree_bytes / (st["t_tree"] * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+            "note": "the whole tree phase (keys, sort, gather, octree levels, geometry, radii) "
+                    "against the traffic of keys, sort and gather alone"}
 
     phases = {k: st[k] for k in ("t_tree", "t_estimate", "t_up", "t_walk", "t_m2l", "t_down",
                                  "t_p2p", "t_total")}
@@ -731,6 +880,10 @@ def main() -> int:
         "direct": direct,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cpu_baseline_fmm": cpu_fmm,
+        "north_star": north,
+        "roofline_fp32": roofline_fp32,
+        "tree": tree,
         "mixed": mixed,
         "active": active,
         "individual_eps": eps_b,
