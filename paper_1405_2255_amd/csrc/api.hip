@@ -130,7 +130,7 @@ struct fmm_ctx {
     DevBuf fa, fb, m2l, m2l2, p2p, p2p2, p2pe, p2pe2, m2l_off, p2p_off, chunks, ccnt, coff, Fpart;
     DevBuf rflag, ranges, rkey, wcode, rup;
     DevBuf pt_n, pt_m, pt_s, pt_off, pt_moff, ptasks, ppart;
-    DevBuf counters, nonfinite, walktmp, coffsets, roots, ckey, ckey2, order, order2;
+    DevBuf counters, nonfinite, walktmp, coffsets, ckey, ckey2, order, order2;
     DevBuf actflag, actf, actinv, actpre, cellact, actbad;   // forces for a listed subset
     DevBuf epsmin;                                           // smallest individual eps
     DevBuf vel4, Md, Fd, jFpart, jo4, jpart;   // jerk: velocities, rates of M and F, M2L
@@ -139,6 +139,7 @@ struct fmm_ctx {
     DevBuf dkey, dsort, dsort2, runstart;   // deep refinement below level 21
     DevBuf plans;                          // output plans of M2M and L2L for order plan_p
     DevBuf Tsh;                            // M2M: each cell's expansion shifted to its parent
+    DevBuf tg, tpre, tsuf, tcell, tcell2, tls;   // tree build: window maxima, cells, levels
     DevBuf M32, sig, Flow;                 // mixed-precision M2L: scaled multipoles, chunk
                                            // scales, FP64 low-degree chunk parts
     DevBuf dspart;                         // exact sums for listed sinks: partial rows
@@ -236,18 +237,13 @@ void build_tree(fmm_ctx *c, int64_t n, const double *pos, const double *mass, in
     } else {
     c->tree_valid = false;
     // cluster offsets and the roots (non-empty clusters) to the device
-    std::vector<int2> roots;
-    for (int k = 0; k < K; ++k)
-        if (off[k + 1] > off[k]) roots.push_back(make_int2((int)off[k], (int)off[k + 1]));
-    const int R = (int)roots.size();
-    char *pin = static_cast<char *>(pinned(c, sizeof(int64_t) * (K + 1) + sizeof(int2) * R));
+    // (the roots, one per non-empty cluster, are the level-0 cells of the build)
+    int R = 0;
+    for (int k = 0; k < K; ++k) R += off[k + 1] > off[k];
+    char *pin = static_cast<char *>(pinned(c, sizeof(int64_t) * (K + 1)));
     std::memcpy(pin, off, sizeof(int64_t) * (K + 1));
-    std::memcpy(pin + sizeof(int64_t) * (K + 1), roots.data(), sizeof(int2) * R);
     int64_t *doff = ensure<int64_t>(c->coffsets, (size_t)K + 1);
-    int2 *droots = ensure<int2>(c->roots, (size_t)R);
     CK(hipMemcpyAsync(doff, pin, sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice, s));
-    CK(hipMemcpyAsync(droots, pin + sizeof(int64_t) * (K + 1), sizeof(int2) * R,
-                      hipMemcpyHostToDevice, s));
     c->nroots = R;
     // keys in each cluster's cube, sort by key and then (stably) by cluster
     unsigned long long *bb = ensure<unsigned long long>(c->bbox, 6 * (size_t)K);
@@ -294,28 +290,39 @@ void build_tree(fmm_ctx *c, int64_t n, const double *pos, const double *mass, in
     c->kdeep = kd;
     c->perm = i1;
     CK(launch_gather(pos, mass, c->perm, n, x, y, z, m, xyzm, s));
-    // octree, level by level, from one root per cluster
-    grow_cells(c, (int)std::min<int64_t>(n + R + 64, 1 << 30), 0);
+    // octree: every cell of every level from the run structure of the keys
+    int *tg = ensure<int>(c->tg, n), *tpre = ensure<int>(c->tpre, n);
+    int *tsuf = ensure<int>(c->tsuf, n);
+    int *tcnt = ensure<int>(c->flags, n + 2);
+    int *total = ptr<int>(c->nonfinite) + 1;
+    CK(launch_tree(k1, kd, n, K, doff, leaf, tg, tpre, tsuf, tcnt, s));
+    CK(exclusive_scan(tcnt, tcnt, n + 1, tmp, total, s));
+    CK(hipMemcpyAsync(c->hint, total, sizeof(int), hipMemcpyDeviceToHost, s));
+    sync(c);
+    const int nc_all = c->hint[0];
+    uint64_t *cl1 = ensure<uint64_t>(c->tcell, nc_all), *cl2 = ensure<uint64_t>(c->tcell2, nc_all);
+    CK(launch_tree_emit(k1, kd, n, K, doff, leaf, tpre, tsuf, tcnt, cl1, s));
+    int *tmp2 = tmp_ints(c, std::max({sort_tmp_ints(n), scan_tmp_ints(n + 1),
+                                      sort_tmp_ints(nc_all)}));
+    CK(radix_sort(&cl1, &cl2, nullptr, nullptr, nc_all, 6, tmp2, s, 32));   // by level, stable
+    int *dls = ensure<int>(c->tls, FMM_MAXLEVEL + 2);
+    CK(launch_tree_levels(cl1, nc_all, dls, s));
+    grow_cells(c, nc_all, 0);
     TreeArrays t = tree_arrays(c);
-    CK(launch_init_roots(t, R, droots, s));
-    c->ls.assign({0, R});
-    int *nch = ensure<int>(c->flags, n + 2);
-    for (int L = 0;; ++L) {
-        const int c0 = c->ls[L], c1 = c->ls[L + 1];
-        if (c1 == c0) break;
-        t = tree_arrays(c);
-        CK(launch_count_children(k1, kd, t, c0, c1, L, leaf, nch, s));
-        CK(hipMemsetAsync(nch + (c1 - c0), 0, sizeof(int), s));
-        int *total = ptr<int>(c->nonfinite) + 1;
-        CK(exclusive_scan(nch, nch, (c1 - c0) + 1, tmp, total, s));
-        CK(hipMemcpyAsync(c->hint, total, sizeof(int), hipMemcpyDeviceToHost, s));
-        sync(c);
-        const int add = c->hint[0];
-        grow_cells(c, c1 + add, c1);
-        t = tree_arrays(c);
-        CK(launch_make_children(k1, kd, t, c0, c1, L, nch, c1, s));
-        c->ls.push_back(c1 + add);
+    CK(launch_tree_cells(k1, kd, n, K, doff, cl1, nc_all, dls, t, s));
+    int hls[FMM_MAXLEVEL + 2];
+    static_assert(sizeof(hls) <= HCNT * sizeof(unsigned long long), "level table mirror");
+    CK(hipMemcpyAsync(c->hcnt, dls, sizeof(hls), hipMemcpyDeviceToHost, s));
+    sync(c);
+    std::memcpy(hls, c->hcnt, sizeof(hls));
+    tmp = tmp2;
+    // ls[L] = first cell of level L up to the deepest level, then ncells twice
+    c->ls.clear();
+    for (int L = 0; L <= FMM_MAXLEVEL + 1; ++L) {
+        c->ls.push_back(hls[L]);
+        if (hls[L] == nc_all) break;
     }
+    c->ls.push_back(nc_all);
     const int ncells = c->ls.back();
     c->ncells = ncells;
     c->depth = (int)c->ls.size() - 3;   // ls ends with two equal entries
@@ -333,7 +340,6 @@ void build_tree(fmm_ctx *c, int64_t n, const double *pos, const double *mass, in
     int *flags = ensure<int>(c->flags, n + 2);
     CK(hipMemsetAsync(flags, 0, sizeof(int) * (n + 1), s));
     CK(launch_leaf_flags(t, ncells, flags, s));
-    int *total = ptr<int>(c->nonfinite) + 1;
     CK(exclusive_scan(flags, flags, n + 1, tmp, total, s));
     CK(hipMemcpyAsync(c->hint, total, sizeof(int), hipMemcpyDeviceToHost, s));
     int *leaf_cell = ensure<int>(c->leaf_cell, ncells);
@@ -936,12 +942,13 @@ void fmm_destroy(fmm_ctx *c) {
                       &c->p2pe2, &c->rflag, &c->ranges, &c->rkey, &c->pt_n, &c->pt_m,
                       &c->pt_s, &c->pt_off, &c->pt_moff, &c->ptasks, &c->ppart, &c->m2l_off,
                       &c->p2p_off, &c->chunks, &c->ccnt, &c->coff, &c->Fpart, &c->counters,
-                      &c->nonfinite, &c->prev_scale, &c->walktmp, &c->coffsets, &c->roots,
+                      &c->nonfinite, &c->prev_scale, &c->walktmp, &c->coffsets,
                       &c->ckey, &c->ckey2, &c->order, &c->order2, &c->wcode, &c->rup,
                       &c->actflag, &c->actf, &c->actinv, &c->actpre, &c->cellact, &c->actbad,
                       &c->dkey, &c->dsort, &c->dsort2, &c->runstart, &c->plans, &c->Tsh,
                       &c->M32, &c->sig, &c->Flow, &c->epsmin, &c->vel4, &c->Md, &c->Fd,
-                      &c->jFpart, &c->jo4, &c->jpart, &c->dspart};
+                      &c->jFpart, &c->jo4, &c->jpart, &c->dspart, &c->tg, &c->tpre, &c->tsuf,
+                      &c->tcell, &c->tcell2, &c->tls};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (auto &e : c->ev) if (e) (void)hipEventDestroy(e);

@@ -67,15 +67,26 @@ hipError_t launch_apply_order2(const uint32_t *order, const uint64_t *key, const
 hipError_t launch_gather(const double *pos, const double *mass, const uint32_t *perm,
                          int64_t n, double *x, double *y, double *z, double *m,
                          double4 *xyzm, hipStream_t s);
-hipError_t launch_init_roots(const TreeArrays &t, int nroots, const int2 *roots, hipStream_t s);
-// children of cells [c0, c1) at one level; *count_out (device) = new cells
-// key: levels 1..21, key2: levels 22..42 (read only below level 21)
-hipError_t launch_count_children(const uint64_t *key, const uint64_t *key2, const TreeArrays &t,
-                                 int c0, int c1, int level, int leaf_size, int *nch,
-                                 hipStream_t s);
-hipError_t launch_make_children(const uint64_t *key, const uint64_t *key2, const TreeArrays &t,
-                                int c0, int c1, int level, const int *child_off, int next0,
-                                hipStream_t s);
+// The octree in one pass over the key-sorted particles (key: levels 1..21,
+// key2: levels 22..42, zero outside refined level-21 cells): g, pre, suf hold
+// n ints of scratch; cnt (n + 1 ints) receives the number of cells whose first
+// particle is each particle (cnt[n] = 0).  After an exclusive scan of cnt,
+// launch_tree_emit writes the cells as (level << 32) | first particle in
+// particle order; stably sorted by level (key bits 32..37) they are numbered
+// level by level and in key order within a level.  launch_tree_levels writes
+// ls[L], L = 0..43, the first cell of each level (ncells past the last), and
+// launch_tree_cells fills begin, end, level, parent, first child and child
+// count of every cell (t sized for ncells).
+hipError_t launch_tree(const uint64_t *key, const uint64_t *key2, int64_t n, int K,
+                       const int64_t *off, int leaf_size, int *g, int *pre, int *suf, int *cnt,
+                       hipStream_t s);
+hipError_t launch_tree_emit(const uint64_t *key, const uint64_t *key2, int64_t n, int K,
+                            const int64_t *off, int leaf_size, const int *pre, const int *suf,
+                            const int *base, uint64_t *cell, hipStream_t s);
+hipError_t launch_tree_levels(const uint64_t *cell, int ncells, int *ls, hipStream_t s);
+hipError_t launch_tree_cells(const uint64_t *key, const uint64_t *key2, int64_t n, int K,
+                             const int64_t *off, const uint64_t *cell, int ncells, const int *ls,
+                             const TreeArrays &t, hipStream_t s);
 hipError_t launch_leaf_flags(const TreeArrays &t, int ncells, int *flags, hipStream_t s);
 hipError_t launch_leaf_ranges(const TreeArrays &t, int ncells, const int *leafscan,
                               int *leaf_cell, int *leaf_of, int64_t n, hipStream_t s);

@@ -242,79 +242,157 @@ __global__ void k_apply_order2(const uint32_t *order, const uint64_t *key, const
     idx_out[i] = idx[j];
 }
 
-// boundaries of the 8 octants at `level + 1` inside the cell's key range
-__device__ void octant_bounds(const uint64_t *key1, const uint64_t *key2, int beg, int end,
-                              int level, int b[9]) {
-    const bool deep = level >= FMM_KEYLEVELS;
-    const uint64_t *key = deep ? key2 : key1;
-    const int shift = 3 * ((deep ? FMM_MAXLEVEL : FMM_KEYLEVELS) - (level + 1));
-    b[0] = beg;
-    b[8] = end;
-#pragma unroll
-    for (int o = 1; o < 8; ++o) {
-        int lo = b[o - 1], hi = end;       // first index with digit >= o
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if ((int)((key[mid] >> shift) & 7u) < o) lo = mid + 1;
-            else hi = mid;
-        }
-        b[o] = lo;
+// ---- the octree from the run structure of the sorted keys -----------------
+// The particles are sorted by (cluster, first key word, second key word), so
+// every cell of the octree is a run of particles with one key prefix: at
+// level L in 1..21 the top L octal digits of the first word, at L in 22..42
+// also the top L - 21 digits of the second word (zero outside level-21 cells
+// holding more than n_L particles, which are the only ones refined further),
+// at level 0 the cluster.  A cell is split when it holds more than n_L
+// particles, so the cell at level L holding particle i exists iff L = 0 or the
+// run at level L - 1 holding i has more than n_L particles.  That run has more
+// than n_L particles iff some window of n_L + 1 consecutive particles
+// containing i shares the prefix of level L - 1, i.e. iff
+//   F(i) = max over j in [i - n_L, i] of g(j) >= L - 1,
+//   g(j) = levels shared by particles j and j + n_L.
+// So particle i lies in cells at levels 0 .. D(i) = min(F(i) + 1, 42) (0 if
+// no window fits), and the cells whose first particle is b are those at the
+// levels from h(b) + 1 to D(b), h(b) = levels shared by b - 1 and b (-1 at the
+// start of a cluster).  Every cell of every level is thus found in one pass
+// over the particles; sorting the cells by level (stable, so key order within
+// a level) numbers them as the level-by-level definition does.
+
+// levels 0..42 on which the cells of particles i and j agree (-1: different
+// clusters); cl holds the cluster of each particle or is null for one cluster
+__device__ __forceinline__ int shared_levels(const uint64_t *key, const uint64_t *key2,
+                                             const int64_t *off, int K, int64_t i, int64_t j) {
+    if (K > 1 && cluster_of(off, K, i) != cluster_of(off, K, j)) return -1;
+    const uint64_t x = key[i] ^ key[j];
+    if (x) return 20 - (63 - __clzll((long long)x)) / 3;
+    const uint64_t x2 = key2[i] ^ key2[j];
+    if (x2) return 41 - (63 - __clzll((long long)x2)) / 3;
+    return FMM_MAXLEVEL;
+}
+
+__global__ void k_tree_window_g(const uint64_t *key, const uint64_t *key2, int64_t n, int K,
+                                const int64_t *off, int leaf_size, int *g) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    g[i] = i + leaf_size < n ? shared_levels(key, key2, off, K, i, i + leaf_size) : -1;
+}
+
+// running maxima of g inside consecutive chunks of w = n_L + 1 entries, from
+// the left (pre) and from the right (suf); the maximum over a window of w
+// entries starting at a is max(suf[a], pre[a + w - 1]) (van Herk / Gil-Werman)
+__global__ void k_tree_window_scan(const int *g, int64_t n, int w, int *pre, int *suf) {
+    const int64_t ch = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t a = ch * w;
+    if (a >= n) return;
+    const int64_t b = min(n, a + w);
+    int m = -1;
+    for (int64_t i = a; i < b; ++i) {
+        m = max(m, g[i]);
+        pre[i] = m;
+    }
+    m = -1;
+    for (int64_t i = b - 1; i >= a; --i) {
+        m = max(m, g[i]);
+        suf[i] = m;
     }
 }
 
-__global__ void k_count_children(const uint64_t *key, const uint64_t *key2, TreeArrays t, int c0,
-                                 int c1, int level, int leaf_size, int *nch) {
-    const int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= c1) return;
-    const int beg = t.beg[c], end = t.end[c];
-    int k = 0;
-    if (end - beg > leaf_size && level < FMM_MAXLEVEL) {
-        int b[9];
-        octant_bounds(key, key2, beg, end, level, b);
-#pragma unroll
-        for (int o = 0; o < 8; ++o) k += b[o + 1] > b[o];
-    }
-    nch[c - c0] = k;
-    t.nchild[c] = k;
+// deepest level of particle i's cells, and the levels it shares with i - 1
+__device__ __forceinline__ void cell_levels(const uint64_t *key, const uint64_t *key2, int64_t n,
+                                            int K, const int64_t *off, int leaf_size,
+                                            const int *pre, const int *suf, int64_t i, int &h,
+                                            int &D) {
+    const int64_t a = i - leaf_size;
+    const int F = a < 0 ? pre[i] : max(suf[a], pre[i]);
+    D = F < 0 ? 0 : min(F + 1, FMM_MAXLEVEL);
+    h = i > 0 ? shared_levels(key, key2, off, K, i - 1, i) : -1;
 }
 
-__global__ void k_make_children(const uint64_t *key, const uint64_t *key2, TreeArrays t, int c0,
-                                int c1, int level, const int *child_off, int next0) {
-    const int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= c1) return;
-    if (t.nchild[c] == 0) {
-        t.child0[c] = -1;
+// cnt[i] = number of cells whose first particle is i; cnt[n] = 0
+__global__ void k_tree_count(const uint64_t *key, const uint64_t *key2, int64_t n, int K,
+                             const int64_t *off, int leaf_size, const int *pre, const int *suf,
+                             int *cnt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    if (i == n) {
+        cnt[n] = 0;
         return;
     }
-    const int first = next0 + child_off[c - c0];
-    t.child0[c] = first;
-    int b[9];
-    octant_bounds(key, key2, t.beg[c], t.end[c], level, b);
-    int k = first;
-#pragma unroll
-    for (int o = 0; o < 8; ++o) {
-        if (b[o + 1] > b[o]) {
-            t.beg[k] = b[o];
-            t.end[k] = b[o + 1];
-            t.parent[k] = c;
-            t.level[k] = level + 1;
-            t.nchild[k] = 0;
-            t.child0[k] = -1;
-            ++k;
-        }
-    }
+    int h, D;
+    cell_levels(key, key2, n, K, off, leaf_size, pre, suf, i, h, D);
+    cnt[i] = max(0, D - h);
 }
 
-// one root per non-empty cluster: particles [rb[r], re[r])
-__global__ void k_init_roots(TreeArrays t, int nroots, const int2 *roots) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nroots) return;
-    t.beg[r] = roots[r].x;
-    t.end[r] = roots[r].y;
-    t.parent[r] = -1;
-    t.level[r] = 0;
-    t.nchild[r] = 0;
-    t.child0[r] = -1;
+// cells in particle order: key (level << 32) | first particle, at the
+// particle's offset from the exclusive scan of the counts
+__global__ void k_tree_emit(const uint64_t *key, const uint64_t *key2, int64_t n, int K,
+                            const int64_t *off, int leaf_size, const int *pre, const int *suf,
+                            const int *base, uint64_t *cell) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c0 = base[i], c1 = base[i + 1];
+    if (c1 == c0) return;
+    int h, D;
+    cell_levels(key, key2, n, K, off, leaf_size, pre, suf, i, h, D);
+    for (int L = h + 1; L <= D; ++L) cell[c0 + (L - h - 1)] = ((uint64_t)L << 32) | (uint64_t)i;
+}
+
+// first cell of each level in the level-sorted cells: ls[L] for L = 0..43
+__global__ void k_tree_levels(const uint64_t *cell, int ncells, int *ls) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > ncells) return;
+    const int L = c < ncells ? (int)(cell[c] >> 32) : FMM_MAXLEVEL + 1;
+    const int Lp = c > 0 ? (int)(cell[c - 1] >> 32) : -1;
+    for (int l = Lp + 1; l <= L; ++l) ls[l] = c;     // levels without cells start here too
+}
+
+// every cell: range, level, parent; links cleared
+__global__ void k_tree_cells(const uint64_t *key, const uint64_t *key2, int64_t n, int K,
+                             const int64_t *off, const uint64_t *cell, int ncells, const int *ls,
+                             TreeArrays t) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncells) return;
+    const int L = (int)(cell[c] >> 32);
+    const int64_t b = (int64_t)(cell[c] & 0xffffffffull);
+    // end: first particle after b that leaves the level-L prefix (the number of
+    // shared levels only falls along the sorted keys)
+    int64_t lo = b + 1, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (shared_levels(key, key2, off, K, b, mid) >= L) lo = mid + 1;
+        else hi = mid;
+    }
+    int parent = -1;
+    if (L > 0) {                      // the last cell of level L - 1 starting at or before b
+        int plo = ls[L - 1], phi = ls[L] - 1;
+        while (plo < phi) {
+            const int mid = (plo + phi + 1) >> 1;
+            if ((int64_t)(cell[mid] & 0xffffffffull) <= b) plo = mid;
+            else phi = mid - 1;
+        }
+        parent = plo;
+    }
+    t.beg[c] = (int)b;
+    t.end[c] = (int)lo;
+    t.level[c] = L;
+    t.parent[c] = parent;
+    t.nchild[c] = 0;
+    t.child0[c] = -1;
+}
+
+// children counted at their parent; the child sharing its parent's first
+// particle is the first child (children are consecutive within their level)
+__global__ void k_tree_links(int ncells, TreeArrays t) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncells) return;
+    const int pc = t.parent[c];
+    if (pc < 0) return;
+    atomicAdd(&t.nchild[pc], 1);
+    if (t.beg[pc] == t.beg[c]) t.child0[pc] = c;
 }
 
 __global__ void k_leaf_flags(TreeArrays t, int ncells, int *flags) {
@@ -538,26 +616,45 @@ hipError_t launch_gather(const double *pos, const double *mass, const uint32_t *
     return hipGetLastError();
 }
 
-hipError_t launch_init_roots(const TreeArrays &t, int nroots, const int2 *roots, hipStream_t s) {
-    hipLaunchKernelGGL(k_init_roots, dim3(blocks(nroots, 256)), dim3(256), 0, s, t, nroots, roots);
+hipError_t launch_tree(const uint64_t *key, const uint64_t *key2, int64_t n, int K,
+                       const int64_t *off, int leaf_size, int *g, int *pre, int *suf, int *cnt,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_tree_window_g, dim3(blocks(n, 256)), dim3(256), 0, s, key, key2, n, K,
+                       off, leaf_size, g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int w = leaf_size + 1;
+    hipLaunchKernelGGL(k_tree_window_scan, dim3(blocks((n + w - 1) / w, 64)), dim3(64), 0, s, g, n,
+                       w, pre, suf);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tree_count, dim3(blocks(n + 1, 256)), dim3(256), 0, s, key, key2, n, K,
+                       off, leaf_size, pre, suf, cnt);
     return hipGetLastError();
 }
 
-hipError_t launch_count_children(const uint64_t *key, const uint64_t *key2, const TreeArrays &t,
-                                 int c0, int c1, int level, int leaf_size, int *nch,
-                                 hipStream_t s) {
-    if (c1 <= c0) return hipSuccess;
-    hipLaunchKernelGGL(k_count_children, dim3(blocks(c1 - c0, 256)), dim3(256), 0, s, key, key2,
-                       t, c0, c1, level, leaf_size, nch);
+hipError_t launch_tree_emit(const uint64_t *key, const uint64_t *key2, int64_t n, int K,
+                            const int64_t *off, int leaf_size, const int *pre, const int *suf,
+                            const int *base, uint64_t *cell, hipStream_t s) {
+    hipLaunchKernelGGL(k_tree_emit, dim3(blocks(n, 256)), dim3(256), 0, s, key, key2, n, K, off,
+                       leaf_size, pre, suf, base, cell);
     return hipGetLastError();
 }
 
-hipError_t launch_make_children(const uint64_t *key, const uint64_t *key2, const TreeArrays &t,
-                                int c0, int c1, int level, const int *child_off, int next0,
-                                hipStream_t s) {
-    if (c1 <= c0) return hipSuccess;
-    hipLaunchKernelGGL(k_make_children, dim3(blocks(c1 - c0, 256)), dim3(256), 0, s, key, key2,
-                       t, c0, c1, level, child_off, next0);
+hipError_t launch_tree_levels(const uint64_t *cell, int ncells, int *ls, hipStream_t s) {
+    hipLaunchKernelGGL(k_tree_levels, dim3(blocks((int64_t)ncells + 1, 256)), dim3(256), 0, s,
+                       cell, ncells, ls);
+    return hipGetLastError();
+}
+
+hipError_t launch_tree_cells(const uint64_t *key, const uint64_t *key2, int64_t n, int K,
+                             const int64_t *off, const uint64_t *cell, int ncells, const int *ls,
+                             const TreeArrays &t, hipStream_t s) {
+    hipLaunchKernelGGL(k_tree_cells, dim3(blocks(ncells, 256)), dim3(256), 0, s, key, key2, n, K,
+                       off, cell, ncells, ls, t);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tree_links, dim3(blocks(ncells, 256)), dim3(256), 0, s, ncells, t);
     return hipGetLastError();
 }
 
