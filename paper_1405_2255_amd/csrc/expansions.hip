@@ -239,19 +239,31 @@ k_m2m_level(int p, TreeArrays t, int c0, int c1, const double *U, double *M, dou
         if (o[q] < 0) continue;
         int n, m;
         nm_of(o[q], n, m);
-        cplx a = {0.0, 0.0};
+        // four partial sums over consecutive terms: independent chains of
+        // multiply-adds instead of one long dependent chain
+        cplx a[4] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
         for (int k = 0; k <= n; ++k) {
             const int nn = n - k;
             const int lmin = max(-k, m - nn), lmax = min(k, m + nn);
             const int bu = k * k + k, bv = nn * nn + nn + m;
-#pragma unroll 4
-            for (int l = lmin; l <= lmax; ++l) {
+            int l = lmin;
+            for (; l + 3 <= lmax; l += 4) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const cplx u = sU[w][bu + l + j], v = sM[w][bv - l - j];
+                    a[j].re = fma(u.re, v.re, fma(-u.im, v.im, a[j].re));
+                    a[j].im = fma(u.re, v.im, fma(u.im, v.re, a[j].im));
+                }
+            }
+            for (; l <= lmax; ++l) {
                 const cplx u = sU[w][bu + l], v = sM[w][bv - l];
-                a.re = fma(u.re, v.re, fma(-u.im, v.im, a.re));
-                a.im = fma(u.re, v.im, fma(u.im, v.re, a.im));
+                a[0].re = fma(u.re, v.re, fma(-u.im, v.im, a[0].re));
+                a[0].im = fma(u.re, v.im, fma(u.im, v.re, a[0].im));
             }
         }
-        Tc[o[q]] = {a.re, m == 0 ? 0.0 : a.im};
+        const double re = (a[0].re + a[1].re) + (a[2].re + a[3].re);
+        const double im = (a[0].im + a[1].im) + (a[2].im + a[3].im);
+        Tc[o[q]] = {re, m == 0 ? 0.0 : im};
     }
 }
 
@@ -309,23 +321,33 @@ k_l2l_level(int p, TreeArrays t, int c0, int c1, const double *U, double *F, con
         if (o[q] < 0) continue;
         int n, m;
         nm_of(o[q], n, m);
-        cplx acc = {0.0, 0.0};
+        // four partial sums over consecutive terms (independent chains)
+        cplx acc[4] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
         for (int k = 0; k <= p - n; ++k) {
             const double sg = (k & 1) ? -1.0 : 1.0;
             const int nk = n + k;
             const int bu = k * k + k, bf = nk * nk + nk + m;
-#pragma unroll 4
-            for (int l = -k; l <= k; ++l) {
+            int l = -k;
+            for (; l + 3 <= k; l += 4) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const cplx u = sU[w][bu + l + j], f = sF[w][bf + l + j];
+                    // conj(sg u) * f
+                    const double ur = sg * u.re, ui = -sg * u.im;
+                    acc[j].re = fma(ur, f.re, fma(-ui, f.im, acc[j].re));
+                    acc[j].im = fma(ur, f.im, fma(ui, f.re, acc[j].im));
+                }
+            }
+            for (; l <= k; ++l) {
                 const cplx u = sU[w][bu + l], f = sF[w][bf + l];
-                // conj(sg u) * f
                 const double ur = sg * u.re, ui = -sg * u.im;
-                acc.re = fma(ur, f.re, fma(-ui, f.im, acc.re));
-                acc.im = fma(ur, f.im, fma(ui, f.re, acc.im));
+                acc[0].re = fma(ur, f.re, fma(-ui, f.im, acc[0].re));
+                acc[0].im = fma(ur, f.im, fma(ui, f.re, acc[0].im));
             }
         }
         cplx &dst = Fc[o[q]];
-        dst.re += acc.re;
-        if (m != 0) dst.im += acc.im;
+        dst.re += (acc[0].re + acc[1].re) + (acc[2].re + acc[3].re);
+        if (m != 0) dst.im += (acc[0].im + acc[1].im) + (acc[2].im + acc[3].im);
     }
 }
 

@@ -234,7 +234,7 @@ hipError_t launch_m2l_rot(int p, int64_t nlist, const uint64_t *list, int sh, co
 // off: ncells + 1 offsets into range (per sink cell).  Planning: per leaf
 // the task counts (ntask, mtask, nsrc_tasks: nleaves + 1 ints each) and their
 // scans task_off, moff; totals[0] = tasks, totals[1] = partial rows.
-#define P2P_TASK 8192
+#define P2P_TASK 2048
 // up[c]: nearest proper ancestor of c with direct-sum ranges (or -1)
 hipError_t launch_range_up(int ncells, const int *parent, const int64_t *off, int *up,
                            hipStream_t s);

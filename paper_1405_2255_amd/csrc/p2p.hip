@@ -7,7 +7,8 @@
 // applies to all particles below it).  A leaf's work is cut into tasks of at
 // most 64 sinks x P2P_TASK sources - a sparse leaf far out in an untruncated
 // halo can be summed against every particle, and as one wavefront's serial
-// loop it would set the kernel time.  One wavefront per task: every lane holds
+// loop it would set the kernel time; short tasks also even out the load of
+// the compute units at the end of a launch.  One wavefront per task: every lane holds
 // two sinks, lanes are (sink group, phase) pairs, the phases stride through
 // each range and are summed through LDS at the end, so small leaves still fill
 // the wavefront and every source load serves two pairs.  A leaf with one task
@@ -190,7 +191,10 @@ k_p2p(int ntasks, const int2 *tasks, const int *leaf_cell, const int *nsrc_tasks
       const int *moff, const int64_t *off, const int2 *range, const int *up, TreeArrays t,
       const double4 *xyzm, double4 *out4, double4 *partial) {
     __shared__ double4 red[4][R * FMM_WAVE];
-    const int task = xcd_block(blockIdx.x, gridDim.x) * 4 + threadIdx.x / FMM_WAVE;
+    // blocks in task order: the hardware deals them to the XCDs in turn, which
+    // spreads the uneven task lengths evenly (a contiguous eighth of the tasks
+    // per XCD left the shorter launches unbalanced)
+    const int task = blockIdx.x * 4 + threadIdx.x / FMM_WAVE;
     if (task >= ntasks) return;
     const int lane = lane_id(), w = threadIdx.x / FMM_WAVE;
     const int2 tk = tasks[task];

@@ -2,7 +2,7 @@
 expansion order 15, leaf size 96, direct-sum threshold 2 (p+1)^3, eps 6e-8,
 on a Plummer sphere of 3e4 particles.  Leaves hold up to 96 particles, so the
 direct-sum kernel cuts a leaf's sinks into two 64-sink chunks, and the mean
-sink has more than 8192 direct sources, so leaves are split into several
+sink has more than 2048 direct sources, so leaves are split into several
 source tasks with ordered partial sums; both are asserted from the tree and
 the counts.  The register M2L kernel of order 15 (FP64 and mixed) and the
 jerk kernels at orders 15, 16 (the wide-column branch of the multipole-rate
@@ -72,7 +72,7 @@ def test_fp64_matches_oracle(gpu_lib, workload, reference):
     # the paths this configuration exercises
     leaves = _leaf_sizes(ctx.export_cells())
     assert len(leaves) == st["n_leaves"] and leaves.max() > 64
-    assert st["n_p2p_pairs"] / N > 8192
+    assert st["n_p2p_pairs"] / N > 2048
     for k in ("n_cells", "n_leaves", "depth", "n_m2l", "n_p2p_pairs"):
         assert st[k] == rs[k], k
     np.testing.assert_allclose(ctx.export_scale(), reference["scale"], rtol=1e-11)
