@@ -166,7 +166,7 @@ def batched_leg(args, fmm, workloads, precision="fp64"):
                  "rms_on_sample": res.rms, "reference_rms_vs_direct": res.ref_rms,
                  "ms_on_sample": res.ms, "tune_s": t_tune}
         print(f"batched ({precision}): tuned {tuned}", file=sys.stderr, flush=True)
-    ctx = fmm.Context(device=0, leaf_size=leaf, p2p_factor=pf, timing=True,
+    ctx = fmm.Context(device=0, centre=args.centre, leaf_size=leaf, p2p_factor=pf, timing=True,
                       precision=precision)
     ctx.forces_batched(off, P, M, 1.0, p, eps, pot, acc)
     torch.cuda.synchronize()
@@ -187,7 +187,7 @@ def batched_leg(args, fmm, workloads, precision="fp64"):
     e = np.concatenate(errs)
     print(f"batched: errors checked on {len(errs)} clusters", file=sys.stderr, flush=True)
     # one call per cluster (after one warm pass that sizes the workspace)
-    single = fmm.Context(device=0, leaf_size=leaf, p2p_factor=pf, precision=precision)
+    single = fmm.Context(device=0, centre=args.centre, leaf_size=leaf, p2p_factor=pf, precision=precision)
     for i in range(k):
         a, b = int(off[i]), int(off[i + 1])
         single.forces(P[a:b], M[a:b], 1.0, p, eps, pot[a:b], acc[a:b])
@@ -224,7 +224,7 @@ def active_leg(args, fmm, pos, mass, params, full_ms):
     import torch
     leaf, pf, p, eps = params
     n = pos.shape[0]
-    full = fmm.Context(device=0, leaf_size=leaf, p2p_factor=pf)
+    full = fmm.Context(device=0, centre=args.centre, leaf_size=leaf, p2p_factor=pf)
     _, acc_full = full.forces(pos, mass, 1.0, p, eps)
     order = torch.argsort(torch.linalg.norm(pos, dim=1))
     rng = np.random.default_rng(args.seed + 9)
@@ -233,7 +233,7 @@ def active_leg(args, fmm, pos, mass, params, full_ms):
         np.sort(rng.choice(n, n // 100, replace=False))).to(pos.device)))
     # reference of the recycled calls: a full call on a recycled tree with the
     # previous call's |a| as the scale
-    prev = fmm.Context(device=0, leaf_size=leaf, p2p_factor=pf, scale_source="previous")
+    prev = fmm.Context(device=0, centre=args.centre, leaf_size=leaf, p2p_factor=pf, scale_source="previous")
     prev.forces(pos, mass, 1.0, p, eps)
     _, acc_prev = prev.forces(pos, mass, 1.0, p, eps, refit=True)
     torch.cuda.synchronize()
@@ -241,7 +241,7 @@ def active_leg(args, fmm, pos, mass, params, full_ms):
     runs = []
     for mode in ("fresh", "recycled"):
         ref = acc_prev if mode == "recycled" else acc_full
-        ctx = fmm.Context(device=0, leaf_size=leaf, p2p_factor=pf, timing=True,
+        ctx = fmm.Context(device=0, centre=args.centre, leaf_size=leaf, p2p_factor=pf, timing=True,
                           scale_source="previous" if mode == "recycled" else "estimate")
         for kind, k, idx in subsets:
             if mode == "recycled":
@@ -284,7 +284,7 @@ def eps_leg(args, fmm, pos, mass, params, full_ms, acc_direct):
     inner = r <= torch.quantile(r[::97], 0.1)
     eps_b = torch.where(inner, torch.tensor(1e-7, dtype=torch.float64, device=pos.device),
                         torch.tensor(1e-5, dtype=torch.float64, device=pos.device)).contiguous()
-    ctx = fmm.Context(device=0, leaf_size=leaf, p2p_factor=pf, timing=True)
+    ctx = fmm.Context(device=0, centre=args.centre, leaf_size=leaf, p2p_factor=pf, timing=True)
     ctx.forces_eps(pos, mass, eps_b, 1.0, p)
     torch.cuda.synchronize()
     ts = []
@@ -323,7 +323,7 @@ def jerk_leg(args, fmm, workloads, pos, mass, params, main_stats):
     _, vel = workloads.plummer(n, args.seed, with_velocities=True)
     V = torch.from_numpy(vel).to(pos.device)
     del vel
-    ctx = fmm.Context(device=0, leaf_size=leaf, p2p_factor=pf, timing=True)
+    ctx = fmm.Context(device=0, centre=args.centre, leaf_size=leaf, p2p_factor=pf, timing=True)
     ctx.forces_jerk(pos, V, mass, 1.0, p, eps)
     torch.cuda.synchronize()
     ts = []
@@ -367,7 +367,7 @@ def c3_leg(args, fmm, workloads):
         del pos, m
         sinks = torch.from_numpy(np.sort(np.random.default_rng(n).choice(n, 4096, replace=False))
                                  ).to(dev)
-        ctx = fmm.Context(device=0, timing=True, precision="mixed")
+        ctx = fmm.Context(device=0, centre=args.centre, timing=True, precision="mixed")
         _, ad = ctx.direct_sinks(P, M, sinks, 1.0)
         for target in (1e-5, 1e-7):
             eps = 0.5 * target
@@ -472,7 +472,7 @@ def serve_leg(args, fmm, workloads, capacity_pfs):
     # accuracy of the last step of every request with N <= 3e5 against the GPU
     # direct sum on the same drifted positions
     checks = []
-    ctx = fmm.Context(device=0)
+    ctx = fmm.Context(device=0, centre=args.centre)
     for i, q in enumerate(reqs):
         if sizes[i] > 300_000:
             continue
@@ -535,7 +535,7 @@ def north_star_leg(args, fmm, workloads, params):
     print(f"north star: {R} requests queued at once in {t_cap:.3f} s, "
           f"{capacity:.4g} particle-forces/s", file=sys.stderr, flush=True)
     # accuracy of the served results of every input against the GPU direct sum
-    ctx = fmm.Context(device=0)
+    ctx = fmm.Context(device=0, centre=args.centre)
     acc_err, pooled = [], []
     for k in range(K):
         _, ad = ctx.direct(inputs[k][0], inputs[k][1], 1.0)
@@ -614,6 +614,8 @@ def main() -> int:
     ap.add_argument("--ns-slots", type=int, default=3)
     ap.add_argument("--ns-loads", type=lambda s: [float(x) for x in s.split(",") if x],
                     default=[0.5, 0.8, 0.95])
+    ap.add_argument("--centre", choices=["auto", "midpoint", "enclosing"], default="auto",
+                    help="expansion-centre rule of every context (Sec. 5.1.1)")
     ap.add_argument("--no-cpu-fmm", action="store_true")
     ap.add_argument("--cpu-fmm-n", type=int, default=50000)
     ap.add_argument("--calib-copy", type=int, default=0,
@@ -681,7 +683,7 @@ def main() -> int:
     mass = torch.from_numpy(m_np).to(dev)
     pot = torch.empty(n, dtype=torch.float64, device=dev)
     acc = torch.empty((n, 3), dtype=torch.float64, device=dev)
-    ctx = fmm.Context(device=0, leaf_size=leaf, p2p_factor=pf, timing=True)
+    ctx = fmm.Context(device=0, centre=args.centre, leaf_size=leaf, p2p_factor=pf, timing=True)
 
     for _ in range(args.warmup):
         ctx.forces(pos, mass, 1.0, p_arg, eps, pot, acc)
@@ -766,7 +768,7 @@ def main() -> int:
     if not args.no_mixed:
         leaf_m, pf_m, p_m, eps_m, tuned_m = params("mixed")
         tuned_mixed = (leaf_m, pf_m, p_m, eps_m)
-        ctxm = fmm.Context(device=0, leaf_size=leaf_m, p2p_factor=pf_m, timing=True,
+        ctxm = fmm.Context(device=0, centre=args.centre, leaf_size=leaf_m, p2p_factor=pf_m, timing=True,
                            precision="mixed")
         for _ in range(max(1, args.warmup)):
             ctxm.forces(pos, mass, 1.0, p_m, eps_m, pot, acc)
@@ -835,7 +837,9 @@ def main() -> int:
         pp = st["p"]
         t3 = time.perf_counter()
         rf = oracle.fmm(pf_pos, pf_m, p=pp, eps=eps, leaf_size=leaf or 32,
-                        p2p_pairs=(pf or 2.0) * (pp + 1) ** 3)
+                        p2p_pairs=(pf or 2.0) * (pp + 1) ** 3,
+                        centre=oracle.CENTRE_MIDPOINT if args.centre == "midpoint"
+                        else oracle.CENTRE_ENCLOSING)
         t_fmm = time.perf_counter() - t3
         cpu_fmm = {"value": nf / t_fmm, "unit": "particle-forces/s", "cores": 1,
                    "kind": "oracle", "seconds": t_fmm,
@@ -872,7 +876,8 @@ def main() -> int:
                                f"eps={eps:g}, p={p}, n_L={leaf or 32}, "
                                f"p2p_factor={pf or 2.0:g}",
                    "n": n, "p": p, "eps": eps, "leaf_size": leaf or 32,
-                   "p2p_factor": pf or 2.0, "parallelism": "single GPU"},
+                   "p2p_factor": pf or 2.0, "centre": args.centre,
+                   "parallelism": "single GPU"},
         "autotune": tuned,
         "errors": {"vs_oracle_sampled": err_oracle, "vs_gpu_direct_all": err_direct,
                    "target_rms": target_rms,

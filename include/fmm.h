@@ -76,6 +76,20 @@ typedef enum {
                              FMM_E_UNSUPPORTED */
 } fmm_m2l_kernel;
 
+/* Expansion centre z = s of every cell (Sec. 5.1.1).  The acceptance test
+ * uses each cell's actual radius about its centre, so the rule changes how
+ * many interactions pass, not the accuracy of those that do. */
+typedef enum {
+    FMM_CENTRE_AUTO = 0,      /* the library's choice (currently FMM_CENTRE_ENCLOSING) */
+    FMM_CENTRE_MIDPOINT = 1,  /* the midpoint of the cell's bounding box */
+    FMM_CENTRE_ENCLOSING = 2  /* an approximation of the centre of the smallest
+                                 sphere enclosing the spheres of the cell's
+                                 grand-daughters (32 core-set steps of Badoiu and
+                                 Clarkson from the midpoint, over the particles at
+                                 a leaf), kept where the cell's radius about it is
+                                 smaller than about the midpoint */
+} fmm_centre;
+
 /* Where min_B{a_b} (or f_b) comes from. */
 typedef enum {
     FMM_SCALE_ESTIMATE = 0, /* low-order FMM estimate (Sec. 5.4.2) inside the call */
@@ -97,6 +111,17 @@ typedef struct {
     int timing;            /* nonzero: record per-phase HIP events (fmm_stats) */
     fmm_precision precision; /* FMM_PREC_FP64 by default (0) */
     fmm_m2l_kernel m2l_kernel; /* FMM_M2L_AUTO by default (0) */
+    fmm_centre centre;     /* FMM_CENTRE_AUTO by default (0) */
+    int64_t n_max;         /* 0: no limit; else a call with more particles (a
+                              batch: in total) fails with FMM_E_INVAL */
+    int p_max;             /* 0: FMM_P_MAX; else 1..FMM_P_MAX, and a call asking
+                              for (or choosing from target_err) a higher order
+                              fails with FMM_E_INVAL */
+    size_t hbm_budget_bytes; /* 0: no limit; else a call whose
+                              fmm_footprint_bytes(n, p, opts) exceeds it fails
+                              with FMM_E_NOMEM before any launch, and fmm_build
+                              fails with FMM_E_NOMEM if the footprint at n_max and
+                              p_max (both set) exceeds it */
 } fmm_opts;
 
 /* Interaction counts and per-phase times of the last fmm_forces call. */
@@ -272,8 +297,11 @@ void fmm_destroy(fmm_ctx *ctx);
  *                    Morton-order particle range of the source cell summed
  *                    directly onto it
  *   FMM_EXPORT_SCALE double per particle (input order): sink scale a_b or f_b used
- *   FMM_EXPORT_CELLS int64 per cell: level << 40 | begin, then end, in cell order */
-enum { FMM_EXPORT_M2L = 1, FMM_EXPORT_P2P = 2, FMM_EXPORT_SCALE = 3, FMM_EXPORT_CELLS = 4 };
+ *   FMM_EXPORT_CELLS int64 per cell: level << 40 | begin, then end, in cell order
+ *   FMM_EXPORT_CENTRES double per cell, cell order: expansion centre x, y, z
+ *                    and the radius rho of the cell's particles about it */
+enum { FMM_EXPORT_M2L = 1, FMM_EXPORT_P2P = 2, FMM_EXPORT_SCALE = 3, FMM_EXPORT_CELLS = 4,
+       FMM_EXPORT_CENTRES = 5 };
 int64_t fmm_export(fmm_ctx *ctx, int what, void *dst, int64_t capacity);
 
 #define FMM_P_MAX 20

@@ -249,6 +249,7 @@ def etilde_factor(rho_zA: float, rho_sB: float) -> float:
 # ---------------------------------------------------------------- plain FMM
 
 MAC_A, MAC_F, MAC_THETA = 0, 1, 2
+CENTRE_MIDPOINT, CENTRE_ENCLOSING = 0, 1
 
 
 class _Params(C.Structure):
@@ -256,7 +257,7 @@ class _Params(C.Structure):
                 ("mac", C.c_int), ("theta_crit", C.c_double), ("p2p_pairs", C.c_double),
                 ("scale_source", C.c_int), ("scale", C.c_void_p), ("G", C.c_double),
                 ("eps_particle", C.c_void_p), ("adaptive_order", C.c_int),
-                ("vel", C.c_void_p), ("jerk", C.c_void_p)]
+                ("vel", C.c_void_p), ("jerk", C.c_void_p), ("centre", C.c_int)]
 
 
 class _Stats(C.Structure):
@@ -268,25 +269,34 @@ class _Stats(C.Structure):
 class _Lists(C.Structure):
     _fields_ = [("m2l", C.c_void_p), ("m2l_cap", C.c_int64), ("m2l_count", C.c_int64),
                 ("p2p", C.c_void_p), ("p2p_cap", C.c_int64), ("p2p_count", C.c_int64),
-                ("scale_est", C.c_void_p)]
+                ("scale_est", C.c_void_p), ("cell_ids", C.c_void_p),
+                ("cell_geo", C.c_void_p), ("cell_cap", C.c_int64), ("cell_count", C.c_int64),
+                ("order", C.c_void_p)]
 
 
 def fmm(pos, mass, *, p: int, eps: float, leaf_size: int, G: float = 1.0,
         mac: int = MAC_A, theta_crit: float = 0.5, p2p_pairs: float = 0.0,
         scale=None, want_lists: bool = False, list_cap: int = 1 << 22, eps_particle=None,
-        adaptive_order: int = 0, vel=None):
+        adaptive_order: int = 0, vel=None, centre: int = CENTRE_ENCLOSING,
+        _cell_cap: int = 0):
     """Plain CPU FMM.  Returns dict with pot, acc, stats and (optionally) the
     interaction lists (arrays of (source id, sink id), id = level<<40 | begin)
     and the per-particle sink scale used by the acceptance test.
     adaptive_order = q_min > 0: each M2L pair at the lowest order in [q_min, p]
     that passes the criterion (Sec. 7); stats["m2l_order_sum"] sums the orders.
-    vel (n, 3): also out["jerk"], the time derivative of acc (Sec. 7, jerk)."""
+    vel (n, 3): also out["jerk"], the time derivative of acc (Sec. 7, jerk).
+    centre: CENTRE_MIDPOINT (box midpoint) or CENTRE_ENCLOSING (approximate
+    smallest-enclosing-sphere centre where it gives the smaller radius,
+    Sec. 5.1.1).  With want_lists, out["cells"] holds per cell (creation order)
+    (id, end), out["cell_geo"] (centre x, y, z, rho, rho about the midpoint)
+    and out["order"] the input index of each Morton position."""
     lib = _load()
     pos = _f64(pos)
     mass = _f64(mass)
     n = mass.shape[0]
     prm = _Params(p, eps, leaf_size, mac, theta_crit, p2p_pairs,
                   1 if scale is not None else 0, None, G, None, int(adaptive_order))
+    prm.centre = int(centre)
     if scale is not None:
         scale = _f64(scale)
         prm.scale = scale.ctypes.data
@@ -311,8 +321,13 @@ def fmm(pos, mass, *, p: int, eps: float, leaf_size: int, G: float = 1.0,
         m2l_buf = np.zeros((list_cap, 2), dtype=np.int64)
         p2p_buf = np.zeros((list_cap, 2), dtype=np.int64)
         sc = np.zeros(n)
+        cell_cap = max(_cell_cap, 2 * n + 64)
+        ids = np.zeros((cell_cap, 2), dtype=np.int64)
+        geo = np.zeros((cell_cap, 5))
+        order = np.zeros(n, dtype=np.int64)
         lists = _Lists(m2l_buf.ctypes.data, list_cap, 0, p2p_buf.ctypes.data, list_cap, 0,
-                       sc.ctypes.data)
+                       sc.ctypes.data, ids.ctypes.data, geo.ctypes.data, cell_cap, 0,
+                       order.ctypes.data)
     rc = lib.or_fmm(C.byref(prm), n, _ptr(pos), _ptr(mass), _ptr(pot), _ptr(acc),
                     C.byref(st), C.byref(lists) if lists is not None else None)
     if rc != 0:
@@ -320,14 +335,19 @@ def fmm(pos, mass, *, p: int, eps: float, leaf_size: int, G: float = 1.0,
     out["pot"], out["acc"] = pot, acc
     out["stats"] = {k: getattr(st, k) for k, _ in _Stats._fields_}
     if want_lists:
-        if lists.m2l_count > list_cap or lists.p2p_count > list_cap:
+        if (lists.m2l_count > list_cap or lists.p2p_count > list_cap
+                or lists.cell_count > cell_cap):
             return fmm(pos, mass, p=p, eps=eps, leaf_size=leaf_size, G=G, mac=mac,
                        theta_crit=theta_crit, p2p_pairs=p2p_pairs, scale=scale,
                        want_lists=True,
-                       list_cap=int(max(lists.m2l_count, lists.p2p_count)) + 1,
-                       eps_particle=eps_particle, adaptive_order=adaptive_order, vel=vel)
+                       list_cap=int(max(list_cap, lists.m2l_count, lists.p2p_count)) + 1,
+                       eps_particle=eps_particle, adaptive_order=adaptive_order, vel=vel,
+                       centre=centre, _cell_cap=int(lists.cell_count))
         out["m2l"] = m2l_buf[: lists.m2l_count].copy()
         out["p2p"] = p2p_buf[: lists.p2p_count].copy()
+        out["cells"] = ids[: lists.cell_count].copy()
+        out["cell_geo"] = geo[: lists.cell_count].copy()
+        out["order"] = order
         out["scale"] = sc
     return out
 

@@ -32,11 +32,13 @@
  * Fdot by M2L of Mdot (same pairs, same order) and L2L, eq:L2P:dot at the
  * particles, and the time derivative of every direct pair.
  *
- * Expansion centre of every cell: z = s = the midpoint of the bounding box of
- * its particles; rho = max distance of its particles from that centre
- * (Sec. 4: rho_z, rho_s definitions).  The paper uses the centre of the
- * smallest enclosing sphere (Sec. 5.1.1); the choice changes the cost of the
- * walk, not its accuracy, because the acceptance test uses the actual radius.
+ * Expansion centre of every cell (z = s): the midpoint of the bounding box of
+ * its particles, or (OR_CENTRE_ENCLOSING) an approximation of the paper's
+ * centre of the smallest sphere enclosing the spheres of the cell's
+ * grand-daughters (Sec. 5.1.1), kept where it gives the smaller radius; rho =
+ * max distance of its particles from that centre (Sec. 4: rho_z, rho_s
+ * definitions).  The choice changes the cost of the walk, not its accuracy,
+ * because the acceptance test uses the actual radius.
  */
 #include "oracle.h"
 
@@ -54,6 +56,8 @@ typedef struct {
     int64_t parent;
     double mass, com[3], rho_com;
     double c[3], rho;
+    double rho_mid;          /* radius about the box midpoint (the default centre) */
+    double bc[3], bR;        /* enclosing-sphere candidate centre and cover radius */
     double smin;
     double complex *M, *F;   /* order p at c */
     double complex *Md, *Fd; /* their time derivatives (jerk only) */
@@ -210,7 +214,160 @@ static void cell_geometry(fmm_t *t, cell_t *C) {
         if (e2 > r2com) r2com = e2;
     }
     C->rho = sqrt(r2max);
+    C->rho_mid = C->rho;
     C->rho_com = sqrt(r2com);
+}
+
+/* ------------------------------------------------- enclosing-sphere centre */
+
+/* Sec. 5.1.1 takes s = z as the centre of the smallest sphere enclosing the
+ * spheres of a cell's grand-daughter cells.  Here that centre is approximated
+ * by the Frank-Wolfe iteration with exact line search for the minimum
+ * enclosing ball (Yildirim 2008, SIAM J. Optim. 19, 1368, Algorithm 1):
+ *   start: a = the point of the set farthest from the box midpoint, b = the
+ *          point farthest from a; c = (a + b)/2, gamma = |a - b|^2/4;
+ *   step:  q = the point farthest from c, D2 = |q - c|^2; stop if gamma <= 0
+ *          or delta = D2/gamma - 1 <= OR_FW_TOL (then the radius about c is
+ *          within sqrt(1 + OR_FW_TOL), 0.1%, of the optimum), else with
+ *          lambda = delta / (2 (1 + delta)) move c += lambda (q - c) and set
+ *          gamma = (1 - lambda) gamma + lambda (1 - lambda) D2;
+ * at most OR_FW_ITERS steps.  gamma is the dual objective, a lower bound of
+ * the squared optimal radius.  The set is, for a leaf, its particles, and for
+ * an internal cell the spheres (b, R) of its grand-daughters, a daughter that
+ * is a leaf standing in for its own daughters.  Particles are compared by
+ * squared distance; "the point farthest from c" of a sphere (x, R) at
+ * distance d = |x - c| is x + (x - c) R/d, at distance d + R (x + (R, 0, 0)
+ * when d = 0), with D2 = (d + R)^2.  Each cell hands its ancestors the sphere
+ * (b, R): b the final c, R the largest distance (d + R) over its set.  Ties in
+ * "farthest" go to the first entry in Morton order, and every operation is a
+ * single rounding in the order written, so the same specification evaluated
+ * elsewhere gives the same bits.  The cell then keeps b if its particles'
+ * radius about b is below that about the midpoint (squared radii compared),
+ * else the midpoint. */
+#ifndef OR_FW_ITERS
+#define OR_FW_ITERS 16
+#endif
+#ifndef OR_FW_TOL
+#define OR_FW_TOL 2e-3
+#endif
+
+typedef struct { double x[3], R; } sphere_t;
+
+static double dist2(const double *a, const double *b) {
+    const double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+    return (dx * dx + dy * dy) + dz * dz;
+}
+
+/* the point q of the set farthest from c (first on ties) and D2 = |q - c|^2.
+ * Particles (R = 0 throughout) are compared by squared distance and q is the
+ * particle itself; spheres by d + R, with D2 = (d + R)^2. */
+static void farthest(const sphere_t *S, int64_t n, int points, const double *c, double *q,
+                     double *D2) {
+    int64_t jmax = 0;
+    if (points) {
+        double best = -1.0;
+        for (int64_t j = 0; j < n; ++j) {
+            const double d2 = dist2(S[j].x, c);
+            if (d2 > best) { best = d2; jmax = j; }
+        }
+        for (int d = 0; d < 3; ++d) q[d] = S[jmax].x[d];
+        *D2 = best;
+        return;
+    }
+    double emax = -1.0, dmax = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        const double d = sqrt(dist2(S[j].x, c));
+        const double e = d + S[j].R;
+        if (e > emax) { emax = e; dmax = d; jmax = j; }
+    }
+    const sphere_t *s = &S[jmax];
+    if (dmax > 0.0) {
+        const double u = s->R / dmax;
+        for (int d = 0; d < 3; ++d) q[d] = s->x[d] + (s->x[d] - c[d]) * u;
+    } else {
+        q[0] = s->x[0] + s->R; q[1] = s->x[1]; q[2] = s->x[2];
+    }
+    *D2 = emax * emax;
+}
+
+/* the iteration over n >= 1 particles or spheres from the midpoint mid;
+ * returns R (the largest distance, or d + R, from the final c), c set */
+static double fw_enclosing(const sphere_t *S, int64_t n, int points, const double *mid,
+                           double *c) {
+    double a[3], b[3], q[3], D2;
+    farthest(S, n, points, mid, a, &D2);
+    farthest(S, n, points, a, b, &D2);
+    for (int d = 0; d < 3; ++d) c[d] = (a[d] + b[d]) * 0.5;
+    double gamma = dist2(a, b) * 0.25;
+    for (int k = 0; k < OR_FW_ITERS; ++k) {
+        farthest(S, n, points, c, q, &D2);
+        if (!(gamma > 0.0)) break;
+        const double delta = D2 / gamma - 1.0;
+        if (!(delta > OR_FW_TOL)) break;
+        const double lambda = delta / (2.0 * (1.0 + delta));
+        for (int d = 0; d < 3; ++d) c[d] = c[d] + lambda * (q[d] - c[d]);
+        const double om = 1.0 - lambda;
+        gamma = om * gamma + (lambda * om) * D2;
+    }
+    if (points) {
+        double m2 = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            const double d2 = dist2(S[j].x, c);
+            if (d2 > m2) m2 = d2;
+        }
+        return sqrt(m2);
+    }
+    double R = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        const double e = sqrt(dist2(S[j].x, c)) + S[j].R;
+        if (e > R) R = e;
+    }
+    return R;
+}
+
+/* candidate (b, R) of cell C from its particles or grand-daughters, then the
+ * choice between b and the midpoint; cells must be visited children first */
+static int cell_enclosing(fmm_t *t, cell_t *C) {
+    int64_t n = 0;
+    sphere_t *S;
+    if (is_leaf(C)) {
+        n = C->end - C->begin;
+        S = (sphere_t *)malloc(sizeof(sphere_t) * (size_t)n);
+        if (!S) return -1;
+        for (int64_t i = 0; i < n; ++i) {
+            for (int d = 0; d < 3; ++d) S[i].x[d] = t->x[3 * (C->begin + i) + d];
+            S[i].R = 0.0;
+        }
+    } else {
+        S = (sphere_t *)malloc(sizeof(sphere_t) * 64);
+        if (!S) return -1;
+        for (int i = 0; i < C->nchild; ++i) {
+            const cell_t *D = &t->cells[C->child[i]];
+            const int nd = is_leaf(D) ? 1 : D->nchild;
+            for (int j = 0; j < nd; ++j) {
+                const cell_t *E = is_leaf(D) ? D : &t->cells[D->child[j]];
+                for (int d = 0; d < 3; ++d) S[n].x[d] = E->bc[d];
+                S[n].R = E->bR;
+                ++n;
+            }
+        }
+    }
+    double c[3];
+    C->bR = fw_enclosing(S, n, is_leaf(C), C->c, c);
+    free(S);
+    for (int d = 0; d < 3; ++d) C->bc[d] = c[d];
+    double r2b = 0.0, r2m = 0.0;
+    for (int64_t i = C->begin; i < C->end; ++i) {
+        const double *x = &t->x[3 * i];
+        const double eb = dist2(x, c), em = dist2(x, C->c);
+        if (eb > r2b) r2b = eb;
+        if (em > r2m) r2m = em;
+    }
+    if (r2b < r2m) {
+        for (int d = 0; d < 3; ++d) C->c[d] = c[d];
+        C->rho = sqrt(r2b);
+    }
+    return 0;
 }
 
 /* ------------------------------------------------------------ direct sums */
@@ -547,6 +704,21 @@ int or_fmm(const or_fmm_params *prm, int64_t n, const double *pos,
         if (C->level > stats->depth) stats->depth = C->level;
     }
     stats->n_cells = t->ncells;
+    if (prm->centre == OR_CENTRE_ENCLOSING)   /* children have larger indices */
+        for (int64_t i = t->ncells - 1; i >= 0; --i)
+            if (cell_enclosing(t, &t->cells[i]) < 0) { release(t); return -2; }
+    if (lists && lists->order)
+        for (int64_t i = 0; i < n; ++i) lists->order[i] = t->orig[i];
+    if (lists && lists->cell_ids) {
+        lists->cell_count = t->ncells;
+        for (int64_t i = 0; i < t->ncells && i < lists->cell_cap; ++i) {
+            const cell_t *C = &t->cells[i];
+            lists->cell_ids[2 * i] = cell_id(C);
+            lists->cell_ids[2 * i + 1] = C->end;
+            double *g = &lists->cell_geo[5 * i];
+            g[0] = C->c[0]; g[1] = C->c[1]; g[2] = C->c[2]; g[3] = C->rho; g[4] = C->rho_mid;
+        }
+    }
     if (prm->vel) {   /* velocities in the final particle order */
         t->v = (double *)malloc(sizeof(double) * 3 * (size_t)n);
         t->jerk = (double *)calloc(3 * (size_t)n, sizeof(double));

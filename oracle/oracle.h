@@ -107,6 +107,7 @@ double or_etilde_factor(double rho_zA, double rho_sB);
 /* ---- the plain FMM (fmm.c) ------------------------------------------ */
 enum { OR_MAC_A = 0, OR_MAC_F = 1, OR_MAC_THETA = 2 };
 enum { OR_SCALE_ESTIMATE = 0, OR_SCALE_GIVEN = 1 };
+enum { OR_CENTRE_MIDPOINT = 0, OR_CENTRE_ENCLOSING = 1 };
 
 typedef struct {
     int p;             /* expansion order, 1..30 */
@@ -132,6 +133,10 @@ typedef struct {
                            Fdot by M2L of Mdot and L2L, eq:L2P:dot at the particles,
                            and the time derivative of the direct sums */
     double *jerk;
+    int centre;         /* OR_CENTRE_MIDPOINT: z = s = the midpoint of the cell's
+                           bounding box; OR_CENTRE_ENCLOSING: an approximation of
+                           the centre of the smallest enclosing sphere (Sec. 5.1.1),
+                           kept where it gives the smaller radius */
 } or_fmm_params;
 
 typedef struct {
@@ -153,6 +158,13 @@ typedef struct {
     int64_t *m2l; int64_t m2l_cap; int64_t m2l_count;
     int64_t *p2p; int64_t p2p_cap; int64_t p2p_count;
     double *scale_est;      /* per particle (input order): the sink scale used */
+    int64_t *cell_ids;      /* NULL, or 2 per cell (creation order, parents
+                               first): its id and its end (Morton order), while
+                               i < cell_cap; cell_count = cells */
+    double *cell_geo;       /* 5 per cell: centre x, y, z, radius rho about it,
+                               radius about the box midpoint */
+    int64_t cell_cap, cell_count;
+    int64_t *order;         /* NULL, or n: input index of Morton position i */
 } or_fmm_lists;
 
 /* pot[i] = physical potential, acc[i*3..] = acceleration of particle i (input

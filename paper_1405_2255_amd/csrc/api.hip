@@ -116,6 +116,11 @@ struct fmm_ctx {
     fmm_opts opts{};
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    // side stream for the enclosing-sphere centres, forked from and joined
+    // back into `stream` by the two events
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool join_pending = false;
     std::atomic<int> busy{0};
     std::string err;
     fmm_stats_t st{};
@@ -125,7 +130,7 @@ struct fmm_ctx {
     uint32_t *perm = nullptr;  // points into idx or idx2
     // cells
     DevBuf beg, end, parent, child0, nchild, level, leaf_lo, leaf_hi, cen, com, mass, lo, hi,
-        rho2, smin, leaf_cell, M, F, P, U, Fe;
+        rho2, bsph, smin, leaf_cell, M, F, P, U, Fe;
     // walk
     DevBuf fa, fb, m2l, m2l2, p2p, p2p2, p2pe, p2pe2, m2l_off, p2p_off, chunks, ccnt, coff, Fpart;
     DevBuf rflag, ranges, rkey, wcode, rup;
@@ -185,6 +190,7 @@ TreeArrays tree_arrays(fmm_ctx *c) {
     t.cen = ptr<double4>(c->cen); t.com = ptr<double4>(c->com); t.mass = ptr<double>(c->mass);
     t.lo = ptr<double>(c->lo); t.hi = ptr<double>(c->hi);
     t.rho2 = ptr<unsigned long long>(c->rho2); t.smin = ptr<double>(c->smin);
+    t.bsph = ptr<double4>(c->bsph);
     return t;
 }
 
@@ -222,9 +228,12 @@ void *pinned(fmm_ctx *c, size_t bytes) {
 // recycling between nearby time steps - and only positions, geometry and
 // radii are refreshed.  The acceptance test uses the true radii, so a
 // recycled tree stays valid; it only gets less efficient as particles drift.
+void join_centres(fmm_ctx *c);
+
 void build_tree(fmm_ctx *c, int64_t n, const double *pos, const double *mass, int K,
                 const int64_t *off, bool refit) {
     hipStream_t s = c->stream;
+    join_centres(c);   // a previous call that ended early may have left side work queued
     const int leaf = c->opts.leaf_size;
     const bool reuse = refit && c->tree_valid && c->tree_n == n &&
                        c->tree_off == std::vector<int64_t>(off, off + K + 1);
@@ -333,7 +342,8 @@ void build_tree(fmm_ctx *c, int64_t n, const double *pos, const double *mass, in
     ensure<int>(c->leaf_lo, ncells); ensure<int>(c->leaf_hi, ncells);
     ensure<double4>(c->cen, ncells); ensure<double4>(c->com, ncells);
     ensure<double>(c->mass, ncells); ensure<double>(c->lo, 3 * (size_t)ncells);
-    ensure<double>(c->hi, 3 * (size_t)ncells); ensure<unsigned long long>(c->rho2, 2 * (size_t)ncells);
+    ensure<double>(c->hi, 3 * (size_t)ncells); ensure<unsigned long long>(c->rho2, 3 * (size_t)ncells);
+    ensure<double4>(c->bsph, ncells);
     ensure<double>(c->smin, ncells);
     t = tree_arrays(c);
     // leaves in key order
@@ -354,11 +364,34 @@ void build_tree(fmm_ctx *c, int64_t n, const double *pos, const double *mass, in
     const int ncells = c->ncells;
     TreeArrays t = tree_arrays(c);
     const int *leaf_of = ptr<int>(c->leaf_of), *leaf_cell = ptr<int>(c->leaf_cell);
-    // geometry bottom up, then the radii of every cell in one pass
+    // geometry bottom up, then the radii about the midpoints and the centres
+    // of mass of every cell in one pass
     for (int L = c->depth; L >= 0; --L)
         CK(launch_geometry_level(t, c->ls[L], c->ls[L + 1], x, y, z, m, s));
-    CK(launch_radii(t, n, leaf_of, leaf_cell, c->depth, x, y, z, s));
+    CK(launch_radii(t, n, leaf_of, leaf_cell, c->depth, x, y, z, false, s));
     CK(launch_radii_finish(t, ncells, s));
+    if (c->opts.centre != FMM_CENTRE_MIDPOINT) {
+        // The enclosing-sphere centres: a chain of small latency-bound
+        // launches, one per level.  They run on the side stream while the
+        // main stream does the sink-scale estimate, which uses only the
+        // centres of mass; join_centres() orders the main stream after them
+        // before anything reads an expansion centre.
+        CK(hipEventRecord(c->ev_fork, s));
+        CK(hipStreamWaitEvent(c->side, c->ev_fork, 0));
+        for (int L = c->depth; L >= 0; --L)
+            CK(launch_enclosing_level(t, c->ls[L], c->ls[L + 1], x, y, z, c->side));
+        CK(launch_radii(t, n, leaf_of, leaf_cell, c->depth, x, y, z, true, c->side));
+        CK(launch_centre_select(t, ncells, c->side));
+        CK(hipEventRecord(c->ev_join, c->side));
+        c->join_pending = true;
+    }
+}
+
+// the main stream waits for the side stream's centres (if any are pending)
+void join_centres(fmm_ctx *c) {
+    if (!c->join_pending) return;
+    CK(hipStreamWaitEvent(c->stream, c->ev_join, 0));
+    c->join_pending = false;
 }
 
 // ------------------------------------------------------------------ walk
@@ -614,6 +647,7 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
     mark(c, PH_TREE);
     const bool want_f = c->opts.mac == FMM_MAC_SCALED;
     if (c->opts.mac != FMM_MAC_THETA) sink_scale(c, want_f, eps_b);
+    join_centres(c);
     mark(c, PH_EST);
     // upward pass
     const int nc = ncplx(p);
@@ -895,6 +929,11 @@ fmm_status fmm_build(fmm_ctx **out, const fmm_opts *o) {
     if (o->m2l_kernel < FMM_M2L_AUTO || o->m2l_kernel > FMM_M2L_ROTATION) return FMM_E_INVAL;
     if (o->scale_source != FMM_SCALE_ESTIMATE && o->scale_source != FMM_SCALE_PREVIOUS)
         return FMM_E_INVAL;
+    if (o->centre < FMM_CENTRE_AUTO || o->centre > FMM_CENTRE_ENCLOSING) return FMM_E_INVAL;
+    if (o->n_max < 0 || o->p_max < 0 || o->p_max > FMM_P_MAX) return FMM_E_INVAL;
+    if (o->hbm_budget_bytes && o->n_max > 0 && o->p_max > 0 &&
+        fmm_footprint_bytes(o->n_max, o->p_max, o) > o->hbm_budget_bytes)
+        return FMM_E_NOMEM;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || o->device < 0 || o->device >= ndev) {
         (void)hipGetLastError();
@@ -912,6 +951,9 @@ fmm_status fmm_build(fmm_ctx **out, const fmm_opts *o) {
             CK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
             c->own_stream = true;
         }
+        CK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+        CK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        CK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
         CK(hipHostMalloc((void **)&c->hcnt, HCNT * sizeof(unsigned long long), hipHostMallocDefault));
         CK(hipHostMalloc((void **)&c->hint, 16 * sizeof(int), hipHostMallocDefault));
         for (auto &e : c->ev) CK(hipEventCreate(&e));
@@ -933,11 +975,12 @@ void fmm_destroy(fmm_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->opts.device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->side) (void)hipStreamSynchronize(c->side);
     DevBuf *bufs[] = {&c->bbox, &c->key, &c->key2, &c->idx, &c->idx2, &c->x, &c->y, &c->z, &c->m,
                       &c->xyzm, &c->leaf_of, &c->out4, &c->est4, &c->scale, &c->flags, &c->tmp,
                       &c->beg, &c->end, &c->parent, &c->child0, &c->nchild, &c->level,
                       &c->leaf_lo, &c->leaf_hi, &c->cen, &c->com, &c->mass, &c->lo, &c->hi,
-                      &c->rho2, &c->smin, &c->leaf_cell, &c->M, &c->F, &c->P, &c->U, &c->Fe,
+                      &c->rho2, &c->bsph, &c->smin, &c->leaf_cell, &c->M, &c->F, &c->P, &c->U, &c->Fe,
                       &c->fa, &c->fb, &c->m2l, &c->m2l2, &c->p2p, &c->p2p2, &c->p2pe,
                       &c->p2pe2, &c->rflag, &c->ranges, &c->rkey, &c->pt_n, &c->pt_m,
                       &c->pt_s, &c->pt_off, &c->pt_moff, &c->ptasks, &c->ppart, &c->m2l_off,
@@ -955,6 +998,9 @@ void fmm_destroy(fmm_ctx *c) {
     for (auto &e : c->ev_m2l) if (e) (void)hipEventDestroy(e);
     for (auto &e : c->ev_p2p) if (e) (void)hipEventDestroy(e);
     for (auto &e : c->ev_walk) if (e) (void)hipEventDestroy(e);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->side) (void)hipStreamDestroy(c->side);
     if (c->hcnt) (void)hipHostFree(c->hcnt);
     if (c->hint) (void)hipHostFree(c->hint);
     if (c->pin) (void)hipHostFree(c->pin);
@@ -979,6 +1025,12 @@ static fmm_status check_common(fmm_ctx *c, int64_t n, const double *pos, const d
     }
     if (*p == 0) return fmm::fail(c, FMM_E_INVAL, "p must be >= 1");
     if (*p > FMM_P_MAX) return fmm::fail(c, FMM_E_UNSUPPORTED, "p above FMM_P_MAX");
+    if (c->opts.n_max > 0 && n > c->opts.n_max)
+        return fmm::fail(c, FMM_E_INVAL, "n above the context's n_max");
+    if (c->opts.p_max > 0 && *p > c->opts.p_max)
+        return fmm::fail(c, FMM_E_INVAL, "p above the context's p_max");
+    if (c->opts.hbm_budget_bytes && fmm_footprint_bytes(n, *p, &c->opts) > c->opts.hbm_budget_bytes)
+        return fmm::fail(c, FMM_E_NOMEM, "footprint above the context's hbm_budget_bytes");
     // the lowest orders whose kernels have a passing device run: FP64 from 3,
     // the mixed-precision M2L from 2
     const int pmin = c->opts.precision == FMM_PREC_MIXED && !jerk ? FMM_P_MIN_MIXED : FMM_P_MIN;
@@ -1424,6 +1476,12 @@ int64_t fmm_export(fmm_ctx *c, int what, void *dst, int64_t capacity) {
                 o[2 * i] = id(i);
                 o[2 * i + 1] = end[i];
             }
+            return bytes;
+        }
+        if (what == FMM_EXPORT_CENTRES) {
+            const int64_t bytes = (int64_t)nc * 32;
+            if (!dst || capacity < bytes) return bytes;
+            if (nc) CK(hipMemcpy(dst, c->cen.p, bytes, hipMemcpyDeviceToHost));
             return bytes;
         }
         return -1;

@@ -47,6 +47,18 @@ __device__ __forceinline__ double ordered_val(unsigned long long k) {
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// ((ax-bx)^2 + (ay-by)^2) + (az-bz)^2 with every operation rounded on its
+// own.  HIP contracts a*b + c into a fused multiply-add by default (and the
+// __dmul_rn / __dadd_rn helpers are plain operators that it contracts too),
+// so contraction is switched off here: the value is the one IEEE double
+// arithmetic gives for this expression on any machine.
+__device__ __forceinline__ double dist2_exact(double ax, double ay, double az, double bx,
+                                              double by, double bz) {
+#pragma clang fp contract(off)
+    const double dx = ax - bx, dy = ay - by, dz = az - bz;
+    return (dx * dx + dy * dy) + dz * dz;
+}
+
 // Inclusive prefix sum over the wavefront (all 64 lanes active).
 __device__ __forceinline__ int wave_incl_scan(int v) {
     const int lane = lane_id();

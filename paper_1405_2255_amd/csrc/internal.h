@@ -35,7 +35,8 @@ struct TreeArrays {
     double4 *com;               // (x, y, z, rho_com): centre of mass, radius about it
     double *mass;
     double *lo, *hi;            // 3 per cell: bounding box of the cell's particles
-    unsigned long long *rho2;   // 2 per cell: atomics scratch for squared radii
+    unsigned long long *rho2;   // 3 per cell: atomics scratch for squared radii
+    double4 *bsph;              // (x, y, z, R): enclosing-sphere candidate and cover radius
     double *smin;               // min over the cell's particles of the sink scale
 };
 
@@ -93,10 +94,19 @@ hipError_t launch_leaf_ranges(const TreeArrays &t, int ncells, const int *leafsc
 hipError_t launch_geometry_level(const TreeArrays &t, int c0, int c1, const double *x,
                                  const double *y, const double *z, const double *m,
                                  hipStream_t s);
+// enclosing-sphere candidates of the cells [c0, c1) of one level (children done)
+hipError_t launch_enclosing_level(const TreeArrays &t, int c0, int c1, const double *x,
+                                  const double *y, const double *z, hipStream_t s);
+// squared radii of every cell: candidate = false about the box midpoint and
+// the centre of mass (rho2 slots 0, 1), true about the enclosing-sphere
+// candidate (slot 2)
 hipError_t launch_radii(const TreeArrays &t, int64_t n, const int *leaf_of,
                         const int *leaf_cell, int maxlevel, const double *x, const double *y,
-                        const double *z, hipStream_t s);
+                        const double *z, bool candidate, hipStream_t s);
+// cen.w and com.w from slots 0, 1
 hipError_t launch_radii_finish(const TreeArrays &t, int ncells, hipStream_t s);
+// the candidate replaces the midpoint where its radius (slot 2) is smaller
+hipError_t launch_centre_select(const TreeArrays &t, int ncells, hipStream_t s);
 hipError_t launch_smin_level(const TreeArrays &t, int c0, int c1, const double *scale,
                              hipStream_t s);
 

@@ -15,9 +15,13 @@
 // level by level, and inside a level in key order.
 //
 // Expansion centre z = s of a cell: the midpoint of its particles' bounding
-// box; rho = the largest distance of its particles from it (the definitions
-// of rho_z and rho_s in Sec. 4).  rho_com likewise about the centre of mass
-// (the centre of the low-order estimate, Sec. 5.4.2).
+// box, or with the enclosing-sphere rule an approximate centre of the
+// smallest enclosing sphere (Sec. 5.1.1) where that gives the smaller radius;
+// rho = the largest distance of its particles from it (the definitions of
+// rho_z and rho_s in Sec. 4).  rho_com likewise about the centre of mass (the
+// centre of the low-order estimate, Sec. 5.4.2).
+#include <climits>
+
 #include "internal.h"
 #include "dev.h"
 
@@ -451,16 +455,16 @@ __global__ void k_geometry_level(TreeArrays t, int c0, int c1, const double *x, 
     t.mass[c] = M;
     t.com[c] = make_double4(sx / M, sy / M, sz / M, 0.0);
     t.cen[c] = make_double4((lo[0] + hi[0]) * 0.5, (lo[1] + hi[1]) * 0.5, (lo[2] + hi[2]) * 0.5, 0.0);
-    t.rho2[2 * c] = 0ull;
-    t.rho2[2 * c + 1] = 0ull;
+    t.rho2[3 * c] = 0ull;
+    t.rho2[3 * c + 1] = 0ull;
+    t.rho2[3 * c + 2] = 0ull;
 }
 
-// Squared distance without contraction into fused multiply-adds, so that the
-// radius of a cell is the same number the definition gives on any machine.
+// Squared distance without fused multiply-adds, so that the radius of a cell
+// is the same number the definition gives on any machine.
 __device__ __forceinline__ double dist2_rn(double ax, double ay, double az, double bx, double by,
                                            double bz) {
-    const double dx = ax - bx, dy = ay - by, dz = az - bz;
-    return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+    return dist2_exact(ax, ay, az, bx, by, bz);
 }
 
 constexpr int RADII_ROWS = 16;   // rows of 64 consecutive particles per wavefront
@@ -471,10 +475,15 @@ constexpr int RADII_ROWS = 16;   // rows of 64 consecutive particles per wavefro
 // distances per cell across the row of 64 lanes (cells are contiguous
 // particle ranges, so equal cells are adjacent lanes), carries the cell that
 // spills into the next row, and commits each cell's maximum with one atomic
-// per wavefront.
+// per wavefront.  CAND = false: squared distances to the box midpoint and the
+// centre of mass, into rho2[3c] and rho2[3c + 1]; CAND = true: to the
+// enclosing-sphere candidate, into rho2[3c + 2].
+template <bool CAND>
 __global__ void __launch_bounds__(256)
 k_radii(TreeArrays t, int64_t n, const int *leaf_of, const int *leaf_cell, int maxlevel,
         const double *x, const double *y, const double *z) {
+    constexpr int NV = CAND ? 1 : 2;
+    constexpr int SLOT = CAND ? 2 : 0;
     const int lane = lane_id();
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / FMM_WAVE;
     const int64_t base = wave * (FMM_WAVE * RADII_ROWS);
@@ -487,29 +496,39 @@ k_radii(TreeArrays t, int64_t n, const int *leaf_of, const int *leaf_cell, int m
     }
     for (int L = maxlevel; L >= 0; --L) {
         int ckey = -1;
-        double cv0 = 0.0, cv1 = 0.0;
+        double cv[NV];
+#pragma unroll
+        for (int u = 0; u < NV; ++u) cv[u] = 0.0;
 #pragma unroll
         for (int j = 0; j < RADII_ROWS; ++j) {
             const int64_t i = base + j * FMM_WAVE + lane;
             int key = -1;
-            double v0 = 0.0, v1 = 0.0;
+            double v[NV];
+#pragma unroll
+            for (int u = 0; u < NV; ++u) v[u] = 0.0;
             if (anc[j] >= 0 && t.level[anc[j]] == L) {
                 key = anc[j];
                 const double px = x[i], py = y[i], pz = z[i];
-                const double4 c = t.cen[key], q = t.com[key];
-                v0 = dist2_rn(px, py, pz, c.x, c.y, c.z);
-                v1 = dist2_rn(px, py, pz, q.x, q.y, q.z);
+                if constexpr (CAND) {
+                    const double4 b = t.bsph[key];
+                    v[0] = dist2_rn(px, py, pz, b.x, b.y, b.z);
+                } else {
+                    const double4 c = t.cen[key], q = t.com[key];
+                    v[0] = dist2_rn(px, py, pz, c.x, c.y, c.z);
+                    v[1] = dist2_rn(px, py, pz, q.x, q.y, q.z);
+                }
                 anc[j] = t.parent[key];
             }
             // segmented maximum towards the first lane of each run of equal keys
 #pragma unroll
             for (int off = 1; off < FMM_WAVE; off <<= 1) {
                 const int ok = __shfl_down(key, off, FMM_WAVE);
-                const double o0 = __shfl_down(v0, off, FMM_WAVE);
-                const double o1 = __shfl_down(v1, off, FMM_WAVE);
+                double o[NV];
+#pragma unroll
+                for (int u = 0; u < NV; ++u) o[u] = __shfl_down(v[u], off, FMM_WAVE);
                 if (lane + off < FMM_WAVE && ok == key) {
-                    v0 = fmax(v0, o0);
-                    v1 = fmax(v1, o1);
+#pragma unroll
+                    for (int u = 0; u < NV; ++u) v[u] = fmax(v[u], o[u]);
                 }
             }
             const int prev = __shfl_up(key, 1, FMM_WAVE);
@@ -519,43 +538,317 @@ k_radii(TreeArrays t, int64_t n, const int *leaf_of, const int *leaf_cell, int m
             // merge or flush the carried run
             if (lane == 0 && ckey >= 0) {
                 if (first == ckey) {
-                    v0 = fmax(v0, cv0);
-                    v1 = fmax(v1, cv1);
+#pragma unroll
+                    for (int u = 0; u < NV; ++u) v[u] = fmax(v[u], cv[u]);
                 } else {
-                    atomicMax(&t.rho2[2 * ckey], dbits(cv0));
-                    atomicMax(&t.rho2[2 * ckey + 1], dbits(cv1));
+#pragma unroll
+                    for (int u = 0; u < NV; ++u) atomicMax(&t.rho2[3 * ckey + SLOT + u], dbits(cv[u]));
                 }
             }
             // the run containing lane 63 may continue into the next row
             const bool open = head && key == last;
             if (head && !open) {
-                atomicMax(&t.rho2[2 * key], dbits(v0));
-                atomicMax(&t.rho2[2 * key + 1], dbits(v1));
+#pragma unroll
+                for (int u = 0; u < NV; ++u) atomicMax(&t.rho2[3 * key + SLOT + u], dbits(v[u]));
             }
             // hand the open run to lane 0 as the new carry
             const unsigned long long om = __ballot(open);
             if (om) {
                 const int src = __ffsll((long long)om) - 1;
-                const double s0 = __shfl(v0, src, FMM_WAVE), s1 = __shfl(v1, src, FMM_WAVE);
+#pragma unroll
+                for (int u = 0; u < NV; ++u) cv[u] = __shfl(v[u], src, FMM_WAVE);
                 ckey = last;
-                cv0 = s0;
-                cv1 = s1;
             } else {
                 ckey = -1;
             }
         }
         if (lane == 0 && ckey >= 0) {
-            atomicMax(&t.rho2[2 * ckey], dbits(cv0));
-            atomicMax(&t.rho2[2 * ckey + 1], dbits(cv1));
+#pragma unroll
+            for (int u = 0; u < NV; ++u) atomicMax(&t.rho2[3 * ckey + SLOT + u], dbits(cv[u]));
         }
     }
 }
 
+// Radii about the midpoint and the centre of mass from the squared maxima.
 __global__ void k_radii_finish(TreeArrays t, int ncells) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncells) return;
-    t.cen[c].w = __dsqrt_rn(bitsd(t.rho2[2 * c]));
-    t.com[c].w = __dsqrt_rn(bitsd(t.rho2[2 * c + 1]));
+    t.cen[c].w = __dsqrt_rn(bitsd(t.rho2[3 * c]));
+    t.com[c].w = __dsqrt_rn(bitsd(t.rho2[3 * c + 1]));
+}
+
+// Each cell takes its enclosing-sphere candidate where the radius about it
+// is strictly smaller than about the midpoint.
+__global__ void k_centre_select(TreeArrays t, int ncells) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncells) return;
+    const double r2b = bitsd(t.rho2[3 * c + 2]);
+    if (r2b < bitsd(t.rho2[3 * c])) {
+        const double4 b = t.bsph[c];
+        t.cen[c] = make_double4(b.x, b.y, b.z, __dsqrt_rn(r2b));
+    }
+}
+
+// ------------------------------------------------- enclosing-sphere centre
+//
+// Sec. 5.1.1 expands about the centre of the smallest sphere enclosing the
+// spheres of a cell's grand-daughters.  That centre is approximated here by
+// the Frank-Wolfe iteration with exact line search for the minimum enclosing
+// ball (Yildirim 2008, SIAM J. Optim. 19, 1368, Algorithm 1): start at the
+// midpoint of a and b, a the point of the set farthest from the box midpoint
+// and b the point farthest from a, with gamma = |a - b|^2 / 4; each step takes
+// the farthest point q (D2 = |q - c|^2), stops when gamma <= 0 or
+// delta = D2 / gamma - 1 <= FW_TOL (the radius about c is then within 0.1% of
+// the optimum, gamma being a lower bound of its square), else moves c by
+// lambda = delta / (2 (1 + delta))
+// of the way to q and sets gamma = (1 - lambda) gamma + lambda (1 - lambda) D2;
+// at most FW_ITERS steps.  The set of a leaf is its particles, compared by
+// squared distance; that of an internal cell the spheres (b, R) of its
+// grand-daughters, where a daughter that is a leaf stands in for its own
+// daughters, compared by d + R (the farthest point of a sphere at distance d
+// from c), with D2 = (d + R)^2.  A cell's sphere is its final c and R, the
+// largest such distance over its set.  Ties in "farthest" go to the first
+// entry in Morton order, and each operation is a single correctly rounded one
+// in a fixed order (contraction into fused multiply-adds is switched off), so
+// the centre is a deterministic function of the particle positions.
+//
+// ENC_G lanes per cell hold the set in registers, ENC_SLOTS entries to a
+// lane (entry i in slot i / ENC_G of lane i % ENC_G), so that a step is
+// arithmetic and lane exchanges only; a leaf with more particles than that
+// reads them from memory at every step.
+constexpr int FW_ITERS = 16;
+constexpr double FW_TOL = 2e-3;   // stop once D2 <= (1 + FW_TOL) gamma
+constexpr int ENC_G = 16;         // one DPP row
+constexpr int ENC_SLOTS = 8;
+constexpr int ENC_REG = ENC_G * ENC_SLOTS;
+
+// Lane exchanges inside a row of 16 lanes by DPP: swap neighbours, swap pairs
+// of a quad, mirror each half-row, mirror the row.  After the four steps of a
+// commutative, associative combine every lane of the row holds the result.
+constexpr int DPP_XOR1 = 0xB1;          // quad_perm [1, 0, 3, 2]
+constexpr int DPP_XOR2 = 0x4E;          // quad_perm [2, 3, 0, 1]
+constexpr int DPP_HALF_MIRROR = 0x141;
+constexpr int DPP_MIRROR = 0x140;
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_int(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_double(double v) {
+    return __hiloint2double(dpp_int<CTRL>(__double2hiint(v)), dpp_int<CTRL>(__double2loint(v)));
+}
+
+template <int CTRL>
+__device__ __forceinline__ void argmax_step(double &e, int &j) {
+    const double oe = dpp_double<CTRL>(e);
+    const int oj = dpp_int<CTRL>(j);
+    if (oe > e || (oe == e && oj < j)) {
+        e = oe;
+        j = oj;
+    }
+}
+
+// largest e over the lane group, ties to the smallest j; every lane ends with it
+__device__ __forceinline__ void group_argmax_first(double &e, int &j) {
+    static_assert(ENC_G == 16, "the DPP steps span one row of 16 lanes");
+    argmax_step<DPP_XOR1>(e, j);
+    argmax_step<DPP_XOR2>(e, j);
+    argmax_step<DPP_HALF_MIRROR>(e, j);
+    argmax_step<DPP_MIRROR>(e, j);
+}
+
+__device__ __forceinline__ double group_max(double v) {
+    v = fmax(v, dpp_double<DPP_XOR1>(v));
+    v = fmax(v, dpp_double<DPP_XOR2>(v));
+    v = fmax(v, dpp_double<DPP_HALF_MIRROR>(v));
+    return fmax(v, dpp_double<DPP_MIRROR>(v));
+}
+
+// cell of entry `item` of the grand-daughter list of internal cell c
+__device__ __forceinline__ int granddaughter(const TreeArrays &t, int c, int item) {
+    const int k0 = t.child0[c], nch = t.nchild[c];
+    for (int k = k0; k < k0 + nch; ++k) {
+        const int nk = t.nchild[k];
+        const int cnt = nk == 0 ? 1 : nk;
+        if (item < cnt) return nk == 0 ? k : t.child0[k] + item;
+        item -= cnt;
+    }
+    return -1;
+}
+
+// One Frank-Wolfe step from (cx, cy, cz) towards q; false if converged.
+__device__ __forceinline__ bool fw_step(double &cx, double &cy, double &cz, double &gamma,
+                                        double qx, double qy, double qz, double D2) {
+#pragma clang fp contract(off)
+    if (!(gamma > 0.0)) return false;
+    const double delta = D2 / gamma - 1.0;
+    if (!(delta > FW_TOL)) return false;
+    const double lambda = delta / (2.0 * (1.0 + delta));
+    cx = cx + lambda * (qx - cx);
+    cy = cy + lambda * (qy - cy);
+    cz = cz + lambda * (qz - cz);
+    const double om = 1.0 - lambda;
+    gamma = om * gamma + (lambda * om) * D2;
+    return true;
+}
+
+// The farthest point q from (px, py, pz) of the set of one cell, held by the
+// lanes of its group, and D2 = |q - p|^2.  points: particles (a leaf),
+// compared by squared distance; else spheres (x, y, z, R), compared by d + R.
+// regs: the entries are in X, Y, Z, R (entry i in slot i / ENC_G of lane
+// i % ENC_G); else a leaf's particles [b, b + n) are read from memory.
+__device__ __forceinline__ double enc_farthest(bool points, bool regs, int n, int sub, int b,
+                                               const double *x, const double *y,
+                                               const double *z, const double (&X)[ENC_SLOTS],
+                                               const double (&Y)[ENC_SLOTS],
+                                               const double (&Z)[ENC_SLOTS],
+                                               const double (&R)[ENC_SLOTS], double px,
+                                               double py, double pz, double &qx, double &qy,
+                                               double &qz) {
+#pragma clang fp contract(off)
+    // each lane's own best entry (the first in its slot order) and its data;
+    // the group's winner is the best of these, sent by the lane that has it
+    double best = -1.0, sx = 0.0, sy = 0.0, sz = 0.0, sr = 0.0;
+    int j = INT_MAX;
+    if (regs) {
+#pragma unroll
+        for (int s = 0; s < ENC_SLOTS; ++s) {
+            const int item = sub + ENC_G * s;
+            if (item < n) {
+                const double d2 = dist2_rn(X[s], Y[s], Z[s], px, py, pz);
+                const double key = points ? d2 : __dsqrt_rn(d2) + R[s];
+                if (key > best) {
+                    best = key;
+                    j = item;
+                    sx = X[s];
+                    sy = Y[s];
+                    sz = Z[s];
+                    sr = R[s];
+                }
+            }
+        }
+    } else {
+        for (int i = sub; i < n; i += ENC_G) {
+            const double d2 = dist2_rn(x[b + i], y[b + i], z[b + i], px, py, pz);
+            if (d2 > best) {
+                best = d2;
+                j = i;
+            }
+        }
+        if (j != INT_MAX) {
+            sx = x[b + j];
+            sy = y[b + j];
+            sz = z[b + j];
+        }
+    }
+    group_argmax_first(best, j);
+    if (j == INT_MAX) j = 0;   // no comparison held (non-finite input): entry 0
+    const int owner = j % ENC_G;
+    if (j == 0 && best < 0.0) {
+        // entry 0 sits in slot 0 of lane 0 (registers) or at b (memory)
+        sx = regs ? X[0] : x[b];
+        sy = regs ? Y[0] : y[b];
+        sz = regs ? Z[0] : z[b];
+        sr = R[0];
+    }
+    sx = __shfl(sx, owner, ENC_G);
+    sy = __shfl(sy, owner, ENC_G);
+    sz = __shfl(sz, owner, ENC_G);
+    if (!points) sr = __shfl(sr, owner, ENC_G);
+    if (points) {
+        qx = sx;
+        qy = sy;
+        qz = sz;
+        return best;
+    }
+    const double d = __dsqrt_rn(dist2_rn(sx, sy, sz, px, py, pz));
+    if (d > 0.0) {
+        const double u = sr / d;
+        qx = sx + (sx - px) * u;
+        qy = sy + (sy - py) * u;
+        qz = sz + (sz - pz) * u;
+    } else {
+        qx = sx + sr;
+        qy = sy;
+        qz = sz;
+    }
+    return best * best;
+}
+
+__global__ void __launch_bounds__(256)
+k_enclosing_level(TreeArrays t, int c0, int c1, const double *x, const double *y,
+                  const double *z) {
+#pragma clang fp contract(off)
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = c0 + (int)(gt / ENC_G);
+    if (c >= c1) return;   // whole lane groups leave together
+    const int sub = (int)(gt % ENC_G);
+    const int nch = t.nchild[c];
+    const bool points = nch == 0;
+    const int b = t.beg[c];
+    int n = 0;
+    if (points) {
+        n = t.end[c] - b;
+    } else {
+        const int k0 = t.child0[c];
+        for (int k = k0; k < k0 + nch; ++k) {
+            const int nk = t.nchild[k];
+            n += nk == 0 ? 1 : nk;
+        }
+    }
+    const bool regs = n <= ENC_REG;
+    double X[ENC_SLOTS], Y[ENC_SLOTS], Z[ENC_SLOTS], R[ENC_SLOTS];
+#pragma unroll
+    for (int s = 0; s < ENC_SLOTS; ++s) {
+        const int item = sub + ENC_G * s;
+        double vx = 0.0, vy = 0.0, vz = 0.0, vr = 0.0;
+        if (regs && item < n) {
+            if (points) {
+                vx = x[b + item];
+                vy = y[b + item];
+                vz = z[b + item];
+            } else {
+                const double4 v = t.bsph[granddaughter(t, c, item)];
+                vx = v.x;
+                vy = v.y;
+                vz = v.z;
+                vr = v.w;
+            }
+        }
+        X[s] = vx;
+        Y[s] = vy;
+        Z[s] = vz;
+        R[s] = vr;
+    }
+    const double4 mid = t.cen[c];
+    double ax, ay, az, bx, by, bz, qx, qy, qz;
+    enc_farthest(points, regs, n, sub, b, x, y, z, X, Y, Z, R, mid.x, mid.y, mid.z, ax, ay, az);
+    enc_farthest(points, regs, n, sub, b, x, y, z, X, Y, Z, R, ax, ay, az, bx, by, bz);
+    double cx = (ax + bx) * 0.5, cy = (ay + by) * 0.5, cz = (az + bz) * 0.5;
+    double gamma = dist2_rn(ax, ay, az, bx, by, bz) * 0.25;
+    for (int k = 0; k < FW_ITERS; ++k) {
+        const double D2 =
+            enc_farthest(points, regs, n, sub, b, x, y, z, X, Y, Z, R, cx, cy, cz, qx, qy, qz);
+        if (!fw_step(cx, cy, cz, gamma, qx, qy, qz, D2)) break;
+    }
+    // the cover radius: largest distance (particles) or d + R (spheres)
+    double m = 0.0;
+    if (regs) {
+#pragma unroll
+        for (int s = 0; s < ENC_SLOTS; ++s)
+            if (sub + ENC_G * s < n) {
+                const double d2 = dist2_rn(X[s], Y[s], Z[s], cx, cy, cz);
+                m = fmax(m, points ? d2 : __dsqrt_rn(d2) + R[s]);
+            }
+    } else {
+        for (int i = sub; i < n; i += ENC_G)
+            m = fmax(m, dist2_rn(x[b + i], y[b + i], z[b + i], cx, cy, cz));
+    }
+    m = group_max(m);
+    const double Rc = points ? __dsqrt_rn(m) : m;
+    if (sub == 0) t.bsph[c] = make_double4(cx, cy, cz, Rc);
 }
 
 __global__ void k_smin_level(TreeArrays t, int c0, int c1, const double *scale) {
@@ -708,17 +1001,34 @@ hipError_t launch_geometry_level(const TreeArrays &t, int c0, int c1, const doub
     return hipGetLastError();
 }
 
+hipError_t launch_enclosing_level(const TreeArrays &t, int c0, int c1, const double *x,
+                                  const double *y, const double *z, hipStream_t s) {
+    if (c1 <= c0) return hipSuccess;
+    hipLaunchKernelGGL(k_enclosing_level, dim3(blocks((int64_t)(c1 - c0) * ENC_G, 256)),
+                       dim3(256), 0, s, t, c0, c1, x, y, z);
+    return hipGetLastError();
+}
+
 hipError_t launch_radii(const TreeArrays &t, int64_t n, const int *leaf_of, const int *leaf_cell,
                         int maxlevel, const double *x, const double *y, const double *z,
-                        hipStream_t s) {
+                        bool candidate, hipStream_t s) {
     const int64_t waves = (n + FMM_WAVE * RADII_ROWS - 1) / (FMM_WAVE * RADII_ROWS);
-    hipLaunchKernelGGL(k_radii, dim3(blocks(waves * FMM_WAVE, 256)), dim3(256), 0, s, t, n,
-                       leaf_of, leaf_cell, maxlevel, x, y, z);
+    if (candidate)
+        hipLaunchKernelGGL(k_radii<true>, dim3(blocks(waves * FMM_WAVE, 256)), dim3(256), 0, s, t,
+                           n, leaf_of, leaf_cell, maxlevel, x, y, z);
+    else
+        hipLaunchKernelGGL(k_radii<false>, dim3(blocks(waves * FMM_WAVE, 256)), dim3(256), 0, s,
+                           t, n, leaf_of, leaf_cell, maxlevel, x, y, z);
     return hipGetLastError();
 }
 
 hipError_t launch_radii_finish(const TreeArrays &t, int ncells, hipStream_t s) {
     hipLaunchKernelGGL(k_radii_finish, dim3(blocks(ncells, 256)), dim3(256), 0, s, t, ncells);
+    return hipGetLastError();
+}
+
+hipError_t launch_centre_select(const TreeArrays &t, int ncells, hipStream_t s) {
+    hipLaunchKernelGGL(k_centre_select, dim3(blocks(ncells, 256)), dim3(256), 0, s, t, ncells);
     return hipGetLastError();
 }
 

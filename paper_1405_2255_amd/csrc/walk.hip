@@ -28,12 +28,10 @@ namespace fmm {
 
 namespace {
 
-// squared distance without fused multiply-adds (the same number as the
-// definition), and its correctly rounded square root
+// distance from the unfused squared distance (the same number as the
+// definition) by the correctly rounded square root
 __device__ __forceinline__ double dist_rn(double4 a, double4 b) {
-    const double dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
-    return __dsqrt_rn(__dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
-                                __dmul_rn(dz, dz)));
+    return __dsqrt_rn(dist2_exact(b.x, b.y, b.z, a.x, a.y, a.z));
 }
 
 // The decision for one cell pair (as the recursive walk would take it).

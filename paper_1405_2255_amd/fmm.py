@@ -30,7 +30,8 @@ MAC_REL, MAC_SCALED, MAC_THETA = 0, 1, 2
 SCALE_ESTIMATE, SCALE_PREVIOUS = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 M2L_AUTO, M2L_DIRECT, M2L_ROTATION = 0, 1, 2
-EXPORT_M2L, EXPORT_P2P, EXPORT_SCALE, EXPORT_CELLS = 1, 2, 3, 4
+CENTRE_AUTO, CENTRE_MIDPOINT, CENTRE_ENCLOSING = 0, 1, 2
+EXPORT_M2L, EXPORT_P2P, EXPORT_SCALE, EXPORT_CELLS, EXPORT_CENTRES = 1, 2, 3, 4, 5
 P_MAX = 20
 P_MIN, P_MIN_MIXED = 3, 2   # lowest accepted orders (FP64 and jerk calls; mixed precision)
 
@@ -49,7 +50,8 @@ class Opts(C.Structure):
     _fields_ = [("device", C.c_int), ("hip_stream", C.c_void_p), ("leaf_size", C.c_int),
                 ("mac", C.c_int), ("theta_crit", C.c_double), ("p2p_factor", C.c_double),
                 ("scale_source", C.c_int), ("timing", C.c_int), ("precision", C.c_int),
-                ("m2l_kernel", C.c_int)]
+                ("m2l_kernel", C.c_int), ("centre", C.c_int), ("n_max", C.c_int64),
+                ("p_max", C.c_int), ("hbm_budget_bytes", C.c_size_t)]
 
 
 class Stats(C.Structure):
@@ -124,7 +126,7 @@ def order_for_error(target_err: float) -> int:
 
 
 def footprint_bytes(n: int, p: int, leaf_size: int = 0) -> int:
-    o = Opts(0, None, leaf_size, 0, 0.0, 0.0, 0, 0, 0, 0)
+    o = Opts(0, None, leaf_size)
     return int(_lib.fmm_footprint_bytes(int(n), int(p), C.byref(o)))
 
 
@@ -143,6 +145,7 @@ _M2L = {"auto": M2L_AUTO, "direct": M2L_DIRECT, "rotation": M2L_ROTATION}
 _MACS = {"a": MAC_REL, "rel": MAC_REL, "f": MAC_SCALED, "scaled": MAC_SCALED,
          "theta": MAC_THETA}
 _SCALES = {"estimate": SCALE_ESTIMATE, "previous": SCALE_PREVIOUS}
+_CENTRES = {"auto": CENTRE_AUTO, "midpoint": CENTRE_MIDPOINT, "enclosing": CENTRE_ENCLOSING}
 
 
 class Context:
@@ -151,7 +154,9 @@ class Context:
     def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None,
                  leaf_size: int = 0, mac: str = "a", theta_crit: float = 0.5,
                  p2p_factor: float = 0.0, scale_source: str = "estimate",
-                 timing: bool = False, precision: str = "fp64", m2l: str = "auto"):
+                 timing: bool = False, precision: str = "fp64", m2l: str = "auto",
+                 centre: str = "auto", n_max: int = 0, p_max: int = 0,
+                 hbm_budget_bytes: int = 0):
         if not torch.cuda.is_available():
             raise RuntimeError("libfmm needs a GPU")
         self.device = int(device)
@@ -159,7 +164,8 @@ class Context:
             self.stream = stream if stream is not None else torch.cuda.current_stream()
         o = Opts(self.device, C.c_void_p(self.stream.cuda_stream), int(leaf_size), _MACS[mac],
                  float(theta_crit), float(p2p_factor), _SCALES[scale_source], int(bool(timing)),
-                 _PRECISIONS[precision], _M2L[m2l])
+                 _PRECISIONS[precision], _M2L[m2l], _CENTRES[centre], int(n_max), int(p_max),
+                 int(hbm_budget_bytes))
         self._opts = o
         h = C.c_void_p()
         st = _lib.fmm_build(C.byref(h), C.byref(o))
@@ -372,3 +378,8 @@ class Context:
         """(id, end) per cell."""
         import numpy as np
         return self._export(EXPORT_CELLS, np.int64).reshape(-1, 2)
+
+    def export_centres(self):
+        """(x, y, z, rho) per cell, cell order: expansion centre and radius."""
+        import numpy as np
+        return self._export(EXPORT_CENTRES, np.float64).reshape(-1, 4)
