@@ -422,7 +422,7 @@ Lists walk(fmm_ctx *c, const WalkParams &wp0, const double *P) {
     int64_t cap_f = std::max<int64_t>({1024, 2 * n, (int64_t)c->nroots, (int64_t)(c->fa.cap / 8)});
     int64_t cap_m = std::max<int64_t>(1024, c->m2l.cap ? (int64_t)(c->m2l.cap / 8) : 8 * n);
     int64_t cap_p = std::max<int64_t>(1024, c->p2p.cap ? (int64_t)(c->p2p.cap / 8) : 4 * n);
-    unsigned long long *cnt = ensure<unsigned long long>(c->counters, 8 + sweeps);
+    unsigned long long *cnt = ensure<unsigned long long>(c->counters, WALK_CUM + 3 * (sweeps + 1));
     unsigned long long *btmp = ensure<unsigned long long>(c->walktmp, walk_tmp_u64());
     const TreeArrays t = tree_arrays(c);
     for (;;) {
@@ -430,7 +430,7 @@ Lists walk(fmm_ctx *c, const WalkParams &wp0, const double *P) {
         uint64_t *ml = ensure<uint64_t>(c->m2l, cap_m), *pl = ensure<uint64_t>(c->p2p, cap_p);
         uint32_t *pe = ensure<uint32_t>(c->p2pe, cap_p);
         uint16_t *code = ensure<uint16_t>(c->wcode, cap_f);
-        CK(hipMemsetAsync(cnt, 0, (8 + sweeps) * sizeof(unsigned long long), s));
+        CK(hipMemsetAsync(cnt, 0, (WALK_CUM + 3 * (sweeps + 1)) * sizeof(unsigned long long), s));
         CK(launch_root_pairs(fa, c->nroots, s));           // (r, r) for every root
         if (c->opts.timing) CK(hipEventRecord(c->ev_walk[0], s));
         // as many sweeps as the last walk of this kind needed (plus one), more

@@ -215,12 +215,18 @@ k_m2m_level(int p, TreeArrays t, int c0, int c1, const double *U, double *M, dou
         nm_of(e, n, m);
         cplx v;
         if (nch > 0) {
+            // the (at most 8) children's terms loaded together, added in order
             v = {0.0, 0.0};
             const int k0 = t.child0[c];
-            for (int ch = k0; ch < k0 + nch; ++ch) {
-                const cplx x = Tb[(size_t)ch * nc + e];
-                v.re += x.re;
-                v.im += x.im;
+            cplx xs[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) xs[j] = Tb[(size_t)(k0 + (j < nch ? j : 0)) * nc + e];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (j < nch) {
+                    v.re += xs[j].re;
+                    v.im += xs[j].im;
+                }
             }
             if (m == 0) v.im = 0.0;
             Mc[e] = v;

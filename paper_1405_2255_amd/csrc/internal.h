@@ -173,12 +173,16 @@ struct WalkBuffers {
     uint64_t *m2l; int64_t cap_m2l;
     uint64_t *p2p; uint32_t *p2p_end; int64_t cap_p2p;   // key, end of the source range
     unsigned long long *counters;   // [0] m2l, [1] direct entries, [2] direct particle
-                                    // pairs, [3] overflow, [4 + i] frontier after sweep i
+                                    // pairs, [3] overflow, [4 + i] frontier after sweep i,
+                                    // [WALK_CUM + 3 i + k] those three totals before sweep i
     uint16_t *code;                 // cap_out: each input pair's decision (count -> write)
 };
 // sweep i reads the frontier size from counters[4 + i - 1] (1 for sweep 0);
 // btmp holds walk_tmp_u64() entries of per-block scratch
 size_t walk_tmp_u64();
+// first of the per-sweep running totals in WalkBuffers::counters, which hold
+// WALK_CUM + 3 (sweeps + 1) entries
+constexpr int WALK_CUM = 4 + 2 * FMM_MAXLEVEL + 4;
 hipError_t launch_root_pairs(uint2 *f, int nroots, hipStream_t s);
 hipError_t launch_walk(const WalkParams &wp, const TreeArrays &t, const double *P,
                        const WalkBuffers &wb, int sweep, unsigned long long *btmp, hipStream_t s);

@@ -43,37 +43,48 @@ __device__ __forceinline__ int first_with_ranges(int c, const int *up, const int
     return off[c + 1] > off[c] ? c : up[c];
 }
 
-// Work of one sink leaf: its direct-sum ranges and those of its ancestors,
-// read as one concatenated list of source particles.
+// Work of one sink leaf: the number of source particles in its direct-sum
+// ranges and those of its ancestors (one concatenated list); every lane of
+// the wavefront ends with it.  Lanes take the range entries in turn.
 __device__ __forceinline__ int64_t leaf_sources(int c, const int *up, const int64_t *off,
                                                 const int2 *range) {
     int64_t s = 0;
     for (int anc = first_with_ranges(c, up, off); anc >= 0; anc = up[anc])
-        for (int64_t r = off[anc]; r < off[anc + 1]; ++r) s += range[r].y - range[r].x;
+        for (int64_t r = off[anc] + lane_id(); r < off[anc + 1]; r += FMM_WAVE)
+            s += range[r].y - range[r].x;
+#pragma unroll
+    for (int o = FMM_WAVE / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, FMM_WAVE);
     return s;
 }
 
-// per leaf: tasks = sink chunks of 64 x source chunks of P2P_TASK sources;
-// mtask = tasks that need a partial-sum row (leaves with more than one task)
-// (active: when not null, leaves whose cell holds no listed sink get no task)
+// per leaf (one wavefront each): tasks = sink chunks of 64 x source chunks of
+// P2P_TASK sources; mtask = tasks that need a partial-sum row (leaves with
+// more than one task) (active: when not null, leaves whose cell holds no
+// listed sink get no task); entry nleaves is zeroed for the scans
 __global__ void k_p2p_count(int nleaves, const int *leaf_cell, const int64_t *off,
                             const int2 *range, const int *up, TreeArrays t,
                             const uint8_t *active, int *ntask, int *mtask, int *nsrc_tasks) {
-    const int leaf = blockIdx.x * blockDim.x + threadIdx.x;
+    const int leaf = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / FMM_WAVE);
     if (leaf > nleaves) return;
+    const bool head = lane_id() == 0;
     if (leaf == nleaves) {
-        ntask[leaf] = 0;
-        mtask[leaf] = 0;
+        if (head) {
+            ntask[leaf] = 0;
+            mtask[leaf] = 0;
+        }
         return;
     }
     const int c = leaf_cell[leaf];
     if (active && !active[c]) {
-        nsrc_tasks[leaf] = 1;
-        ntask[leaf] = 0;
-        mtask[leaf] = 0;
+        if (head) {
+            nsrc_tasks[leaf] = 1;
+            ntask[leaf] = 0;
+            mtask[leaf] = 0;
+        }
         return;
     }
     const int64_t S = leaf_sources(c, up, off, range);
+    if (!head) return;
     const int nsc = (t.end[c] - t.beg[c] + FMM_WAVE - 1) / FMM_WAVE;
     const int nts = (int)max((int64_t)1, (S + P2P_TASK - 1) / P2P_TASK);
     nsrc_tasks[leaf] = nts;
@@ -81,10 +92,12 @@ __global__ void k_p2p_count(int nleaves, const int *leaf_cell, const int64_t *of
     mtask[leaf] = nsc * nts > 1 ? nsc * nts : 0;
 }
 
+// the task list: (leaf, index within the leaf), one wavefront per leaf
 __global__ void k_p2p_tasks(int nleaves, const int *task_off, int2 *tasks) {
-    const int leaf = blockIdx.x * blockDim.x + threadIdx.x;
+    const int leaf = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / FMM_WAVE);
     if (leaf >= nleaves) return;
-    for (int k = task_off[leaf]; k < task_off[leaf + 1]; ++k) tasks[k] = make_int2(leaf, k - task_off[leaf]);
+    const int k0 = task_off[leaf], k1 = task_off[leaf + 1];
+    for (int k = k0 + lane_id(); k < k1; k += FMM_WAVE) tasks[k] = make_int2(leaf, k - k0);
 }
 
 template <int WANT_F, int WITH_POT>
@@ -290,9 +303,18 @@ __global__ void k_p2p_reduce(int64_t n, const int *leaf_of, const int *leaf_cell
     const int k = (int)(i - t.beg[c]);
     const int sc = k / FMM_WAVE, slot = k % FMM_WAVE, nts = nsrc_tasks[leaf];
     double4 v = out4[i];
-    for (int ts = 0; ts < nts; ++ts) {
-        const double4 q = partial[((int64_t)moff[leaf] + sc * nts + ts) * FMM_WAVE + slot];
-        v.x += q.x; v.y += q.y; v.z += q.z; v.w += q.w;
+    const double4 *row = partial + ((int64_t)moff[leaf] + sc * nts) * FMM_WAVE + slot;
+    // eight rows' loads in flight at a time, added in task order
+    for (int t0 = 0; t0 < nts; t0 += 8) {
+        double4 q[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) q[j] = row[(int64_t)min(t0 + j, nts - 1) * FMM_WAVE];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (t0 + j < nts) {
+                v.x += q[j].x; v.y += q[j].y; v.z += q[j].z; v.w += q[j].w;
+            }
+        }
     }
     out4[i] = v;
 }
@@ -514,8 +536,9 @@ hipError_t launch_p2p_plan(int nleaves, const int *leaf_cell, const int64_t *off
                            const int2 *range, const int *up, const TreeArrays &t,
                            const uint8_t *active, int *ntask, int *mtask, int *nsrc_tasks,
                            int *task_off, int *moff, int *tmp, int *totals, hipStream_t s) {
-    hipLaunchKernelGGL(k_p2p_count, dim3(blocks(nleaves + 1, 256)), dim3(256), 0, s, nleaves,
-                       leaf_cell, off, range, up, t, active, ntask, mtask, nsrc_tasks);
+    hipLaunchKernelGGL(k_p2p_count, dim3(blocks((int64_t)(nleaves + 1) * FMM_WAVE, 256)),
+                       dim3(256), 0, s, nleaves, leaf_cell, off, range, up, t, active, ntask,
+                       mtask, nsrc_tasks);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = exclusive_scan(ntask, task_off, nleaves + 1, tmp, totals, s);
@@ -524,8 +547,8 @@ hipError_t launch_p2p_plan(int nleaves, const int *leaf_cell, const int64_t *off
 }
 
 hipError_t launch_p2p_tasks(int nleaves, const int *task_off, int2 *tasks, hipStream_t s) {
-    hipLaunchKernelGGL(k_p2p_tasks, dim3(blocks(nleaves, 256)), dim3(256), 0, s, nleaves,
-                       task_off, tasks);
+    hipLaunchKernelGGL(k_p2p_tasks, dim3(blocks((int64_t)nleaves * FMM_WAVE, 256)), dim3(256), 0,
+                       s, nleaves, task_off, tasks);
     return hipGetLastError();
 }
 

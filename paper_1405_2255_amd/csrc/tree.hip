@@ -41,10 +41,10 @@ __device__ __forceinline__ int cluster_of(const int64_t *off, int K, int64_t i) 
 }
 
 // bounding box of every cluster: bb[6k..6k+5] = min x, y, z, max x, y, z as
-// order-preserving keys.  A wavefront keeps the box of its current cluster
-// over its chunks of the grid-stride loop and commits it (6 atomics) only when
-// the cluster changes and at the end; a chunk that spans clusters commits
-// per lane.
+// order-preserving keys.  Each lane keeps the box of the wavefront's current
+// cluster over the chunks of its grid-stride loop; the wavefront reduces the
+// lanes' boxes and commits them (6 atomics) only when its cluster changes and
+// at the end.  A chunk that spans clusters commits per lane.
 __device__ __forceinline__ void commit_box(unsigned long long *bb, int c, const double *lo,
                                            const double *hi) {
 #pragma unroll
@@ -54,55 +54,57 @@ __device__ __forceinline__ void commit_box(unsigned long long *bb, int c, const 
     }
 }
 
+__device__ __forceinline__ void commit_run(unsigned long long *bb, int run, double *lo,
+                                           double *hi) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+#pragma unroll
+        for (int o = FMM_WAVE / 2; o > 0; o >>= 1) {
+            lo[d] = fmin(lo[d], __shfl_xor(lo[d], o, FMM_WAVE));
+            hi[d] = fmax(hi[d], __shfl_xor(hi[d], o, FMM_WAVE));
+        }
+    }
+    if (lane_id() == 0) commit_box(bb, run, lo, hi);
+}
+
 __global__ void k_bbox(const double *pos, int64_t n, int K, const int64_t *off,
                        unsigned long long *bb) {
     const int lane = lane_id();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    int run = -1;
+    int run = -1;   // the wavefront's current cluster
     double rlo[3] = {INFINITY, INFINITY, INFINITY}, rhi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(FMM_WAVE - 1));
          base < n; base += stride) {
         const int64_t i = base + lane;
         const bool valid = i < n;
         const int cl = valid ? cluster_of(off, K, i) : -1;
-        double lo[3], hi[3];
+        double v[3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const double v = valid ? pos[3 * i + d] : 0.0;
-            lo[d] = valid ? v : INFINITY;
-            hi[d] = valid ? v : -INFINITY;
-        }
+        for (int d = 0; d < 3; ++d) v[d] = valid ? pos[3 * i + d] : 0.0;
         const int c0 = __shfl(cl, 0, FMM_WAVE);
         const bool uniform = __ballot(valid && cl != c0) == 0ull;
         if (uniform) {
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-#pragma unroll
-                for (int o = FMM_WAVE / 2; o > 0; o >>= 1) {
-                    lo[d] = fmin(lo[d], __shfl_xor(lo[d], o, FMM_WAVE));
-                    hi[d] = fmax(hi[d], __shfl_xor(hi[d], o, FMM_WAVE));
-                }
-            }
             if (c0 != run) {
-                if (run >= 0 && lane == 0) commit_box(bb, run, rlo, rhi);
+                if (run >= 0) commit_run(bb, run, rlo, rhi);
                 run = c0;
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    rlo[d] = lo[d];
-                    rhi[d] = hi[d];
+                    rlo[d] = INFINITY;
+                    rhi[d] = -INFINITY;
                 }
-            } else {
+            }
+            if (valid) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    rlo[d] = fmin(rlo[d], lo[d]);
-                    rhi[d] = fmax(rhi[d], hi[d]);
+                    rlo[d] = fmin(rlo[d], v[d]);
+                    rhi[d] = fmax(rhi[d], v[d]);
                 }
             }
         } else if (valid) {
-            commit_box(bb, cl, lo, hi);
+            commit_box(bb, cl, v, v);
         }
     }
-    if (run >= 0 && lane == 0) commit_box(bb, run, rlo, rhi);
+    if (run >= 0) commit_run(bb, run, rlo, rhi);
 }
 
 __global__ void k_bbox_init(int K, unsigned long long *bb) {
@@ -427,7 +429,9 @@ __global__ void k_geometry_level(TreeArrays t, int c0, int c1, const double *x, 
     double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
     const int nch = t.nchild[c];
     if (nch == 0) {
-        for (int i = t.beg[c]; i < t.end[c]; ++i) {
+        const int e = t.end[c];
+#pragma unroll 8
+        for (int i = t.beg[c]; i < e; ++i) {
             const double a = x[i], b = y[i], d = z[i], w = m[i];
             lo[0] = fmin(lo[0], a); hi[0] = fmax(hi[0], a);
             lo[1] = fmin(lo[1], b); hi[1] = fmax(hi[1], b);
@@ -435,16 +439,33 @@ __global__ void k_geometry_level(TreeArrays t, int c0, int c1, const double *x, 
             M += w; sx = fma(w, a, sx); sy = fma(w, b, sy); sz = fma(w, d, sz);
         }
     } else {
-        const int c0_ = t.child0[c];
-        for (int k = c0_; k < c0_ + nch; ++k) {
+        // the loads of all (at most 8) children first, so that they are in
+        // flight together; a missing child reads the first one and is skipped
+        const int k0 = t.child0[c];
+        double clo[8][3], chi[8][3], cw[8];
+        double4 cq[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = k0 + (j < nch ? j : 0);
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                lo[d] = fmin(lo[d], t.lo[3 * k + d]);
-                hi[d] = fmax(hi[d], t.hi[3 * k + d]);
+                clo[j][d] = t.lo[3 * k + d];
+                chi[j][d] = t.hi[3 * k + d];
             }
-            const double w = t.mass[k];
-            const double4 q = t.com[k];
-            M += w; sx = fma(w, q.x, sx); sy = fma(w, q.y, sy); sz = fma(w, q.z, sz);
+            cw[j] = t.mass[k];
+            cq[j] = t.com[k];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (j < nch) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    lo[d] = fmin(lo[d], clo[j][d]);
+                    hi[d] = fmax(hi[d], chi[j][d]);
+                }
+                const double w = cw[j];
+                M += w; sx = fma(w, cq[j].x, sx); sy = fma(w, cq[j].y, sy); sz = fma(w, cq[j].z, sz);
+            }
         }
     }
 #pragma unroll
@@ -467,14 +488,26 @@ __device__ __forceinline__ double dist2_rn(double ax, double ay, double az, doub
     return dist2_exact(ax, ay, az, bx, by, bz);
 }
 
-constexpr int RADII_ROWS = 16;   // rows of 64 consecutive particles per wavefront
+constexpr int RADII_ROWS = 4;   // rows of 64 consecutive particles per wavefront
+
+// atomicMax that first reads the current value and skips the atomic when it
+// cannot raise it: the top cells get one commit per wavefront, and most of
+// those atomics on a few addresses are needless once the maximum is in place.
+// A stale read is never above the current value, so nothing needed is
+// skipped.
+__device__ __forceinline__ void max_commit(unsigned long long *a, double v) {
+    const unsigned long long b = dbits(v);
+    if (b > __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(a, b);
+}
 
 // Radii of every cell at every level in one pass over the particles.  Each
-// wavefront owns 64*16 consecutive particles; it walks each particle's
-// ancestor chain level by level (deepest first), reduces the squared
-// distances per cell across the row of 64 lanes (cells are contiguous
-// particle ranges, so equal cells are adjacent lanes), carries the cell that
-// spills into the next row, and commits each cell's maximum with one atomic
+// wavefront owns 64 * RADII_ROWS consecutive particles, holds their positions
+// and their current ancestors (with the ancestors' levels: a parent is one
+// level up), and goes up the tree level by level (deepest first): the centre
+// loads of all rows are issued together, then per row the squared distances
+// are reduced per cell across the 64 lanes (cells are contiguous particle
+// ranges, so equal cells are adjacent lanes), the cell that spills into the
+// next row is carried, and each cell's maximum is committed with one atomic
 // per wavefront.  CAND = false: squared distances to the box midpoint and the
 // centre of mass, into rho2[3c] and rho2[3c + 1]; CAND = true: to the
 // enclosing-sphere candidate, into rho2[3c + 2].
@@ -488,75 +521,92 @@ k_radii(TreeArrays t, int64_t n, const int *leaf_of, const int *leaf_cell, int m
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / FMM_WAVE;
     const int64_t base = wave * (FMM_WAVE * RADII_ROWS);
     if (base >= n) return;
-    int anc[RADII_ROWS];
+    int anc[RADII_ROWS], alev[RADII_ROWS];
+    double px[RADII_ROWS], py[RADII_ROWS], pz[RADII_ROWS];
 #pragma unroll
     for (int j = 0; j < RADII_ROWS; ++j) {
         const int64_t i = base + j * FMM_WAVE + lane;
         anc[j] = i < n ? leaf_cell[leaf_of[i]] : -1;
+        px[j] = i < n ? x[i] : 0.0;
+        py[j] = i < n ? y[i] : 0.0;
+        pz[j] = i < n ? z[i] : 0.0;
     }
+#pragma unroll
+    for (int j = 0; j < RADII_ROWS; ++j) alev[j] = anc[j] >= 0 ? t.level[anc[j]] : -1;
     for (int L = maxlevel; L >= 0; --L) {
+        // this level's cell of every row, its squared distances, the next
+        // ancestor; the loads are unconditional (cell 0 stands in for a row
+        // with no cell at this level) so that all rows' loads are in flight
+        // together
+        int key[RADII_ROWS], par[RADII_ROWS];
+        double4 ca[RADII_ROWS], cb[RADII_ROWS];
+#pragma unroll
+        for (int j = 0; j < RADII_ROWS; ++j) {
+            key[j] = alev[j] == L ? anc[j] : -1;
+            const int kk = key[j] >= 0 ? key[j] : 0;
+            par[j] = t.parent[kk];
+            if constexpr (CAND) {
+                ca[j] = t.bsph[kk];
+            } else {
+                ca[j] = t.cen[kk];
+                cb[j] = t.com[kk];
+            }
+        }
+        double v[RADII_ROWS][NV];
+#pragma unroll
+        for (int j = 0; j < RADII_ROWS; ++j) {
+            const bool has = key[j] >= 0;
+            v[j][0] = has ? dist2_rn(px[j], py[j], pz[j], ca[j].x, ca[j].y, ca[j].z) : 0.0;
+            if constexpr (!CAND)
+                v[j][1] = has ? dist2_rn(px[j], py[j], pz[j], cb[j].x, cb[j].y, cb[j].z) : 0.0;
+            anc[j] = has ? par[j] : anc[j];
+            alev[j] = has ? L - 1 : alev[j];
+        }
         int ckey = -1;
         double cv[NV];
 #pragma unroll
         for (int u = 0; u < NV; ++u) cv[u] = 0.0;
 #pragma unroll
         for (int j = 0; j < RADII_ROWS; ++j) {
-            const int64_t i = base + j * FMM_WAVE + lane;
-            int key = -1;
-            double v[NV];
-#pragma unroll
-            for (int u = 0; u < NV; ++u) v[u] = 0.0;
-            if (anc[j] >= 0 && t.level[anc[j]] == L) {
-                key = anc[j];
-                const double px = x[i], py = y[i], pz = z[i];
-                if constexpr (CAND) {
-                    const double4 b = t.bsph[key];
-                    v[0] = dist2_rn(px, py, pz, b.x, b.y, b.z);
-                } else {
-                    const double4 c = t.cen[key], q = t.com[key];
-                    v[0] = dist2_rn(px, py, pz, c.x, c.y, c.z);
-                    v[1] = dist2_rn(px, py, pz, q.x, q.y, q.z);
-                }
-                anc[j] = t.parent[key];
-            }
+            const int kj = key[j];
             // segmented maximum towards the first lane of each run of equal keys
 #pragma unroll
             for (int off = 1; off < FMM_WAVE; off <<= 1) {
-                const int ok = __shfl_down(key, off, FMM_WAVE);
+                const int ok = __shfl_down(kj, off, FMM_WAVE);
                 double o[NV];
 #pragma unroll
-                for (int u = 0; u < NV; ++u) o[u] = __shfl_down(v[u], off, FMM_WAVE);
-                if (lane + off < FMM_WAVE && ok == key) {
+                for (int u = 0; u < NV; ++u) o[u] = __shfl_down(v[j][u], off, FMM_WAVE);
+                if (lane + off < FMM_WAVE && ok == kj) {
 #pragma unroll
-                    for (int u = 0; u < NV; ++u) v[u] = fmax(v[u], o[u]);
+                    for (int u = 0; u < NV; ++u) v[j][u] = fmax(v[j][u], o[u]);
                 }
             }
-            const int prev = __shfl_up(key, 1, FMM_WAVE);
-            const bool head = key >= 0 && (lane == 0 || prev != key);
-            const int last = __shfl(key, FMM_WAVE - 1, FMM_WAVE);
-            const int first = __shfl(key, 0, FMM_WAVE);
+            const int prev = __shfl_up(kj, 1, FMM_WAVE);
+            const bool head = kj >= 0 && (lane == 0 || prev != kj);
+            const int last = __shfl(kj, FMM_WAVE - 1, FMM_WAVE);
+            const int first = __shfl(kj, 0, FMM_WAVE);
             // merge or flush the carried run
             if (lane == 0 && ckey >= 0) {
                 if (first == ckey) {
 #pragma unroll
-                    for (int u = 0; u < NV; ++u) v[u] = fmax(v[u], cv[u]);
+                    for (int u = 0; u < NV; ++u) v[j][u] = fmax(v[j][u], cv[u]);
                 } else {
 #pragma unroll
-                    for (int u = 0; u < NV; ++u) atomicMax(&t.rho2[3 * ckey + SLOT + u], dbits(cv[u]));
+                    for (int u = 0; u < NV; ++u) max_commit(&t.rho2[3 * ckey + SLOT + u], cv[u]);
                 }
             }
             // the run containing lane 63 may continue into the next row
-            const bool open = head && key == last;
+            const bool open = head && kj == last;
             if (head && !open) {
 #pragma unroll
-                for (int u = 0; u < NV; ++u) atomicMax(&t.rho2[3 * key + SLOT + u], dbits(v[u]));
+                for (int u = 0; u < NV; ++u) max_commit(&t.rho2[3 * kj + SLOT + u], v[j][u]);
             }
             // hand the open run to lane 0 as the new carry
             const unsigned long long om = __ballot(open);
             if (om) {
                 const int src = __ffsll((long long)om) - 1;
 #pragma unroll
-                for (int u = 0; u < NV; ++u) cv[u] = __shfl(v[u], src, FMM_WAVE);
+                for (int u = 0; u < NV; ++u) cv[u] = __shfl(v[j][u], src, FMM_WAVE);
                 ckey = last;
             } else {
                 ckey = -1;
@@ -564,7 +614,7 @@ k_radii(TreeArrays t, int64_t n, const int *leaf_of, const int *leaf_cell, int m
         }
         if (lane == 0 && ckey >= 0) {
 #pragma unroll
-            for (int u = 0; u < NV; ++u) atomicMax(&t.rho2[3 * ckey + SLOT + u], dbits(cv[u]));
+            for (int u = 0; u < NV; ++u) max_commit(&t.rho2[3 * ckey + SLOT + u], cv[u]);
         }
     }
 }
@@ -857,10 +907,17 @@ __global__ void k_smin_level(TreeArrays t, int c0, int c1, const double *scale) 
     double s = INFINITY;
     const int nch = t.nchild[c];
     if (nch == 0) {
-        for (int i = t.beg[c]; i < t.end[c]; ++i) s = fmin(s, scale[i]);
+        const int e = t.end[c];
+#pragma unroll 8
+        for (int i = t.beg[c]; i < e; ++i) s = fmin(s, scale[i]);
     } else {
+        // all children's loads in flight together (a missing child re-reads the first)
         const int k0 = t.child0[c];
-        for (int k = k0; k < k0 + nch; ++k) s = fmin(s, t.smin[k]);
+        double v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = t.smin[k0 + (j < nch ? j : 0)];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s = fmin(s, v[j]);
     }
     t.smin[c] = s;
 }

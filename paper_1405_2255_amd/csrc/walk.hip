@@ -93,9 +93,10 @@ __device__ __forceinline__ Decision decide(const WalkParams &wp, const TreeArray
 }
 
 // Sweeps run without host round trips: sweep i reads its frontier size from
-// counters[4 + i - 1].  Each sweep is three launches over a fixed grid of
+// counters[4 + i - 1].  Each sweep is two launches over a fixed grid of
 // WALK_BLOCKS blocks, block b owning a contiguous chunk of the frontier:
-// count (per-block totals), scan (block offsets, list sizes), write (the
+// count (per-block totals) and write (each block sums the totals of the
+// blocks before it for its offsets, block 0 the sweep's totals; then the
 // outputs at their offsets, in frontier order).  No atomics; the output order
 // is deterministic.
 constexpr int WALK_BLOCKS = 1024;
@@ -194,63 +195,70 @@ k_walk_count(WalkParams wp, TreeArrays t, const double *P, WalkBuffers wb, int s
     }
 }
 
-// one block of WALK_BLOCKS threads: exclusive offsets of every block in the
-// three outputs, and the new totals
-__global__ void __launch_bounds__(WALK_BLOCKS)
-k_walk_scan(WalkParams wp, WalkBuffers wb, int sweep, unsigned long long *btot) {
-    unsigned long long *cnt = wb.counters;
-    const int b = threadIdx.x, lane = lane_id(), w = b / FMM_WAVE;
-    constexpr int NW = WALK_BLOCKS / FMM_WAVE;
-    __shared__ unsigned long long ws[NW][4];
-    unsigned long long v[4], inc[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        v[k] = btot[4 * b + k];
-        inc[k] = v[k];
-#pragma unroll
-        for (int off = 1; off < FMM_WAVE; off <<= 1) {
-            const unsigned long long o = __shfl_up(inc[k], off, FMM_WAVE);
-            if (lane >= off) inc[k] += o;
-        }
-        if (lane == FMM_WAVE - 1) ws[w][k] = inc[k];
-    }
-    __syncthreads();
-    unsigned long long pre[4] = {0, 0, 0, 0}, tot[4] = {0, 0, 0, 0};
-    for (int i = 0; i < NW; ++i)
+// Offsets of this block's outputs (the sum of the count pass's totals of the
+// blocks before it) and, in block 0, the sweep's totals: the frontier size
+// for the next sweep and the running list sizes, kept per sweep in
+// counters[WALK_CUM + 3 i + k] so that no block reads a value another block of
+// this launch writes.
+__device__ __forceinline__ void walk_offsets(const unsigned long long *btot, bool need_prefix,
+                                             unsigned long long (&pre)[3],
+                                             unsigned long long (&tot)[4]) {
+    const int b = blockIdx.x;
+    const bool want_tot = b == 0;
+    unsigned long long v[7] = {0, 0, 0, 0, 0, 0, 0};   // pre[0..2], tot[0..3]
+    const int jend = want_tot ? WALK_BLOCKS : (need_prefix ? b : 0);
+    for (int j = threadIdx.x; j < jend; j += WALK_THREADS) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            if (i < w) pre[k] += ws[i][k];
-            tot[k] += ws[i][k];
+            const unsigned long long x = btot[4 * j + k];
+            if (k < 3 && j < b) v[k] += x;
+            v[3 + k] += x;
         }
-    const unsigned long long m0 = cnt[0], p0 = cnt[1];
-    // offsets: frontier from 0, lists after what earlier sweeps appended
-    btot[4 * b + 0] = pre[0] + inc[0] - v[0];
-    btot[4 * b + 1] = m0 + pre[1] + inc[1] - v[1];
-    btot[4 * b + 2] = p0 + pre[2] + inc[2] - v[2];
+    }
+#pragma unroll
+    for (int k = 0; k < 7; ++k)
+#pragma unroll
+        for (int o = FMM_WAVE / 2; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, FMM_WAVE);
+    __shared__ unsigned long long red[WALK_THREADS / FMM_WAVE][7];
+    const int w = threadIdx.x / FMM_WAVE;
+    if (lane_id() == 0)
+#pragma unroll
+        for (int k = 0; k < 7; ++k) red[w][k] = v[k];
     __syncthreads();
-    if (b == 0) {
-        const int64_t n_in = sweep_input(wp, cnt, sweep);
-        if (n_in > wb.cap_out) cnt[3] = 1ull;
-        cnt[4 + sweep] = tot[0];
-        cnt[0] = m0 + tot[1];
-        cnt[1] = p0 + tot[2];
-        cnt[2] += tot[3];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        unsigned long long a = 0;
+#pragma unroll
+        for (int i = 0; i < WALK_THREADS / FMM_WAVE; ++i) a += red[i][k];
+        if (k < 3) pre[k] = a;
+        else tot[k - 3] = a;
     }
 }
 
 __global__ void __launch_bounds__(WALK_THREADS)
 k_walk_write(WalkParams wp, TreeArrays t, const double *P, WalkBuffers wb, int sweep,
-             const unsigned long long *boff) {
-    const unsigned long long *cnt = wb.counters;
-    // the scan kernel already replaced this sweep's output count: read the
-    // input size from the previous slot (unchanged)
+             const unsigned long long *btot) {
+    unsigned long long *cnt = wb.counters;
     const int64_t n_in = sweep_input(wp, cnt, sweep);
-    if (n_in > wb.cap_out) return;
     const int64_t chunk = (n_in + WALK_BLOCKS - 1) / WALK_BLOCKS;
     const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(n_in, lo + chunk);
-    int64_t of = (int64_t)boff[4 * blockIdx.x + 0];
-    int64_t om = (int64_t)boff[4 * blockIdx.x + 1];
-    int64_t op = (int64_t)boff[4 * blockIdx.x + 2];
+    const bool fits = n_in <= wb.cap_out;
+    if (blockIdx.x != 0 && (!fits || lo >= hi)) return;   // nothing to write
+    unsigned long long pre[3], tot[4];
+    walk_offsets(btot, fits && lo < hi, pre, tot);
+    unsigned long long *cum = cnt + WALK_CUM + 3 * sweep;   // totals before this sweep
+    const unsigned long long m0 = cum[0], p0 = cum[1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (!fits) cnt[3] = 1ull;
+        cnt[4 + sweep] = tot[0];
+        cum[3] = cnt[0] = m0 + tot[1];
+        cum[4] = cnt[1] = p0 + tot[2];
+        cum[5] = cnt[2] = cum[2] + tot[3];
+    }
+    if (!fits) return;
+    int64_t of = (int64_t)pre[0];
+    int64_t om = (int64_t)(m0 + pre[1]);
+    int64_t op = (int64_t)(p0 + pre[2]);
     for (int64_t base = lo; base < hi; base += WALK_THREADS) {
         const int64_t i = base + threadIdx.x;
         Decision d = {0, 0, 0.0};
@@ -411,9 +419,6 @@ hipError_t launch_walk(const WalkParams &wp, const TreeArrays &t, const double *
     hipLaunchKernelGGL(k_walk_count, dim3(WALK_BLOCKS), dim3(WALK_THREADS), 0, s, wp, t, P, wb,
                        sweep, btmp);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_walk_scan, dim3(1), dim3(WALK_BLOCKS), 0, s, wp, wb, sweep, btmp);
-    e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_walk_write, dim3(WALK_BLOCKS), dim3(WALK_THREADS), 0, s, wp, t, P, wb,
                        sweep, (const unsigned long long *)btmp);
