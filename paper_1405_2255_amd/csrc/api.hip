@@ -479,12 +479,15 @@ Lists walk(fmm_ctx *c, const WalkParams &wp0, const double *P) {
     }
 }
 
-// sort a list by (sink, source) and compute the per-sink offsets
+// group a list (sink << sh | source) by sink and compute the per-sink
+// offsets.  The sort is stable and keys only on the sink bits, so each sink's
+// sources keep the walk's (deterministic) order; the M2L kernels take a
+// sink's sources in any order.
 uint64_t *sort_list(fmm_ctx *c, DevBuf &a, DevBuf &b, int64_t nlist, int nsinks, DevBuf &offb) {
     uint64_t *k1 = ptr<uint64_t>(a);
     uint64_t *k2 = ensure<uint64_t>(b, std::max<int64_t>(nlist, 1));
     int *tmp = tmp_ints(c, sort_tmp_ints(nlist));
-    CK(radix_sort(&k1, &k2, nullptr, nullptr, nlist, 2 * c->sh, tmp, c->stream));
+    CK(radix_sort(&k1, &k2, nullptr, nullptr, nlist, c->sh, tmp, c->stream, c->sh));
     int64_t *off = ensure<int64_t>(offb, (size_t)nsinks + 1);
     CK(launch_list_offsets(k1, nlist, nsinks, c->sh, off, c->stream));
     return k1;
@@ -657,10 +660,10 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
     CK(launch_p2m(p, t, ptr<int>(c->leaf_cell), c->nleaves, ptr<double>(c->x), ptr<double>(c->y),
                   ptr<double>(c->z), ptr<double>(c->m), M, s));
     if (c->ncells > 1) CK(launch_shift_upsilon(p, t, 1, c->ncells, U, s));
-    short *plans = ensure<short>(c->plans, 2 * FMM_PLAN_SIZE);
+    short *plans = ensure<short>(c->plans, 2 * XP_SIZE);
     if (c->plan_p != p) {
-        std::vector<short> h(2 * FMM_PLAN_SIZE);
-        translation_plans(p, h.data(), h.data() + FMM_PLAN_SIZE);
+        std::vector<short> h(2 * XP_SIZE);
+        translation_plans(p, h.data(), h.data() + XP_SIZE);
         CK(hipMemcpyAsync(plans, h.data(), h.size() * sizeof(short), hipMemcpyHostToDevice, s));
         sync(c);
         c->plan_p = p;
@@ -767,10 +770,10 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
     // downward pass, far field at the particles
     for (int Lv = 1; Lv <= c->depth; ++Lv) {
         CK(launch_l2l_level(p, t, c->ls[Lv], c->ls[Lv + 1], U, F,
-                            ptr<short>(c->plans) + FMM_PLAN_SIZE, s, cell_active));
+                            ptr<short>(c->plans) + XP_SIZE, s, cell_active));
         if (vel)
             CK(launch_l2l_level(p, t, c->ls[Lv], c->ls[Lv + 1], U, ptr<double>(c->Fd),
-                                ptr<short>(c->plans) + FMM_PLAN_SIZE, s, cell_active));
+                                ptr<short>(c->plans) + XP_SIZE, s, cell_active));
     }
     double4 *o4 = ensure<double4>(c->out4, n);
     CK(launch_l2p(p, t, ptr<int>(c->leaf_of), ptr<int>(c->leaf_cell), n, ptr<double>(c->x),

@@ -5,6 +5,7 @@
 // Storage: per cell the complex X_n^m for 0 <= m <= n <= p at complex index
 // tri(n, m) = n(n+1)/2 + m, (Re, Im) adjacent, Im = 0 for m = 0.
 #include <algorithm>
+#include <stdexcept>
 #include <vector>
 
 #include "internal.h"
@@ -124,16 +125,7 @@ __device__ __forceinline__ cplx ld(const cplx *X, int n, int q) {
     return sym(X[tri(n, q < 0 ? -q : q)], q);
 }
 
-constexpr int NCMAX = tri(FMM_PMAX + 1, 0);   // complex coefficients at the largest order
 constexpr int NFULL = (FMM_PMAX + 1) * (FMM_PMAX + 1);   // all orders -n..n
-constexpr int OUT_PER_LANE = (NCMAX + FMM_WAVE - 1) / FMM_WAVE;
-
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // degree and order of coefficient index o (o = tri(n, m))
 __device__ __forceinline__ void nm_of(int o, int &n, int &m) {
     n = 0;
@@ -141,76 +133,38 @@ __device__ __forceinline__ void nm_of(int o, int &n, int &m) {
     m = o - tri(n, 0);
 }
 
-// Staging of an expansion into LDS as all orders -n <= q <= n at index
-// n^2 + n + q (eq:sym for q < 0).  Lane `lane` handles entries
-// e = lane + 64 r, r < STAGE_R; all its loads are issued before any is used.
-constexpr int STAGE_R = (NFULL + FMM_WAVE - 1) / FMM_WAVE;
-
-struct StageMap {
-    int src[STAGE_R];   // stored index tri(n, |q|), or -1 past the end
-    int q[STAGE_R];
-};
-
-__device__ __forceinline__ StageMap stage_map(int p, int lane) {
-    StageMap sm;
-    const int nf = (p + 1) * (p + 1);
-#pragma unroll
-    for (int r = 0; r < STAGE_R; ++r) {
-        const int e = lane + r * FMM_WAVE;
-        int n = (int)sqrtf((float)e);
-        while (n * n > e) --n;
-        while ((n + 1) * (n + 1) <= e) ++n;
-        const int q = e - n * n - n;
-        sm.src[r] = e < nf ? tri(n, q < 0 ? -q : q) : -1;
-        sm.q[r] = q;
-    }
-    return sm;
-}
-
-__device__ __forceinline__ void stage_load(const cplx *X, const StageMap &sm,
-                                           cplx (&v)[STAGE_R]) {
-#pragma unroll
-    for (int r = 0; r < STAGE_R; ++r)
-        if (sm.src[r] >= 0) v[r] = X[sm.src[r]];
-}
-
-__device__ __forceinline__ void stage_store(cplx *dst, const StageMap &sm, int lane,
-                                            const cplx (&v)[STAGE_R]) {
-#pragma unroll
-    for (int r = 0; r < STAGE_R; ++r)
-        if (sm.src[r] >= 0) dst[lane + r * FMM_WAVE] = sym(v[r], sm.q[r]);
-}
-
-// ---- M2M: one wavefront per cell, lanes over coefficients ---------------------
-// Level by level from the bottom.  The wavefront of cell c first completes
-// M(c): for an internal cell the sum, in child order, of the children's
-// shifted expansions T(child) written by the previous level's launch (a leaf
-// keeps its P2M result); then, unless c is a root, it shifts M(c) to the
-// parent's centre,
+// ---- M2M: one block per cell, threads over (output, rows of k) items ---------
+// Level by level from the bottom.  The block of cell c first completes M(c):
+// for an internal cell the sum, in child order, of the children's shifted
+// expansions T(child) written by the previous level's launch (a leaf keeps
+// its P2M result); then, unless c is a root, it shifts M(c) to the parent's
+// centre,
 //   T_n^m(c) = sum_{k=0}^{n} sum_{l=-k}^{k} Upsilon_k^l(z_c - z_parent) M_{n-k}^{m-l}(c),
-// with M(c) and the shift Upsilon staged (all orders) in the wavefront's LDS.
-// plan[q * 64 + lane] is the lane's q-th output (or -1): outputs sorted by
-// their number of terms and dealt out in snake order, for balanced lanes.
-__global__ void __launch_bounds__(256)
-k_m2m_level(int p, TreeArrays t, int c0, int c1, const double *U, double *M, double *T,
+// with M(c) and the shift Upsilon staged (all orders) in LDS.  The sum of
+// each output is cut into items of consecutive k (the plan); each thread
+// adds its items' terms, and each output then adds its items in order, so
+// that no thread's chain of multiply-adds is longer than about 1/256 of the
+// cell's work (the upper levels hold few cells, and there the chain sets the
+// time of the launch).
+__device__ __forceinline__ int isqrt_full(int f) {
+    int n = (int)sqrtf((float)f);
+    while (n * n > f) --n;
+    while ((n + 1) * (n + 1) <= f) ++n;
+    return n;
+}
+
+__global__ void __launch_bounds__(XF_THREADS)
+k_m2m_level(int p, TreeArrays t, int c0, const double *U, double *M, double *T,
             const short *plan) {
-    __shared__ cplx sU[4][NFULL], sM[4][NFULL];
-    const int w = threadIdx.x / FMM_WAVE, lane = lane_id();
-    const int c = c0 + blockIdx.x * 4 + w;
-    if (c >= c1) return;
+    __shared__ cplx sU[NFULL], sM[NFULL], part[XF_ITEMS];
+    const int c = c0 + blockIdx.x, tid = threadIdx.x;
     const int nc = tri(p + 1, 0);
     const int nch = t.nchild[c];
     const bool shift = t.parent[c] >= 0;
-    int o[OUT_PER_LANE];
-#pragma unroll
-    for (int q = 0; q < OUT_PER_LANE; ++q) o[q] = plan[q * FMM_WAVE + lane];
-    const StageMap sm = stage_map(p, lane);
-    cplx ru[STAGE_R];
-    if (shift) stage_load(reinterpret_cast<const cplx *>(U) + (size_t)c * nc, sm, ru);
     cplx *Mc = reinterpret_cast<cplx *>(M) + (size_t)c * nc;
     const cplx *Tb = reinterpret_cast<const cplx *>(T);
-    // complete M(c) (stored half, lanes over stored coefficients) and stage it
-    for (int e = lane; e < nc; e += FMM_WAVE) {
+    // complete M(c) (threads over stored coefficients) and stage it
+    for (int e = tid; e < nc; e += XF_THREADS) {
         int n, m;
         nm_of(e, n, m);
         cplx v;
@@ -233,22 +187,25 @@ k_m2m_level(int p, TreeArrays t, int c0, int c1, const double *U, double *M, dou
         } else {
             v = Mc[e];
         }
-        sM[w][n * n + n + m] = v;
-        if (m > 0) sM[w][n * n + n - m] = sym(v, -m);
+        sM[n * n + n + m] = v;
+        if (m > 0) sM[n * n + n - m] = sym(v, -m);
     }
     if (!shift) return;
-    stage_store(sU[w], sm, lane, ru);
-    wave_lds_sync();
-    cplx *Tc = reinterpret_cast<cplx *>(T) + (size_t)c * nc;
+    const cplx *Uc = reinterpret_cast<const cplx *>(U) + (size_t)c * nc;
+    for (int f = tid; f < (p + 1) * (p + 1); f += XF_THREADS) {
+        const int n = isqrt_full(f), q = f - n * n - n;
+        sU[f] = ld(Uc, n, q);
+    }
+    __syncthreads();
 #pragma unroll
-    for (int q = 0; q < OUT_PER_LANE; ++q) {
-        if (o[q] < 0) continue;
-        int n, m;
-        nm_of(o[q], n, m);
-        // four partial sums over consecutive terms: independent chains of
-        // multiply-adds instead of one long dependent chain
+    for (int r = 0; r < XF_IT; ++r) {
+        const int it = plan[XP_LANE + r * XF_THREADS + tid];
+        if (it < 0) continue;
+        const int n = plan[XP_N + it], m = plan[XP_M + it];
+        const int k0 = plan[XP_K0 + it], k1 = plan[XP_K1 + it];
+        // four partial sums over consecutive terms: independent chains
         cplx a[4] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-        for (int k = 0; k <= n; ++k) {
+        for (int k = k0; k <= k1; ++k) {
             const int nn = n - k;
             const int lmin = max(-k, m - nn), lmax = min(k, m + nn);
             const int bu = k * k + k, bv = nn * nn + nn + m;
@@ -256,20 +213,31 @@ k_m2m_level(int p, TreeArrays t, int c0, int c1, const double *U, double *M, dou
             for (; l + 3 <= lmax; l += 4) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const cplx u = sU[w][bu + l + j], v = sM[w][bv - l - j];
+                    const cplx u = sU[bu + l + j], v = sM[bv - l - j];
                     a[j].re = fma(u.re, v.re, fma(-u.im, v.im, a[j].re));
                     a[j].im = fma(u.re, v.im, fma(u.im, v.re, a[j].im));
                 }
             }
             for (; l <= lmax; ++l) {
-                const cplx u = sU[w][bu + l], v = sM[w][bv - l];
+                const cplx u = sU[bu + l], v = sM[bv - l];
                 a[0].re = fma(u.re, v.re, fma(-u.im, v.im, a[0].re));
                 a[0].im = fma(u.re, v.im, fma(u.im, v.re, a[0].im));
             }
         }
-        const double re = (a[0].re + a[1].re) + (a[2].re + a[3].re);
-        const double im = (a[0].im + a[1].im) + (a[2].im + a[3].im);
-        Tc[o[q]] = {re, m == 0 ? 0.0 : im};
+        part[it] = {(a[0].re + a[1].re) + (a[2].re + a[3].re),
+                    (a[0].im + a[1].im) + (a[2].im + a[3].im)};
+    }
+    __syncthreads();
+    cplx *Tc = reinterpret_cast<cplx *>(T) + (size_t)c * nc;
+    for (int e = tid; e < nc; e += XF_THREADS) {
+        cplx v = {0.0, 0.0};
+        for (int i = plan[XP_OUT + e]; i < plan[XP_OUT + e + 1]; ++i) {
+            v.re += part[i].re;
+            v.im += part[i].im;
+        }
+        int n, m;
+        nm_of(e, n, m);
+        Tc[e] = {v.re, m == 0 ? 0.0 : v.im};
     }
 }
 
@@ -293,43 +261,37 @@ __global__ void k_power(int p, int ncells, const double *M, double *P) {
     }
 }
 
-// ---- L2L: one wavefront per child, lanes over output coefficients ------------
+// ---- L2L: one block per child, threads over (output, rows of k) items --------
 // F_n^m(s') += sum_{k=0}^{p-n} sum_l conj(Upsilon_k^l(s - s')) F_{n+k}^{m+l}(s),
 // with Upsilon_k^l(s - s') = (-1)^k Upsilon_k^l(s' - s) from the stored shift;
-// the parent's F and the child's shift are staged (all orders) in LDS; plan
-// as for M2M.
-__global__ void __launch_bounds__(256)
-k_l2l_level(int p, TreeArrays t, int c0, int c1, const double *U, double *F, const short *plan,
+// the parent's F and the child's shift are staged (all orders) in LDS; items
+// and their order as for M2M.
+__global__ void __launch_bounds__(XF_THREADS)
+k_l2l_level(int p, TreeArrays t, int c0, const double *U, double *F, const short *plan,
             const uint8_t *active) {
-    __shared__ cplx sU[4][NFULL], sF[4][NFULL];
-    const int w = threadIdx.x / FMM_WAVE, lane = lane_id();
-    const int c = c0 + blockIdx.x * 4 + w;
-    if (c >= c1) return;
+    __shared__ cplx sU[NFULL], sF[NFULL], part[XF_ITEMS];
+    const int c = c0 + blockIdx.x, tid = threadIdx.x;
     if (active && !active[c]) return;      // no listed sink below c
     const int pc = t.parent[c];
     if (pc < 0) return;
     const int nc = tri(p + 1, 0);
-    int o[OUT_PER_LANE];
-#pragma unroll
-    for (int q = 0; q < OUT_PER_LANE; ++q) o[q] = plan[q * FMM_WAVE + lane];
-    const StageMap sm = stage_map(p, lane);
-    {
-        cplx ru[STAGE_R], rf[STAGE_R];
-        stage_load(reinterpret_cast<const cplx *>(U) + (size_t)c * nc, sm, ru);
-        stage_load(reinterpret_cast<const cplx *>(F) + (size_t)pc * nc, sm, rf);
-        stage_store(sU[w], sm, lane, ru);
-        stage_store(sF[w], sm, lane, rf);
+    const cplx *Uc = reinterpret_cast<const cplx *>(U) + (size_t)c * nc;
+    const cplx *Fp = reinterpret_cast<const cplx *>(F) + (size_t)pc * nc;
+    for (int f = tid; f < (p + 1) * (p + 1); f += XF_THREADS) {
+        const int n = isqrt_full(f), q = f - n * n - n;
+        sU[f] = ld(Uc, n, q);
+        sF[f] = ld(Fp, n, q);
     }
-    wave_lds_sync();
-    cplx *Fc = reinterpret_cast<cplx *>(F) + (size_t)c * nc;
+    __syncthreads();
 #pragma unroll
-    for (int q = 0; q < OUT_PER_LANE; ++q) {
-        if (o[q] < 0) continue;
-        int n, m;
-        nm_of(o[q], n, m);
+    for (int r = 0; r < XF_IT; ++r) {
+        const int it = plan[XP_LANE + r * XF_THREADS + tid];
+        if (it < 0) continue;
+        const int n = plan[XP_N + it], m = plan[XP_M + it];
+        const int k0 = plan[XP_K0 + it], k1 = plan[XP_K1 + it];
         // four partial sums over consecutive terms (independent chains)
         cplx acc[4] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-        for (int k = 0; k <= p - n; ++k) {
+        for (int k = k0; k <= k1; ++k) {
             const double sg = (k & 1) ? -1.0 : 1.0;
             const int nk = n + k;
             const int bu = k * k + k, bf = nk * nk + nk + m;
@@ -337,7 +299,7 @@ k_l2l_level(int p, TreeArrays t, int c0, int c1, const double *U, double *F, con
             for (; l + 3 <= k; l += 4) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const cplx u = sU[w][bu + l + j], f = sF[w][bf + l + j];
+                    const cplx u = sU[bu + l + j], f = sF[bf + l + j];
                     // conj(sg u) * f
                     const double ur = sg * u.re, ui = -sg * u.im;
                     acc[j].re = fma(ur, f.re, fma(-ui, f.im, acc[j].re));
@@ -345,15 +307,28 @@ k_l2l_level(int p, TreeArrays t, int c0, int c1, const double *U, double *F, con
                 }
             }
             for (; l <= k; ++l) {
-                const cplx u = sU[w][bu + l], f = sF[w][bf + l];
+                const cplx u = sU[bu + l], f = sF[bf + l];
                 const double ur = sg * u.re, ui = -sg * u.im;
                 acc[0].re = fma(ur, f.re, fma(-ui, f.im, acc[0].re));
                 acc[0].im = fma(ur, f.im, fma(ui, f.re, acc[0].im));
             }
         }
-        cplx &dst = Fc[o[q]];
-        dst.re += (acc[0].re + acc[1].re) + (acc[2].re + acc[3].re);
-        if (m != 0) dst.im += (acc[0].im + acc[1].im) + (acc[2].im + acc[3].im);
+        part[it] = {(acc[0].re + acc[1].re) + (acc[2].re + acc[3].re),
+                    (acc[0].im + acc[1].im) + (acc[2].im + acc[3].im)};
+    }
+    __syncthreads();
+    cplx *Fc = reinterpret_cast<cplx *>(F) + (size_t)c * nc;
+    for (int e = tid; e < nc; e += XF_THREADS) {
+        cplx v = {0.0, 0.0};
+        for (int i = plan[XP_OUT + e]; i < plan[XP_OUT + e + 1]; ++i) {
+            v.re += part[i].re;
+            v.im += part[i].im;
+        }
+        int n, m;
+        nm_of(e, n, m);
+        cplx &dst = Fc[e];
+        dst.re += v.re;
+        if (m != 0) dst.im += v.im;
     }
 }
 
@@ -483,39 +458,78 @@ inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
 
-// Outputs sorted by their number of terms (most first, ties by index) and
-// dealt to the 64 lanes in snake order, row by row.
-void translation_plans(int p, short *m2m, short *l2l) {
-    static_assert(OUT_PER_LANE == FMM_PLAN_ROWS && FMM_PLAN_SIZE == FMM_PLAN_ROWS * FMM_WAVE, "plan rows");
+// The items of one translation: each output's rows of k are cut, in order,
+// into items of at most T terms (T = the larger of the cell's terms / 256
+// and the longest row), then the items are dealt longest first to the
+// thread with the least work (ties to the lower thread), at most XF_IT each;
+// 4 extra units per item stand for its set-up.  Deterministic.
+static void item_plan(int p, bool m2m, short *plan) {
     const int nc = tri(p + 1, 0);
-    auto deal = [&](auto work, short *plan) {
-        std::vector<int> order(nc);
-        for (int o = 0; o < nc; ++o) order[o] = o;
-        std::vector<long> w(nc);
-        for (int n = 0; n <= p; ++n)
-            for (int m = 0; m <= n; ++m) w[tri(n, m)] = work(n, m);
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return w[a] > w[b]; });
-        for (int i = 0; i < FMM_PLAN_ROWS * FMM_WAVE; ++i) plan[i] = -1;
-        for (int i = 0; i < nc; ++i) {
-            const int r = i / FMM_WAVE, pos = i % FMM_WAVE;
-            const int lane = (r & 1) ? FMM_WAVE - 1 - pos : pos;
-            plan[r * FMM_WAVE + lane] = (short)order[i];
-        }
+    auto row = [&](int n, int m, int k) -> int {
+        if (!m2m) return 2 * k + 1;
+        const int nn = n - k;
+        const int lo = std::max(-k, m - nn), hi = std::min(k, m + nn);
+        return hi >= lo ? hi - lo + 1 : 0;
     };
-    deal([&](int n, int m) {
-        long c = 0;
-        for (int k = 0; k <= n; ++k) {
-            const int nn = n - k;
-            const int lo = std::max(-k, m - nn), hi = std::min(k, m + nn);
-            if (hi >= lo) c += hi - lo + 1;
+    long total = 0;
+    int longest = 0;
+    for (int n = 0; n <= p; ++n)
+        for (int m = 0; m <= n; ++m)
+            for (int k = 0; k <= (m2m ? n : p - n); ++k) {
+                total += row(n, m, k);
+                longest = std::max(longest, row(n, m, k));
+            }
+    const long T = std::max<long>((total + XF_THREADS - 1) / XF_THREADS, longest);
+    struct Item { int n, m, k0, k1; long cost; };
+    std::vector<Item> items;
+    std::vector<int> first(nc + 1);
+    for (int n = 0; n <= p; ++n)
+        for (int m = 0; m <= n; ++m) {
+            first[tri(n, m)] = (int)items.size();
+            const int kmax = m2m ? n : p - n;
+            long cur = 0;
+            int k0 = 0;
+            for (int k = 0; k <= kmax; ++k) {
+                const int r = row(n, m, k);
+                if (cur > 0 && cur + r > T) {
+                    items.push_back({n, m, k0, k - 1, cur});
+                    cur = 0;
+                    k0 = k;
+                }
+                cur += r;
+            }
+            items.push_back({n, m, k0, kmax, cur});
         }
-        return c;
-    }, m2m);
-    deal([&](int n, int) {
-        long c = 0;
-        for (int k = 0; k <= p - n; ++k) c += 2 * k + 1;
-        return c;
-    }, l2l);
+    first[nc] = (int)items.size();
+    if ((int)items.size() > XF_ITEMS) throw std::runtime_error("translation plan: too many items");
+    std::vector<int> order(items.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return items[a].cost > items[b].cost; });
+    std::vector<long> load(XF_THREADS, 0);
+    std::vector<int> cnt(XF_THREADS, 0);
+    for (int i = 0; i < XP_SIZE; ++i) plan[i] = -1;
+    for (int i : order) {
+        int best = -1;
+        for (int l = 0; l < XF_THREADS; ++l)
+            if (cnt[l] < XF_IT && (best < 0 || load[l] < load[best])) best = l;
+        if (best < 0) throw std::runtime_error("translation plan: too few threads");
+        plan[XP_LANE + cnt[best] * XF_THREADS + best] = (short)i;
+        ++cnt[best];
+        load[best] += items[i].cost + 4;
+    }
+    for (size_t i = 0; i < items.size(); ++i) {
+        plan[XP_N + i] = (short)items[i].n;
+        plan[XP_M + i] = (short)items[i].m;
+        plan[XP_K0 + i] = (short)items[i].k0;
+        plan[XP_K1 + i] = (short)items[i].k1;
+    }
+    for (int e = 0; e <= nc; ++e) plan[XP_OUT + e] = (short)first[e];
+}
+
+void translation_plans(int p, short *m2m, short *l2l) {
+    item_plan(p, true, m2m);
+    item_plan(p, false, l2l);
 }
 
 hipError_t launch_p2m(int p, const TreeArrays &t, const int *leaf_cell, int nleaves,
@@ -542,8 +556,8 @@ hipError_t launch_shift_upsilon(int p, const TreeArrays &t, int c0, int c1, doub
 hipError_t launch_m2m_level(int p, const TreeArrays &t, int c0, int c1, const double *U,
                             double *M, double *T, const short *plan, hipStream_t s) {
     if (c1 <= c0) return hipSuccess;
-    hipLaunchKernelGGL(k_m2m_level, dim3(blocks(c1 - c0, 4)), dim3(256), 0, s, p, t, c0, c1, U, M,
-                       T, plan);
+    hipLaunchKernelGGL(k_m2m_level, dim3((unsigned)(c1 - c0)), dim3(XF_THREADS), 0, s, p, t, c0, U,
+                       M, T, plan);
     return hipGetLastError();
 }
 
@@ -555,8 +569,8 @@ hipError_t launch_power(int p, int ncells, const double *M, double *P, hipStream
 hipError_t launch_l2l_level(int p, const TreeArrays &t, int c0, int c1, const double *U,
                             double *F, const short *plan, hipStream_t s, const uint8_t *active) {
     if (c1 <= c0) return hipSuccess;
-    hipLaunchKernelGGL(k_l2l_level, dim3(blocks(c1 - c0, 4)), dim3(256), 0, s, p, t, c0, c1, U, F,
-                       plan, active);
+    hipLaunchKernelGGL(k_l2l_level, dim3((unsigned)(c1 - c0)), dim3(XF_THREADS), 0, s, p, t, c0, U,
+                       F, plan, active);
     return hipGetLastError();
 }
 

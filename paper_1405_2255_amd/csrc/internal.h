@@ -120,11 +120,25 @@ hipError_t launch_p2m(int p, const TreeArrays &t, const int *leaf_cell, int nlea
                       double *M, hipStream_t s);
 hipError_t launch_shift_upsilon(int p, const TreeArrays &t, int c0, int c1, double *U,
                                 hipStream_t s);
-// Output plans of the translation kernels: plan[q * 64 + lane] = the lane's
-// q-th coefficient index (or -1), q < FMM_PLAN_ROWS; m2m and l2l each hold
-// 64 * FMM_PLAN_ROWS entries.
-#define FMM_PLAN_ROWS 4
-#define FMM_PLAN_SIZE (FMM_PLAN_ROWS * 64)
+// Work plans of the translation kernels (M2M, L2L), one block of XF_THREADS
+// threads per cell.  Each output coefficient's sum over k is cut into items
+// of consecutive k with about equal numbers of terms, the items are dealt to
+// the threads (at most XF_IT each, longest first to the least loaded), and
+// each output adds its items' partial sums in item order.  Layout (short):
+// item i has degree n, order m and rows k0..k1 at XP_N/XP_M/XP_K0/XP_K1 + i;
+// thread t's r-th item (or -1) at XP_LANE + r * XF_THREADS + t; the items of
+// output e (stored index tri(n, m)) are [XP_OUT + e], [XP_OUT + e + 1]).
+// A plan for m2m and one for l2l, XP_SIZE shorts each.
+#define XF_THREADS 256
+#define XF_ITEMS 512
+#define XF_IT 3
+#define XP_N 0
+#define XP_M XF_ITEMS
+#define XP_K0 (2 * XF_ITEMS)
+#define XP_K1 (3 * XF_ITEMS)
+#define XP_LANE (4 * XF_ITEMS)
+#define XP_OUT (XP_LANE + XF_IT * XF_THREADS)
+#define XP_SIZE (XP_OUT + (FMM_PMAX + 1) * (FMM_PMAX + 2) / 2 + 1)
 void translation_plans(int p, short *m2m, short *l2l);
 // Cells [c0, c1) of one level: complete M (internal cells: sum of the
 // children's T) and write T = M shifted to the parent's centre (not for
