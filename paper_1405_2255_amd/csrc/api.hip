@@ -134,7 +134,7 @@ struct fmm_ctx {
     // walk
     DevBuf fa, fb, m2l, m2l2, p2p, p2p2, p2pe, p2pe2, m2l_off, p2p_off, chunks, ccnt, coff, Fpart;
     DevBuf rflag, ranges, rkey, wcode, rup;
-    DevBuf pt_n, pt_m, pt_s, pt_off, pt_moff, ptasks, ppart;
+    DevBuf pt_n, pt_m, pt_s, pt_off, pt_moff, ptasks, pchain, ppart;
     DevBuf counters, nonfinite, walktmp, coffsets, ckey, ckey2, order, order2;
     DevBuf actflag, actf, actinv, actpre, cellact, actbad;   // forces for a listed subset
     DevBuf epsmin;                                           // smallest individual eps
@@ -541,8 +541,9 @@ void run_p2p(fmm_ctx *c, int want_f, int with_pot, int mixed, double4 *out4, boo
     const int2 *rg = ptr<int2>(c->ranges);
     int *up = ensure<int>(c->rup, (size_t)std::max(c->ncells, 1));
     CK(launch_range_up(c->ncells, t.parent, off, up, s));
+    int *chain = ensure<int>(c->pchain, (size_t)std::max(nl, 1) * P2P_CHAIN);
     CK(launch_p2p_plan(nl, ptr<int>(c->leaf_cell), off, rg, up, t, active, ntask, mtask, nts, toff,
-                       moff, tmp, totals, s));
+                       moff, chain, tmp, totals, s));
     CK(hipMemcpyAsync(c->hint, totals, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     sync(c);
     const int ntasks = c->hint[0], prows = c->hint[1];
@@ -557,7 +558,7 @@ void run_p2p(fmm_ctx *c, int want_f, int with_pot, int mixed, double4 *out4, boo
                            ptr<double4>(c->xyzm), v4, out4, jo4, part, jpart, s));
     } else {
         CK(launch_p2p(want_f, with_pot, mixed, ntasks, tasks, ptr<int>(c->leaf_cell), nts, moff,
-                      off, rg, up, t, ptr<double4>(c->xyzm), out4, part, s));
+                      off, rg, chain, t, ptr<double4>(c->xyzm), out4, part, s));
     }
     if (timed && c->opts.timing) CK(hipEventRecord(c->ev_p2p[1], s));
     if (prows > 0) {
@@ -986,7 +987,7 @@ void fmm_destroy(fmm_ctx *c) {
                       &c->rho2, &c->bsph, &c->smin, &c->leaf_cell, &c->M, &c->F, &c->P, &c->U, &c->Fe,
                       &c->fa, &c->fb, &c->m2l, &c->m2l2, &c->p2p, &c->p2p2, &c->p2pe,
                       &c->p2pe2, &c->rflag, &c->ranges, &c->rkey, &c->pt_n, &c->pt_m,
-                      &c->pt_s, &c->pt_off, &c->pt_moff, &c->ptasks, &c->ppart, &c->m2l_off,
+                      &c->pt_s, &c->pt_off, &c->pt_moff, &c->ptasks, &c->pchain, &c->ppart, &c->m2l_off,
                       &c->p2p_off, &c->chunks, &c->ccnt, &c->coff, &c->Fpart, &c->counters,
                       &c->nonfinite, &c->prev_scale, &c->walktmp, &c->coffsets,
                       &c->ckey, &c->ckey2, &c->order, &c->order2, &c->wcode, &c->rup,

@@ -266,16 +266,22 @@ hipError_t launch_m2l_rot(int p, int64_t nlist, const uint64_t *list, int sh, co
 // up[c]: nearest proper ancestor of c with direct-sum ranges (or -1)
 hipError_t launch_range_up(int ncells, const int *parent, const int64_t *off, int *up,
                            hipStream_t s);
+// chain: P2P_CHAIN ints per leaf, [0] = the number of cells on the leaf's
+// chain of ancestors that hold direct-sum ranges (the leaf first), then their
+// indices; written by the plan, read by the direct-sum kernel
+#define P2P_CHAIN (FMM_MAXLEVEL + 2)
 hipError_t launch_p2p_plan(int nleaves, const int *leaf_cell, const int64_t *off,
                            const int2 *range, const int *up, const TreeArrays &t,
                            const uint8_t *active, int *ntask, int *mtask, int *nsrc_tasks,
-                           int *task_off, int *moff, int *tmp, int *totals, hipStream_t s);
+                           int *task_off, int *moff, int *chain, int *tmp, int *totals,
+                           hipStream_t s);
 hipError_t launch_p2p_tasks(int nleaves, const int *task_off, int2 *tasks, hipStream_t s);
 // mixed != 0: FP32 pair arithmetic (separations in FP64, sums flushed to FP64)
 hipError_t launch_p2p(int want_f, int with_pot, int mixed, int ntasks, const int2 *tasks,
                       const int *leaf_cell, const int *nsrc_tasks, const int *moff,
-                      const int64_t *off, const int2 *range, const int *up, const TreeArrays &t,
-                      const double4 *xyzm, double4 *out4, double4 *partial, hipStream_t s);
+                      const int64_t *off, const int2 *range, const int *chain,
+                      const TreeArrays &t, const double4 *xyzm, double4 *out4, double4 *partial,
+                      hipStream_t s);
 hipError_t launch_p2p_reduce(int64_t n, const int *leaf_of, const int *leaf_cell,
                              const int *nsrc_tasks, const int *moff, const TreeArrays &t,
                              const double4 *partial, double4 *out4, hipStream_t s);

@@ -43,6 +43,12 @@ __device__ __forceinline__ int first_with_ranges(int c, const int *up, const int
     return off[c + 1] > off[c] ? c : up[c];
 }
 
+__device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
+    const int lo = __builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)v, l);
+    const int hi = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+
 // Work of one sink leaf: the number of source particles in its direct-sum
 // ranges and those of its ancestors (one concatenated list); every lane of
 // the wavefront ends with it.  Lanes take the range entries in turn.
@@ -60,10 +66,13 @@ __device__ __forceinline__ int64_t leaf_sources(int c, const int *up, const int6
 // per leaf (one wavefront each): tasks = sink chunks of 64 x source chunks of
 // P2P_TASK sources; mtask = tasks that need a partial-sum row (leaves with
 // more than one task) (active: when not null, leaves whose cell holds no
-// listed sink get no task); entry nleaves is zeroed for the scans
+// listed sink get no task); entry nleaves is zeroed for the scans.  Also the
+// leaf's chain of ancestors with ranges, so that the direct-sum tasks load it
+// at once instead of following it one dependent load at a time.
 __global__ void k_p2p_count(int nleaves, const int *leaf_cell, const int64_t *off,
                             const int2 *range, const int *up, TreeArrays t,
-                            const uint8_t *active, int *ntask, int *mtask, int *nsrc_tasks) {
+                            const uint8_t *active, int *ntask, int *mtask, int *nsrc_tasks,
+                            int *chain) {
     const int leaf = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / FMM_WAVE);
     if (leaf > nleaves) return;
     const bool head = lane_id() == 0;
@@ -75,13 +84,20 @@ __global__ void k_p2p_count(int nleaves, const int *leaf_cell, const int64_t *of
         return;
     }
     const int c = leaf_cell[leaf];
+    int *ch = chain + (size_t)leaf * P2P_CHAIN;
     if (active && !active[c]) {
         if (head) {
             nsrc_tasks[leaf] = 1;
             ntask[leaf] = 0;
             mtask[leaf] = 0;
+            ch[0] = 0;
         }
         return;
+    }
+    if (head) {
+        int k = 0;
+        for (int anc = first_with_ranges(c, up, off); anc >= 0; anc = up[anc]) ch[1 + k++] = anc;
+        ch[0] = k;
     }
     const int64_t S = leaf_sources(c, up, off, range);
     if (!head) return;
@@ -201,7 +217,7 @@ __device__ __forceinline__ void sum_range(const double4 *p, const double4 *pe, i
 template <int R, int WANT_F, int WITH_POT, int MIXED>
 __global__ void __launch_bounds__(256)
 k_p2p(int ntasks, const int2 *tasks, const int *leaf_cell, const int *nsrc_tasks,
-      const int *moff, const int64_t *off, const int2 *range, const int *up, TreeArrays t,
+      const int *moff, const int64_t *off, const int2 *range, const int *chain, TreeArrays t,
       const double4 *xyzm, double4 *out4, double4 *partial) {
     __shared__ double4 red[4][R * FMM_WAVE];
     // blocks in task order: the hardware deals them to the XCDs in turn, which
@@ -231,12 +247,17 @@ k_p2p(int ntasks, const int2 *tasks, const int *leaf_cell, const int *nsrc_tasks
         xb[k] = *self[k];
         f[k] = make_double4(0.0, 0.0, 0.0, 0.0);
     }
+    // the chain of ancestors with ranges and their list offsets, one per lane
+    const int *ch = chain + (size_t)leaf * P2P_CHAIN;
+    const int nchain = ch[0];
+    const int myanc = lane < nchain ? ch[1 + lane] : 0;
+    const int64_t mr0 = lane < nchain ? off[myanc] : 0, mr1 = lane < nchain ? off[myanc + 1] : 0;
     // sources [ts * P2P_TASK, (ts + 1) * P2P_TASK) of the leaf's list; the range
     // descriptors are read 64 at a time (one per lane) and broadcast in turn
     int64_t skip = (int64_t)ts * P2P_TASK, left = P2P_TASK;
-    for (int anc = first_with_ranges(c, up, off); anc >= 0 && left > 0; anc = up[anc]) {
-        const int64_t r1 = off[anc + 1];
-        for (int64_t rb = off[anc]; rb < r1 && left > 0; rb += FMM_WAVE) {
+    for (int ci = 0; ci < nchain && left > 0; ++ci) {
+        const int64_t r0 = readlane64(mr0, ci), r1 = readlane64(mr1, ci);
+        for (int64_t rb = r0; rb < r1 && left > 0; rb += FMM_WAVE) {
           const int2 mine = rb + lane < r1 ? range[rb + lane] : make_int2(0, 0);
           const int nbat = (int)min((int64_t)FMM_WAVE, r1 - rb);
           for (int j = 0; j < nbat && left > 0; ++j) {
@@ -535,10 +556,11 @@ hipError_t launch_range_up(int ncells, const int *parent, const int64_t *off, in
 hipError_t launch_p2p_plan(int nleaves, const int *leaf_cell, const int64_t *off,
                            const int2 *range, const int *up, const TreeArrays &t,
                            const uint8_t *active, int *ntask, int *mtask, int *nsrc_tasks,
-                           int *task_off, int *moff, int *tmp, int *totals, hipStream_t s) {
+                           int *task_off, int *moff, int *chain, int *tmp, int *totals,
+                           hipStream_t s) {
     hipLaunchKernelGGL(k_p2p_count, dim3(blocks((int64_t)(nleaves + 1) * FMM_WAVE, 256)),
                        dim3(256), 0, s, nleaves, leaf_cell, off, range, up, t, active, ntask,
-                       mtask, nsrc_tasks);
+                       mtask, nsrc_tasks, chain);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = exclusive_scan(ntask, task_off, nleaves + 1, tmp, totals, s);
@@ -554,13 +576,14 @@ hipError_t launch_p2p_tasks(int nleaves, const int *task_off, int2 *tasks, hipSt
 
 hipError_t launch_p2p(int want_f, int with_pot, int mixed, int ntasks, const int2 *tasks,
                       const int *leaf_cell, const int *nsrc_tasks, const int *moff,
-                      const int64_t *off, const int2 *range, const int *up, const TreeArrays &t,
-                      const double4 *xyzm, double4 *out4, double4 *partial, hipStream_t s) {
+                      const int64_t *off, const int2 *range, const int *chain,
+                      const TreeArrays &t, const double4 *xyzm, double4 *out4, double4 *partial,
+                      hipStream_t s) {
     if (ntasks <= 0) return hipSuccess;
     const dim3 g(blocks(ntasks, 4)), b(256);
 #define FMM_P2P_LAUNCH(F, P, X)                                                                  \
     hipLaunchKernelGGL((k_p2p<P2P_R, F, P, X>), g, b, 0, s, ntasks, tasks, leaf_cell, nsrc_tasks, \
-                       moff, off, range, up, t, xyzm, out4, partial)
+                       moff, off, range, chain, t, xyzm, out4, partial)
     if (mixed) {
         if (want_f) FMM_P2P_LAUNCH(1, 0, 1);
         else if (with_pot) FMM_P2P_LAUNCH(0, 1, 1);
