@@ -255,7 +255,7 @@ void build_tree(fmm_ctx *c, int64_t n, const double *pos, const double *mass, in
     CK(hipMemcpyAsync(doff, pin, sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice, s));
     c->nroots = R;
     // keys in each cluster's cube, sort by key and then (stably) by cluster
-    unsigned long long *bb = ensure<unsigned long long>(c->bbox, 6 * (size_t)K);
+    unsigned long long *bb = ensure<unsigned long long>(c->bbox, 6 * (size_t)std::max(K, 1 + BBOX_WAVES));
     uint64_t *k1 = ensure<uint64_t>(c->key, n), *k2 = ensure<uint64_t>(c->key2, n);
     uint32_t *i1 = ensure<uint32_t>(c->idx, n), *i2 = ensure<uint32_t>(c->idx2, n);
     CK(launch_bbox(pos, n, K, doff, bb, s));

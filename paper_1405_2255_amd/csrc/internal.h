@@ -40,7 +40,10 @@ struct TreeArrays {
     double *smin;               // min over the cell's particles of the sink scale
 };
 
-// K clusters: particles [off[k], off[k+1]) (device int64 offsets); bb holds 6K keys
+// K clusters: particles [off[k], off[k+1]) (device int64 offsets); bb holds
+// 6 max(K, 1 + BBOX_WAVES) keys (the box of cluster k in bb[6k..6k+5]; with
+// K = 1 the rest is per-wavefront scratch)
+#define BBOX_WAVES 1024
 hipError_t launch_bbox(const double *pos, int64_t n, int K, const int64_t *off,
                        unsigned long long *bb, hipStream_t s);
 hipError_t launch_keys(const double *pos, int64_t n, int K, const int64_t *off,

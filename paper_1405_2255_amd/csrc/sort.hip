@@ -69,6 +69,37 @@ k_tile_scan(const int *in, int *out, int64_t n, const int *offs, int *total) {
     if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_THREADS - 1) *total = run;
 }
 
+// One block scans an array of up to SCAN1_MAX ints in a single launch (the
+// radix sort's digit counts, for instance), instead of the three launches of
+// the tiled scan: each thread sums a contiguous chunk, the block scans the
+// chunk sums, and each thread writes its chunk's prefixes.  in and out may be
+// the same array (each thread reads its chunk before it writes it).
+constexpr int SCAN1_THREADS = 1024;
+constexpr int64_t SCAN1_MAX = 1 << 14;
+
+__global__ void __launch_bounds__(SCAN1_THREADS)
+k_scan_single(const int *in, int *out, int64_t n, int *total) {
+    __shared__ int wsum[SCAN1_THREADS / FMM_WAVE];
+    const int t = threadIdx.x, lane = lane_id(), w = t / FMM_WAVE;
+    const int64_t chunk = (n + SCAN1_THREADS - 1) / SCAN1_THREADS;
+    const int64_t lo = min(n, (int64_t)t * chunk), hi = min(n, lo + chunk);
+    int s = 0;
+#pragma unroll 8
+    for (int64_t i = lo; i < hi; ++i) s += in[i];
+    const int inc = wave_incl_scan(s);
+    if (lane == FMM_WAVE - 1) wsum[w] = inc;
+    __syncthreads();
+    int run = inc - s;
+    for (int i = 0; i < w; ++i) run += wsum[i];
+    if (total && t == SCAN1_THREADS - 1) *total = run + s;
+#pragma unroll 8
+    for (int64_t i = lo; i < hi; ++i) {
+        const int v = in[i];
+        out[i] = run;
+        run += v;
+    }
+}
+
 // ---- radix sort -------------------------------------------------------
 constexpr int RS_THREADS = 256;
 constexpr int RS_ROUNDS = 8;              // rounds of 256 keys per tile
@@ -152,6 +183,10 @@ hipError_t exclusive_scan(const int *in, int *out, int64_t n, int *tmp, int *tot
         return hipSuccess;
     }
     const int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (tiles > 1 && n <= SCAN1_MAX) {
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(SCAN1_THREADS), 0, s, in, out, n, total);
+        return hipGetLastError();
+    }
     if (tiles == 1) {
         hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(SCAN_THREADS), 0, s, in, out, n,
                            (const int *)nullptr, total);

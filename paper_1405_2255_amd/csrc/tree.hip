@@ -67,8 +67,11 @@ __device__ __forceinline__ void commit_run(unsigned long long *bb, int run, doub
     if (lane_id() == 0) commit_box(bb, run, lo, hi);
 }
 
+// part (one cluster only): each wavefront writes its box to its own six
+// slots instead of committing atomics (a thousand wavefronts' atomics on the
+// same six addresses serialize), and k_bbox_parts reduces the slots.
 __global__ void k_bbox(const double *pos, int64_t n, int K, const int64_t *off,
-                       unsigned long long *bb) {
+                       unsigned long long *bb, unsigned long long *part) {
     const int lane = lane_id();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int run = -1;   // the wavefront's current cluster
@@ -104,7 +107,53 @@ __global__ void k_bbox(const double *pos, int64_t n, int K, const int64_t *off,
             commit_box(bb, cl, v, v);
         }
     }
+    if (part) {
+        const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / FMM_WAVE;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+#pragma unroll
+            for (int o = FMM_WAVE / 2; o > 0; o >>= 1) {
+                rlo[d] = fmin(rlo[d], __shfl_xor(rlo[d], o, FMM_WAVE));
+                rhi[d] = fmax(rhi[d], __shfl_xor(rhi[d], o, FMM_WAVE));
+            }
+            if (lane == 0) {
+                part[6 * wave + d] = ordered_key(rlo[d]);
+                part[6 * wave + 3 + d] = ordered_key(rhi[d]);
+            }
+        }
+        return;
+    }
     if (run >= 0) commit_run(bb, run, rlo, rhi);
+}
+
+// the box of the single cluster from the wavefronts' slots (one block)
+__global__ void __launch_bounds__(256) k_bbox_parts(const unsigned long long *part, int nwaves,
+                                                    unsigned long long *bb) {
+    __shared__ unsigned long long red[4][6];
+    unsigned long long v[6] = {~0ull, ~0ull, ~0ull, 0ull, 0ull, 0ull};
+    for (int w = threadIdx.x; w < nwaves; w += blockDim.x)
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            const unsigned long long x = part[6 * w + d];
+            v[d] = d < 3 ? (x < v[d] ? x : v[d]) : (x > v[d] ? x : v[d]);
+        }
+#pragma unroll
+    for (int d = 0; d < 6; ++d)
+#pragma unroll
+        for (int o = FMM_WAVE / 2; o > 0; o >>= 1) {
+            const unsigned long long x = __shfl_xor(v[d], o, FMM_WAVE);
+            v[d] = d < 3 ? (x < v[d] ? x : v[d]) : (x > v[d] ? x : v[d]);
+        }
+    if (lane_id() == 0)
+#pragma unroll
+        for (int d = 0; d < 6; ++d) red[threadIdx.x / FMM_WAVE][d] = v[d];
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int d = threadIdx.x;
+        unsigned long long r = red[0][d];
+        for (int w = 1; w < 4; ++w) r = d < 3 ? (red[w][d] < r ? red[w][d] : r) : (red[w][d] > r ? red[w][d] : r);
+        bb[d] = r;
+    }
 }
 
 __global__ void k_bbox_init(int K, unsigned long long *bb) {
@@ -928,12 +977,21 @@ inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 hipError_t launch_bbox(const double *pos, int64_t n, int K, const int64_t *off,
                        unsigned long long *bb, hipStream_t s) {
+    unsigned g = blocks(n, 256);
+    if (g > 256) g = 256;
+    if (K == 1) {
+        unsigned long long *part = bb + 6;   // 6 keys per wavefront of the launch
+        hipLaunchKernelGGL(k_bbox, dim3(g), dim3(256), 0, s, pos, n, K, off, bb, part);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_bbox_parts, dim3(1), dim3(256), 0, s, part, (int)(g * 4), bb);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_bbox_init, dim3(blocks(6 * (int64_t)K, 256)), dim3(256), 0, s, K, bb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    unsigned g = blocks(n, 256);
-    if (g > 256) g = 256;
-    hipLaunchKernelGGL(k_bbox, dim3(g), dim3(256), 0, s, pos, n, K, off, bb);
+    hipLaunchKernelGGL(k_bbox, dim3(g), dim3(256), 0, s, pos, n, K, off, bb,
+                       (unsigned long long *)nullptr);
     return hipGetLastError();
 }
 
