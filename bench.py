@@ -136,6 +136,7 @@ def batched_leg(args, fmm, workloads, precision="fp64"):
     # over all particles is measured and reported below)
     eps = args.eps if args.eps is not None else 8e-8
     leaf, pf, p = args.leaf, args.p2p_factor, args.p
+    centre = args.centre or "auto"
     tuned = None
     explicit = bool(args.leaf or args.p2p_factor or args.p >= 0 or args.eps is not None)
     from paper_1405_2255_amd import autotune
@@ -144,6 +145,7 @@ def batched_leg(args, fmm, workloads, precision="fp64"):
     if hit is not None:
         cand, rec = hit
         leaf, pf, p, eps = cand.leaf_size, cand.p2p_factor, cand.p, cand.eps
+        centre = args.centre or cand.centre
         tuned = dict(rec, source="table")
     elif not (args.no_tune or explicit):
         # n_L, threshold factor, p and eps picked by the autotuner on every 8th
@@ -160,13 +162,14 @@ def batched_leg(args, fmm, workloads, precision="fp64"):
         if res.best is not None:
             b = res.best
             leaf, pf, p, eps = b.leaf_size, b.p2p_factor, b.p, b.eps
+            centre = args.centre or b.centre
         tuned = {"source": "tuned now",
                  "picked": None if res.best is None else dataclasses.asdict(res.best),
                  "sample_clusters": len(sub), "candidates": len(res.table),
                  "rms_on_sample": res.rms, "reference_rms_vs_direct": res.ref_rms,
                  "ms_on_sample": res.ms, "tune_s": t_tune}
         print(f"batched ({precision}): tuned {tuned}", file=sys.stderr, flush=True)
-    ctx = fmm.Context(device=0, centre=args.centre, leaf_size=leaf, p2p_factor=pf, timing=True,
+    ctx = fmm.Context(device=0, centre=centre, leaf_size=leaf, p2p_factor=pf, timing=True,
                       precision=precision)
     ctx.forces_batched(off, P, M, 1.0, p, eps, pot, acc)
     torch.cuda.synchronize()
@@ -187,7 +190,7 @@ def batched_leg(args, fmm, workloads, precision="fp64"):
     e = np.concatenate(errs)
     print(f"batched: errors checked on {len(errs)} clusters", file=sys.stderr, flush=True)
     # one call per cluster (after one warm pass that sizes the workspace)
-    single = fmm.Context(device=0, centre=args.centre, leaf_size=leaf, p2p_factor=pf, precision=precision)
+    single = fmm.Context(device=0, centre=centre, leaf_size=leaf, p2p_factor=pf, precision=precision)
     for i in range(k):
         a, b = int(off[i]), int(off[i + 1])
         single.forces(P[a:b], M[a:b], 1.0, p, eps, pot[a:b], acc[a:b])
@@ -222,9 +225,9 @@ def active_leg(args, fmm, pos, mass, params, full_ms):
     block time-step scheme would.  Each result is compared with the full call's
     values for the same particles (equal bitwise by construction)."""
     import torch
-    leaf, pf, p, eps = params
+    leaf, pf, p, eps, centre = params
     n = pos.shape[0]
-    full = fmm.Context(device=0, centre=args.centre, leaf_size=leaf, p2p_factor=pf)
+    full = fmm.Context(device=0, centre=centre, leaf_size=leaf, p2p_factor=pf)
     _, acc_full = full.forces(pos, mass, 1.0, p, eps)
     order = torch.argsort(torch.linalg.norm(pos, dim=1))
     rng = np.random.default_rng(args.seed + 9)
@@ -233,7 +236,7 @@ def active_leg(args, fmm, pos, mass, params, full_ms):
         np.sort(rng.choice(n, n // 100, replace=False))).to(pos.device)))
     # reference of the recycled calls: a full call on a recycled tree with the
     # previous call's |a| as the scale
-    prev = fmm.Context(device=0, centre=args.centre, leaf_size=leaf, p2p_factor=pf, scale_source="previous")
+    prev = fmm.Context(device=0, centre=centre, leaf_size=leaf, p2p_factor=pf, scale_source="previous")
     prev.forces(pos, mass, 1.0, p, eps)
     _, acc_prev = prev.forces(pos, mass, 1.0, p, eps, refit=True)
     torch.cuda.synchronize()
@@ -241,7 +244,7 @@ def active_leg(args, fmm, pos, mass, params, full_ms):
     runs = []
     for mode in ("fresh", "recycled"):
         ref = acc_prev if mode == "recycled" else acc_full
-        ctx = fmm.Context(device=0, centre=args.centre, leaf_size=leaf, p2p_factor=pf, timing=True,
+        ctx = fmm.Context(device=0, centre=centre, leaf_size=leaf, p2p_factor=pf, timing=True,
                           scale_source="previous" if mode == "recycled" else "estimate")
         for kind, k, idx in subsets:
             if mode == "recycled":
@@ -278,13 +281,13 @@ def eps_leg(args, fmm, pos, mass, params, full_ms, acc_direct):
     leaf size and threshold), timed against the main leg's global-eps call; rms
     relative force error of each group against the GPU direct sum."""
     import torch
-    leaf, pf, p, eps = params
+    leaf, pf, p, eps, centre = params
     n = pos.shape[0]
     r = torch.linalg.norm(pos, dim=1)
     inner = r <= torch.quantile(r[::97], 0.1)
     eps_b = torch.where(inner, torch.tensor(1e-7, dtype=torch.float64, device=pos.device),
                         torch.tensor(1e-5, dtype=torch.float64, device=pos.device)).contiguous()
-    ctx = fmm.Context(device=0, centre=args.centre, leaf_size=leaf, p2p_factor=pf, timing=True)
+    ctx = fmm.Context(device=0, centre=centre, leaf_size=leaf, p2p_factor=pf, timing=True)
     ctx.forces_eps(pos, mass, eps_b, 1.0, p)
     torch.cuda.synchronize()
     ts = []
@@ -318,12 +321,12 @@ def jerk_leg(args, fmm, workloads, pos, mass, params, main_stats):
     relative jerk and force errors on 2048 seeded sinks against the GPU
     direct sums."""
     import torch
-    leaf, pf, p, eps = params
+    leaf, pf, p, eps, centre = params
     n = pos.shape[0]
     _, vel = workloads.plummer(n, args.seed, with_velocities=True)
     V = torch.from_numpy(vel).to(pos.device)
     del vel
-    ctx = fmm.Context(device=0, centre=args.centre, leaf_size=leaf, p2p_factor=pf, timing=True)
+    ctx = fmm.Context(device=0, centre=centre, leaf_size=leaf, p2p_factor=pf, timing=True)
     ctx.forces_jerk(pos, V, mass, 1.0, p, eps)
     torch.cuda.synchronize()
     ts = []
@@ -367,7 +370,7 @@ def c3_leg(args, fmm, workloads):
         del pos, m
         sinks = torch.from_numpy(np.sort(np.random.default_rng(n).choice(n, 4096, replace=False))
                                  ).to(dev)
-        ctx = fmm.Context(device=0, centre=args.centre, timing=True, precision="mixed")
+        ctx = fmm.Context(device=0, centre=args.centre or "auto", timing=True, precision="mixed")
         _, ad = ctx.direct_sinks(P, M, sinks, 1.0)
         for target in (1e-5, 1e-7):
             eps = 0.5 * target
@@ -472,7 +475,7 @@ def serve_leg(args, fmm, workloads, capacity_pfs):
     # accuracy of the last step of every request with N <= 3e5 against the GPU
     # direct sum on the same drifted positions
     checks = []
-    ctx = fmm.Context(device=0, centre=args.centre)
+    ctx = fmm.Context(device=0, centre=args.centre or "auto")
     for i, q in enumerate(reqs):
         if sizes[i] > 300_000:
             continue
@@ -510,7 +513,7 @@ def north_star_leg(args, fmm, workloads, params):
     submission to result, and throughput."""
     import torch
     from paper_1405_2255_amd import serve
-    leaf, pf, p, eps = params
+    leaf, pf, p, eps, centre = params
     n, R, K = 10 ** 6, args.ns_requests, 4
     dev = torch.device("cuda:0")
     inputs = []
@@ -518,7 +521,7 @@ def north_star_leg(args, fmm, workloads, params):
         pos, m = workloads.cluster("plummer", n, args.seed + 7000 + k)
         inputs.append((torch.from_numpy(pos).to(dev), torch.from_numpy(m).to(dev)))
     srv = serve.Server(device=0, slots=args.ns_slots, leaf_size=leaf, p2p_factor=pf,
-                       precision="mixed")
+                       precision="mixed", centre=centre)
 
     def make(i):
         P, M = inputs[i % K]
@@ -535,7 +538,7 @@ def north_star_leg(args, fmm, workloads, params):
     print(f"north star: {R} requests queued at once in {t_cap:.3f} s, "
           f"{capacity:.4g} particle-forces/s", file=sys.stderr, flush=True)
     # accuracy of the served results of every input against the GPU direct sum
-    ctx = fmm.Context(device=0, centre=args.centre)
+    ctx = fmm.Context(device=0, centre=centre)
     acc_err, pooled = [], []
     for k in range(K):
         _, ad = ctx.direct(inputs[k][0], inputs[k][1], 1.0)
@@ -614,8 +617,9 @@ def main() -> int:
     ap.add_argument("--ns-slots", type=int, default=3)
     ap.add_argument("--ns-loads", type=lambda s: [float(x) for x in s.split(",") if x],
                     default=[0.5, 0.8, 0.95])
-    ap.add_argument("--centre", choices=["auto", "midpoint", "enclosing"], default="auto",
-                    help="expansion-centre rule of every context (Sec. 5.1.1)")
+    ap.add_argument("--centre", choices=["auto", "midpoint", "enclosing"], default=None,
+                    help="expansion-centre rule of every context (Sec. 5.1.1); default: the "
+                         "tuned rule where the parameters are tuned, else the library's")
     ap.add_argument("--no-cpu-fmm", action="store_true")
     ap.add_argument("--cpu-fmm-n", type=int, default=50000)
     ap.add_argument("--calib-copy", type=int, default=0,
@@ -647,20 +651,22 @@ def main() -> int:
     explicit = bool(args.leaf or args.p2p_factor or args.p >= 0 or args.eps is not None)
 
     def params(precision):
-        """(leaf, p2p_factor, p, eps, autotune record): the autotuner's choice
-        for rms <= target on a calibration sample (the same workload with
-        another seed) from the committed table, or tuned now (--retune or no
-        table entry); the library defaults and eps = 8e-8 (calibrated on this
-        workload) when parameters are given or --no-tune."""
+        """(leaf, p2p_factor, p, eps, centre rule, autotune record): the
+        autotuner's choice for rms <= target on a calibration sample (the same
+        workload with another seed) from the committed table, or tuned now
+        (--retune or no table entry); the library defaults and eps = 8e-8
+        (calibrated on this workload) when parameters are given or --no-tune.
+        --centre overrides the tuned rule."""
         if args.no_tune or explicit:
             return (args.leaf, args.p2p_factor, args.p,
-                    args.eps if args.eps is not None else 8e-8, None)
+                    args.eps if args.eps is not None else 8e-8, args.centre or "auto", None)
         from paper_1405_2255_amd import autotune
         hit = None if args.retune or n != 10 ** 6 else autotune.table_lookup("plummer_1e6",
                                                                               precision)
         if hit is not None:
             b, rec = hit
-            return b.leaf_size, b.p2p_factor, b.p, b.eps, dict(rec, source="table")
+            return (b.leaf_size, b.p2p_factor, b.p, b.eps, args.centre or b.centre,
+                    dict(rec, source="table"))
         cp, cm = workloads.cluster("plummer", n, args.seed + 1000)
         cp, cm = torch.from_numpy(cp).to(dev), torch.from_numpy(cm).to(dev)
         t0 = time.perf_counter()
@@ -673,17 +679,17 @@ def main() -> int:
                "picked": None if res.best is None else dataclasses.asdict(res.best)}
         print(f"autotune ({precision}): {rec}", file=sys.stderr, flush=True)
         if res.best is None:
-            return args.leaf, args.p2p_factor, args.p, 8e-8, rec
+            return args.leaf, args.p2p_factor, args.p, 8e-8, args.centre or "auto", rec
         b = res.best
-        return b.leaf_size, b.p2p_factor, b.p, b.eps, rec
+        return b.leaf_size, b.p2p_factor, b.p, b.eps, args.centre or b.centre, rec
 
-    leaf, pf, p_arg, eps, tuned = params("fp64")
+    leaf, pf, p_arg, eps, centre, tuned = params("fp64")
     pos_np, m_np = workloads.cluster("plummer", n, args.seed)
     pos = torch.from_numpy(pos_np).to(dev)
     mass = torch.from_numpy(m_np).to(dev)
     pot = torch.empty(n, dtype=torch.float64, device=dev)
     acc = torch.empty((n, 3), dtype=torch.float64, device=dev)
-    ctx = fmm.Context(device=0, centre=args.centre, leaf_size=leaf, p2p_factor=pf, timing=True)
+    ctx = fmm.Context(device=0, centre=centre, leaf_size=leaf, p2p_factor=pf, timing=True)
 
     for _ in range(args.warmup):
         ctx.forces(pos, mass, 1.0, p_arg, eps, pot, acc)
@@ -766,9 +772,9 @@ def main() -> int:
     roofline_fp32 = None
     tuned_mixed = None
     if not args.no_mixed:
-        leaf_m, pf_m, p_m, eps_m, tuned_m = params("mixed")
-        tuned_mixed = (leaf_m, pf_m, p_m, eps_m)
-        ctxm = fmm.Context(device=0, centre=args.centre, leaf_size=leaf_m, p2p_factor=pf_m, timing=True,
+        leaf_m, pf_m, p_m, eps_m, centre_m, tuned_m = params("mixed")
+        tuned_mixed = (leaf_m, pf_m, p_m, eps_m, centre_m)
+        ctxm = fmm.Context(device=0, centre=centre_m, leaf_size=leaf_m, p2p_factor=pf_m, timing=True,
                            precision="mixed")
         for _ in range(max(1, args.warmup)):
             ctxm.forces(pos, mass, 1.0, p_m, eps_m, pot, acc)
@@ -809,11 +815,11 @@ def main() -> int:
             roofline_fp32[k]["frac"] = roofline_fp32[k]["achieved"] / FP32_PEAK_TFLOPS
         mixed["roofline_fp32"] = roofline_fp32
     active = None if args.no_active else active_leg(args, fmm, pos, mass,
-                                                    (leaf, pf, p_arg, eps), ms_per_step)
-    eps_b = None if args.no_eps else eps_leg(args, fmm, pos, mass, (leaf, pf, st["p"], eps),
-                                             ms_per_step, ad_all)
+                                                    (leaf, pf, p_arg, eps, centre), ms_per_step)
+    eps_b = None if args.no_eps else eps_leg(args, fmm, pos, mass,
+                                             (leaf, pf, st["p"], eps, centre), ms_per_step, ad_all)
     jerk = None if args.no_jerk else jerk_leg(args, fmm, workloads, pos, mass,
-                                              (leaf, pf, st["p"], eps), st)
+                                              (leaf, pf, st["p"], eps, centre), st)
     batched = None
     if not args.no_batched:
         batched = {"fp64": batched_leg(args, fmm, workloads, "fp64"),
@@ -822,9 +828,9 @@ def main() -> int:
     served = None if args.no_serve else serve_leg(args, fmm, workloads, value)
     north = None
     if not args.no_north_star and tuned_mixed is not None:
-        lm, pfm, pm_, em = tuned_mixed
+        lm, pfm, pm_, em, cm = tuned_mixed
         north = north_star_leg(args, fmm, workloads,
-                               (lm or 32, pfm or 2.0, pm_ if pm_ > 0 else st["p"], em))
+                               (lm or 32, pfm or 2.0, pm_ if pm_ > 0 else st["p"], em, cm))
         north["roofline_fp32"] = roofline_fp32
         north["vs_plain_fp64"] = north["value"] / value
         north["vs_gpu_direct"] = north["value"] / direct["value"] if direct else None
@@ -838,7 +844,7 @@ def main() -> int:
         t3 = time.perf_counter()
         rf = oracle.fmm(pf_pos, pf_m, p=pp, eps=eps, leaf_size=leaf or 32,
                         p2p_pairs=(pf or 2.0) * (pp + 1) ** 3,
-                        centre=oracle.CENTRE_MIDPOINT if args.centre == "midpoint"
+                        centre=oracle.CENTRE_MIDPOINT if centre == "midpoint"
                         else oracle.CENTRE_ENCLOSING)
         t_fmm = time.perf_counter() - t3
         cpu_fmm = {"value": nf / t_fmm, "unit": "particle-forces/s", "cores": 1,
@@ -874,9 +880,9 @@ def main() -> int:
         "config": {"workload": f"Plummer sphere N={n}, equal masses, G=1, untruncated, seed "
                                f"{args.seed}; FP64 FMM, criterion a (eq:mac:better:a), "
                                f"eps={eps:g}, p={p}, n_L={leaf or 32}, "
-                               f"p2p_factor={pf or 2.0:g}",
+                               f"p2p_factor={pf or 2.0:g}, expansion centres: {centre}",
                    "n": n, "p": p, "eps": eps, "leaf_size": leaf or 32,
-                   "p2p_factor": pf or 2.0, "centre": args.centre,
+                   "p2p_factor": pf or 2.0, "centre": centre,
                    "parallelism": "single GPU"},
         "autotune": tuned,
         "errors": {"vs_oracle_sampled": err_oracle, "vs_gpu_direct_all": err_direct,

@@ -36,6 +36,7 @@ class Candidate:
     p2p_factor: float
     eps: float
     p: int
+    centre: str = "auto"    # expansion-centre rule: "auto", "midpoint" or "enclosing"
 
 
 @dataclasses.dataclass
@@ -48,19 +49,24 @@ class Result:
 
 
 def candidates(target: float, leaf_sizes=(32, 48, 64, 96, 128, 192), p2p_factors=(1.0, 2.0, 3.0),
-               kappas=(0.6, 0.75, 0.9), order_offsets=(0, 1)) -> list[Candidate]:
+               kappas=(0.6, 0.75, 0.9), order_offsets=(0, 1),
+               centres=("midpoint", "enclosing")) -> list[Candidate]:
     """The search grid: eps = kappa * target, p = the library's order for eps
-    plus an offset."""
+    plus an offset, and both expansion-centre rules (the enclosing-sphere
+    centre accepts more interactions at the same eps, which changes the error
+    of the worst particles as well as the cost, so the rule is tuned with the
+    rest)."""
     from . import fmm
     out = []
-    for leaf in leaf_sizes:
-        for pf in p2p_factors:
-            for k in kappas:
-                eps = k * target
-                p0 = fmm.order_for_error(eps)
-                for d in order_offsets:
-                    p = min(fmm.P_MAX, max(fmm.P_MIN, p0 + d))
-                    out.append(Candidate(int(leaf), float(pf), float(eps), int(p)))
+    for centre in centres:
+        for leaf in leaf_sizes:
+            for pf in p2p_factors:
+                for k in kappas:
+                    eps = k * target
+                    p0 = fmm.order_for_error(eps)
+                    for d in order_offsets:
+                        p = min(fmm.P_MAX, max(fmm.P_MIN, p0 + d))
+                        out.append(Candidate(int(leaf), float(pf), float(eps), int(p), centre))
     return list(dict.fromkeys(out))
 
 
@@ -171,7 +177,7 @@ def tune(pos, mass, target: float, *, offsets=None, precision: str = "fp64",
     table = []
     for cand in (grid if grid is not None else candidates(target)):
         ctx = fmm.Context(device=device, leaf_size=cand.leaf_size, p2p_factor=cand.p2p_factor,
-                          precision=precision)
+                          precision=precision, centre=cand.centre)
         acc = run(ctx, cand.p, cand.eps)
         d = rel(acc, a_ref)
         rms = float(torch.sqrt(torch.mean(d * d))) if d.numel() else 0.0
@@ -182,7 +188,7 @@ def tune(pos, mass, target: float, *, offsets=None, precision: str = "fp64",
     for row in ok[:finalists]:
         cand = row[0]
         ctx = fmm.Context(device=device, leaf_size=cand.leaf_size, p2p_factor=cand.p2p_factor,
-                          precision=precision)
+                          precision=precision, centre=cand.centre)
         run(ctx, cand.p, cand.eps)
         row[1] = min(row[1], _time(run, ctx, cand, repeats))
         ctx.close()
@@ -193,7 +199,7 @@ def tune(pos, mass, target: float, *, offsets=None, precision: str = "fp64",
         for row in sorted((r for r in table if r[2] <= margin * target), key=lambda r: r[1]):
             cand = row[0]
             ctx = fmm.Context(device=device, leaf_size=cand.leaf_size,
-                              p2p_factor=cand.p2p_factor, precision=precision)
+                              p2p_factor=cand.p2p_factor, precision=precision, centre=cand.centre)
             ss, cnt = row[2] ** 2 * pos.shape[0], pos.shape[0]
             for (vp, vm, voff), va in vrefs:
                 d = rel(_run(ctx, vp, vm, voff, cand.p, cand.eps), va)
@@ -248,7 +254,8 @@ def table_lookup(key: str, precision: str, path: str = TABLE_PATH):
     except (OSError, KeyError, ValueError):
         return None
     c = rec["picked"]
-    return Candidate(int(c["leaf_size"]), float(c["p2p_factor"]), float(c["eps"]), int(c["p"])), rec
+    return Candidate(int(c["leaf_size"]), float(c["p2p_factor"]), float(c["eps"]), int(c["p"]),
+                     str(c.get("centre", "auto"))), rec
 
 
 def _bench_workloads():

@@ -96,7 +96,8 @@ class Request:
 
 class Server:
     def __init__(self, device: int = 0, slots: int = 4, budget_bytes: int | None = None,
-                 leaf_size: int = 0, p2p_factor: float = 0.0, precision: str = "fp64"):
+                 leaf_size: int = 0, p2p_factor: float = 0.0, precision: str = "fp64",
+                 centre: str = "auto"):
         self.device = device
         if budget_bytes is None:
             free, total = torch.cuda.mem_get_info(device)
@@ -114,7 +115,7 @@ class Server:
                 st = torch.cuda.Stream(device=device)       # default priority
                 self.streams.append(st)
                 self.contexts.append(fmm.Context(device=device, stream=st, leaf_size=leaf_size,
-                                                 p2p_factor=p2p_factor,
+                                                 p2p_factor=p2p_factor, centre=centre,
                                                  scale_source="previous", timing=True,
                                                  precision=precision))
         self._threads = [threading.Thread(target=self._loop, daemon=True)

@@ -6,14 +6,18 @@ import pytest
 from paper_1405_2255_amd import autotune as A
 
 
-def test_grid_spans_leaf_threshold_and_order():
+def test_grid_spans_leaf_threshold_order_and_centre_rule():
     g = A.candidates(1e-7)
-    assert len(g) == len(set(g)) == 6 * 3 * 3 * 2
+    assert len(g) == len(set(g)) == 6 * 3 * 3 * 2 * 2
     from paper_1405_2255_amd import fmm
     for c in g:
         assert fmm.P_MIN <= c.p <= fmm.P_MAX
         assert c.eps in (0.6e-7, 0.75e-7, 0.9e-7)
         assert c.p - fmm.order_for_error(c.eps) in (0, 1)
+        assert c.centre in ("midpoint", "enclosing")
+    # each point of the grid under both centre rules
+    assert {(c.leaf_size, c.p2p_factor, c.eps, c.p) for c in g if c.centre == "midpoint"} == \
+        {(c.leaf_size, c.p2p_factor, c.eps, c.p) for c in g if c.centre == "enclosing"}
     # the library's own defaults (n_L = 32, factor 2, p from eps) are in the grid
     assert any(c.leaf_size == 32 and c.p2p_factor == 2.0 and c.p == fmm.order_for_error(c.eps)
                for c in g)
