@@ -32,7 +32,7 @@ def test_tune_single_cluster(gpu_lib):
     ok = [row for row in res.table if row[2] <= 0.9 * target]
     assert res.ms == min(row[1] for row in ok)
     b = res.best
-    ctx = gpu_lib.Context(leaf_size=b.leaf_size, p2p_factor=b.p2p_factor)
+    ctx = gpu_lib.Context(leaf_size=b.leaf_size, p2p_factor=b.p2p_factor, centre=b.centre)
     _, acc = ctx.forces(P, M, 1.0, b.p, b.eps)
     _, ad = ctx.direct(P, M, 1.0)
     torch.cuda.synchronize()

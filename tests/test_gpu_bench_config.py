@@ -1,12 +1,15 @@
-"""Parity with the oracle in the configuration the N = 10^6 benchmark runs:
-expansion order 15, leaf size 96, direct-sum threshold 2 (p+1)^3, eps 6e-8,
-on a Plummer sphere of 3e4 particles.  Leaves hold up to 96 particles, so the
-direct-sum kernel cuts a leaf's sinks into two 64-sink chunks, and the mean
-sink has more than 2048 direct sources, so leaves are split into several
-source tasks with ordered partial sums; both are asserted from the tree and
-the counts.  The register M2L kernel of order 15 (FP64 and mixed) and the
-jerk kernels at orders 15, 16 (the wide-column branch of the multipole-rate
-kernel) and 18 (the generic M2L of the rates) run here against the oracle.
+"""Parity with the oracle in the configurations the N = 10^6 benchmark runs
+(the tuned table): FP64 with leaf size 48, direct-sum threshold 2 (p+1)^3 and
+box-midpoint centres; mixed precision with leaf size 96, threshold 3 (p+1)^3
+and box-midpoint centres; both at order 15 and eps 6e-8, on a Plummer sphere
+of 3e4 particles.  A third FP64 case, leaf size 96 with enclosing-sphere
+centres, has leaves of more than 64 particles, so the direct-sum kernel cuts
+a leaf's sinks into two 64-sink chunks.  The mean sink has more than 2048
+direct sources, so leaves are split into several source tasks with ordered
+partial sums; both are asserted from the tree and the counts.  The register
+M2L kernel of order 15 (FP64 and mixed) and the jerk kernels at orders 15,
+16 (the wide-column branch of the multipole-rate kernel) and 18 (the generic
+M2L of the rates) run here against the oracle.
 
 Bounds as in the other parity tests: FP64 forces and potentials to 1e-10
 relative per particle, jerks to 1e-9; mixed precision within 64 u32 f_b of
@@ -19,8 +22,13 @@ from paper_1405_2255_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-N, P, LEAF, FACTOR, EPS = 30000, 15, 96, 2.0, 6e-8
+N, P, EPS = 30000, 15, 6e-8
 U32 = 2.0 ** -24
+CENTRE = {"midpoint": oracle.CENTRE_MIDPOINT, "enclosing": oracle.CENTRE_ENCLOSING}
+# (leaf size, threshold factor, centre rule)
+FP64_CASES = [(48, 2.0, "midpoint"), (96, 2.0, "enclosing")]
+MIXED_CASE = (96, 3.0, "midpoint")
+_refs = {}
 
 
 def _dev(a):
@@ -53,59 +61,70 @@ def workload():
     return pos, vel, np.full(N, 1.0 / N)
 
 
-@pytest.fixture(scope="module")
-def reference(workload):
-    pos, _, m = workload
-    return oracle.fmm(pos, m, p=P, eps=EPS, leaf_size=LEAF, p2p_pairs=FACTOR * (P + 1) ** 3,
-                      want_lists=True)
+def reference(workload, leaf, factor, centre):
+    key = (leaf, factor, centre)
+    if key not in _refs:
+        pos, _, m = workload
+        _refs[key] = oracle.fmm(pos, m, p=P, eps=EPS, leaf_size=leaf,
+                                p2p_pairs=factor * (P + 1) ** 3, want_lists=True,
+                                centre=CENTRE[centre])
+    return _refs[key]
 
 
-def test_fp64_matches_oracle(gpu_lib, workload, reference):
+@pytest.mark.parametrize("leaf,factor,centre", FP64_CASES)
+def test_fp64_matches_oracle(gpu_lib, workload, leaf, factor, centre):
     import torch
     pos, _, m = workload
-    print(f"bench config fp64 n={N} p={P} leaf={LEAF}", flush=True)
-    ctx = gpu_lib.Context(leaf_size=LEAF, p2p_factor=FACTOR)
+    print(f"bench config fp64 n={N} p={P} leaf={leaf} factor={factor} centre={centre}",
+          flush=True)
+    ref = reference(workload, leaf, factor, centre)
+    ctx = gpu_lib.Context(leaf_size=leaf, p2p_factor=factor, centre=centre)
     pot, acc = ctx.forces(_dev(pos), _dev(m), p=P, target_err=EPS)
     torch.cuda.synchronize()
     pot, acc = pot.cpu().numpy(), acc.cpu().numpy()
-    st, rs = ctx.stats(), reference["stats"]
+    st, rs = ctx.stats(), ref["stats"]
     # the paths this configuration exercises
     leaves = _leaf_sizes(ctx.export_cells())
-    assert len(leaves) == st["n_leaves"] and leaves.max() > 64
+    assert len(leaves) == st["n_leaves"]
+    if leaf > 64:
+        assert leaves.max() > 64
     assert st["n_p2p_pairs"] / N > 2048
     for k in ("n_cells", "n_leaves", "depth", "n_m2l", "n_p2p_pairs"):
         assert st[k] == rs[k], k
-    np.testing.assert_allclose(ctx.export_scale(), reference["scale"], rtol=1e-11)
-    e = _rel(acc, reference["acc"])
+    np.testing.assert_allclose(ctx.export_scale(), ref["scale"], rtol=1e-11)
+    e = _rel(acc, ref["acc"])
     print(f"max rel acc diff {e.max():.3e}", flush=True)
     assert e.max() < 1e-10
-    assert np.max(np.abs(pot - reference["pot"]) / np.abs(reference["pot"])) < 1e-10
+    assert np.max(np.abs(pot - ref["pot"]) / np.abs(ref["pot"])) < 1e-10
 
 
-def test_mixed_within_fp32_bound_of_oracle(gpu_lib, workload, reference):
+def test_mixed_within_fp32_bound_of_oracle(gpu_lib, workload):
     import torch
     pos, _, m = workload
-    print(f"bench config mixed n={N} p={P} leaf={LEAF}", flush=True)
-    ctx = gpu_lib.Context(leaf_size=LEAF, p2p_factor=FACTOR, precision="mixed")
+    leaf, factor, centre = MIXED_CASE
+    print(f"bench config mixed n={N} p={P} leaf={leaf} factor={factor} centre={centre}",
+          flush=True)
+    ref = reference(workload, leaf, factor, centre)
+    ctx = gpu_lib.Context(leaf_size=leaf, p2p_factor=factor, precision="mixed", centre=centre)
     pot, acc = ctx.forces(_dev(pos), _dev(m), p=P, target_err=EPS)
     torch.cuda.synchronize()
     pot, acc = pot.cpu().numpy(), acc.cpu().numpy()
     st = ctx.stats()
-    assert st["n_m2l"] == reference["stats"]["n_m2l"]
-    assert st["n_p2p_pairs"] == reference["stats"]["n_p2p_pairs"]
+    assert st["n_m2l"] == ref["stats"]["n_m2l"]
+    assert st["n_p2p_pairs"] == ref["stats"]["n_p2p_pairs"]
     p0, _, f0 = oracle.direct(pos, m)
-    ra = np.linalg.norm(reference["acc"], axis=1)
-    da = np.linalg.norm(acc - reference["acc"], axis=1)
+    ra = np.linalg.norm(ref["acc"], axis=1)
+    da = np.linalg.norm(acc - ref["acc"], axis=1)
     bound = 64 * U32 * f0 + 1e-10 * ra
     assert np.all(da <= bound), float(np.max(da / bound))
-    assert np.all(np.abs(pot - reference["pot"]) <= 64 * U32 * np.abs(p0)
-                  + 1e-10 * np.abs(reference["pot"]))
+    assert np.all(np.abs(pot - ref["pot"]) <= 64 * U32 * np.abs(p0)
+                  + 1e-10 * np.abs(ref["pot"]))
     rms = np.sqrt(np.mean((da / ra) ** 2))
     print(f"mixed vs fp64 oracle rms {rms:.3e}", flush=True)
     assert rms < 0.5e-7
 
 
-@pytest.mark.parametrize("n,p,leaf", [(N, P, LEAF), (8000, 16, 64), (5000, 18, 48)])
+@pytest.mark.parametrize("n,p,leaf", [(N, P, 96), (8000, 16, 64), (5000, 18, 48)])
 def test_jerk_matches_oracle(gpu_lib, workload, n, p, leaf):
     import torch
     if n == N:
@@ -114,11 +133,11 @@ def test_jerk_matches_oracle(gpu_lib, workload, n, p, leaf):
         pos, vel = W.plummer(n, 300 + p, with_velocities=True)
         m = np.full(n, 1.0 / n)
     print(f"bench config jerk n={n} p={p} leaf={leaf}", flush=True)
-    ctx = gpu_lib.Context(leaf_size=leaf, p2p_factor=FACTOR)
+    ctx = gpu_lib.Context(leaf_size=leaf, p2p_factor=2.0)
     pot, acc, jerk = ctx.forces_jerk(_dev(pos), _dev(vel), _dev(m), G=1.3, p=p, target_err=EPS)
     torch.cuda.synchronize()
     st = ctx.stats()
-    ref = oracle.fmm(pos, m, p=p, eps=EPS, leaf_size=leaf, p2p_pairs=FACTOR * (p + 1) ** 3,
+    ref = oracle.fmm(pos, m, p=p, eps=EPS, leaf_size=leaf, p2p_pairs=2.0 * (p + 1) ** 3,
                      G=1.3, vel=vel)
     assert st["n_m2l"] == ref["stats"]["n_m2l"] > 0
     assert st["n_p2p_pairs"] == ref["stats"]["n_p2p_pairs"]
