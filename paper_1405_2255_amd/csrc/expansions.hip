@@ -28,77 +28,97 @@ constexpr InvTable make_inv_table() {
 }
 __constant__ InvTable kInvN2M2 = make_inv_table();
 
-// ---- P2M: one wavefront per leaf, a lane per (particle, column m) ------------
-// M_n^m(z) = sum_a mu_a Upsilon_n^m(x_a - z).  Lanes are (particle slot,
-// column): C lanes per particle, lane `col` generates column m = col of its
-// particle's Upsilon - the diagonal Upsilon_m^m = prod_{j<=m} (x+iy)/(2j),
-// then Upsilon_{m+1}^m = z Upsilon_m^m and
-// (n^2 - m^2) Upsilon_n^m = (2n-1) z Upsilon_{n-1}^m - r^2 Upsilon_{n-2}^m -
-// and keeps the running sums of that column; the particle slots are added
-// with two cross-lane steps at the end.
+// ---- P2M: one wavefront per leaf, a lane per (particle, pair of columns) -----
+// M_n^m(z) = sum_a mu_a Upsilon_n^m(x_a - z).  Lanes are (particle slot, j):
+// CP lanes per particle, lane j generates columns m = j and m = P - j of its
+// particle's Upsilon (P + 2 coefficients in all, the same number on every
+// lane, where a lane per column would leave the upper triangle n < m idle):
+// the diagonal Upsilon_m^m = prod_{i<=m} (x+iy)/(2i), then
+// Upsilon_{m+1}^m = z Upsilon_m^m and
+// (n^2 - m^2) Upsilon_n^m = (2n-1) z Upsilon_{n-1}^m - r^2 Upsilon_{n-2}^m,
+// step t of the lane's sequence being (n, m) = (j + t, j) for t <= P - j and
+// (t - 1, P - j) after that.  Each lane keeps the running sums of its
+// sequence; the particle slots are added with cross-lane steps at the end.
+// For even P the middle column (j = P / 2) is generated once.
 template <int P>
 __global__ void __launch_bounds__(256)
 k_p2m(TreeArrays t, const int *leaf_cell, int nleaves, const double *x, const double *y,
       const double *z, const double *m, double *M) {
-    constexpr int C = P < 16 ? 16 : 32;       // lanes per particle (columns 0..P)
-    constexpr int SL = FMM_WAVE / C;          // particles per step
+    constexpr int NJ = P / 2 + 1;                              // column pairs (j <= P / 2)
+    constexpr int CP = NJ <= 2 ? 2 : NJ <= 4 ? 4 : NJ <= 8 ? 8 : NJ <= 16 ? 16 : 32;
+    constexpr int SL = FMM_WAVE / CP;                          // particles per step
+    constexpr int T = P + 2;                                   // steps per lane
     const int leaf = blockIdx.x * 4 + threadIdx.x / FMM_WAVE;
     if (leaf >= nleaves) return;
-    const int lane = lane_id(), col = lane % C, slot = lane / C;
+    const int lane = lane_id(), j = lane % CP, slot = lane / CP;
+    const bool on = j < NJ;
+    const int c1 = on ? j : 0, c2 = P - c1;
+    const int L1 = P + 1 - c1;             // steps of the first column
+    const bool two = c2 > c1;              // a second column (not the middle one)
     const int c = leaf_cell[leaf];
     const int beg = t.beg[c], end = t.end[c];
     const double4 cen = t.cen[c];
-    cplx acc[P + 1];
+    cplx acc[T];
 #pragma unroll
-    for (int n = 0; n <= P; ++n) acc[n] = {0.0, 0.0};
+    for (int q = 0; q < T; ++q) acc[q] = {0.0, 0.0};
     for (int i0 = beg; i0 < end; i0 += SL) {
         const int i = i0 + slot;
-        const bool valid = i < end && col <= P;
+        const bool valid = i < end && on;
         const double mu = valid ? m[i] : 0.0;
         const double dx = valid ? x[i] - cen.x : 0.0, dy = valid ? y[i] - cen.y : 0.0,
                      dz = valid ? z[i] - cen.z : 0.0;
         const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-        cplx d = {1.0, 0.0};
+        // the diagonals of both columns from one running product
+        cplx d = {1.0, 0.0}, d1 = {1.0, 0.0};
 #pragma unroll
-        for (int j = 1; j <= P; ++j) {
-            if (j <= col) {
-                const double h = 1.0 / (2.0 * j);
+        for (int k = 1; k <= P; ++k) {
+            if (k <= c2) {
+                const double h = 1.0 / (2.0 * k);
                 d = {h * (dx * d.re - dy * d.im), h * (dx * d.im + dy * d.re)};
             }
+            if (k == c1) d1 = d;
         }
         cplx u1 = {0.0, 0.0}, u2 = {0.0, 0.0};
 #pragma unroll
-        for (int n = 0; n <= P; ++n) {
+        for (int q = 0; q < T; ++q) {
+            const bool first = q < L1;
+            const int col = first ? c1 : c2;
+            const int n = first ? c1 + q : q - 1;
             cplx u;
-            if (n < col) {
-                u = {0.0, 0.0};
-            } else if (n == col) {
-                u = d;
+            if (q == 0 || q == L1) {
+                u = first ? d1 : d;
             } else if (n == col + 1) {
                 u = {dz * u1.re, dz * u1.im};
             } else {
-                const double inv = kInvN2M2.v[n][col < FMM_PMAX ? col : FMM_PMAX];
-                const double s = (2.0 * n - 1.0) * dz;
-                u = {(s * u1.re - r2 * u2.re) * inv, (s * u1.im - r2 * u2.im) * inv};
+                const double inv = kInvN2M2.v[n][col];
+                const double sc = (2.0 * n - 1.0) * dz;
+                u = {(sc * u1.re - r2 * u2.re) * inv, (sc * u1.im - r2 * u2.im) * inv};
             }
-            acc[n].re = fma(mu, u.re, acc[n].re);
-            acc[n].im = fma(mu, u.im, acc[n].im);
+            if (first || two) {
+                acc[q].re = fma(mu, u.re, acc[q].re);
+                acc[q].im = fma(mu, u.im, acc[q].im);
+            }
             u2 = u1;
             u1 = u;
         }
     }
 #pragma unroll
-    for (int off = C; off < FMM_WAVE; off <<= 1)
+    for (int off = CP; off < FMM_WAVE; off <<= 1)
 #pragma unroll
-        for (int n = 0; n <= P; ++n) {
-            acc[n].re += __shfl_xor(acc[n].re, off, FMM_WAVE);
-            acc[n].im += __shfl_xor(acc[n].im, off, FMM_WAVE);
+        for (int q = 0; q < T; ++q) {
+            acc[q].re += __shfl_xor(acc[q].re, off, FMM_WAVE);
+            acc[q].im += __shfl_xor(acc[q].im, off, FMM_WAVE);
         }
-    if (slot != 0 || col > P) return;
+    if (slot != 0 || !on) return;
     cplx *Mc = reinterpret_cast<cplx *>(M) + (size_t)c * tri(P + 1, 0);
 #pragma unroll
-    for (int n = 0; n <= P; ++n)
-        if (n >= col) Mc[tri(n, col)] = {acc[n].re, col == 0 ? 0.0 : acc[n].im};
+    for (int q = 0; q < T; ++q) {
+        const bool first = q < L1;
+        if (!first && !two) continue;
+        const int col = first ? c1 : c2;
+        const int n = first ? c1 + q : q - 1;
+        Mc[tri(n, col)] = {acc[q].re, col == 0 ? 0.0 : acc[q].im};
+    }
 }
 
 // ---- Upsilon of each cell's offset from its parent's centre -----------------

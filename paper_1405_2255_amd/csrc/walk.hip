@@ -101,6 +101,7 @@ __device__ __forceinline__ Decision decide(const WalkParams &wp, const TreeArray
 // is deterministic.
 constexpr int WALK_BLOCKS = 1024;
 constexpr int WALK_THREADS = 256;
+constexpr int WALK_WBATCH = 4;  // rounds whose loads the write kernel issues together
 
 __device__ __forceinline__ int64_t sweep_input(const WalkParams &wp,
                                                const unsigned long long *cnt, int sweep) {
@@ -259,63 +260,83 @@ k_walk_write(WalkParams wp, TreeArrays t, const double *P, WalkBuffers wb, int s
     int64_t of = (int64_t)pre[0];
     int64_t om = (int64_t)(m0 + pre[1]);
     int64_t op = (int64_t)(p0 + pre[2]);
-    for (int64_t base = lo; base < hi; base += WALK_THREADS) {
-        const int64_t i = base + threadIdx.x;
-        Decision d = {0, 0, 0.0};
-        int A = 0, B = 0;
-        if (i < hi) {                 // the decision the count pass took for this pair
-            const uint2 pr = wb.in[i];
-            A = (int)pr.x;
-            B = (int)pr.y;
-            const unsigned code = wb.code[i];
-            d.kind = (int)(code & 7u);
-            d.nf = (int)(code >> 3);
+    // WALK_WBATCH rounds of WALK_THREADS pairs at a time: the pairs, their
+    // decisions and the cell data their outputs need are loaded for all rounds
+    // first, then the rounds are scanned and written in frontier order
+    for (int64_t base0 = lo; base0 < hi; base0 += (int64_t)WALK_THREADS * WALK_WBATCH) {
+        int A[WALK_WBATCH], B[WALK_WBATCH], kind[WALK_WBATCH], nf[WALK_WBATCH];
+#pragma unroll
+        for (int r = 0; r < WALK_WBATCH; ++r) {
+            const int64_t i = base0 + (int64_t)r * WALK_THREADS + threadIdx.x;
+            const bool v = i < hi;    // the decision the count pass took for this pair
+            const uint2 pr = v ? wb.in[i] : make_uint2(0u, 0u);
+            const unsigned code = v ? wb.code[i] : 0u;
+            A[r] = (int)pr.x;
+            B[r] = (int)pr.y;
+            kind[r] = (int)(code & 7u);
+            nf[r] = (int)(code >> 3);
         }
-        int sf = d.nf, sm = d.kind == 5, sp = d.kind == 4;
-        int tot[3];
-        block_scan3(sf, sm, sp, tot);
-        const int64_t pf = of + sf - d.nf, pm = om + sm - (d.kind == 5), pp = op + sp - (d.kind == 4);
-        switch (d.kind) {
-        case 1: {   // all ordered daughter pairs of A
-            const int k0 = t.child0[A], nch = t.nchild[A];
-            if (pf + d.nf <= wb.cap_out)
-                for (int a = 0; a < nch; ++a)
-                    for (int b = 0; b < nch; ++b)
-                        wb.out[pf + a * nch + b] = make_uint2(k0 + a, k0 + b);
-            break;
+        int kA[WALK_WBATCH], kB[WALK_WBATCH], nchA[WALK_WBATCH], begA[WALK_WBATCH],
+            endA[WALK_WBATCH];
+#pragma unroll
+        for (int r = 0; r < WALK_WBATCH; ++r) {
+            kA[r] = t.child0[A[r]];
+            kB[r] = t.child0[B[r]];
+            nchA[r] = t.nchild[A[r]];
+            begA[r] = t.beg[A[r]];
+            endA[r] = t.end[A[r]];
         }
-        case 2: {
-            const int k0 = t.child0[A];
-            if (pf + d.nf <= wb.cap_out)
-                for (int a = 0; a < d.nf; ++a) wb.out[pf + a] = make_uint2(k0 + a, B);
-            break;
-        }
-        case 3: {
-            const int k0 = t.child0[B];
-            if (pf + d.nf <= wb.cap_out)
-                for (int b = 0; b < d.nf; ++b) wb.out[pf + b] = make_uint2(A, k0 + b);
-            break;
-        }
-        case 4:     // direct sum of A's particles onto B's (B may be any cell)
-            if (pp + 1 <= wb.cap_p2p) {
-                if (wp.pack) {
-                    wb.p2p[pp] = ((uint64_t)B << (2 * wp.pb)) | ((uint64_t)t.beg[A] << wp.pb) |
-                                 (uint64_t)t.end[A];
-                } else {
-                    wb.p2p[pp] = ((uint64_t)B << wp.pb) | (uint64_t)t.beg[A];
-                    wb.p2p_end[pp] = (uint32_t)t.end[A];
-                }
+#pragma unroll
+        for (int r = 0; r < WALK_WBATCH; ++r) {
+            if (base0 + (int64_t)r * WALK_THREADS >= hi) break;   // uniform over the block
+            const int k = kind[r], n = nf[r];
+            int sf = n, sm = k == 5, sp = k == 4;
+            int tot[3];
+            block_scan3(sf, sm, sp, tot);
+            const int64_t pf = of + sf - n, pm = om + sm - (k == 5), pp = op + sp - (k == 4);
+            const int a0 = A[r], b0 = B[r];
+            switch (k) {
+            case 1: {   // all ordered daughter pairs of A
+                const int k0 = kA[r], nch = nchA[r];
+                if (pf + n <= wb.cap_out)
+                    for (int a = 0; a < nch; ++a)
+                        for (int b = 0; b < nch; ++b)
+                            wb.out[pf + a * nch + b] = make_uint2(k0 + a, k0 + b);
+                break;
             }
-            break;
-        case 5:
-            if (pm + 1 <= wb.cap_m2l) wb.m2l[pm] = ((uint64_t)B << wp.sh) | (uint64_t)A;
-            break;
-        default:
-            break;
+            case 2: {
+                const int k0 = kA[r];
+                if (pf + n <= wb.cap_out)
+                    for (int a = 0; a < n; ++a) wb.out[pf + a] = make_uint2(k0 + a, b0);
+                break;
+            }
+            case 3: {
+                const int k0 = kB[r];
+                if (pf + n <= wb.cap_out)
+                    for (int b = 0; b < n; ++b) wb.out[pf + b] = make_uint2(a0, k0 + b);
+                break;
+            }
+            case 4:     // direct sum of A's particles onto B's (B may be any cell)
+                if (pp + 1 <= wb.cap_p2p) {
+                    if (wp.pack) {
+                        wb.p2p[pp] = ((uint64_t)b0 << (2 * wp.pb)) |
+                                     ((uint64_t)begA[r] << wp.pb) | (uint64_t)endA[r];
+                    } else {
+                        wb.p2p[pp] = ((uint64_t)b0 << wp.pb) | (uint64_t)begA[r];
+                        wb.p2p_end[pp] = (uint32_t)endA[r];
+                    }
+                }
+                break;
+            case 5:
+                if (pm + 1 <= wb.cap_m2l) wb.m2l[pm] = ((uint64_t)b0 << wp.sh) | (uint64_t)a0;
+                break;
+            default:
+                break;
+            }
+            of += tot[0];
+            om += tot[1];
+            op += tot[2];
         }
-        of += tot[0];
-        om += tot[1];
-        op += tot[2];
     }
 }
 
