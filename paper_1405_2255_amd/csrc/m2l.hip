@@ -7,7 +7,9 @@
 // (m2l_impl.h): for each source it generates Theta(s_B - z_A) one degree j at
 // a time (two rows of registers) and immediately adds every term with
 // n + k = j into its accumulators, reading the needed M_k of the source from
-// memory; when the accumulators of all (p+1)(p+2)/2 outputs would not fit in
+// memory (the multipoles of each row's first output degree, and the next
+// source's index and centre, one step ahead, since at one wavefront per SIMD
+// nothing else hides a load's latency); when the accumulators of all (p+1)(p+2)/2 outputs would not fit in
 // registers, the outputs are split by degree n into passes over the chunk,
 // each regenerating Theta.  Higher orders use the generic kernel below.
 // Each chunk writes its partial F; a second kernel adds the partial sums of

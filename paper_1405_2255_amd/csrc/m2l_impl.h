@@ -17,36 +17,54 @@ __host__ __device__ constexpr int pass_end(int p, int n0) {
     return n;
 }
 
-template <int P, int N0, int N1, int J>
-__device__ __forceinline__ void contract_row(cplx *acc, const cplx *th, const cplx *Ma) {
+// first output degree a row of the pass handles: the highest one, whose
+// multipoles (degree k = J - n, the fewest) are loaded one row ahead
+__host__ __device__ constexpr int first_n(int J, int N1) { return J < N1 ? J : N1; }
+
+template <int P, int N0, int J, int n>
+__device__ __forceinline__ void contract_one(cplx *acc, const cplx *th, const cplx *mk) {
+    constexpr int k = J - n;
 #pragma unroll
-    for (int n = N0; n <= (N1 < J ? N1 : J); ++n) {
-        const int k = J - n;
-        // M_k^l for l = 0..k, loaded once for this row
+    for (int m = 0; m <= n; ++m) {
+        cplx &a = acc[tri(n, m) - tri(N0, 0)];
+#pragma unroll
+        for (int l = -k; l <= k; ++l) {
+            const int q = m + l;
+            if (q > J || q < -J) continue;
+            // conj(M_k^l): for l < 0, M_k^l = (-1)^l conj(M_k^{-l})
+            const cplx mv = mk[l < 0 ? -l : l];
+            const double sl = (l < 0 && (l & 1)) ? -1.0 : 1.0;
+            const double cr = sl * mv.re;
+            const double ci = (l < 0) ? sl * mv.im : -mv.im;   // conj(M_k^l) = cr + i ci
+            const cplx tv = th[q < 0 ? -q : q];
+            const double sq = (q < 0 && (q & 1)) ? -1.0 : 1.0;
+            const double tr = sq * tv.re;
+            const double ti = (q < 0) ? -sq * tv.im : tv.im;    // Theta_J^q = tr + i ti
+            a.re = fma(cr, tr, fma(-ci, ti, a.re));
+            if (m != 0) a.im = fma(cr, ti, fma(ci, tr, a.im));
+        }
+    }
+}
+
+// row J, output degrees n = n1 .. N0 (descending): loads M_k (k = J - n) of
+// the source and adds the terms; degree first_n is done by the caller from
+// the multipoles it loaded one row ahead
+template <int P, int N0, int N1, int J, int n>
+__device__ __forceinline__ void contract_rest(cplx *acc, const cplx *th, const cplx *Ma) {
+    if constexpr (n >= N0) {
+        constexpr int k = J - n;
         cplx mk[P + 1];
 #pragma unroll
         for (int l = 0; l <= k; ++l) mk[l] = Ma[tri(k, l)];
-#pragma unroll
-        for (int m = 0; m <= n; ++m) {
-            cplx &a = acc[tri(n, m) - tri(N0, 0)];
-#pragma unroll
-            for (int l = -k; l <= k; ++l) {
-                const int q = m + l;
-                if (q > J || q < -J) continue;
-                // conj(M_k^l): for l < 0, M_k^l = (-1)^l conj(M_k^{-l})
-                const cplx mv = mk[l < 0 ? -l : l];
-                const double sl = (l < 0 && (l & 1)) ? -1.0 : 1.0;
-                const double cr = sl * mv.re;
-                const double ci = (l < 0) ? sl * mv.im : -mv.im;   // conj(M_k^l) = cr + i ci
-                const cplx tv = th[q < 0 ? -q : q];
-                const double sq = (q < 0 && (q & 1)) ? -1.0 : 1.0;
-                const double tr = sq * tv.re;
-                const double ti = (q < 0) ? -sq * tv.im : tv.im;    // Theta_J^q = tr + i ti
-                a.re = fma(cr, tr, fma(-ci, ti, a.re));
-                if (m != 0) a.im = fma(cr, ti, fma(ci, tr, a.im));
-            }
-        }
+        contract_one<P, N0, J, n>(acc, th, mk);
+        contract_rest<P, N0, N1, J, n - 1>(acc, th, Ma);
     }
+}
+
+// every term of row J for the output degrees N0..N1, multipoles loaded here
+template <int P, int N0, int N1, int J>
+__device__ __forceinline__ void contract_row(cplx *acc, const cplx *th, const cplx *Ma) {
+    contract_rest<P, N0, N1, J, first_n(J, N1)>(acc, th, Ma);
 }
 
 template <int P, int N0, int N1>
@@ -58,19 +76,44 @@ __device__ __forceinline__ void m2l_pass(int B, int e0, int e1, const uint64_t *
 #pragma unroll
     for (int i = 0; i < NACC; ++i) acc[i] = {0.0, 0.0};
     const double4 cb = t.cen[B];
+    int A = (int)(list[e0] & mask);
+    double4 ca = t.cen[A];
     for (int e = e0; e < e1; ++e) {
-        const int A = (int)(list[e] & mask);
-        const double4 ca = t.cen[A];
+        // the next source's index now, its centre a few rows into this one, so
+        // that neither load stalls the start of the next source
+        const int An = (int)(list[e + 1 < e1 ? e + 1 : e] & mask);
+        double4 can;
         const cplx *Ma = M + (size_t)A * tri(P + 1, 0);
         RowGen<P> g;
         g.theta_start(cb.x - ca.x, cb.y - ca.y, cb.z - ca.z);
+        // multipoles of the first output degree of each row, loaded during
+        // the row before (a row's loads otherwise stall its first terms)
+        cplx pre[P + 1];
+        if constexpr (N0 == 0) pre[0] = Ma[0];
         auto row = [&]<int J>() {
             if constexpr (J > 0) g.template theta_row<J>();
-            if constexpr (J >= N0) contract_row<P, N0, N1, J>(acc, g.template row<J>(), Ma);
+            constexpr int k1 = (J + 1) - first_n(J + 1, N1);
+            cplx nxt[P + 1];
+            if constexpr (J + 1 <= P && J + 1 >= N0) {
+#pragma unroll
+                for (int l = 0; l <= k1; ++l) nxt[l] = Ma[tri(k1, l)];
+            }
+            if constexpr (J == (P < 4 ? P : 4)) can = t.cen[An];
+            if constexpr (J >= N0) {
+                constexpr int n1 = first_n(J, N1);
+                contract_rest<P, N0, N1, J, n1 - 1>(acc, g.template row<J>(), Ma);
+                contract_one<P, N0, J, n1>(acc, g.template row<J>(), pre);
+            }
             // reload the multipoles for every degree instead of keeping them live
             __asm__ volatile("" ::: "memory");
+            if constexpr (J + 1 <= P && J + 1 >= N0) {
+#pragma unroll
+                for (int l = 0; l <= k1; ++l) pre[l] = nxt[l];
+            }
         };
         Unroll<0, P>::run(row);
+        A = An;
+        ca = can;
     }
 #pragma unroll
     for (int i = 0; i < NACC; ++i) out[tri(N0, 0) + i] = acc[i];
