@@ -24,18 +24,32 @@ from . import fmm
 
 
 class Admission:
-    """FIFO admission by slots and bytes (no GPU needed).  The head request
-    waits until a slot is free and its footprint fits next to the running
-    ones; a request larger than the whole budget is refused."""
+    """FIFO admission by slots and bytes (no GPU needed).
+
+    Each slot's library context keeps its buffers at the largest size it has
+    needed, so the budget counts what every slot holds, idle or not: held[s]
+    is the largest footprint slot s has run.  The head request starts on the
+    free slot that grows least, once the held bytes after it fit the budget.
+    If they fit only without some idle slots' buffers, those slots are listed
+    to be emptied first (the caller recreates their contexts).  A request
+    larger than the whole budget is refused."""
 
     def __init__(self, slots: int, budget_bytes: int):
         if slots < 1 or budget_bytes <= 0:
             raise ValueError("need at least one slot and a positive budget")
         self.slots = slots
         self.budget = int(budget_bytes)
-        self.used = 0
-        self.running = 0
+        self.held = [0] * slots
+        self.free = list(range(slots))
         self.queue: collections.deque = collections.deque()
+
+    @property
+    def running(self) -> int:
+        return self.slots - len(self.free)
+
+    @property
+    def used(self) -> int:
+        return sum(self.held)
 
     def push(self, item, nbytes: int) -> bool:
         if nbytes > self.budget:
@@ -44,20 +58,32 @@ class Admission:
         return True
 
     def pop_admissible(self):
-        """The head of the queue if it can start now, else None."""
-        if not self.queue or self.running >= self.slots:
+        """(item, nbytes, slot, slots to empty first) for the head of the
+        queue if it can start now, else None."""
+        if not self.queue or not self.free:
             return None
         item, nbytes = self.queue[0]
-        if self.used + nbytes > self.budget:
+        # the free slot that needs the least growth; ties to the lower slot
+        slot = min(self.free, key=lambda s: (max(0, nbytes - self.held[s]), s))
+        need = self.used - self.held[slot] + max(self.held[slot], nbytes)
+        empty = []
+        for s in sorted((s for s in self.free if s != slot and self.held[s] > 0),
+                        key=lambda s: (-self.held[s], s)):
+            if need <= self.budget:
+                break
+            need -= self.held[s]
+            empty.append(s)
+        if need > self.budget:
             return None
         self.queue.popleft()
-        self.used += nbytes
-        self.running += 1
-        return item, nbytes
+        for s in empty:
+            self.held[s] = 0
+        self.held[slot] = max(self.held[slot], nbytes)
+        self.free.remove(slot)
+        return item, nbytes, slot, empty
 
-    def release(self, nbytes: int):
-        self.used -= nbytes
-        self.running -= 1
+    def release(self, slot: int):
+        self.free.append(slot)
 
 
 @dataclasses.dataclass
@@ -107,21 +133,22 @@ class Server:
         self.closed = False
         self.completed: list[Request] = []
         self.max_running = 0
-        self._free_slots = list(range(slots))
+        self._ctx_args = dict(device=device, leaf_size=leaf_size, p2p_factor=p2p_factor,
+                              centre=centre, scale_source="previous", timing=True,
+                              precision=precision)
         self.streams = []
         self.contexts = []
         with torch.cuda.device(device):
-            for _ in range(slots):
-                st = torch.cuda.Stream(device=device)       # default priority
-                self.streams.append(st)
-                self.contexts.append(fmm.Context(device=device, stream=st, leaf_size=leaf_size,
-                                                 p2p_factor=p2p_factor, centre=centre,
-                                                 scale_source="previous", timing=True,
-                                                 precision=precision))
+            for s in range(slots):
+                self.streams.append(torch.cuda.Stream(device=device))   # default priority
+                self.contexts.append(self._context(s))
         self._threads = [threading.Thread(target=self._loop, daemon=True)
                          for _ in range(slots)]
         for t in self._threads:
             t.start()
+
+    def _context(self, slot: int):
+        return fmm.Context(stream=self.streams[slot], **self._ctx_args)
 
     # ------------------------------------------------------------- client
     def submit(self, req: Request) -> Request:
@@ -154,14 +181,16 @@ class Server:
         while True:
             with self.cv:
                 while True:
-                    got = self.adm.pop_admissible() if self._free_slots else None
+                    got = self.adm.pop_admissible()
                     if got is not None:
                         break
                     if self.closed and not self.adm.queue:
                         return
                     self.cv.wait()
-                req, nbytes = got
-                slot = self._free_slots.pop()
+                req, nbytes, slot, empty = got
+                for s in empty:     # idle slots whose buffers must go for this one
+                    self.contexts[s].close()
+                    self.contexts[s] = self._context(s)
                 self.max_running = max(self.max_running, self.adm.running)
             try:
                 self._run(slot, req)
@@ -170,8 +199,7 @@ class Server:
             finally:
                 req.t_end = time.perf_counter()
                 with self.cv:
-                    self.adm.release(nbytes)
-                    self._free_slots.append(slot)
+                    self.adm.release(slot)
                     self.completed.append(req)
                     self.cv.notify_all()
                 req.done.set()
