@@ -494,8 +494,12 @@ uint64_t *sort_list(fmm_ctx *c, DevBuf &a, DevBuf &b, int64_t nlist, int nsinks,
 }
 
 // sort the direct-sum entries by (sink cell, first source particle), merge
-// adjacent source ranges of each sink and index the ranges by sink cell
-void prepare_p2p(fmm_ctx *c, int64_t nlist) {
+// adjacent source ranges of each sink and index the ranges by sink cell.
+// by_source false: by sink cell only (stable, so each sink keeps the walk's
+// order), merging the ranges that the walk emitted next to each other - two
+// radix passes fewer; used for the estimate's short lists, where the longer
+// range lists cost the direct-sum kernel nothing measurable
+void prepare_p2p(fmm_ctx *c, int64_t nlist, bool by_source) {
     hipStream_t s = c->stream;
     uint64_t *k1 = ptr<uint64_t>(c->p2p);
     uint64_t *k2 = ensure<uint64_t>(c->p2p2, std::max<int64_t>(nlist, 1));
@@ -503,8 +507,12 @@ void prepare_p2p(fmm_ctx *c, int64_t nlist) {
     uint32_t *v2 = ensure<uint32_t>(c->p2pe2, std::max<int64_t>(nlist, 1));
     int *tmp = tmp_ints(c, std::max(sort_tmp_ints(nlist), scan_tmp_ints(nlist + 1)));
     // packed keys (the range end in the low pb bits) sort without a value array
-    if (c->pack) CK(radix_sort(&k1, &k2, nullptr, nullptr, nlist, c->sh + c->pb, tmp, s, c->pb));
-    else CK(radix_sort(&k1, &k2, &v1, &v2, nlist, c->sh + c->pb, tmp, s));
+    // key bits sorted on: (sink, first particle), or the sink alone
+    const int first = c->pack ? c->pb : 0;   // lowest bit of the first particle
+    const int lo = by_source ? first : first + c->pb;
+    const int bits = by_source ? c->sh + c->pb : c->sh;
+    if (c->pack) CK(radix_sort(&k1, &k2, nullptr, nullptr, nlist, bits, tmp, s, lo));
+    else CK(radix_sort(&k1, &k2, &v1, &v2, nlist, bits, tmp, s, lo));
     c->p2p_sorted = k1;
     c->p2pe_sorted = v1;
     int *flag = ensure<int>(c->rflag, (size_t)nlist + 2);
@@ -593,7 +601,7 @@ void sink_scale(fmm_ctx *c, bool want_f, const double *eps_b) {
         c->st.n_est_m2l = L.n_m2l;
         c->st.n_est_p2p_pairs = L.pairs;
         uint64_t *ml = sort_list(c, c->m2l, c->m2l2, L.n_m2l, c->ncells, c->m2l_off);
-        prepare_p2p(c, L.n_p2p);
+        prepare_p2p(c, L.n_p2p, false);
         double4 *Fe = ensure<double4>(c->Fe, c->ncells);
         CK(launch_est_m2l(want_f, t, c->ncells, ptr<int64_t>(c->m2l_off), ml, c->sh, Fe, s));
         for (int Lv = 1; Lv <= c->depth; ++Lv)
@@ -702,7 +710,7 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
     c->st.n_p2p_lists = L.n_p2p;
     c->st.n_p2p_pairs = L.pairs;
     c->m2l_sorted = sort_list(c, c->m2l, c->m2l2, L.n_m2l, c->ncells, c->m2l_off);
-    prepare_p2p(c, L.n_p2p);
+    prepare_p2p(c, L.n_p2p, true);
     mark(c, PH_WALK);
     // M2L: the rotation kernel over 64-entry windows of the list, or the
     // direct kernel by chunks of one sink's list
