@@ -480,9 +480,15 @@ inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 // The items of one translation: each output's rows of k are cut, in order,
 // into items of at most T terms (T = the larger of the cell's terms / 256
-// and the longest row), then the items are dealt longest first to the
-// thread with the least work (ties to the lower thread), at most XF_IT each;
-// 4 extra units per item stand for its set-up.  Deterministic.
+// and the longest row).  The lanes of a wavefront run their items' loops in
+// lockstep (rows of k, then the terms of each row), so a wavefront costs the
+// longest of its lanes at every step: items are therefore ordered by shape
+// (number of rows, first row, then longest first) and dealt in runs of 64
+// consecutive ones, one run per wavefront and round; runs go, costliest
+// first, to the wavefront with the least work so far (at most XF_IT each).
+// A run's cost models its lockstep loops: per row a fixed set-up, per four
+// terms of the row's longest lane one unrolled step, per leftover term one
+// single step.  Deterministic.
 static void item_plan(int p, bool m2m, short *plan) {
     const int nc = tri(p + 1, 0);
     auto row = [&](int n, int m, int k) -> int {
@@ -524,19 +530,49 @@ static void item_plan(int p, bool m2m, short *plan) {
     if ((int)items.size() > XF_ITEMS) throw std::runtime_error("translation plan: too many items");
     std::vector<int> order(items.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return items[a].cost > items[b].cost; });
-    std::vector<long> load(XF_THREADS, 0);
-    std::vector<int> cnt(XF_THREADS, 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const Item &x = items[a], &y = items[b];
+        if (x.k1 - x.k0 != y.k1 - y.k0) return x.k1 - x.k0 < y.k1 - y.k0;
+        if (x.k0 != y.k0) return x.k0 < y.k0;
+        return x.cost > y.cost;
+    });
+    constexpr int W = 64;                        // lanes per wavefront
+    constexpr int NW = XF_THREADS / W;
+    struct Run { int begin, end; long cost; };
+    std::vector<Run> runs;
+    for (int j = 0; j < (int)order.size(); j += W) {
+        Run r{j, std::min(j + W, (int)order.size()), 10};
+        for (int row_i = 0;; ++row_i) {
+            int longest_q = -1, longest_r = 0;
+            for (int t = r.begin; t < r.end; ++t) {
+                const Item &it = items[order[t]];
+                if (it.k0 + row_i > it.k1) continue;
+                const int len = row(it.n, it.m, it.k0 + row_i);
+                longest_q = std::max(longest_q, len / 4);
+                longest_r = std::max(longest_r, len % 4);
+            }
+            if (longest_q < 0) break;
+            r.cost += 20 + 20 * longest_q + 8 * longest_r;
+        }
+        runs.push_back(r);
+    }
+    std::vector<int> by_cost(runs.size());
+    for (size_t i = 0; i < by_cost.size(); ++i) by_cost[i] = (int)i;
+    std::stable_sort(by_cost.begin(), by_cost.end(),
+                     [&](int a, int b) { return runs[a].cost > runs[b].cost; });
+    std::vector<long> load(NW, 0);
+    std::vector<int> rounds(NW, 0);
     for (int i = 0; i < XP_SIZE; ++i) plan[i] = -1;
-    for (int i : order) {
+    for (int ri : by_cost) {
         int best = -1;
-        for (int l = 0; l < XF_THREADS; ++l)
-            if (cnt[l] < XF_IT && (best < 0 || load[l] < load[best])) best = l;
+        for (int w = 0; w < NW; ++w)
+            if (rounds[w] < XF_IT && (best < 0 || load[w] < load[best])) best = w;
         if (best < 0) throw std::runtime_error("translation plan: too few threads");
-        plan[XP_LANE + cnt[best] * XF_THREADS + best] = (short)i;
-        ++cnt[best];
-        load[best] += items[i].cost + 4;
+        for (int t = runs[ri].begin; t < runs[ri].end; ++t)
+            plan[XP_LANE + rounds[best] * XF_THREADS + best * W + (t - runs[ri].begin)] =
+                (short)order[t];
+        ++rounds[best];
+        load[best] += runs[ri].cost;
     }
     for (size_t i = 0; i < items.size(); ++i) {
         plan[XP_N + i] = (short)items[i].n;

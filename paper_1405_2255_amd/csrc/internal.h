@@ -126,8 +126,9 @@ hipError_t launch_shift_upsilon(int p, const TreeArrays &t, int c0, int c1, doub
 // Work plans of the translation kernels (M2M, L2L), one block of XF_THREADS
 // threads per cell.  Each output coefficient's sum over k is cut into items
 // of consecutive k with about equal numbers of terms, the items are dealt to
-// the threads (at most XF_IT each, longest first to the least loaded), and
-// each output adds its items' partial sums in item order.  Layout (short):
+// the threads (at most XF_IT each, in runs of 64 items of one shape per
+// wavefront), and each output adds its items' partial sums in item order.
+// Layout (short):
 // item i has degree n, order m and rows k0..k1 at XP_N/XP_M/XP_K0/XP_K1 + i;
 // thread t's r-th item (or -1) at XP_LANE + r * XF_THREADS + t; the items of
 // output e (stored index tri(n, m)) are [XP_OUT + e], [XP_OUT + e + 1]).
