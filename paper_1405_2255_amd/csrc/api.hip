@@ -657,43 +657,51 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
         cell_active = ca;
     }
     mark(c, PH_TREE);
-    const bool want_f = c->opts.mac == FMM_MAC_SCALED;
-    if (c->opts.mac != FMM_MAC_THETA) sink_scale(c, want_f, eps_b);
-    join_centres(c);
-    mark(c, PH_EST);
-    // upward pass
+    // Upward pass on the side stream, after the tree (and, on the same stream,
+    // after the enclosing-sphere centres): it overlaps the sink-scale estimate,
+    // which reads only centres of mass and masses, and writes nothing the
+    // estimate reads.  The main stream joins it before the walk, which needs
+    // the expansion centres and the multipole powers.  Both are chains of
+    // small latency-bound launches, so each fills the other's idle units.
     const int nc = ncplx(p);
     double *M = ensure<double>(c->M, 2 * (size_t)nc * c->ncells);
     double *U = ensure<double>(c->U, 2 * (size_t)nc * c->ncells);
     double *P = ensure<double>(c->P, (size_t)(p + 1) * c->ncells);
-    CK(launch_p2m(p, t, ptr<int>(c->leaf_cell), c->nleaves, ptr<double>(c->x), ptr<double>(c->y),
-                  ptr<double>(c->z), ptr<double>(c->m), M, s));
-    if (c->ncells > 1) CK(launch_shift_upsilon(p, t, 1, c->ncells, U, s));
     short *plans = ensure<short>(c->plans, 2 * XP_SIZE);
+    double *Tsh = ensure<double>(c->Tsh, 2 * (size_t)nc * c->ncells);
+    double4 *v4 = vel ? ensure<double4>(c->vel4, n) : nullptr;
+    double *Md = vel ? ensure<double>(c->Md, 2 * (size_t)nc * c->ncells) : nullptr;
+    const hipStream_t us = c->side;
+    CK(hipEventRecord(c->ev_fork, s));
+    CK(hipStreamWaitEvent(us, c->ev_fork, 0));
     if (c->plan_p != p) {
         std::vector<short> h(2 * XP_SIZE);
         translation_plans(p, h.data(), h.data() + XP_SIZE);
-        CK(hipMemcpyAsync(plans, h.data(), h.size() * sizeof(short), hipMemcpyHostToDevice, s));
-        sync(c);
+        CK(hipMemcpyAsync(plans, h.data(), h.size() * sizeof(short), hipMemcpyHostToDevice, us));
+        CK(hipStreamSynchronize(us));
         c->plan_p = p;
     }
-    double *Tsh = ensure<double>(c->Tsh, 2 * (size_t)nc * c->ncells);
+    CK(launch_p2m(p, t, ptr<int>(c->leaf_cell), c->nleaves, ptr<double>(c->x), ptr<double>(c->y),
+                  ptr<double>(c->z), ptr<double>(c->m), M, us));
+    if (c->ncells > 1) CK(launch_shift_upsilon(p, t, 1, c->ncells, U, us));
     for (int L = c->depth; L >= 0; --L)
-        CK(launch_m2m_level(p, t, c->ls[L], c->ls[L + 1], U, M, Tsh, plans, s));
-    CK(launch_power(p, c->ncells, M, P, s));
+        CK(launch_m2m_level(p, t, c->ls[L], c->ls[L + 1], U, M, Tsh, plans, us));
+    CK(launch_power(p, c->ncells, M, P, us));
     // jerk: rates of the multipoles (eq:P2M:dot, then the same M2M with the
     // centres at rest; Tsh is free again once M is complete)
-    double4 *v4 = nullptr;
-    double *Md = nullptr;
     if (vel) {
-        v4 = ensure<double4>(c->vel4, n);
-        Md = ensure<double>(c->Md, 2 * (size_t)nc * c->ncells);
-        CK(launch_gather_vel(n, c->perm, vel, v4, s));
+        CK(launch_gather_vel(n, c->perm, vel, v4, us));
         CK(launch_p2m_dot(p, t, ptr<int>(c->leaf_cell), c->nleaves, ptr<double>(c->x),
-                          ptr<double>(c->y), ptr<double>(c->z), ptr<double>(c->m), v4, Md, s));
+                          ptr<double>(c->y), ptr<double>(c->z), ptr<double>(c->m), v4, Md, us));
         for (int L = c->depth; L >= 0; --L)
-            CK(launch_m2m_level(p, t, c->ls[L], c->ls[L + 1], U, Md, Tsh, plans, s));
+            CK(launch_m2m_level(p, t, c->ls[L], c->ls[L + 1], U, Md, Tsh, plans, us));
     }
+    CK(hipEventRecord(c->ev_join, us));
+    c->join_pending = true;
+    const bool want_f = c->opts.mac == FMM_MAC_SCALED;
+    if (c->opts.mac != FMM_MAC_THETA) sink_scale(c, want_f, eps_b);
+    mark(c, PH_EST);
+    join_centres(c);
     mark(c, PH_UP);
     // walk
     WalkParams wp{c->opts.mac == FMM_MAC_THETA ? 1 : 0, p, eps, c->opts.theta_crit,
