@@ -136,7 +136,10 @@ typedef struct {
     int64_t n_est_m2l, n_est_p2p_pairs; /* the same for the estimate pass */
     int walk_iterations;         /* breadth-first walk sweeps (main pass) */
     /* milliseconds, measured with HIP events when fmm_opts.timing != 0
-       (phases as in the paper's tab:complexity) */
+       (phases as in the paper's tab:complexity).  Two pairs of phases run at
+       the same time on two streams: t_up is the part of the upward pass that
+       the estimate does not hide, and t_m2l includes the sorting and merging
+       of the direct-sum list, which runs beside M2L. */
     double t_tree, t_estimate, t_up, t_walk, t_m2l, t_p2p, t_down, t_total;
     /* average duration of one launch of the M2L and P2P kernels (ms) */
     double t_m2l_kernel, t_p2p_kernel;

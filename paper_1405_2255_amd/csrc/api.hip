@@ -126,7 +126,8 @@ struct fmm_ctx {
     fmm_stats_t st{};
 
     // particles
-    DevBuf bbox, key, key2, idx, idx2, x, y, z, m, xyzm, leaf_of, out4, est4, scale, flags, tmp;
+    DevBuf bbox, key, key2, idx, idx2, x, y, z, m, xyzm, leaf_of, out4, est4, scale, flags, tmp,
+        tmp_side;
     uint32_t *perm = nullptr;  // points into idx or idx2
     // cells
     DevBuf beg, end, parent, child0, nchild, level, leaf_lo, leaf_hi, cen, com, mass, lo, hi,
@@ -499,13 +500,17 @@ uint64_t *sort_list(fmm_ctx *c, DevBuf &a, DevBuf &b, int64_t nlist, int nsinks,
 // order), merging the ranges that the walk emitted next to each other - two
 // radix passes fewer; used for the estimate's short lists, where the longer
 // range lists cost the direct-sum kernel nothing measurable
-void prepare_p2p(fmm_ctx *c, int64_t nlist, bool by_source) {
-    hipStream_t s = c->stream;
+// side: on the side stream, with its own scratch, device counter and host
+// slot, so that it can run while the main stream does M2L (the caller joins
+// the side stream before the lists are used)
+void prepare_p2p(fmm_ctx *c, int64_t nlist, bool by_source, bool side = false) {
+    const hipStream_t s = side ? c->side : c->stream;
     uint64_t *k1 = ptr<uint64_t>(c->p2p);
     uint64_t *k2 = ensure<uint64_t>(c->p2p2, std::max<int64_t>(nlist, 1));
     uint32_t *v1 = ptr<uint32_t>(c->p2pe);
     uint32_t *v2 = ensure<uint32_t>(c->p2pe2, std::max<int64_t>(nlist, 1));
-    int *tmp = tmp_ints(c, std::max(sort_tmp_ints(nlist), scan_tmp_ints(nlist + 1)));
+    const size_t ntmp = std::max(sort_tmp_ints(nlist), scan_tmp_ints(nlist + 1));
+    int *tmp = side ? ensure<int>(c->tmp_side, ntmp) : tmp_ints(c, ntmp);
     // packed keys (the range end in the low pb bits) sort without a value array
     // key bits sorted on: (sink, first particle), or the sink alone
     const int first = c->pack ? c->pb : 0;   // lowest bit of the first particle
@@ -518,14 +523,15 @@ void prepare_p2p(fmm_ctx *c, int64_t nlist, bool by_source) {
     int *flag = ensure<int>(c->rflag, (size_t)nlist + 2);
     int2 *rg = ensure<int2>(c->ranges, std::max<int64_t>(nlist, 1));
     uint64_t *rk = ensure<uint64_t>(c->rkey, std::max<int64_t>(nlist, 1));
-    int *total = ptr<int>(c->nonfinite) + 1;
+    int *total = ptr<int>(c->nonfinite) + (side ? 3 : 1);
+    int *host = c->hint + (side ? 3 : 0);
     int64_t runs = 0;
     if (nlist > 0) {
         CK(launch_range_merge(k1, v1, nlist, c->pb, c->pack, flag, tmp, total, rg, rk, false, s));
-        CK(hipMemcpyAsync(c->hint, total, sizeof(int), hipMemcpyDeviceToHost, s));
+        CK(hipMemcpyAsync(host, total, sizeof(int), hipMemcpyDeviceToHost, s));
         CK(launch_range_merge(k1, v1, nlist, c->pb, c->pack, flag, tmp, total, rg, rk, true, s));
-        sync(c);
-        runs = c->hint[0];
+        CK(hipStreamSynchronize(s));
+        runs = *host;
     }
     c->n_ranges = runs;
     int64_t *off = ensure<int64_t>(c->p2p_off, (size_t)c->ncells + 1);
@@ -717,8 +723,11 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
     c->st.n_m2l = L.n_m2l;
     c->st.n_p2p_lists = L.n_p2p;
     c->st.n_p2p_pairs = L.pairs;
+    // The direct-sum list is sorted and merged on the side stream while the
+    // main stream sorts the M2L list and runs M2L: M2L holds one wavefront
+    // per SIMD and no LDS, which leaves room for the sort's small waves.
+    CK(hipEventRecord(c->ev_fork, s));
     c->m2l_sorted = sort_list(c, c->m2l, c->m2l2, L.n_m2l, c->ncells, c->m2l_off);
-    prepare_p2p(c, L.n_p2p, true);
     mark(c, PH_WALK);
     // M2L: the rotation kernel over 64-entry windows of the list, or the
     // direct kernel by chunks of one sink's list
@@ -783,6 +792,11 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
             CK(launch_m2l_reduce(p, c->ncells, coff, Fp, Fd, s));
         }
     }
+    // the direct-sum lists, on the side stream (overlapping M2L, queued above)
+    CK(hipStreamWaitEvent(c->side, c->ev_fork, 0));
+    prepare_p2p(c, L.n_p2p, true, true);
+    CK(hipEventRecord(c->ev_join, c->side));
+    c->join_pending = true;
     mark(c, PH_M2L);
     // downward pass, far field at the particles
     for (int Lv = 1; Lv <= c->depth; ++Lv) {
@@ -803,7 +817,7 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
                           ptr<double>(c->Fd), jo4, s, cell_active));
     }
     mark(c, PH_DOWN);
-    // near field
+    join_centres(c);   // the direct-sum lists from the side stream
     // near field (with the jerk: FP64, potential and acceleration as the force-only
     // FP64 kernel sums them)
     run_p2p(c, 0, 1, c->opts.precision == FMM_PREC_MIXED && !vel, o4, true, cell_active, v4,
@@ -1006,7 +1020,7 @@ void fmm_destroy(fmm_ctx *c) {
                       &c->pt_s, &c->pt_off, &c->pt_moff, &c->ptasks, &c->pchain, &c->ppart, &c->m2l_off,
                       &c->p2p_off, &c->chunks, &c->ccnt, &c->coff, &c->Fpart, &c->counters,
                       &c->nonfinite, &c->prev_scale, &c->walktmp, &c->coffsets,
-                      &c->ckey, &c->ckey2, &c->order, &c->order2, &c->wcode, &c->rup,
+                      &c->ckey, &c->ckey2, &c->order, &c->order2, &c->wcode, &c->rup, &c->tmp_side,
                       &c->actflag, &c->actf, &c->actinv, &c->actpre, &c->cellact, &c->actbad,
                       &c->dkey, &c->dsort, &c->dsort2, &c->runstart, &c->plans, &c->Tsh,
                       &c->M32, &c->sig, &c->Flow, &c->epsmin, &c->vel4, &c->Md, &c->Fd,
