@@ -540,48 +540,76 @@ void prepare_p2p(fmm_ctx *c, int64_t nlist, bool by_source, bool side = false) {
 
 // direct sums of every leaf (prepared ranges), added into out4; with v4 (sorted
 // velocities) the FP64 kernel that also adds each pair's jerk into jo4
-void run_p2p(fmm_ctx *c, int want_f, int with_pot, int mixed, double4 *out4, bool timed,
-             const uint8_t *active = nullptr, const double4 *v4 = nullptr,
-             double4 *jo4 = nullptr) {
-    hipStream_t s = c->stream;
+// Direct-sum tasks of the prepared lists: per leaf the task counts, the
+// ancestor chains and the task list (active: leaves without listed sinks get
+// none).  side: on the side stream with its own scratch, counters and host
+// slots (the caller joins the side stream before the tasks run).
+struct P2PPlan {
+    int ntasks = 0, prows = 0;
+    int2 *tasks = nullptr;
+    int *nts = nullptr, *moff = nullptr, *chain = nullptr, *up = nullptr;
+};
+
+P2PPlan plan_p2p(fmm_ctx *c, const uint8_t *active, bool side = false) {
+    const hipStream_t s = side ? c->side : c->stream;
     const int nl = c->nleaves;
     TreeArrays t = tree_arrays(c);
+    P2PPlan pl;
     int *ntask = ensure<int>(c->pt_n, (size_t)nl + 1), *mtask = ensure<int>(c->pt_m, (size_t)nl + 1);
-    int *nts = ensure<int>(c->pt_s, (size_t)nl + 1), *toff = ensure<int>(c->pt_off, (size_t)nl + 1);
-    int *moff = ensure<int>(c->pt_moff, (size_t)nl + 1);
-    int *tmp = tmp_ints(c, scan_tmp_ints(nl + 1));
-    int *totals = ptr<int>(c->nonfinite) + 1;
+    pl.nts = ensure<int>(c->pt_s, (size_t)nl + 1);
+    int *toff = ensure<int>(c->pt_off, (size_t)nl + 1);
+    pl.moff = ensure<int>(c->pt_moff, (size_t)nl + 1);
+    int *tmp = side ? ensure<int>(c->tmp_side, scan_tmp_ints(nl + 1)) : tmp_ints(c, scan_tmp_ints(nl + 1));
+    int *totals = ptr<int>(c->nonfinite) + (side ? 6 : 1);
+    int *host = c->hint + (side ? 4 : 0);
     const int64_t *off = ptr<int64_t>(c->p2p_off);
     const int2 *rg = ptr<int2>(c->ranges);
-    int *up = ensure<int>(c->rup, (size_t)std::max(c->ncells, 1));
-    CK(launch_range_up(c->ncells, t.parent, off, up, s));
-    int *chain = ensure<int>(c->pchain, (size_t)std::max(nl, 1) * P2P_CHAIN);
-    CK(launch_p2p_plan(nl, ptr<int>(c->leaf_cell), off, rg, up, t, active, ntask, mtask, nts, toff,
-                       moff, chain, tmp, totals, s));
-    CK(hipMemcpyAsync(c->hint, totals, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-    sync(c);
-    const int ntasks = c->hint[0], prows = c->hint[1];
-    int2 *tasks = ensure<int2>(c->ptasks, std::max(ntasks, 1));
-    double4 *part = ensure<double4>(c->ppart, (size_t)std::max(prows, 1) * 64);
-    CK(launch_p2p_tasks(nl, toff, tasks, s));
+    pl.up = ensure<int>(c->rup, (size_t)std::max(c->ncells, 1));
+    CK(launch_range_up(c->ncells, t.parent, off, pl.up, s));
+    pl.chain = ensure<int>(c->pchain, (size_t)std::max(nl, 1) * P2P_CHAIN);
+    CK(launch_p2p_plan(nl, ptr<int>(c->leaf_cell), off, rg, pl.up, t, active, ntask, mtask, pl.nts,
+                       toff, pl.moff, pl.chain, tmp, totals, s));
+    CK(hipMemcpyAsync(host, totals, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    pl.ntasks = host[0];
+    pl.prows = host[1];
+    pl.tasks = ensure<int2>(c->ptasks, std::max(pl.ntasks, 1));
+    CK(launch_p2p_tasks(nl, toff, pl.tasks, s));
+    return pl;
+}
+
+// the direct sums of a plan, added into out4 (and the jerk into jo4)
+void exec_p2p(fmm_ctx *c, const P2PPlan &pl, int want_f, int with_pot, int mixed, double4 *out4,
+              bool timed, const double4 *v4 = nullptr, double4 *jo4 = nullptr) {
+    hipStream_t s = c->stream;
+    TreeArrays t = tree_arrays(c);
+    const int64_t *off = ptr<int64_t>(c->p2p_off);
+    const int2 *rg = ptr<int2>(c->ranges);
+    double4 *part = ensure<double4>(c->ppart, (size_t)std::max(pl.prows, 1) * 64);
     if (timed && c->opts.timing) CK(hipEventRecord(c->ev_p2p[0], s));
     double4 *jpart = nullptr;
     if (v4) {
-        jpart = ensure<double4>(c->jpart, (size_t)std::max(prows, 1) * 64);
-        CK(launch_p2p_jerk(ntasks, tasks, ptr<int>(c->leaf_cell), nts, moff, off, rg, up, t,
-                           ptr<double4>(c->xyzm), v4, out4, jo4, part, jpart, s));
+        jpart = ensure<double4>(c->jpart, (size_t)std::max(pl.prows, 1) * 64);
+        CK(launch_p2p_jerk(pl.ntasks, pl.tasks, ptr<int>(c->leaf_cell), pl.nts, pl.moff, off, rg,
+                           pl.up, t, ptr<double4>(c->xyzm), v4, out4, jo4, part, jpart, s));
     } else {
-        CK(launch_p2p(want_f, with_pot, mixed, ntasks, tasks, ptr<int>(c->leaf_cell), nts, moff,
-                      off, rg, chain, t, ptr<double4>(c->xyzm), out4, part, s));
+        CK(launch_p2p(want_f, with_pot, mixed, pl.ntasks, pl.tasks, ptr<int>(c->leaf_cell), pl.nts,
+                      pl.moff, off, rg, pl.chain, t, ptr<double4>(c->xyzm), out4, part, s));
     }
     if (timed && c->opts.timing) CK(hipEventRecord(c->ev_p2p[1], s));
-    if (prows > 0) {
-        CK(launch_p2p_reduce(c->n, ptr<int>(c->leaf_of), ptr<int>(c->leaf_cell), nts, moff, t,
-                             part, out4, s));
+    if (pl.prows > 0) {
+        CK(launch_p2p_reduce(c->n, ptr<int>(c->leaf_of), ptr<int>(c->leaf_cell), pl.nts, pl.moff,
+                             t, part, out4, s));
         if (v4)
-            CK(launch_p2p_reduce(c->n, ptr<int>(c->leaf_of), ptr<int>(c->leaf_cell), nts, moff, t,
-                                 jpart, jo4, s));
+            CK(launch_p2p_reduce(c->n, ptr<int>(c->leaf_of), ptr<int>(c->leaf_cell), pl.nts,
+                                 pl.moff, t, jpart, jo4, s));
     }
+}
+
+void run_p2p(fmm_ctx *c, int want_f, int with_pot, int mixed, double4 *out4, bool timed,
+             const uint8_t *active = nullptr, const double4 *v4 = nullptr,
+             double4 *jo4 = nullptr) {
+    exec_p2p(c, plan_p2p(c, active), want_f, with_pot, mixed, out4, timed, v4, jo4);
 }
 
 // ------------------------------------------------------------ sink scale
@@ -795,6 +823,7 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
     // the direct-sum lists, on the side stream (overlapping M2L, queued above)
     CK(hipStreamWaitEvent(c->side, c->ev_fork, 0));
     prepare_p2p(c, L.n_p2p, true, true);
+    const P2PPlan near = plan_p2p(c, cell_active, true);
     CK(hipEventRecord(c->ev_join, c->side));
     c->join_pending = true;
     mark(c, PH_M2L);
@@ -817,11 +846,10 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
                           ptr<double>(c->Fd), jo4, s, cell_active));
     }
     mark(c, PH_DOWN);
-    join_centres(c);   // the direct-sum lists from the side stream
+    join_centres(c);   // the direct-sum lists and tasks from the side stream
     // near field (with the jerk: FP64, potential and acceleration as the force-only
     // FP64 kernel sums them)
-    run_p2p(c, 0, 1, c->opts.precision == FMM_PREC_MIXED && !vel, o4, true, cell_active, v4,
-            jo4);
+    exec_p2p(c, near, 0, 1, c->opts.precision == FMM_PREC_MIXED && !vel, o4, true, v4, jo4);
     mark(c, PH_P2P);
     int *nonfinite = ptr<int>(c->nonfinite);
     CK(hipMemsetAsync(nonfinite, 0, sizeof(int), s));
