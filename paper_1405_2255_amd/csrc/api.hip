@@ -229,12 +229,12 @@ void *pinned(fmm_ctx *c, size_t bytes) {
 // recycling between nearby time steps - and only positions, geometry and
 // radii are refreshed.  The acceptance test uses the true radii, so a
 // recycled tree stays valid; it only gets less efficient as particles drift.
-void join_centres(fmm_ctx *c);
+void join_side(fmm_ctx *c);
 
 void build_tree(fmm_ctx *c, int64_t n, const double *pos, const double *mass, int K,
                 const int64_t *off, bool refit) {
     hipStream_t s = c->stream;
-    join_centres(c);   // a previous call that ended early may have left side work queued
+    join_side(c);   // a previous call that ended early may have left side work queued
     const int leaf = c->opts.leaf_size;
     const bool reuse = refit && c->tree_valid && c->tree_n == n &&
                        c->tree_off == std::vector<int64_t>(off, off + K + 1);
@@ -375,7 +375,7 @@ void build_tree(fmm_ctx *c, int64_t n, const double *pos, const double *mass, in
         // The enclosing-sphere centres: a chain of small latency-bound
         // launches, one per level.  They run on the side stream while the
         // main stream does the sink-scale estimate, which uses only the
-        // centres of mass; join_centres() orders the main stream after them
+        // centres of mass; join_side() orders the main stream after them
         // before anything reads an expansion centre.
         CK(hipEventRecord(c->ev_fork, s));
         CK(hipStreamWaitEvent(c->side, c->ev_fork, 0));
@@ -388,8 +388,9 @@ void build_tree(fmm_ctx *c, int64_t n, const double *pos, const double *mass, in
     }
 }
 
-// the main stream waits for the side stream's centres (if any are pending)
-void join_centres(fmm_ctx *c) {
+// the main stream waits for the work queued on the side stream (enclosing
+// centres, upward pass, direct-sum lists), if any is pending
+void join_side(fmm_ctx *c) {
     if (!c->join_pending) return;
     CK(hipStreamWaitEvent(c->stream, c->ev_join, 0));
     c->join_pending = false;
@@ -735,7 +736,7 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
     const bool want_f = c->opts.mac == FMM_MAC_SCALED;
     if (c->opts.mac != FMM_MAC_THETA) sink_scale(c, want_f, eps_b);
     mark(c, PH_EST);
-    join_centres(c);
+    join_side(c);   // the centres and the upward pass from the side stream
     mark(c, PH_UP);
     // walk
     WalkParams wp{c->opts.mac == FMM_MAC_THETA ? 1 : 0, p, eps, c->opts.theta_crit,
@@ -846,7 +847,7 @@ void forces(fmm_ctx *c, int64_t n, const double *pos, const double *mass, double
                           ptr<double>(c->Fd), jo4, s, cell_active));
     }
     mark(c, PH_DOWN);
-    join_centres(c);   // the direct-sum lists and tasks from the side stream
+    join_side(c);   // the direct-sum lists and tasks from the side stream
     // near field (with the jerk: FP64, potential and acceleration as the force-only
     // FP64 kernel sums them)
     exec_p2p(c, near, 0, 1, c->opts.precision == FMM_PREC_MIXED && !vel, o4, true, v4, jo4);
