@@ -32,8 +32,8 @@ Prints ONE JSON line (rank 0): metric, value, ... plus
                 mixed profiles and error targets, 10 drift steps each with the
                 tree recycled, mixed precision) through the serving loop:
                 p50/p99 latency and throughput at an offered load of 0.8
-  the benchmark spec    the form the project targets: a stream of N = 1e6 mixed-
-                precision force evaluations (rms 1e-7) through the serving loop
+  stream_1e6    a stream of N = 1e6 mixed-precision force evaluations
+                (rms 1e-7) through the serving loop
                 (continuous batching, HBM admission): the served capacity with
                 every request queued at once, then p50/p99 latency and
                 throughput for Poisson arrivals at offered loads of it; with the
@@ -500,7 +500,7 @@ def serve_leg(args, fmm, workloads, capacity_pfs):
             "all_within_target": bool(all(c["rms"] <= c["target_rms"] for c in checks))}
 
 
-def north_star_leg(args, fmm, workloads, params):
+def stream_leg(args, fmm, workloads, params):
     """N = 1e6 mixed-precision force evaluations through the serving loop.
 
     R requests cycle over K seeded Plummer inputs (N = 1e6 each, seeds other
@@ -535,7 +535,7 @@ def north_star_leg(args, fmm, workloads, params):
         q.result(600)
     t_cap = max(q.t_end for q in reqs) - t0
     capacity = R * n / t_cap
-    print(f"north star: {R} requests queued at once in {t_cap:.3f} s, "
+    print(f"stream: {R} requests queued at once in {t_cap:.3f} s, "
           f"{capacity:.4g} particle-forces/s", file=sys.stderr, flush=True)
     # accuracy of the served results of every input against the GPU direct sum
     ctx = fmm.Context(device=0, centre=centre)
@@ -565,7 +565,7 @@ def north_star_leg(args, fmm, workloads, params):
         t_all = max(q.t_end for q in rq) - t_start
         loads.append({"offered_load": load, "latency": serve.latency_summary(rq),
                       "value": R * n / t_all, "unit": "particle-forces/s", "seconds": t_all})
-        print(f"north star at load {load}: {loads[-1]['latency']}", file=sys.stderr, flush=True)
+        print(f"stream at load {load}: {loads[-1]['latency']}", file=sys.stderr, flush=True)
     srv.close()
     single_ms = float(np.median([q.t_end - q.t_start for q in reqs[:args.ns_slots]]))
     return {"workload": f"{R} requests, each one full mixed-precision evaluation of a Plummer "
@@ -612,7 +612,7 @@ def main() -> int:
     ap.add_argument("--serve-load", type=float, default=0.8)
     ap.add_argument("--serve-other-loads", type=lambda s: [float(x) for x in s.split(",") if x],
                     default=[0.5, 0.95])
-    ap.add_argument("--no-north-star", action="store_true")
+    ap.add_argument("--no-stream", action="store_true")
     ap.add_argument("--ns-requests", type=int, default=120)
     ap.add_argument("--ns-slots", type=int, default=3)
     ap.add_argument("--ns-loads", type=lambda s: [float(x) for x in s.split(",") if x],
@@ -826,14 +826,14 @@ def main() -> int:
                    "mixed": batched_leg(args, fmm, workloads, "mixed")}
     c3 = None if args.no_c3 else c3_leg(args, fmm, workloads)
     served = None if args.no_serve else serve_leg(args, fmm, workloads, value)
-    north = None
-    if not args.no_north_star and tuned_mixed is not None:
+    stream = None
+    if not args.no_stream and tuned_mixed is not None:
         lm, pfm, pm_, em, cm = tuned_mixed
-        north = north_star_leg(args, fmm, workloads,
+        stream = stream_leg(args, fmm, workloads,
                                (lm or 32, pfm or 2.0, pm_ if pm_ > 0 else st["p"], em, cm))
-        north["roofline_fp32"] = roofline_fp32
-        north["vs_plain_fp64"] = north["value"] / value
-        north["vs_gpu_direct"] = north["value"] / direct["value"] if direct else None
+        stream["roofline_fp32"] = roofline_fp32
+        stream["vs_plain_fp64"] = stream["value"] / value
+        stream["vs_gpu_direct"] = stream["value"] / direct["value"] if direct else None
     cpu_fmm = None
     if not args.no_cpu_fmm:
         # the CPU oracle's plain FMM (single-threaded recursion, FP64) on a
@@ -892,7 +892,7 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "cpu_baseline_fmm": cpu_fmm,
-        "north_star": north,
+        "stream_1e6": stream,
         "roofline_fp32": roofline_fp32,
         "tree": tree,
         "mixed": mixed,
