@@ -86,8 +86,15 @@ def _measured_traffic(kernel: str, config: dict):
     if h.hexdigest() != rec["sha256"]:
         return None
     want = rec.get("config", {})
-    if any(k not in config or abs(float(config[k]) - float(v)) > 1e-12 * abs(float(v))
-           for k, v in want.items()) or not want:
+
+    def differs(k, v):
+        if k not in config:
+            return True
+        if isinstance(v, str):
+            return str(config[k]) != v
+        return abs(float(config[k]) - float(v)) > 1e-12 * abs(float(v))
+
+    if not want or any(differs(k, v) for k, v in want.items()):
         return None
     return rec["fetch_bytes"] + rec["write_bytes"]
 
@@ -754,7 +761,7 @@ def main() -> int:
                 "frac": achieved / FP64_PEAK_TFLOPS,
                 "traffic": _measured_traffic(kname, {"n": n, "leaf_size": leaf or 32,
                                                      "p2p_factor": pf or 2.0, "p": p,
-                                                     "eps": eps}),
+                                                     "eps": eps, "centre": centre}),
                 "launch_ms": kms, "algorithmic_flop_per_launch": kflop,
                 "other": {"k_m2l": {"ms": m2l_ms, "tflops": m2l_f / (m2l_ms * 1e-3) / 1e12},
                           "k_p2p": {"ms": p2p_ms, "tflops": p2p_f / (p2p_ms * 1e-3) / 1e12}}}
@@ -788,7 +795,7 @@ def main() -> int:
         mixed = {"value": n / (ms_m * 1e-3), "unit": "particle-forces/s", "ms_per_step": ms_m,
                  "vs_fp64": ms_per_step / ms_m,
                  "params": {"leaf_size": leaf_m or 32, "p2p_factor": pf_m or 2.0, "p": stm["p"],
-                            "eps": eps_m},
+                            "eps": eps_m, "centre": centre_m},
                  "autotune": tuned_m,
                  "phases_ms": {k: stm[k] for k in ("t_tree", "t_estimate", "t_up", "t_walk",
                                                    "t_m2l", "t_down", "t_p2p", "t_total")},
