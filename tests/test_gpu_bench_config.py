@@ -1,11 +1,10 @@
 """Parity with the oracle in the configurations the N = 10^6 benchmark runs
-(the tuned table): FP64 with leaf size 48, direct-sum threshold 2 (p+1)^3 and
-enclosing-sphere centres; mixed precision with leaf size 64, threshold
-2 (p+1)^3 and box-midpoint centres; both at order 15 and eps 6e-8, on a
-Plummer sphere of 3e4 particles.  Further cases: FP64 at leaf size 48 with
-box-midpoint centres, and leaf size 96 (FP64 with enclosing-sphere centres,
-mixed with threshold 3 (p+1)^3), whose leaves of more than 64 particles make
-the direct-sum kernel cut a leaf's sinks into two 64-sink chunks.  The mean sink has more than 2048
+(the tuned table): FP64 and mixed precision with leaf size 80, direct-sum
+threshold 2 (p+1)^3 and box-midpoint centres, at order 15 and eps 6e-8, on a
+Plummer sphere of 3e4 particles; leaves of more than 64 particles make the
+direct-sum kernel cut a leaf's sinks into two chunks.  Further cases: FP64 at
+leaf sizes 48 and 96 with enclosing-sphere centres, and mixed precision at
+leaf size 96 with threshold 3 (p+1)^3.  The mean sink has more than 2048
 direct sources, so leaves are split into several source tasks with ordered
 partial sums; both are asserted from the tree and the counts.  The register
 M2L kernel of order 15 (FP64 and mixed) and the jerk kernels at orders 15,
@@ -27,8 +26,8 @@ N, P, EPS = 30000, 15, 6e-8
 U32 = 2.0 ** -24
 CENTRE = {"midpoint": oracle.CENTRE_MIDPOINT, "enclosing": oracle.CENTRE_ENCLOSING}
 # (leaf size, threshold factor, centre rule)
-FP64_CASES = [(48, 2.0, "enclosing"), (48, 2.0, "midpoint"), (96, 2.0, "enclosing")]
-MIXED_CASES = [(64, 2.0, "midpoint"), (96, 3.0, "midpoint")]
+FP64_CASES = [(80, 2.0, "midpoint"), (48, 2.0, "enclosing"), (96, 2.0, "enclosing")]
+MIXED_CASES = [(80, 2.0, "midpoint"), (96, 3.0, "midpoint")]
 _refs = {}
 
 
