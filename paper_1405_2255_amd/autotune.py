@@ -48,7 +48,7 @@ class Result:
     ref_rms: float = 0.0   # sampled rms of the reference against the direct sum
 
 
-def candidates(target: float, leaf_sizes=(32, 40, 48, 56, 64, 80, 96, 128, 192),
+def candidates(target: float, leaf_sizes=(32, 40, 48, 56, 64, 72, 80, 88, 96, 128, 192),
                p2p_factors=(1.0, 1.5, 2.0, 2.5, 3.0),
                kappas=(0.6, 0.75, 0.9), order_offsets=(0, 1),
                centres=("midpoint", "enclosing")) -> list[Candidate]:

@@ -8,7 +8,7 @@ from paper_1405_2255_amd import autotune as A
 
 def test_grid_spans_leaf_threshold_order_and_centre_rule():
     g = A.candidates(1e-7)
-    assert len(g) == len(set(g)) == 9 * 5 * 3 * 2 * 2
+    assert len(g) == len(set(g)) == 11 * 5 * 3 * 2 * 2
     from paper_1405_2255_amd import fmm
     for c in g:
         assert fmm.P_MIN <= c.p <= fmm.P_MAX
