@@ -86,6 +86,14 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
     return fma(y * 0.5, e, y);
 }
 
+// 2/sqrt(x): the same Newton step without its factor 1/2, one multiply fewer
+// (y (3 - x y^2)).  The direct-sum kernels sum with it and undo the powers of
+// two once per sink (exact).
+__device__ __forceinline__ double rsqrt2_nr(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    return y * fma(-(x * y), y, 3.0);
+}
+
 // XCD-aware block order.  Workgroups are handed to the 8 XCDs of the chip in
 // turn (block b to XCD b % 8), and each XCD has its own L2.  Work items in
 // Morton order that are close share their inputs (neighbouring sinks read

@@ -209,11 +209,17 @@ struct Sink {
     double jx, jy, jz;
 };
 
+// Summed with 2/|r| in place of 1/|r|, as the force-only direct sums are
+// (the same operations, so potential and acceleration equal theirs bit for
+// bit): potential times 2, acceleration and jerk times 8, scaled back once per
+// sink.
+constexpr double JERK_POT_BACK = 0.5, JERK_ACC_BACK = 0.125;
+
 __device__ __forceinline__ void pair_jerk(const double4 s, const double4 va, bool skip, Sink &k) {
     const double dx = s.x - k.x.x, dy = s.y - k.x.y, dz = s.z - k.x.z;
     const double r2 = skip ? 1.0 : fma(dx, dx, fma(dy, dy, dz * dz));
     const double mu = skip ? 0.0 : s.w;
-    const double ri = rsqrt_nr(r2);
+    const double ri = rsqrt2_nr(r2);            // 2/|r|
     const double q = mu * ri;
     const double q3 = q * ri * ri;
     k.f.x += q;
@@ -221,7 +227,8 @@ __device__ __forceinline__ void pair_jerk(const double4 s, const double4 va, boo
     k.f.z = fma(q3, dy, k.f.z);
     k.f.w = fma(q3, dz, k.f.w);
     const double ux = va.x - k.v.x, uy = va.y - k.v.y, uz = va.z - k.v.z;
-    const double rv = 3.0 * fma(dx, ux, fma(dy, uy, dz * uz)) * (ri * ri);
+    // 3 (r.u)/r^2 = 0.75 (r.u) (2/|r|)^2
+    const double rv = 0.75 * fma(dx, ux, fma(dy, uy, dz * uz)) * (ri * ri);
     k.jx = fma(q3, fma(-rv, dx, ux), k.jx);
     k.jy = fma(q3, fma(-rv, dy, uy), k.jy);
     k.jz = fma(q3, fma(-rv, dz, uz), k.jz);
@@ -325,6 +332,13 @@ k_p2p_jerk(int ntasks, const int2 *tasks, const int *leaf_cell, const int *nsrc_
         v.x += q.x; v.y += q.y; v.z += q.z; v.w += q.w;
         jv.y += qj.y; jv.z += qj.z; jv.w += qj.w;
     }
+    v.x *= JERK_POT_BACK;
+    v.y *= JERK_ACC_BACK;
+    v.z *= JERK_ACC_BACK;
+    v.w *= JERK_ACC_BACK;
+    jv.y *= JERK_ACC_BACK;
+    jv.z *= JERK_ACC_BACK;
+    jv.w *= JERK_ACC_BACK;
     const int bo = sb + lane;
     if (moff[leaf + 1] == moff[leaf]) {        // the leaf's only task
         double4 o = out4[bo];

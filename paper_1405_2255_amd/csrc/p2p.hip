@@ -116,6 +116,11 @@ __global__ void k_p2p_tasks(int nleaves, const int *task_off, int2 *tasks) {
     for (int k = k0 + lane_id(); k < k1; k += FMM_WAVE) tasks[k] = make_int2(leaf, k - k0);
 }
 
+// Potentials and accelerations are summed with 2/|r| in place of 1/|r|
+// (rsqrt2_nr), that is times 2 and times 8; the sums of a sink are scaled back
+// once, before they leave the kernel (exact: powers of two).
+constexpr double P2P_POT_BACK = 0.5, P2P_ACC_BACK = 0.125;
+
 template <int WANT_F, int WITH_POT>
 __device__ __forceinline__ void pair(const double4 s, const double4 xb, bool skip, double &pot,
                                      double &ax, double &ay, double &az) {
@@ -125,7 +130,7 @@ __device__ __forceinline__ void pair(const double4 s, const double4 xb, bool ski
     if (WANT_F) {
         pot += mu / r2;
     } else {
-        const double ri = rsqrt_nr(r2);
+        const double ri = rsqrt2_nr(r2);        // 2/|r|
         const double q = mu * ri;
         const double q3 = q * ri * ri;
         if (WITH_POT) pot += q;
@@ -181,12 +186,15 @@ __device__ __forceinline__ void sum_range32(const double4 *p, const double4 *pe,
                 pair32<WANT_F, WITH_POT>(a, xb[k], CHECK && p == self[k], g[k].x, g[k].y, g[k].z,
                                          g[k].w);
         }
+        // into the FP64 sums at their scale (times 2 and 8, as in pair())
+        constexpr double sp = WANT_F ? 1.0 : 1.0 / P2P_POT_BACK;
+        constexpr double sa = WANT_F ? 1.0 : 1.0 / P2P_ACC_BACK;
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            f[k].x += (double)g[k].x;
-            f[k].y += (double)g[k].y;
-            f[k].z += (double)g[k].z;
-            f[k].w += (double)g[k].w;
+            f[k].x = fma((double)g[k].x, sp, f[k].x);
+            f[k].y = fma((double)g[k].y, sa, f[k].y);
+            f[k].z = fma((double)g[k].z, sa, f[k].z);
+            f[k].w = fma((double)g[k].w, sa, f[k].w);
         }
     }
 }
@@ -301,6 +309,12 @@ k_p2p(int ntasks, const int2 *tasks, const int *leaf_cell, const int *nsrc_tasks
     for (int ph = 1; ph < S; ++ph) {
         const double4 q = red[w][lane + ph * R * ng];
         v.x += q.x; v.y += q.y; v.z += q.z; v.w += q.w;
+    }
+    if (!WANT_F) {
+        v.x *= P2P_POT_BACK;
+        v.y *= P2P_ACC_BACK;
+        v.z *= P2P_ACC_BACK;
+        v.w *= P2P_ACC_BACK;
     }
     const int bi = sb + lane;
     if (moff[leaf + 1] == moff[leaf]) {          // the leaf's only task
