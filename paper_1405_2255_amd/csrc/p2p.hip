@@ -140,10 +140,6 @@ __device__ __forceinline__ void pair(const double4 s, const double4 xb, bool ski
     }
 }
 
-// One lane's share of a source range for its R sinks: sources p[0],
-// p[stride], ... below pe, the next source loaded before the current one is
-// summed.  CHECK: the range may contain the sinks themselves (skipped by
-// address); other ranges need no test.
 // Mixed precision: the separation is formed in FP64 and rounded once; the
 // squared distance, reciprocal square root, products and the running sums
 // are FP32 (every pair's contribution carries a relative error of a few
@@ -171,22 +167,84 @@ __device__ __forceinline__ void pair32(const double4 s, const double4 xb, bool s
 // are added into the FP64 sums
 constexpr int P2P_CHUNK32 = 32;
 
-template <int R, int WANT_F, int WITH_POT, bool CHECK>
-__device__ __forceinline__ void sum_range32(const double4 *p, const double4 *pe, int stride,
-                                            const double4 (&xb)[R],
-                                            const double4 *const (&self)[R], double4 (&f)[R]) {
-    while (p < pe) {
+// One lane's share of a source range that overlaps its R sinks' own leaf:
+// sources p[0], p[stride], ... below pe (the sinks themselves skipped by
+// address), the next source loaded before the current one is summed.  Always
+// FP64.
+template <int R, int WANT_F, int WITH_POT>
+__device__ __forceinline__ void sum_own(const double4 *p, const double4 *pe, int stride,
+                                        const double4 (&xb)[R], const double4 *const (&self)[R],
+                                        double4 (&f)[R]) {
+    if (p >= pe) return;
+    double4 a = p[0];
+    for (;;) {
+        const double4 *q = p + stride;
+        const bool more = q < pe;
+        const double4 b = (more ? q : p)[0];
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            pair<WANT_F, WITH_POT>(a, xb[k], p == self[k], f[k].x, f[k].y, f[k].z, f[k].w);
+        if (!more) break;
+        p = q;
+        a = b;
+    }
+}
+
+// A range start that is the same in every lane, moved to scalar registers so
+// that the loads below take it as their scalar base with a 32-bit per-lane
+// byte offset (one 32-bit add and compare per source instead of 64-bit ones).
+// (The pointer is marked global: through the integer round trip a generic
+// pointer would turn the loads into flat ones.)
+using gchar = __attribute__((address_space(1))) const char;
+typedef double d4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ double4 load_source(gchar *q) {
+    const d4v v = *(__attribute__((address_space(1))) const d4v *)q;
+    return make_double4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ gchar *uniform_base(const double4 *base) {
+    const uint64_t bu = reinterpret_cast<uint64_t>(base);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)bu);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(bu >> 32));
+    return (gchar *)(((uint64_t)hi << 32) | lo);
+}
+static_assert((int64_t)P2P_TASK * sizeof(double4) < (int64_t(1) << 32),
+              "byte offsets within a task's source range fit 32 bits");
+
+// One lane's share of a source range that holds none of its sinks: sources
+// base[i], base[i + stride], ... below base[n] (n <= P2P_TASK).
+template <int R, int WANT_F, int WITH_POT>
+__device__ __forceinline__ void sum_far(const double4 *base, uint32_t i, uint32_t n,
+                                        uint32_t stride, const double4 (&xb)[R],
+                                        double4 (&f)[R]) {
+    gchar *b = uniform_base(base);
+    const uint32_t oe = n * 32u, st = stride * 32u;
+    for (uint32_t o = i * 32u; o < oe; o += st) {
+        const double4 a = load_source(b + o);
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            pair<WANT_F, WITH_POT>(a, xb[k], false, f[k].x, f[k].y, f[k].z, f[k].w);
+    }
+}
+
+// The same in mixed precision: FP32 partial sums over at most P2P_CHUNK32
+// sources per lane, then added into the FP64 sums.
+template <int R, int WANT_F, int WITH_POT>
+__device__ __forceinline__ void sum_far32(const double4 *base, uint32_t i, uint32_t n,
+                                          uint32_t stride, const double4 (&xb)[R],
+                                          double4 (&f)[R]) {
+    gchar *b = uniform_base(base);
+    const uint32_t oe = n * 32u, st = stride * 32u;
+    uint32_t o = i * 32u;
+    while (o < oe) {
         float4 g[R];
 #pragma unroll
         for (int k = 0; k < R; ++k) g[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-        for (int it = 0; it < P2P_CHUNK32 && p < pe; ++it, p += stride) {
-            const double4 a = p[0];
+        for (int it = 0; it < P2P_CHUNK32 && o < oe; ++it, o += st) {
+            const double4 a = load_source(b + o);
 #pragma unroll
             for (int k = 0; k < R; ++k)
-                pair32<WANT_F, WITH_POT>(a, xb[k], CHECK && p == self[k], g[k].x, g[k].y, g[k].z,
-                                         g[k].w);
+                pair32<WANT_F, WITH_POT>(a, xb[k], false, g[k].x, g[k].y, g[k].z, g[k].w);
         }
-        // into the FP64 sums at their scale (times 2 and 8, as in pair())
         constexpr double sp = WANT_F ? 1.0 : 1.0 / P2P_POT_BACK;
         constexpr double sa = WANT_F ? 1.0 : 1.0 / P2P_ACC_BACK;
 #pragma unroll
@@ -196,26 +254,6 @@ __device__ __forceinline__ void sum_range32(const double4 *p, const double4 *pe,
             f[k].z = fma((double)g[k].z, sa, f[k].z);
             f[k].w = fma((double)g[k].w, sa, f[k].w);
         }
-    }
-}
-
-template <int R, int WANT_F, int WITH_POT, bool CHECK>
-__device__ __forceinline__ void sum_range(const double4 *p, const double4 *pe, int stride,
-                                          const double4 (&xb)[R], const double4 *const (&self)[R],
-                                          double4 (&f)[R]) {
-    if (p >= pe) return;
-    double4 a = p[0];
-    for (;;) {
-        const double4 *q = p + stride;
-        const bool more = q < pe;
-        const double4 b = (more ? q : p)[0];
-#pragma unroll
-        for (int k = 0; k < R; ++k)
-            pair<WANT_F, WITH_POT>(a, xb[k], CHECK && p == self[k], f[k].x, f[k].y, f[k].z,
-                                   f[k].w);
-        if (!more) break;
-        p = q;
-        a = b;
     }
 }
 
@@ -281,17 +319,14 @@ k_p2p(int ntasks, const int2 *tasks, const int *leaf_cell, const int *nsrc_tasks
             if (rg.y - rg.x > left) rg.y = rg.x + (int)left;
             left -= rg.y - rg.x;
             if (!active) continue;
-            const double4 *p = xyzm + rg.x + phase, *pe = xyzm + rg.y;
             const bool own = rg.x < sb + nb && rg.y > sb;   // overlaps the task's sinks
-            if (MIXED) {
-                // the sinks' own leaf holds their nearest neighbours, the largest
-                // terms: summed in FP64 also in mixed precision
-                if (own) sum_range<R, WANT_F, WITH_POT, true>(p, pe, S, xb, self, f);
-                else sum_range32<R, WANT_F, WITH_POT, false>(p, pe, S, xb, self, f);
-            } else {
-                if (own) sum_range<R, WANT_F, WITH_POT, true>(p, pe, S, xb, self, f);
-                else sum_range<R, WANT_F, WITH_POT, false>(p, pe, S, xb, self, f);
-            }
+            // the sinks' own leaf holds their nearest neighbours, the largest
+            // terms: summed in FP64 also in mixed precision
+            const uint32_t nr = (uint32_t)(rg.y - rg.x);
+            if (own)
+                sum_own<R, WANT_F, WITH_POT>(xyzm + rg.x + phase, xyzm + rg.y, S, xb, self, f);
+            else if (MIXED) sum_far32<R, WANT_F, WITH_POT>(xyzm + rg.x, phase, nr, S, xb, f);
+            else sum_far<R, WANT_F, WITH_POT>(xyzm + rg.x, phase, nr, S, xb, f);
           }
         }
     }
