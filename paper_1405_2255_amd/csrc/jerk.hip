@@ -256,7 +256,21 @@ __device__ __forceinline__ void sum_range_jerk(const double4 *xyzm, const double
     }
 }
 
-__global__ void __launch_bounds__(256)
+// The same for a range that holds none of the sinks, read from its start in
+// scalar registers: sources xs[i], xs[i + stride], ... below xs[n] with their
+// velocities vs[...] (n <= P2P_TASK).
+__device__ __forceinline__ void sum_far_jerk(const double4 *xs, const double4 *vs, uint32_t i,
+                                             uint32_t n, uint32_t stride, Sink (&k)[JR]) {
+    gchar *bx = uniform_base(xs), *bv = uniform_base(vs);
+    const uint32_t oe = n * 32u, st = stride * 32u;
+    for (uint32_t o = i * 32u; o < oe; o += st) {
+        const double4 s = load_source(bx + o), va = load_source(bv + o);
+#pragma unroll
+        for (int r = 0; r < JR; ++r) pair_jerk(s, va, false, k[r]);
+    }
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 k_p2p_jerk(int ntasks, const int2 *tasks, const int *leaf_cell, const int *nsrc_tasks,
            const int *moff, const int64_t *off, const int2 *range, const int *up, TreeArrays t,
            const double4 *xyzm, const double4 *v4, double4 *out4, double4 *jo4,
@@ -309,7 +323,7 @@ k_p2p_jerk(int ntasks, const int2 *tasks, const int *leaf_cell, const int *nsrc_
                 if (!active) continue;
                 const bool own = rg.x < sb + nb && rg.y > sb;   // overlaps the task's sinks
                 if (own) sum_range_jerk<true>(xyzm, v4, rg.x + phase, rg.y, S, self, k);
-                else sum_range_jerk<false>(xyzm, v4, rg.x + phase, rg.y, S, self, k);
+                else sum_far_jerk(xyzm + rg.x, v4 + rg.x, phase, (uint32_t)(rg.y - rg.x), S, k);
             }
         }
     }

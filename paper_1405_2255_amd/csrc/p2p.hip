@@ -190,23 +190,6 @@ __device__ __forceinline__ void sum_own(const double4 *p, const double4 *pe, int
     }
 }
 
-// A range start that is the same in every lane, moved to scalar registers so
-// that the loads below take it as their scalar base with a 32-bit per-lane
-// byte offset (one 32-bit add and compare per source instead of 64-bit ones).
-// (The pointer is marked global: through the integer round trip a generic
-// pointer would turn the loads into flat ones.)
-using gchar = __attribute__((address_space(1))) const char;
-typedef double d4v __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ double4 load_source(gchar *q) {
-    const d4v v = *(__attribute__((address_space(1))) const d4v *)q;
-    return make_double4(v.x, v.y, v.z, v.w);
-}
-__device__ __forceinline__ gchar *uniform_base(const double4 *base) {
-    const uint64_t bu = reinterpret_cast<uint64_t>(base);
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)bu);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(bu >> 32));
-    return (gchar *)(((uint64_t)hi << 32) | lo);
-}
 static_assert((int64_t)P2P_TASK * sizeof(double4) < (int64_t(1) << 32),
               "byte offsets within a task's source range fit 32 bits");
 
