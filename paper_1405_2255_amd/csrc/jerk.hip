@@ -12,6 +12,7 @@
 // the rates from the row or column they already generate.
 #include "jerk.h"
 #include "harmonics.h"
+#include "range_loads.h"
 
 namespace fmm {
 

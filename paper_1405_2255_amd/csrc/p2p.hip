@@ -19,6 +19,7 @@
 
 #include "internal.h"
 #include "dev.h"
+#include "range_loads.h"
 
 namespace fmm {
 
