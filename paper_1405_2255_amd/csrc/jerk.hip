@@ -235,13 +235,12 @@ __device__ __forceinline__ void pair_jerk(const double4 s, const double4 va, boo
     k.jz = fma(q3, fma(-rv, dz, uz), k.jz);
 }
 
-// one lane's share of a source range: sources a, a + stride, ... below e, the
-// next source loaded before the current one is summed; CHECK: the range may
-// hold the sinks themselves (skipped by index)
-template <bool CHECK>
-__device__ __forceinline__ void sum_range_jerk(const double4 *xyzm, const double4 *v4, int a,
-                                               int e, int stride, const int (&self)[JR],
-                                               Sink (&k)[JR]) {
+// one lane's share of a source range that overlaps its sinks' own leaf:
+// sources a, a + stride, ... below e (the sinks themselves skipped by index),
+// the next source loaded before the current one is summed
+__device__ __forceinline__ void sum_own_jerk(const double4 *xyzm, const double4 *v4, int a,
+                                             int e, int stride, const int (&self)[JR],
+                                             Sink (&k)[JR]) {
     if (a >= e) return;
     double4 s = xyzm[a], va = v4[a];
     for (;;) {
@@ -249,7 +248,7 @@ __device__ __forceinline__ void sum_range_jerk(const double4 *xyzm, const double
         const bool more = b < e;
         const double4 s2 = xyzm[more ? b : a], vb = v4[more ? b : a];
 #pragma unroll
-        for (int r = 0; r < JR; ++r) pair_jerk(s, va, CHECK && a == self[r], k[r]);
+        for (int r = 0; r < JR; ++r) pair_jerk(s, va, a == self[r], k[r]);
         if (!more) break;
         a = b;
         s = s2;
@@ -323,7 +322,7 @@ k_p2p_jerk(int ntasks, const int2 *tasks, const int *leaf_cell, const int *nsrc_
                 left -= rg.y - rg.x;
                 if (!active) continue;
                 const bool own = rg.x < sb + nb && rg.y > sb;   // overlaps the task's sinks
-                if (own) sum_range_jerk<true>(xyzm, v4, rg.x + phase, rg.y, S, self, k);
+                if (own) sum_own_jerk(xyzm, v4, rg.x + phase, rg.y, S, self, k);
                 else sum_far_jerk(xyzm + rg.x, v4 + rg.x, phase, (uint32_t)(rg.y - rg.x), S, k);
             }
         }

@@ -144,13 +144,14 @@ __device__ __forceinline__ void pair(const double4 s, const double4 xb, bool ski
 // Mixed precision: the separation is formed in FP64 and rounded once; the
 // squared distance, reciprocal square root, products and the running sums
 // are FP32 (every pair's contribution carries a relative error of a few
-// FP32 units).
+// FP32 units).  Only ranges without the sinks themselves come here: no
+// self-pair test.
 template <int WANT_F, int WITH_POT>
-__device__ __forceinline__ void pair32(const double4 s, const double4 xb, bool skip, float &pot,
-                                       float &ax, float &ay, float &az) {
+__device__ __forceinline__ void pair32(const double4 s, const double4 xb, float &pot, float &ax,
+                                       float &ay, float &az) {
     const float dx = (float)(s.x - xb.x), dy = (float)(s.y - xb.y), dz = (float)(s.z - xb.z);
-    const float r2 = skip ? 1.0f : fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-    const float mu = skip ? 0.0f : (float)s.w;
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    const float mu = (float)s.w;
     if (WANT_F) {
         pot += mu * __builtin_amdgcn_rcpf(r2);
     } else {
@@ -227,7 +228,7 @@ __device__ __forceinline__ void sum_far32(const double4 *base, uint32_t i, uint3
             const double4 a = load_source(b + o);
 #pragma unroll
             for (int k = 0; k < R; ++k)
-                pair32<WANT_F, WITH_POT>(a, xb[k], false, g[k].x, g[k].y, g[k].z, g[k].w);
+                pair32<WANT_F, WITH_POT>(a, xb[k], g[k].x, g[k].y, g[k].z, g[k].w);
         }
         constexpr double sp = WANT_F ? 1.0 : 1.0 / P2P_POT_BACK;
         constexpr double sa = WANT_F ? 1.0 : 1.0 / P2P_ACC_BACK;
